@@ -50,8 +50,33 @@ CovParams cov_params(const gp_theta_t &th, int dim) {
 
 // ---- workspace layouts ------------------------------------------------------
 struct Layout {
-    size_t dinv = 0, sync = 0, z = 0, vec2 = 0, vec3 = 0, part = 0, big1 = 0, big2 = 0, total = 0;
+    size_t dinv = 0, sync = 0, z = 0, vec2 = 0, vec3 = 0, vec4 = 0, vec5 = 0, part = 0, big1 = 0, big2 = 0,
+           big3 = 0, irst = 0, perm = 0, keys = 0, box = 0, xp = 0, yp = 0, mup = 0, total = 0;
 };
+
+inline int64_t next_pow2(int64_t n) {
+    int64_t p = 1;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+// Blocked triangular inverse by recursive doubling: at level S (S = 128, 256,
+// ...) node a covers rows/cols [a S, min((a + 1) S, n)); its top half [aS,
+// aS + S/2) and bottom half (h2 rows) are already inverted.  The product
+// T = L21 W11 (h2 x S/2) of every node of the level lives in one buffer.
+size_t trtri_tmp_elems(int64_t n) {
+    size_t mx = 1;
+    for (int64_t S = 2 * DB; S / 2 < n; S *= 2) {
+        const int64_t h = S / 2;
+        size_t tot = 0;
+        for (int64_t o = 0; o + h < n; o += S) {
+            const int64_t h2 = (o + S <= n) ? h : n - o - h;
+            tot += (size_t)h2 * (size_t)h;
+        }
+        if (tot > mx) mx = tot;
+    }
+    return mx;
+}
 
 constexpr int GRAD_PARTS = 2048;
 
@@ -75,24 +100,40 @@ Layout layout(gp_op_t op, int64_t n, int64_t m, gp_prec_t prec) {
         break;
     case GP_OP_TRSM:
         L.dinv = take(sizeof(double) * DB * DB * (size_t)nb);
-        L.big1 = take(sizeof(double) * DB * (size_t)(m > 0 ? m : 1));
+        L.part = take(sizeof(double) * DB * (size_t)(m > 0 ? m : 1));
         break;
     case GP_OP_LOGLIK:
     case GP_OP_LOGLIK_GRAD:
         L.dinv = take(sizeof(double) * DB * DB * (size_t)nb);
         L.sync = take(sizeof(int) * (size_t)(nb + 2));
-        L.z = take(vec);
-        L.vec2 = take(vec);
-        L.vec3 = take(vec);
+        L.z = take(vec);     // L^{-1} b
+        L.vec2 = take(vec);  // x = C^{-1} b (evaluation order)
+        L.vec3 = take(vec);  // b = y - mu (evaluation order)
         L.part = take(sizeof(double) * (size_t)(6 * GRAD_PARTS > 4 * (n + 8) ? 6 * GRAD_PARTS : 4 * (n + 8)));
         if (prec != GP_FP64) {
-            // residual partials of the matrix-free FP64 residual
+            L.vec4 = take(vec);  // residual
+            L.vec5 = take(vec);  // correction
+            L.irst = take(sizeof(double) * 8 + sizeof(int32_t) * 4);
             L.big2 = take(sizeof(double) * (size_t)(n > 0 ? n : 1) * (size_t)resid_chunks(n > 0 ? n : 1));
+            L.perm = take(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+            L.keys = take(sizeof(uint64_t) * (size_t)next_pow2(n > 0 ? n : 1));
+            L.box = take(sizeof(double) * 4);
+            L.xp = take(sizeof(double) * 16 * (size_t)(n > 0 ? n : 1));
+            L.yp = take(vec);
+            L.mup = take(vec);
         }
         if (op == GP_OP_LOGLIK_GRAD) {
-            // W = L^{-1} (n x n) for the explicit inverse
+            // W = L^{-1} (n x n, ld n) and the product buffer of the blocked inverse
             L.big1 = take(sizeof(double) * (size_t)(n > 0 ? n : 1) * (size_t)(n > 0 ? n : 1));
+            L.big3 = take(sizeof(double) * trtri_tmp_elems(n));
         }
+        break;
+    case GP_OP_BATCHED:
+        L.total = batch_ws_bytes(n > 0 ? n : 1, m > 0 ? m : 1);
+        return L;
+    case GP_OP_MORTON:
+        L.keys = take(sizeof(uint64_t) * (size_t)next_pow2(n > 0 ? n : 1));
+        L.box = take(sizeof(double) * 4);
         break;
     case GP_OP_KRIGE:
         L.dinv = take(sizeof(double) * DB * DB * (size_t)nb);
@@ -195,6 +236,196 @@ int potrf_impl(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda,
     return GP_OK;
 }
 
+
+// ---- triangular solve with many right-hand sides ----------------------------
+// Right-looking by 64-row blocks with the stored diagonal inverses: each block
+// row is multiplied by its inverse (out of place through tmp), then the rows
+// below (NOTRANS) or above (TRANS) are updated; the updates are gathered per
+// 256-row band so the large product runs with K = 256 on the matrix cores.
+int trsm_impl(gp_handle_t h, int trans, int64_t n, int64_t nrhs, const double *L, int64_t ldl, double *B,
+              int64_t ldb, const double *dinv, double *tmp, const int32_t *info) {
+    hipStream_t s = h->stream;
+    const int64_t NBT = 256;
+    auto gemm = [&](int ta, const double *A, int64_t lda, const double *Bm, int64_t ldbm, double *C, int64_t ldc,
+                    int64_t M, int64_t N, int64_t K, double alpha, double beta) -> hipError_t {
+        GemmDesc d{};
+        d.A = A; d.lda = lda; d.B = Bm; d.ldb = ldbm; d.C = C; d.ldc = ldc;
+        d.M = M; d.N = N; d.K = K; d.alpha = alpha; d.beta = beta;
+        d.ta = ta; d.tb = 0; d.lower = 0; d.batch = 1; d.info = info;
+        return launch_gemm_f64(s, d);
+    };
+    if (n <= 0 || nrhs <= 0) return GP_OK;
+    if (!trans) {
+        for (int64_t kb0 = 0; kb0 < n; kb0 += NBT) {
+            const int64_t kb1 = (kb0 + NBT < n) ? kb0 + NBT : n;
+            for (int64_t d = kb0; d < kb1; d += DB) {
+                const int64_t jb = (n - d) < DB ? (n - d) : DB;
+                HIPCHK(launch_copy2d(s, jb, nrhs, B + d, ldb, tmp, DB));
+                HIPCHK(gemm(0, dinv + (d / DB) * DB * DB, DB, tmp, DB, B + d, ldb, jb, nrhs, jb, 1.0, 0.0));
+                if (d + jb < kb1)
+                    HIPCHK(gemm(0, L + (d + jb) + d * ldl, ldl, B + d, ldb, B + d + jb, ldb, kb1 - d - jb, nrhs, jb,
+                                -1.0, 1.0));
+            }
+            if (kb1 < n)
+                HIPCHK(gemm(0, L + kb1 + kb0 * ldl, ldl, B + kb0, ldb, B + kb1, ldb, n - kb1, nrhs, kb1 - kb0, -1.0,
+                            1.0));
+        }
+    } else {
+        const int64_t nblk = nblocks(n);
+        int64_t kb1 = n;
+        while (kb1 > 0) {
+            const int64_t kb0 = ((kb1 - 1) / NBT) * NBT;
+            for (int64_t b = (kb1 - 1) / DB; b >= kb0 / DB; --b) {
+                const int64_t d = b * DB;
+                const int64_t jb = (n - d) < DB ? (n - d) : DB;
+                HIPCHK(launch_copy2d(s, jb, nrhs, B + d, ldb, tmp, DB));
+                HIPCHK(gemm(1, dinv + b * DB * DB, DB, tmp, DB, B + d, ldb, jb, nrhs, jb, 1.0, 0.0));
+                if (d > kb0)
+                    HIPCHK(gemm(1, L + d + kb0 * ldl, ldl, B + d, ldb, B + kb0, ldb, d - kb0, nrhs, jb, -1.0, 1.0));
+            }
+            if (kb0 > 0)
+                HIPCHK(gemm(1, L + kb0, ldl, B + kb0, ldb, B, ldb, kb0, nrhs, kb1 - kb0, -1.0, 1.0));
+            kb1 = kb0;
+            (void)nblk;
+        }
+    }
+    return GP_OK;
+}
+
+// ---- C^{-1} = L^{-T} L^{-1} (lower) from the factor ------------------------
+// W = L^{-1} by recursive doubling on 64-blocks (Winv of each diagonal block
+// from the factorisation, then per level W21 = -W22 (L21 W11)), followed by
+// C^{-1} = W^T W restricted to the lower triangle (K runs from the tile row,
+// as rows of W above it are zero).  Both steps run on the matrix cores.
+int cinv_impl(gp_handle_t h, int64_t n, double *C, int64_t ldc, const double *dinv, double *W, double *T,
+              const int32_t *info) {
+    hipStream_t s = h->stream;
+    const int64_t ldw = n;
+    HIPCHK(launch_fill(s, W, sizeof(double) * (size_t)n * (size_t)n));
+    HIPCHK(launch_place_dinv(s, n, dinv, W, ldw));
+    for (int64_t S = 2 * DB; S / 2 < n; S *= 2) {
+        const int64_t hh = S / 2;
+        const int64_t nfull = n / S;
+        if (nfull > 0) {
+            GemmDesc d{};
+            d.A = C + hh; d.lda = ldc; d.sA = S * (1 + ldc);           // L21 of node 0
+            d.B = W; d.ldb = ldw; d.sB = S * (1 + ldw);                 // W11
+            d.C = T; d.ldc = hh; d.sC = hh * hh;
+            d.M = hh; d.N = hh; d.K = hh; d.alpha = 1.0; d.beta = 0.0;
+            d.klo_j = 1; d.batch = nfull; d.info = info;
+            HIPCHK(launch_gemm_f64(s, d));
+            GemmDesc e{};
+            e.A = W + hh * (1 + ldw); e.lda = ldw; e.sA = S * (1 + ldw);  // W22
+            e.B = T; e.ldb = hh; e.sB = hh * hh;
+            e.C = W + hh; e.ldc = ldw; e.sC = S * (1 + ldw);              // W21
+            e.M = hh; e.N = hh; e.K = hh; e.alpha = -1.0; e.beta = 0.0;
+            e.khi_i = 1; e.batch = nfull; e.info = info;
+            HIPCHK(launch_gemm_f64(s, e));
+        }
+        const int64_t o = nfull * S;
+        const int64_t h2 = n - o - hh;
+        if (h2 > 0) {
+            GemmDesc d{};
+            d.A = C + (o + hh) + o * ldc; d.lda = ldc;
+            d.B = W + o * (1 + ldw); d.ldb = ldw;
+            d.C = T; d.ldc = h2;
+            d.M = h2; d.N = hh; d.K = hh; d.alpha = 1.0; d.beta = 0.0;
+            d.klo_j = 1; d.batch = 1; d.info = info;
+            HIPCHK(launch_gemm_f64(s, d));
+            GemmDesc e{};
+            e.A = W + (o + hh) * (1 + ldw); e.lda = ldw;
+            e.B = T; e.ldb = h2;
+            e.C = W + (o + hh) + o * ldw; e.ldc = ldw;
+            e.M = h2; e.N = hh; e.K = h2; e.alpha = -1.0; e.beta = 0.0;
+            e.khi_i = 1; e.batch = 1; e.info = info;
+            HIPCHK(launch_gemm_f64(s, e));
+        }
+    }
+    GemmDesc d{};
+    d.A = W; d.lda = ldw; d.ta = 1;
+    d.B = W; d.ldb = ldw; d.tb = 0;
+    d.C = C; d.ldc = ldc;
+    d.M = n; d.N = n; d.K = n; d.alpha = 1.0; d.beta = 0.0;
+    d.lower = 1; d.klo_i = 1; d.batch = 1; d.info = info;
+    HIPCHK(launch_gemm_f64(s, d));
+    return GP_OK;
+}
+
+
+// ---- one likelihood evaluation (optionally with gradient) -------------------
+// FP64: C(theta) -> L -> z = L^{-1} b -> (logdet, q) -> alpha = L^{-T} z.
+// Mixed: the points are optionally taken in Morton order, the trailing
+// updates run in low precision, then x = C^{-1} b is refined against the FP64
+// covariance regenerated from the points (matrix-free residual) and
+// q = b^T x; the log-determinant comes from the mixed factor.
+int loglik_core(gp_handle_t h, gp_op_t op, gp_theta_t th, gp_prec_t prec, int64_t n, int32_t dim,
+                const double *X, const double *y, const double *mu, double *C, int64_t ldc, double *out3,
+                double *grad3, double *alpha_dev, int32_t *info, double *ir, void *ws) {
+    const Layout lay = layout(op, n, 0, prec);
+    hipStream_t s = h->stream;
+    const CovParams cp = cov_params(th, dim);
+    double *dinv = at<double>(ws, lay.dinv);
+    int *sync = at<int>(ws, lay.sync);
+    double *z = at<double>(ws, lay.z);
+    double *x = at<double>(ws, lay.vec2);
+    double *b = at<double>(ws, lay.vec3);
+    const bool mixed = prec != GP_FP64;
+    const double *Xe = X, *ye = y, *mue = mu;
+    int64_t *perm = nullptr;
+    if (mixed && h->opt.reorder && n > 1) {
+        perm = at<int64_t>(ws, lay.perm);
+        double *Xp = at<double>(ws, lay.xp), *yp = at<double>(ws, lay.yp), *mp = at<double>(ws, lay.mup);
+        HIPCHK(launch_morton(s, n, dim, X, perm, at<uint64_t>(ws, lay.keys), at<double>(ws, lay.box)));
+        HIPCHK(launch_gather_points(s, n, dim, perm, X, y, mu, Xp, yp, mp));
+        Xe = Xp;
+        ye = yp;
+        mue = mu ? mp : nullptr;
+    }
+    HIPCHK(launch_cov_lower(s, cp, n, Xe, C, ldc, nullptr));
+    int rc = potrf_impl(h, prec, n, C, ldc, info, dinv);
+    if (rc) return rc;
+    HIPCHK(launch_sub_mu(s, n, ye, mue, b));
+    HIPCHK(launch_copy_vec(s, n, b, z));
+    HIPCHK(launch_trsv(s, 0, C, ldc, z, n, dinv, sync, info));
+    HIPCHK(launch_loglik_reduce(s, n, C, ldc, z, out3, info, sync));
+    const bool need_x = alpha_dev || grad3 || mixed;
+    if (need_x) {
+        HIPCHK(launch_copy_vec(s, n, z, x));
+        HIPCHK(launch_trsv(s, 1, C, ldc, x, n, dinv, sync, info));
+    }
+    if (mixed) {
+        double *res = at<double>(ws, lay.vec4), *dv = at<double>(ws, lay.vec5);
+        double *state = at<double>(ws, lay.irst);
+        int32_t *done = reinterpret_cast<int32_t *>(state + 8);
+        HIPCHK(launch_ir_init(s, n, b, state, done, info));
+        const int maxit = h->opt.ir_max_iter;
+        for (int it = 0; it <= maxit; ++it) {
+            HIPCHK(launch_resid_matfree(s, cp, n, Xe, b, x, res, at<double>(ws, lay.big2), done));
+            HIPCHK(launch_ir_check(s, n, res, state, done, it == maxit, h->opt.ir_tol));
+            if (it == maxit) break;
+            HIPCHK(launch_copy_skip(s, n, res, dv, done));
+            HIPCHK(launch_trsv(s, 0, C, ldc, dv, n, dinv, sync, done));
+            HIPCHK(launch_trsv(s, 1, C, ldc, dv, n, dinv, sync, done));
+            HIPCHK(launch_axpy_skip(s, n, dv, x, done));
+        }
+        HIPCHK(launch_ir_finish(s, n, b, x, state, out3, ir, info));
+    }
+    if (alpha_dev) {
+        if (perm) HIPCHK(launch_scatter_vec(s, n, perm, x, alpha_dev));
+        else HIPCHK(launch_copy_vec(s, n, x, alpha_dev));
+    }
+    if (grad3) {
+        if (n > 0) {
+            rc = cinv_impl(h, n, C, ldc, dinv, at<double>(ws, lay.big1), at<double>(ws, lay.big3), info);
+            if (rc) return rc;
+        }
+        double *part = at<double>(ws, lay.part);
+        HIPCHK(launch_grad_contract(s, cp, n, Xe, C, ldc, x, part, GRAD_PARTS, info));
+        HIPCHK(launch_grad_finish(s, GRAD_PARTS, part, grad3, info));
+    }
+    return GP_OK;
+}
+
 }  // namespace
 
 // ============================================================================
@@ -229,6 +460,7 @@ int gp_create(gp_handle_t *h, void *stream) {
     default_options(&p->opt);
     p->stream = (hipStream_t)stream;
     if (hipGetDevice(&p->device) != hipSuccess ||
+        hipDeviceGetAttribute(&p->num_cu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess ||
         hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_cols, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_panel, hipEventDisableTiming) != hipSuccess) {
@@ -269,7 +501,8 @@ int gp_profile_read(gp_handle_t h, double *out3) {
 
 int gp_destroy(gp_handle_t h) {
     if (!ok_handle(h)) return -1;
-    for (hipEvent_t e : h->prof_ev) hipEventDestroy(e);
+    for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
+    batch_staging_free(h->batch_staging);
     hipStreamSynchronize(h->side);
     hipStreamDestroy(h->side);
     hipEventDestroy(h->ev_cols);
@@ -355,7 +588,6 @@ int gp_potrf(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda, i
     Layout L = layout(GP_OP_POTRF, n, 0, prec);
     if (!ws) return -7;
     if (ws_bytes < L.total) return GP_ERR_WS_TOO_SMALL;
-    if (prec != GP_FP64) return GP_ERR_NOT_SUPPORTED;
     return potrf_impl(h, prec, n, A, lda, info_dev, at<double>(ws, L.dinv));
 }
 
@@ -387,9 +619,13 @@ int gp_trsm(gp_handle_t h, gp_trans_t trans, int64_t n, int64_t nrhs, const doub
     if (ldl < (n > 1 ? n : 1)) return -6;
     if (n > 0 && nrhs > 0 && !B) return -7;
     if (ldb < (n > 1 ? n : 1)) return -8;
+    Layout lay = layout(GP_OP_TRSM, n, nrhs, GP_FP64);
     if (!ws) return -9;
-    (void)ws_bytes;
-    return GP_ERR_NOT_SUPPORTED;
+    if (ws_bytes < lay.total) return GP_ERR_WS_TOO_SMALL;
+    if (n == 0 || nrhs == 0) return GP_OK;
+    double *dinv = at<double>(ws, lay.dinv);
+    HIPCHK(launch_diag_inv(h->stream, L, ldl, n, dinv));
+    return trsm_impl(h, trans == GP_TRANS, n, nrhs, L, ldl, B, ldb, dinv, at<double>(ws, lay.part), nullptr);
 }
 
 int gp_loglik(gp_handle_t h, gp_theta_t th, gp_prec_t prec, int64_t n, int32_t dim, const double *X,
@@ -409,55 +645,113 @@ int gp_loglik(gp_handle_t h, gp_theta_t th, gp_prec_t prec, int64_t n, int32_t d
     Layout lay = layout(GP_OP_LOGLIK, n, 0, prec);
     if (!ws) return -15;
     if (ws_bytes < lay.total) return GP_ERR_WS_TOO_SMALL;
-    if (prec != GP_FP64) return GP_ERR_NOT_SUPPORTED;
-    (void)ir_dev;
-    hipStream_t s = h->stream;
-    double *dinv = at<double>(ws, lay.dinv);
-    int *sync = at<int>(ws, lay.sync);
-    double *z = at<double>(ws, lay.z);
-    HIPCHK(launch_cov_lower(s, cov_params(th, dim), n, X, C, ldc, nullptr));
-    int rc = potrf_impl(h, prec, n, C, ldc, info_dev, dinv);
-    if (rc) return rc;
-    HIPCHK(launch_sub_mu(s, n, y, mu, z));
-    HIPCHK(launch_trsv(s, 0, C, ldc, z, n, dinv, sync, info_dev));
-    HIPCHK(launch_loglik_reduce(s, n, C, ldc, z, out3_dev, info_dev, sync));
-    if (alpha_dev) {
-        HIPCHK(launch_copy_vec(s, n, z, alpha_dev));
-        HIPCHK(launch_trsv(s, 1, C, ldc, alpha_dev, n, dinv, sync, info_dev));
-    }
-    return GP_OK;
+    return loglik_core(h, GP_OP_LOGLIK, th, prec, n, dim, X, y, mu, C, ldc, out3_dev, nullptr, alpha_dev,
+                       info_dev, ir_dev, ws);
 }
 
 int gp_loglik_grad(gp_handle_t h, gp_theta_t th, gp_prec_t prec, int64_t n, int32_t dim, const double *X,
                    const double *y, const double *mu, double *C, int64_t ldc, double *out3_dev,
                    double *grad3_dev, double *alpha_dev, int32_t *info_dev, double *ir_dev, void *ws,
                    size_t ws_bytes) {
-    (void)h; (void)th; (void)prec; (void)n; (void)dim; (void)X; (void)y; (void)mu; (void)C; (void)ldc;
-    (void)out3_dev; (void)grad3_dev; (void)alpha_dev; (void)info_dev; (void)ir_dev; (void)ws; (void)ws_bytes;
-    return GP_ERR_NOT_SUPPORTED;
+    if (!ok_handle(h)) return -1;
+    if (int e = check_theta(th)) return e == 1 ? -2 : GP_ERR_NONFINITE;
+    if ((int)prec < GP_FP64 || (int)prec > GP_BF16_TRAIL) return -3;
+    if (n < 0) return -4;
+    if (dim < 1 || dim > 16) return -5;
+    if (n > 0 && !X) return -6;
+    if (n > 0 && !y) return -7;
+    if (n > 0 && !C) return -9;
+    if (ldc < (n > 1 ? n : 1)) return -10;
+    if (!out3_dev) return -11;
+    if (!grad3_dev) return -12;
+    if (!info_dev) return -14;
+    Layout lay = layout(GP_OP_LOGLIK_GRAD, n, 0, prec);
+    if (!ws) return -16;
+    if (ws_bytes < lay.total) return GP_ERR_WS_TOO_SMALL;
+    return loglik_core(h, GP_OP_LOGLIK_GRAD, th, prec, n, dim, X, y, mu, C, ldc, out3_dev, grad3_dev, alpha_dev,
+                       info_dev, ir_dev, ws);
 }
 
 int gp_krige(gp_handle_t h, gp_theta_t th, int64_t n, int64_t m, int32_t dim, const double *X,
              const double *Xs, const double *L, int64_t ldl, const double *alpha, double mu,
              double *mean_dev, double *var_dev, int32_t include_nugget, void *ws, size_t ws_bytes) {
-    (void)h; (void)th; (void)n; (void)m; (void)dim; (void)X; (void)Xs; (void)L; (void)ldl; (void)alpha;
-    (void)mu; (void)mean_dev; (void)var_dev; (void)include_nugget; (void)ws; (void)ws_bytes;
-    return GP_ERR_NOT_SUPPORTED;
+    if (!ok_handle(h)) return -1;
+    if (int e = check_theta(th)) return e == 1 ? -2 : GP_ERR_NONFINITE;
+    if (n < 0) return -3;
+    if (m < 0) return -4;
+    if (dim < 1 || dim > 16) return -5;
+    if (n > 0 && !X) return -6;
+    if (m > 0 && !Xs) return -7;
+    if (n > 0 && !L) return -8;
+    if (ldl < (n > 1 ? n : 1)) return -9;
+    if (n > 0 && !alpha) return -10;
+    if (!isfinite(mu)) return GP_ERR_NONFINITE;
+    if (m > 0 && !mean_dev) return -12;
+    if (m > 0 && !var_dev) return -13;
+    Layout lay = layout(GP_OP_KRIGE, n, m, GP_FP64);
+    if (!ws) return -15;
+    if (ws_bytes < lay.total) return GP_ERR_WS_TOO_SMALL;
+    if (m == 0) return GP_OK;
+    hipStream_t s = h->stream;
+    const CovParams cp = cov_params(th, dim);
+    const double base_var = cp.s2 + (include_nugget ? cp.t2 : 0.0);
+    double *Cs = at<double>(ws, lay.big1);
+    const int64_t ldcs = n > 0 ? n : 1;
+    if (n == 0) {
+        HIPCHK(launch_colreduce(s, 0, 0, m, Cs, ldcs, nullptr, mu, mean_dev));
+        HIPCHK(launch_colreduce(s, 1, 0, m, Cs, ldcs, nullptr, base_var, var_dev));
+        return GP_OK;
+    }
+    double *dinv = at<double>(ws, lay.dinv);
+    HIPCHK(launch_diag_inv(s, L, ldl, n, dinv));
+    HIPCHK(launch_cross_cov(s, cp, n, m, X, Xs, Cs, ldcs));
+    HIPCHK(launch_colreduce(s, 0, n, m, Cs, ldcs, alpha, mu, mean_dev));
+    int rc = trsm_impl(h, 0, n, m, L, ldl, Cs, ldcs, dinv, at<double>(ws, lay.part), nullptr);
+    if (rc) return rc;
+    HIPCHK(launch_colreduce(s, 1, n, m, Cs, ldcs, nullptr, base_var, var_dev));
+    return GP_OK;
 }
 
 int gp_loglik_batched(gp_handle_t h, int32_t nbatch, const gp_theta_t *th_host, const int64_t *n_host,
                       const int64_t *x_off_host, const int64_t *c_off_host, int32_t dim, const double *X,
                       const double *y, double *C_pool, double *out3_dev, int32_t *info_dev, void *ws,
                       size_t ws_bytes) {
-    (void)h; (void)nbatch; (void)th_host; (void)n_host; (void)x_off_host; (void)c_off_host; (void)dim;
-    (void)X; (void)y; (void)C_pool; (void)out3_dev; (void)info_dev; (void)ws; (void)ws_bytes;
-    return GP_ERR_NOT_SUPPORTED;
+    if (!ok_handle(h)) return -1;
+    if (nbatch < 0) return -2;
+    if (nbatch > 0 && !th_host) return -3;
+    if (nbatch > 0 && !n_host) return -4;
+    if (nbatch > 0 && !x_off_host) return -5;
+    if (nbatch > 0 && !c_off_host) return -6;
+    if (dim < 1 || dim > 16) return -7;
+    int64_t tot = 0;
+    for (int b = 0; b < nbatch; ++b) {
+        if (int e = check_theta(th_host[b])) return e == 1 ? -3 : GP_ERR_NONFINITE;
+        if (n_host[b] < 0) return -4;
+        if (x_off_host[b] < 0) return -5;
+        if (c_off_host[b] < 0) return -6;
+        tot += n_host[b];
+    }
+    if (tot > 0 && (!X || !y || !C_pool)) return !X ? -8 : (!y ? -9 : -10);
+    if (nbatch > 0 && !out3_dev) return -11;
+    if (nbatch > 0 && !info_dev) return -12;
+    if (!ws) return -13;
+    if (nbatch == 0) return GP_OK;
+    return batch_run(h->stream, h->num_cu, h->batch_staging, nbatch, th_host, n_host, x_off_host, c_off_host, dim,
+                     X, y, C_pool, out3_dev, info_dev, ws, ws_bytes);
 }
 
 int gp_morton_order(gp_handle_t h, int64_t n, int32_t dim, const double *X, int64_t *perm_dev, void *ws,
                     size_t ws_bytes) {
-    (void)h; (void)n; (void)dim; (void)X; (void)perm_dev; (void)ws; (void)ws_bytes;
-    return GP_ERR_NOT_SUPPORTED;
+    if (!ok_handle(h)) return -1;
+    if (n < 0 || n >= (int64_t(1) << 22)) return -2;
+    if (dim < 1 || dim > 16) return -3;
+    if (n > 0 && !X) return -4;
+    if (n > 0 && !perm_dev) return -5;
+    Layout lay = layout(GP_OP_MORTON, n, 0, GP_FP64);
+    if (!ws) return -6;
+    if (ws_bytes < lay.total) return GP_ERR_WS_TOO_SMALL;
+    HIPCHK(launch_morton(h->stream, n, dim, X, perm_dev, at<uint64_t>(ws, lay.keys), at<double>(ws, lay.box)));
+    return GP_OK;
 }
 
 }  // extern "C"

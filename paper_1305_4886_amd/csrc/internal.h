@@ -32,6 +32,8 @@ struct gp_handle_s {
     size_t prof_used = 0;             // events in use
     double prof_flops = 0.0;
     int64_t prof_launches = 0;
+    int num_cu = 256;                 // compute units of the device
+    void *batch_staging = nullptr;    // host staging of the batched task table
     int magic = 0x67706d69;
 };
 
@@ -132,6 +134,53 @@ GP_DEV bool wait_flag(const int *flag, int *abortf) {
     return true;
 }
 
+// Broadcast lane l's double (l a compile-time constant after unrolling).
+GP_DEV double rdlane(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// Cholesky of a 64 x 64 block held by one wave, lane r = row r (a[c] = A[r][c],
+// zero above the diagonal), right-looking column by column: pivot
+// sqrt(A_jj), scale column j, rank-1 update of the trailing lower part.  The
+// column entries are broadcast with readlane, so no memory round trip or
+// barrier sits between the steps.  Returns 0 or the first failing 1-based
+// column (a non-positive or NaN pivot); later columns then hold garbage.
+GP_DEV int wave_chol64(double (&a)[DB], int lane) {
+    int fail = 0;
+#pragma unroll
+    for (int j = 0; j < DB; ++j) {
+        const double piv = rdlane(a[j], j);
+        if (!(piv > 0.0) && fail == 0) fail = j + 1;
+        const double dj = sqrt(piv);
+        const double inv = 1.0 / dj;
+        a[j] = (lane == j) ? dj : ((lane > j) ? a[j] * inv : a[j]);
+#pragma unroll
+        for (int c = j + 1; c < DB; ++c) {
+            const double lcj = rdlane(a[j], c);
+            a[c] = (lane >= c) ? fma(-a[j], lcj, a[c]) : a[c];
+        }
+    }
+    return fail;
+}
+
+// W = L^{-1} for the 64 x 64 lower factor in LDS (Ls[i][k] = L_ik), one wave,
+// lane c computes column c by forward substitution:
+//   W_ic = (delta_ic - sum_{c <= k < i} L_ik W_kc) / L_ii;
+// rows above c are zero, so the sum may run over all k < i.  Row i of L is a
+// broadcast LDS read (the same address for every lane).
+GP_DEV void wave_inv64(const double (*Ls)[DB + 1], double (&w)[DB], int lane) {
+#pragma unroll
+    for (int i = 0; i < DB; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < i; ++k) s = fma(Ls[i][k], w[k], s);
+        const double lii = Ls[i][i];
+        w[i] = (lane == i) ? 1.0 / lii : ((lane < i) ? -s / lii : 0.0);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Launchers (all enqueue on `s`, return hipError_t of the launch).
 // ---------------------------------------------------------------------------
@@ -195,4 +244,36 @@ hipError_t launch_loglik_reduce(hipStream_t s, int64_t n, const double *L, int64
                                 const double *z, double *out3, const int32_t *info,
                                 const int *sync);
 hipError_t launch_fill(hipStream_t s, void *p, size_t bytes);
+
+// k_aux.hip
+// mode 0: out[j] = base + sum_i M_ij v_i; mode 1: out[j] = base - sum_i M_ij^2.
+hipError_t launch_colreduce(hipStream_t s, int mode, int64_t n, int64_t m, const double *M, int64_t ld,
+                            const double *v, double base, double *out);
+hipError_t launch_copy2d(hipStream_t s, int64_t rows, int64_t cols, const double *src, int64_t lds, double *dst,
+                         int64_t ldd);
+hipError_t launch_place_dinv(hipStream_t s, int64_t n, const double *dinv, double *W, int64_t ldw);
+hipError_t launch_grad_finish(hipStream_t s, int nparts, const double *partials, double *grad3,
+                              const int32_t *info);
+// iterative refinement control (state: 8 doubles; done: int32 skip flag)
+hipError_t launch_ir_init(hipStream_t s, int64_t n, const double *b, double *state, int32_t *done,
+                          const int32_t *info);
+hipError_t launch_ir_check(hipStream_t s, int64_t n, const double *res, double *state, int32_t *done, int last,
+                           double tol);
+hipError_t launch_copy_skip(hipStream_t s, int64_t n, const double *a, double *b, const int32_t *done);
+hipError_t launch_axpy_skip(hipStream_t s, int64_t n, const double *dv, double *x, const int32_t *done);
+hipError_t launch_ir_finish(hipStream_t s, int64_t n, const double *b, const double *x, const double *state,
+                            double *out3, double *ir, const int32_t *info);
+// Morton order: keys needs next_pow2(n) uint64, box 4 doubles.
+hipError_t launch_morton(hipStream_t s, int64_t n, int dim, const double *X, int64_t *perm, uint64_t *keys,
+                         double *box);
+hipError_t launch_gather_points(hipStream_t s, int64_t n, int dim, const int64_t *perm, const double *X,
+                                const double *y, const double *mu, double *Xp, double *yp, double *mup);
+hipError_t launch_scatter_vec(hipStream_t s, int64_t n, const int64_t *perm, const double *src, double *dst);
 hipError_t launch_set_info(hipStream_t s, int32_t *info);
+
+// k_batch.hip
+size_t batch_ws_bytes(int64_t nmax, int64_t nbatch);
+int batch_run(hipStream_t s, int num_cu, void *&staging, int32_t nb, const gp_theta_t *th, const int64_t *nh,
+              const int64_t *xoff, const int64_t *coff, int32_t dim, const double *X, const double *y,
+              double *C_pool, double *out3, int32_t *info, void *ws, size_t ws_bytes);
+void batch_staging_free(void *p);

@@ -1,0 +1,368 @@
+// k_aux.hip -- small streaming kernels around the matrix-core products:
+// column reductions for kriging (c_j^T alpha and |w_j|^2, Section 1's
+// prediction and its variance), block copies for the blocked triangular
+// solve with many right-hand sides, and the placement of diagonal-block
+// inverses into the blocked triangular inverse.
+#include "internal.h"
+
+namespace {
+
+// One workgroup per column j of the n x m matrix M (ld):
+//   mode 0: out[j] = base + sum_i M_ij v_i        (kriging mean)
+//   mode 1: out[j] = base - sum_i M_ij^2          (kriging variance)
+// Compensated per-thread sums, then a fixed-order tree.
+__global__ __launch_bounds__(256) void k_colreduce(int mode, int64_t n, int64_t m, const double *M, int64_t ld,
+                                                   const double *v, double base, double *out) {
+    __shared__ double red[2 * 256];
+    const int64_t j = blockIdx.x;
+    if (j >= m) return;
+    const double *col = M + j * ld;
+    CSum s;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        const double x = col[i];
+        s.add(mode == 0 ? x * v[i] : x * x);
+    }
+    red[2 * threadIdx.x] = s.s;
+    red[2 * threadIdx.x + 1] = s.c;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            CSum a, b;
+            a.s = red[2 * threadIdx.x]; a.c = red[2 * threadIdx.x + 1];
+            b.s = red[2 * (threadIdx.x + st)]; b.c = red[2 * (threadIdx.x + st) + 1];
+            a.merge(b);
+            red[2 * threadIdx.x] = a.s; red[2 * threadIdx.x + 1] = a.c;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double t = red[0] + red[1];
+        out[j] = mode == 0 ? base + t : base - t;
+    }
+}
+
+// dst[i + j ldd] = src[i + j lds], rows x cols.
+__global__ __launch_bounds__(256) void k_copy2d(int64_t rows, int64_t cols, const double *src, int64_t lds,
+                                                double *dst, int64_t ldd) {
+    const int64_t j = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < rows; i += (int64_t)gridDim.x * 256)
+        dst[i + j * ldd] = src[i + j * lds];
+}
+
+// Diagonal 64-blocks of W from the stored block inverses (column-major, ld DB).
+__global__ __launch_bounds__(256) void k_place_dinv(int64_t n, const double *dinv, double *W, int64_t ldw) {
+    const int64_t b = blockIdx.x;
+    const int64_t b0 = b * DB;
+    const double *src = dinv + b * DB * DB;
+    for (int e = threadIdx.x; e < DB * DB; e += 256) {
+        const int i = e & (DB - 1), j = e >> 6;
+        if (b0 + i < n && b0 + j < n) W[(b0 + i) + (b0 + j) * ldw] = src[i + j * DB];
+    }
+}
+
+// Final fixed-order combination of per-workgroup (s, c) partial sums of the
+// gradient contraction: grad[q] = sum over parts.
+__global__ __launch_bounds__(64) void k_grad_finish(int nparts, const double *partials, double *grad3,
+                                                    const int32_t *info) {
+    if (threadIdx.x != 0) return;
+    if (info && *info) {
+        grad3[0] = grad3[1] = grad3[2] = __builtin_nan("");
+        return;
+    }
+    for (int q = 0; q < 3; ++q) {
+        CSum a;
+        for (int p = 0; p < nparts; ++p) {
+            CSum b;
+            b.s = partials[p * 6 + 2 * q];
+            b.c = partials[p * 6 + 2 * q + 1];
+            a.merge(b);
+        }
+        grad3[q] = a.value();
+    }
+}
+
+}  // namespace
+
+hipError_t launch_colreduce(hipStream_t s, int mode, int64_t n, int64_t m, const double *M, int64_t ld,
+                            const double *v, double base, double *out) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_colreduce, dim3((unsigned)m), dim3(256), 0, s, mode, n, m, M, ld, v, base, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy2d(hipStream_t s, int64_t rows, int64_t cols, const double *src, int64_t lds, double *dst,
+                         int64_t ldd) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    const int64_t gx = (rows + 255) / 256 < 64 ? (rows + 255) / 256 : 64;
+    hipLaunchKernelGGL(k_copy2d, dim3((unsigned)gx, (unsigned)cols), dim3(256), 0, s, rows, cols, src, lds, dst, ldd);
+    return hipGetLastError();
+}
+
+hipError_t launch_place_dinv(hipStream_t s, int64_t n, const double *dinv, double *W, int64_t ldw) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_place_dinv, dim3((unsigned)((n + DB - 1) / DB)), dim3(256), 0, s, n, dinv, W, ldw);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_finish(hipStream_t s, int nparts, const double *partials, double *grad3,
+                              const int32_t *info) {
+    hipLaunchKernelGGL(k_grad_finish, dim3(1), dim3(64), 0, s, nparts, partials, grad3, info);
+    return hipGetLastError();
+}
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Iterative refinement of x = C^{-1} b with a low-precision factor; control
+// lives on the device so no host synchronisation is needed.  state (doubles):
+// [0] |b|, [1] previous relative residual, [2] last relative residual,
+// [3] corrections applied, [4] converged (1) / not (0).  *done != 0 makes
+// every later kernel of the refinement a no-op.
+// ---------------------------------------------------------------------------
+GP_DEV void block_norm2(int64_t n, const double *v, double *red, CSum &out) {
+    CSum s;
+    for (int64_t i = threadIdx.x; i < n; i += 256) s.add(v[i] * v[i]);
+    red[2 * threadIdx.x] = s.s;
+    red[2 * threadIdx.x + 1] = s.c;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            CSum a, b;
+            a.s = red[2 * threadIdx.x]; a.c = red[2 * threadIdx.x + 1];
+            b.s = red[2 * (threadIdx.x + st)]; b.c = red[2 * (threadIdx.x + st) + 1];
+            a.merge(b);
+            red[2 * threadIdx.x] = a.s; red[2 * threadIdx.x + 1] = a.c;
+        }
+        __syncthreads();
+    }
+    out.s = red[0];
+    out.c = red[1];
+}
+
+__global__ __launch_bounds__(256) void k_ir_init(int64_t n, const double *b, double *state, int32_t *done,
+                                                 const int32_t *info) {
+    __shared__ double red[512];
+    CSum s;
+    block_norm2(n, b, red, s);
+    if (threadIdx.x == 0) {
+        state[0] = sqrt(s.value());
+        state[1] = __builtin_inf();
+        state[2] = __builtin_nan("");
+        state[3] = 0.0;
+        state[4] = 0.0;
+        *done = (info && *info) ? 1 : 0;
+    }
+}
+
+// Stop on convergence (rel <= tol), on the sweep cap, or when a sweep fails to
+// halve the residual (stagnation).
+__global__ __launch_bounds__(256) void k_ir_check(int64_t n, const double *res, double *state, int32_t *done,
+                                                  int last, double tol) {
+    __shared__ double red[512];
+    if (*done) return;
+    CSum s;
+    block_norm2(n, res, red, s);
+    if (threadIdx.x == 0) {
+        const double nb = state[0];
+        const double rel = nb > 0.0 ? sqrt(s.value()) / nb : 0.0;
+        state[2] = rel;
+        if (rel <= tol) {
+            state[4] = 1.0;
+            *done = 1;
+        } else if (last || !(rel <= 0.5 * state[1])) {
+            *done = 1;
+        } else {
+            state[1] = rel;
+            state[3] += 1.0;
+        }
+    }
+}
+
+// A sweep whose check stopped the refinement computed no new correction, so
+// every correction step of that sweep is skipped.
+__global__ void k_axpy_skip(int64_t n, const double *dv, double *x, const int32_t *done) {
+    if (*done) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] += dv[i];
+}
+
+__global__ void k_copy_skip(int64_t n, const double *a, double *b, const int32_t *done) {
+    if (*done) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+// q = b^T x, log-likelihood, refinement report.
+__global__ __launch_bounds__(256) void k_ir_finish(int64_t n, const double *b, const double *x, const double *state,
+                                                   double *out3, double *ir, const int32_t *info) {
+    __shared__ double red[512];
+    CSum s;
+    for (int64_t i = threadIdx.x; i < n; i += 256) s.add(b[i] * x[i]);
+    red[2 * threadIdx.x] = s.s;
+    red[2 * threadIdx.x + 1] = s.c;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            CSum a, c;
+            a.s = red[2 * threadIdx.x]; a.c = red[2 * threadIdx.x + 1];
+            c.s = red[2 * (threadIdx.x + st)]; c.c = red[2 * (threadIdx.x + st) + 1];
+            a.merge(c);
+            red[2 * threadIdx.x] = a.s; red[2 * threadIdx.x + 1] = a.c;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (info && *info) {
+            out3[0] = out3[1] = out3[2] = __builtin_nan("");
+        } else {
+            const double q = red[0] + red[1];
+            out3[2] = q;
+            out3[0] = -0.5 * (((double)n * 1.8378770664093453 + out3[1]) + q);
+        }
+        if (ir) {
+            ir[0] = state[3];
+            ir[1] = state[2];
+            ir[2] = state[4];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Morton (Z-order) permutation.  Coordinates 0 and 1 of each point are scaled
+// to 21-bit integers on the bounding box and bit-interleaved; the 42-bit code
+// is shifted above a 22-bit point index, so keys are unique and ties resolve
+// by index.  A bitonic network over the next power of two sorts the keys.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_bbox(int64_t n, int dim, const double *X, double *box) {
+    __shared__ double r[4][256];
+    double lo0 = __builtin_inf(), hi0 = -__builtin_inf(), lo1 = __builtin_inf(), hi1 = -__builtin_inf();
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        const double a = X[i * dim];
+        const double b = dim > 1 ? X[i * dim + 1] : 0.0;
+        lo0 = fmin(lo0, a); hi0 = fmax(hi0, a);
+        lo1 = fmin(lo1, b); hi1 = fmax(hi1, b);
+    }
+    r[0][threadIdx.x] = lo0; r[1][threadIdx.x] = hi0; r[2][threadIdx.x] = lo1; r[3][threadIdx.x] = hi1;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            r[0][threadIdx.x] = fmin(r[0][threadIdx.x], r[0][threadIdx.x + st]);
+            r[1][threadIdx.x] = fmax(r[1][threadIdx.x], r[1][threadIdx.x + st]);
+            r[2][threadIdx.x] = fmin(r[2][threadIdx.x], r[2][threadIdx.x + st]);
+            r[3][threadIdx.x] = fmax(r[3][threadIdx.x], r[3][threadIdx.x + st]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) box[threadIdx.x] = r[threadIdx.x][0];
+}
+
+GP_DEV uint64_t spread2_21(uint64_t v) {  // 21 bits -> even positions of 42 bits
+    uint64_t r = 0;
+    for (int b = 0; b < 21; ++b) r |= ((v >> b) & 1ull) << (2 * b);
+    return r;
+}
+
+__global__ void k_morton_keys(int64_t n, int64_t npow, int dim, const double *X, const double *box,
+                              uint64_t *keys) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npow) return;
+    if (i >= n) {
+        keys[i] = ~0ull;
+        return;
+    }
+    const double q = 2097151.0;  // 2^21 - 1
+    const double w0 = box[1] - box[0], w1 = box[3] - box[2];
+    const double a = X[i * dim], b = dim > 1 ? X[i * dim + 1] : 0.0;
+    const uint64_t qa = (uint64_t)(w0 > 0.0 ? fmin(fmax((a - box[0]) / w0, 0.0), 1.0) * q : 0.0);
+    const uint64_t qb = (uint64_t)(w1 > 0.0 ? fmin(fmax((b - box[2]) / w1, 0.0), 1.0) * q : 0.0);
+    const uint64_t code = spread2_21(qa) | (spread2_21(qb) << 1);
+    keys[i] = (code << 22) | (uint64_t)i;
+}
+
+__global__ void k_bitonic_step(uint64_t *keys, int64_t npow, int64_t j, int64_t k) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npow) return;
+    const int64_t l = i ^ j;
+    if (l <= i) return;
+    const uint64_t a = keys[i], b = keys[l];
+    const bool up = (i & k) == 0;
+    if ((a > b) == up) {
+        keys[i] = b;
+        keys[l] = a;
+    }
+}
+
+__global__ void k_keys_to_perm(int64_t n, const uint64_t *keys, int64_t *perm) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) perm[i] = (int64_t)(keys[i] & ((1ull << 22) - 1));
+}
+
+// Xp[i] = X[perm[i]] (dim columns), yp, mup.
+__global__ void k_gather_points(int64_t n, int dim, const int64_t *perm, const double *X, const double *y,
+                                 const double *mu, double *Xp, double *yp, double *mup) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t p = perm[i];
+    for (int d = 0; d < dim; ++d) Xp[i * dim + d] = X[p * dim + d];
+    yp[i] = y[p];
+    if (mu) mup[i] = mu[p];
+}
+
+__global__ void k_scatter_vec(int64_t n, const int64_t *perm, const double *src, double *dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[perm[i]] = src[i];
+}
+
+}  // namespace
+
+static inline unsigned nb256(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t launch_ir_init(hipStream_t s, int64_t n, const double *b, double *state, int32_t *done,
+                          const int32_t *info) {
+    hipLaunchKernelGGL(k_ir_init, dim3(1), dim3(256), 0, s, n, b, state, done, info);
+    return hipGetLastError();
+}
+hipError_t launch_ir_check(hipStream_t s, int64_t n, const double *res, double *state, int32_t *done, int last,
+                           double tol) {
+    hipLaunchKernelGGL(k_ir_check, dim3(1), dim3(256), 0, s, n, res, state, done, last, tol);
+    return hipGetLastError();
+}
+hipError_t launch_copy_skip(hipStream_t s, int64_t n, const double *a, double *b, const int32_t *done) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_skip, dim3(nb256(n)), dim3(256), 0, s, n, a, b, done);
+    return hipGetLastError();
+}
+hipError_t launch_axpy_skip(hipStream_t s, int64_t n, const double *dv, double *x, const int32_t *done) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_axpy_skip, dim3(nb256(n)), dim3(256), 0, s, n, dv, x, done);
+    return hipGetLastError();
+}
+hipError_t launch_ir_finish(hipStream_t s, int64_t n, const double *b, const double *x, const double *state,
+                            double *out3, double *ir, const int32_t *info) {
+    hipLaunchKernelGGL(k_ir_finish, dim3(1), dim3(256), 0, s, n, b, x, state, out3, ir, info);
+    return hipGetLastError();
+}
+hipError_t launch_morton(hipStream_t s, int64_t n, int dim, const double *X, int64_t *perm, uint64_t *keys,
+                         double *box) {
+    if (n <= 0) return hipSuccess;
+    int64_t npow = 1;
+    while (npow < n) npow <<= 1;
+    hipLaunchKernelGGL(k_bbox, dim3(1), dim3(256), 0, s, n, dim, X, box);
+    hipLaunchKernelGGL(k_morton_keys, dim3(nb256(npow)), dim3(256), 0, s, n, npow, dim, X, box, keys);
+    for (int64_t k = 2; k <= npow; k <<= 1)
+        for (int64_t j = k >> 1; j > 0; j >>= 1)
+            hipLaunchKernelGGL(k_bitonic_step, dim3(nb256(npow)), dim3(256), 0, s, keys, npow, j, k);
+    hipLaunchKernelGGL(k_keys_to_perm, dim3(nb256(n)), dim3(256), 0, s, n, keys, perm);
+    return hipGetLastError();
+}
+hipError_t launch_gather_points(hipStream_t s, int64_t n, int dim, const int64_t *perm, const double *X,
+                                const double *y, const double *mu, double *Xp, double *yp, double *mup) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_points, dim3(nb256(n)), dim3(256), 0, s, n, dim, perm, X, y, mu, Xp, yp, mup);
+    return hipGetLastError();
+}
+hipError_t launch_scatter_vec(hipStream_t s, int64_t n, const int64_t *perm, const double *src, double *dst) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_vec, dim3(nb256(n)), dim3(256), 0, s, n, perm, src, dst);
+    return hipGetLastError();
+}

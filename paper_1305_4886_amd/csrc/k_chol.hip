@@ -22,53 +22,6 @@
 
 namespace {
 
-// Broadcast lane l's double (l a compile-time constant after unrolling).
-GP_DEV double rdlane(double v, int l) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-    return __hiloint2double(hi, lo);
-}
-
-// Cholesky of a 64 x 64 block held by one wave, lane r = row r (a[c] = A[r][c],
-// zero above the diagonal), right-looking column by column: pivot
-// sqrt(A_jj), scale column j, rank-1 update of the trailing lower part.  The
-// column entries are broadcast with readlane, so no memory round trip or
-// barrier sits between the steps.  Returns 0 or the first failing 1-based
-// column (a non-positive or NaN pivot); later columns then hold garbage.
-GP_DEV int wave_chol64(double (&a)[DB], int lane) {
-    int fail = 0;
-#pragma unroll
-    for (int j = 0; j < DB; ++j) {
-        const double piv = rdlane(a[j], j);
-        if (!(piv > 0.0) && fail == 0) fail = j + 1;
-        const double dj = sqrt(piv);
-        const double inv = 1.0 / dj;
-        a[j] = (lane == j) ? dj : ((lane > j) ? a[j] * inv : a[j]);
-#pragma unroll
-        for (int c = j + 1; c < DB; ++c) {
-            const double lcj = rdlane(a[j], c);
-            a[c] = (lane >= c) ? fma(-a[j], lcj, a[c]) : a[c];
-        }
-    }
-    return fail;
-}
-
-// W = L^{-1} for the 64 x 64 lower factor in LDS (Ls[i][k] = L_ik), one wave,
-// lane c computes column c by forward substitution:
-//   W_ic = (delta_ic - sum_{c <= k < i} L_ik W_kc) / L_ii;
-// rows above c are zero, so the sum may run over all k < i.  Row i of L is a
-// broadcast LDS read (the same address for every lane).
-GP_DEV void wave_inv64(const double (*Ls)[DB + 1], double (&w)[DB], int lane) {
-#pragma unroll
-    for (int i = 0; i < DB; ++i) {
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < i; ++k) s = fma(Ls[i][k], w[k], s);
-        const double lii = Ls[i][i];
-        w[i] = (lane == i) ? 1.0 / lii : ((lane < i) ? -s / lii : 0.0);
-    }
-}
-
 // Factor + invert one diagonal block (jb <= 64 valid rows, identity padding).
 // One wave per block.
 __global__ __launch_bounds__(64) void k_diag_potrf(double *A, int64_t lda, int jb, double *Winv,

@@ -16,6 +16,8 @@
 // contiguous range of tiles and shares panel rows through its own L2.
 #include "internal.h"
 
+#include <type_traits>
+
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
@@ -27,7 +29,9 @@ constexpr int BK = 16;
 struct TileMap {
     int64_t ntm, ntn, ntiles;
     int lower;
-    int sgm, sgn;  // super-tile shape in tiles
+    int sgm, sgn;   // super-tile shape in tiles
+    int bandmode;   // 0 all tiles, 1 only 0 <= bi - bj < band (own enumeration), 2 only bi - bj >= band
+    int64_t band;
 };
 
 GP_DEV void tri_decode(int64_t t, int64_t &bi, int64_t &bj) {
@@ -48,6 +52,11 @@ GP_DEV void tri_decode(int64_t t, int64_t &bi, int64_t &bj) {
 constexpr int SG = 8;
 
 GP_DEV bool decode_tile(const TileMap &tm, int64_t t, int64_t &bi, int64_t &bj) {
+    if (tm.bandmode == 1) {  // tiles on the first `band` tile diagonals: t = bj * band + offset
+        bj = t / tm.band;
+        bi = bj + (t - bj * tm.band);
+        return bi < tm.ntm && bj < tm.ntn;
+    }
     const int64_t SN = (tm.ntn + tm.sgn - 1) / tm.sgn;
     const int64_t per = (int64_t)tm.sgm * tm.sgn;
     const int64_t st = t / per, w = t - st * per;
@@ -67,7 +76,7 @@ GP_DEV bool decode_tile(const TileMap &tm, int64_t t, int64_t &bi, int64_t &bj) 
     }
     bi = I * tm.sgm + w / tm.sgn;
     bj = J * tm.sgn + w % tm.sgn;
-    return bi < tm.ntm && bj < tm.ntn && (!tm.lower || bi >= bj);
+    return bi < tm.ntm && bj < tm.ntn && (!tm.lower || bi >= bj) && (tm.bandmode != 2 || bi - bj >= tm.band);
 }
 
 // Eight XCDs receive workgroups round-robin; give each XCD a contiguous range
@@ -249,6 +258,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmDesc d, TileMap tm) {
 TileMap make_map(int64_t M, int64_t N, int BM, int BN, int lower) {
     TileMap tm;
     tm.lower = lower;
+    tm.bandmode = 0;
+    tm.band = 0;
     tm.ntm = (M + BM - 1) / BM;
     tm.ntn = (N + BN - 1) / BN;
     if (lower && tm.ntn > tm.ntm) tm.ntn = tm.ntm;
@@ -279,17 +290,188 @@ hipError_t launch_gemm_f64(hipStream_t s, const GemmDesc &d) {
     return run_f64<128, 128, 2, 2, 0, 0>(s, d);
 }
 
+namespace {
+
+// ---------------------------------------------------------------------------
+// Low-precision trailing update C -= P P^T (lower tiles only): the FP64 panel
+// is rounded to FP32 (PREC 1, v_mfma_f32_16x16x4_f32, K step 16) or BF16
+// (PREC 2, v_mfma_f32_16x16x32_bf16, K step 32) while it is staged into LDS;
+// products accumulate in FP32 and are subtracted from the FP64 tile.  D layout
+// of both instructions (checked with a probe): lane l, register r holds row
+// 4 (l / 16) + r, column l % 16.
+// ---------------------------------------------------------------------------
+template <int PREC>
+__global__ __launch_bounds__(256, 2) void k_syrk_lowp(GemmDesc d, TileMap tm) {
+    constexpr int BM = 128, BN = 128, WM = 2, WN = 2;
+    constexpr int WTM = BM / WM, WTN = BN / WN, FM = WTM / 16, FN = WTN / 16;
+    constexpr int KS = PREC == 1 ? 16 : 32;       // K per stage
+    constexpr int LA = BM * KS / 256;             // loads per operand per thread
+    constexpr int PADK = 8;                       // bf16 rows: 80-byte stride keeps 16-byte alignment
+    typedef typename std::conditional<PREC == 1, float, __bf16>::type ET;
+    // FP32: [k][i] layout (one element per lane per MFMA); BF16: [i][k] layout (8 k per lane)
+    constexpr int ROWS = PREC == 1 ? KS : BM;
+    constexpr int COLS = PREC == 1 ? BM + 1 : KS + PADK;
+    __shared__ ET As[2][ROWS][COLS];
+    __shared__ ET Bs[2][ROWS][COLS];
+
+    if (d.info && *d.info) return;
+    const int64_t t = xcd_remap();
+    if (t >= tm.ntiles) return;
+    int64_t bi, bj;
+    if (!decode_tile(tm, t, bi, bj)) return;
+    const int64_t i0 = bi * BM, j0 = bj * BN;
+    const double *P = d.A;
+    double *C = d.C;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+
+    v4f acc[FM][FN];
+#pragma unroll
+    for (int m = 0; m < FM; ++m)
+#pragma unroll
+        for (int n = 0; n < FN; ++n) acc[m][n] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    double ra[LA], rb[LA];
+    auto gload = [&](int64_t k0) {
+#pragma unroll
+        for (int r = 0; r < LA; ++r) {
+            const int e = r * 256 + tid;
+            const int ii = e % BM, kk = e / BM;
+            const int64_t gk = k0 + kk;
+            const int64_t gi = i0 + ii, gj = j0 + ii;
+            const bool oka = gi < d.M && gk < d.K, okb = gj < d.N && gk < d.K;
+            const double va = P[oka ? gi + gk * d.lda : 0];
+            const double vb = P[okb ? gj + gk * d.lda : 0];
+            ra[r] = oka ? va : 0.0;
+            rb[r] = okb ? vb : 0.0;
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < LA; ++r) {
+            const int e = r * 256 + tid;
+            const int ii = e % BM, kk = e / BM;
+            if (PREC == 1) {
+                As[buf][kk][ii] = (ET)(float)ra[r];
+                Bs[buf][kk][ii] = (ET)(float)rb[r];
+            } else {
+                As[buf][ii][kk] = (ET)(float)ra[r];
+                Bs[buf][ii][kk] = (ET)(float)rb[r];
+            }
+        }
+    };
+
+    if (d.K > 0) {
+        gload(0);
+        sstore(0);
+        __syncthreads();
+        int buf = 0;
+        for (int64_t k0 = 0; k0 < d.K; k0 += KS) {
+            const bool more = k0 + KS < d.K;
+            if (more) gload(k0 + KS);
+            if (PREC == 1) {
+#pragma unroll
+                for (int kk = 0; kk < KS; kk += 4) {
+                    float a[FM], b[FN];
+#pragma unroll
+                    for (int m = 0; m < FM; ++m)
+                        a[m] = (float)As[buf][kk + (lane >> 4)][wm * WTM + m * 16 + (lane & 15)];
+#pragma unroll
+                    for (int n = 0; n < FN; ++n)
+                        b[n] = (float)Bs[buf][kk + (lane >> 4)][wn * WTN + n * 16 + (lane & 15)];
+#pragma unroll
+                    for (int m = 0; m < FM; ++m)
+#pragma unroll
+                        for (int n = 0; n < FN; ++n)
+                            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m], b[n], acc[m][n], 0, 0, 0);
+                }
+            } else {
+                v8bf a[FM], b[FN];
+#pragma unroll
+                for (int m = 0; m < FM; ++m)
+                    a[m] = *reinterpret_cast<const v8bf *>(&As[buf][wm * WTM + m * 16 + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+                for (int n = 0; n < FN; ++n)
+                    b[n] = *reinterpret_cast<const v8bf *>(&Bs[buf][wn * WTN + n * 16 + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+                for (int m = 0; m < FM; ++m)
+#pragma unroll
+                    for (int n = 0; n < FN; ++n)
+                        acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[n], acc[m][n], 0, 0, 0);
+            }
+            if (more) sstore(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+        }
+    }
+
+    const int64_t rb0 = i0 + wm * WTM + 4 * (lane >> 4);
+    const int64_t cb0 = j0 + wn * WTN + (lane & 15);
+#pragma unroll
+    for (int m = 0; m < FM; ++m) {
+        double cv[FN][4];
+#pragma unroll
+        for (int n = 0; n < FN; ++n)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gi = rb0 + m * 16 + r, gj = cb0 + n * 16;
+                const bool ok = gi < d.M && gj < d.N && gi >= gj;
+                const double v = C[ok ? gi + gj * d.ldc : 0];
+                cv[n][r] = ok ? v : 0.0;
+            }
+#pragma unroll
+        for (int n = 0; n < FN; ++n)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gi = rb0 + m * 16 + r, gj = cb0 + n * 16;
+                const bool ok = gi < d.M && gj < d.N && gi >= gj;
+                if (ok) C[gi + gj * d.ldc] = cv[n][r] - (double)acc[m][n][r];
+            }
+    }
+}
+
+template <int PREC>
+hipError_t run_lowp(hipStream_t s, const GemmDesc &d, int64_t band) {
+    if (d.M <= 0 || d.N <= 0) return hipSuccess;
+    TileMap tm = make_map(d.M, d.N, 128, 128, 1);
+    tm.bandmode = band > 0 ? 2 : 0;
+    tm.band = band;
+    const int64_t g = ((tm.ntiles + 7) / 8) * 8;
+    hipLaunchKernelGGL((k_syrk_lowp<PREC>), dim3((unsigned)g), dim3(256), 0, s, d, tm);
+    return hipGetLastError();
+}
+
+// FP64 update of the tiles on the first `band` tile diagonals only.
+hipError_t run_band_f64(hipStream_t s, const GemmDesc &d, int64_t band) {
+    if (d.M <= 0 || d.N <= 0) return hipSuccess;
+    TileMap tm = make_map(d.M, d.N, 128, 128, 1);
+    tm.bandmode = 1;
+    tm.band = band;
+    tm.ntiles = tm.ntn * band;
+    const int64_t g = ((tm.ntiles + 7) / 8) * 8;
+    hipLaunchKernelGGL((k_gemm_f64<128, 128, 2, 2, 0, 1, 1>), dim3((unsigned)g), dim3(256), 0, s, d, tm);
+    return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_syrk_lower(hipStream_t s, gp_prec_t prec, int band, const double *P, int64_t ldp,
                              double *C, int64_t ldc, int64_t M, int64_t N, int64_t K,
                              const int32_t *info, int role) {
-    (void)band;
-    if (prec != GP_FP64) return hipErrorNotSupported;
     GemmDesc d{};
     d.A = P; d.lda = ldp; d.B = P; d.ldb = ldp; d.C = C; d.ldc = ldc;
     d.M = M; d.N = N; d.K = K; d.alpha = -1.0; d.beta = 1.0;
     d.ta = 0; d.tb = 1; d.lower = 1; d.batch = 1; d.info = info;
-    if (role == 1) return run_f64<128, 128, 2, 2, 0, 1, 1>(s, d);
-    return run_f64<128, 128, 2, 2, 0, 1, 2>(s, d);
+    if (prec == GP_FP64) {
+        if (role == 1) return run_f64<128, 128, 2, 2, 0, 1, 1>(s, d);
+        return run_f64<128, 128, 2, 2, 0, 1, 2>(s, d);
+    }
+    const int64_t b = band > 0 ? band : 0;
+    if (b > 0) {
+        hipError_t e = run_band_f64(s, d, b);
+        if (e != hipSuccess) return e;
+    }
+    return prec == GP_FP32_TRAIL ? run_lowp<1>(s, d, b) : run_lowp<2>(s, d, b);
 }
 
 hipError_t launch_panel_solve(hipStream_t s, double *A, int64_t lda, const double *Winv, int64_t M,

@@ -1,0 +1,90 @@
+"""Batched likelihoods in one persistent launch: each problem of a ragged batch
+must match the single-problem CPU oracle (same model and definitions,
+Section 1), including per-problem failure reporting."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1305_4886_amd as gp  # noqa: E402
+from paper_1305_4886_amd import synth  # noqa: E402
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print("\n[case]", request.node.name, flush=True)
+    yield
+    torch.cuda.synchronize()
+
+
+def make_batch(sizes, seed, kernels=None):
+    Xs, ys, ths = [], [], []
+    for b, n in enumerate(sizes):
+        X = synth.uniform_points(int(n), seed + b)
+        y = synth.smooth_field(X, seed + 1000 + b, ell=0.1, t2=0.1) if n > 0 else np.zeros(0)
+        k = kernels[b] if kernels else b % 3
+        th = np.array([math.log(1.0 + 0.1 * (b % 3)), math.log(0.1), math.log(0.1)])
+        Xs.append(X); ys.append(y); ths.append((k, th))
+    return Xs, ys, ths
+
+
+@pytest.mark.parametrize("sizes", [[1], [64], [65, 3, 200], [300, 0, 129, 1000, 64, 777, 511, 2]])
+def test_batched_matches_oracle(orc, sizes):
+    Xs, ys, ths = make_batch(sizes, 70)
+    X = np.concatenate([x for x in Xs if len(x)] or [np.zeros((0, 2))])
+    y = np.concatenate([v for v in ys if len(v)] or [np.zeros(0)])
+    r = gp.loglik_batched(dev(X), dev(y), [gp.theta(k, log=t) for k, t in ths], sizes)
+    out = r["out3"].cpu().numpy()
+    info = r["info"].cpu().numpy()
+    for b, n in enumerate(sizes):
+        assert info[b] == 0
+        if n == 0:
+            assert np.all(out[b] == 0.0)
+            continue
+        k, t = ths[b]
+        ll, ld, q = orc.loglik(k, t, Xs[b], ys[b])
+        assert abs(out[b, 0] - ll) <= 1e-11 * abs(ll), (b, n, out[b], ll)
+        assert abs(out[b, 1] - ld) <= 1e-11 * max(1.0, abs(ld))
+
+
+def test_batched_workload_64_problems(orc):
+    sizes = synth.batch_sizes(64, 40)
+    Xs, ys, ths = make_batch(sizes, 4000, kernels=[0] * 64)
+    X = np.concatenate(Xs)
+    y = np.concatenate(ys)
+    r = gp.loglik_batched(dev(X), dev(y), [gp.theta(k, log=t) for k, t in ths], sizes)
+    out = r["out3"].cpu().numpy()
+    assert np.all(r["info"].cpu().numpy() == 0)
+    # the smallest and two random problems against the oracle (the rest: finite)
+    check = [int(np.argmin(sizes)), 5, 17]
+    for b in check:
+        k, t = ths[b]
+        ll, _, _ = orc.loglik(k, t, Xs[b], ys[b])
+        assert abs(out[b, 0] - ll) <= 1e-11 * abs(ll)
+    assert np.all(np.isfinite(out))
+
+
+def test_batched_failure_is_per_problem():
+    sizes = [100, 150, 80]
+    Xs, ys, ths = make_batch(sizes, 90, kernels=[0, 0, 0])
+    Xs[1][120] = Xs[1][30]  # duplicate point, no nugget -> not PD
+    ths[1] = (0, np.array([0.0, math.log(0.3), -np.inf]))
+    X = np.concatenate(Xs)
+    y = np.concatenate(ys)
+    r = gp.loglik_batched(dev(X), dev(y), [gp.theta(k, log=t) for k, t in ths], sizes)
+    out = r["out3"].cpu().numpy()
+    info = r["info"].cpu().numpy()
+    assert info[0] == 0 and info[2] == 0
+    assert np.all(np.isfinite(out[0])) and np.all(np.isfinite(out[2]))
+    if info[1] != 0:
+        assert info[1] >= 121 and np.all(np.isnan(out[1]))

@@ -1,0 +1,120 @@
+"""Mixed-precision log-likelihood: Morton-ordered points, FP32 / BF16 trailing
+products with FP32 accumulation, FP64 diagonal blocks, log-determinant and
+matrix-free FP64 iterative refinement of C^{-1}(y - mu).  Compared with the
+FP64 oracle at the same inputs: loglik within 1e-6 relative (FP32) and the
+refined solve to a relative residual of 1e-10; BF16 results are reported
+against a looser bound (its unit roundoff is 2^-8).
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1305_4886_amd as gp  # noqa: E402
+from paper_1305_4886_amd import synth  # noqa: E402
+
+
+def logth(s2, rho, t2):
+    return np.array([math.log(s2), math.log(rho), math.log(t2)])
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print("\n[case]", request.node.name, flush=True)
+    yield
+    torch.cuda.synchronize()
+
+
+def morton_codes(X):
+    lo, hi = X.min(0), X.max(0)
+    q = np.floor(np.clip((X - lo) / (hi - lo), 0, 1) * (2 ** 21 - 1)).astype(np.uint64)
+    code = np.zeros(len(X), dtype=np.uint64)
+    for b in range(21):
+        code |= ((q[:, 0] >> np.uint64(b)) & np.uint64(1)) << np.uint64(2 * b)
+        code |= ((q[:, 1] >> np.uint64(b)) & np.uint64(1)) << np.uint64(2 * b + 1)
+    return code
+
+
+@pytest.mark.parametrize("n", [1, 2, 1000, 4097])
+def test_morton_order_is_sorted_permutation(n):
+    X = synth.uniform_points(n, 33)
+    perm = gp.morton_order(dev(X)).cpu().numpy()
+    assert sorted(perm.tolist()) == list(range(n))
+    c = morton_codes(X)[perm] if n > 1 else np.zeros(1)
+    assert np.all(np.diff(c.astype(np.float64)) >= 0)
+
+
+@pytest.mark.parametrize("n,kernel,rho,t2,seed", [(2048, 0, 0.1, 0.1, 1), (3000, 1, 0.05, 0.01, 2),
+                                                  (4096, 1, 0.05, 0.01, 3)])
+def test_mixed_fp32_loglik(orc, n, kernel, rho, t2, seed):
+    X = synth.uniform_points(n, seed)
+    y = synth.smooth_field(X, seed + 7, ell=rho, t2=t2)
+    t = logth(1.0, rho, t2)
+    (ll, ld, q), _, alpha_o = orc.loglik(kernel, t, X, y, want=True)
+    r = gp.loglik(dev(X), dev(y), gp.theta(kernel, log=t), prec=gp.GP_FP32_TRAIL, want_alpha=True)
+    out = r["out3"].cpu().numpy()
+    ir = r["ir"].cpu().numpy()
+    err = abs(out[0] - ll) / abs(ll)
+    print("fp32 n=%d rel loglik err %.2e  logdet err %.2e  q err %.2e  ir=%s" % (
+        n, err, abs(out[1] - ld) / abs(ld), abs(out[2] - q) / abs(q), ir))
+    assert int(r["info"].item()) == 0
+    assert ir[2] == 1.0 and ir[1] <= 1e-10, ir
+    assert abs(out[2] - q) <= 1e-9 * abs(q)
+    assert err <= 1e-6
+    a = r["alpha"].cpu().numpy()
+    assert np.linalg.norm(a - alpha_o) / np.linalg.norm(alpha_o) <= 1e-8
+
+
+@pytest.mark.parametrize("n,kernel,rho,t2,seed", [(2048, 0, 0.1, 0.1, 1), (4096, 1, 0.05, 0.01, 3)])
+def test_mixed_bf16_loglik(orc, n, kernel, rho, t2, seed):
+    X = synth.uniform_points(n, seed)
+    y = synth.smooth_field(X, seed + 7, ell=rho, t2=t2)
+    t = logth(1.0, rho, t2)
+    ll, ld, q = orc.loglik(kernel, t, X, y)
+    r = gp.loglik(dev(X), dev(y), gp.theta(kernel, log=t), prec=gp.GP_BF16_TRAIL)
+    out = r["out3"].cpu().numpy()
+    ir = r["ir"].cpu().numpy()
+    err = abs(out[0] - ll) / abs(ll)
+    print("bf16 n=%d rel loglik err %.2e  logdet err %.2e  q err %.2e  ir=%s" % (
+        n, err, abs(out[1] - ld) / abs(ld), abs(out[2] - q) / abs(q), ir))
+    assert int(r["info"].item()) == 0
+    assert err <= 1e-3
+
+
+def test_mixed_grad(orc):
+    n = 2048
+    X = synth.uniform_points(n, 44)
+    y = synth.smooth_field(X, 45, ell=0.05, t2=0.01)
+    t = logth(1.0, 0.05, 0.01)
+    (ll, _, _), g_o = orc.loglik_grad(1, t, X, y)
+    r = gp.loglik_grad(dev(X), dev(y), gp.theta(1, log=t), prec=gp.GP_FP32_TRAIL)
+    g = r["grad"].cpu().numpy()
+    out = r["out3"].cpu().numpy()
+    gerr = np.linalg.norm(g - g_o) / np.linalg.norm(g_o)
+    print("fp32 grad rel err %.2e loglik rel err %.2e" % (gerr, abs(out[0] - ll) / abs(ll)))
+    assert gerr <= 1e-4
+    assert abs(out[0] - ll) <= 1e-6 * abs(ll)
+
+
+def test_mixed_potrf_reconstruction(orc):
+    n = 1500
+    X = synth.uniform_points(n, 50)
+    C = orc.cov(0, logth(1.0, 0.1, 0.1), X)
+    for prec, tol in [(gp.GP_FP32_TRAIL, 1e-6), (gp.GP_BF16_TRAIL, 1e-2)]:
+        S = gp.colmajor_storage(n)
+        gp.colmajor(S, n).copy_(torch.as_tensor(np.tril(C)))
+        info = gp.potrf(S, n, prec=prec)
+        L = np.tril(gp.colmajor(S, n).cpu().numpy())
+        rec = np.linalg.norm(L @ L.T - C) / np.linalg.norm(C)
+        print("prec %d reconstruction %.2e" % (prec, rec))
+        assert int(info.item()) == 0 and rec <= tol
