@@ -1,19 +1,18 @@
-// k_batch.hip -- many independent Gaussian-process likelihoods in one
-// persistent launch (the same model and quantities as the single-problem
-// path: C(theta), L L^T = C, L^{-1} y, log|C|, loglik; Section 1).
+// k_batch.hip -- many independent Gaussian-process likelihoods, batched
+// (the same model and quantities as the single-problem path: C(theta),
+// L L^T = C, L^{-1} y, log|C|, loglik; Section 1).
 //
-// Work is a host-built table of tasks on 64 x 64 tiles.  For problem b:
-//   tile (i, j), i >= j:  build C_ij from the points, subtract
-//       sum_{k < j} L_ik L_jk^T (left-looking, matrix cores), then factor +
-//       invert it (i == j, one wave in registers) or multiply by the diagonal
-//       block's inverse (i > j) -- the block Cholesky of Section 2.1 / Fig. 1;
-//   solve i:  z_i = Winv_ii (y_i - sum_{k < i} L_ik z_k);
-//   reduce:   log|C| = 2 sum log L_ii, q = z^T z, loglik.
-// Tasks are ordered by dependency level (tile (j,j): 4j, tile (i>j, j): 4j + 2,
-// solve i: 4i + 3, reduce: 4 nt + 1), then by problem size, so every task
-// waits only on tasks with smaller tickets.  Workgroups take tickets from an
-// atomic counter, hence every waited-on task belongs to a running workgroup
-// and the launch cannot deadlock; each wait is bounded (abort flag).
+// Level-synchronous tile Cholesky over the whole batch on 64 x 64 tiles.  For
+// tile column j = 0, 1, ... two launches cover every problem at once:
+//   diag(j):  C_jj - sum_{k<j} L_jk L_jk^T (left-looking, matrix cores), then
+//             factor + invert it in one wave's registers (the diagonal-block
+//             Cholesky of Section 2.1 / Fig. 1);
+//   panel(j): for every tile i > j of every problem,
+//             L_ij = (C_ij - sum_{k<j} L_ik L_jk^T) Winv_jj^T.
+// Covariance tiles are generated from the points inside these kernels (C is
+// never written as a whole).  A final launch runs, per problem, the forward
+// solve z = L^{-1} y and the log-determinant / quadratic-form reductions.
+// No workgroup ever waits on another: kernel boundaries order the steps.
 #include "internal.h"
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -21,316 +20,267 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 namespace {
 
 struct BProb {
-    int64_t n, x_off, c_off, tflag_off, zflag_off, z_off, w_off;
+    int64_t n, x_off, c_off, z_off, w_off;
     double s2, inv_rho, t2;
     int32_t kind, nt;
 };
-struct BTask {
-    int32_t prob, i, j, type;  // type 0 tile, 1 solve, 2 reduce
+struct BTile {
+    int32_t prob, i;
 };
 
 constexpr int T = 64;
 
-GP_DEV int64_t tri_index(int64_t i, int64_t j) { return i * (i + 1) / 2 + j; }
-
-// Workgroup-uniform wait: returns the flag value (1 ready, 2 failed) or 0 on
-// timeout / abort.
-GP_DEV int wg_wait(const int *f, int *abortf, int *s_flag) {
-    if (threadIdx.x == 0) {
-        int spins = 0, v;
-        while ((v = ld_acquire_agent(f)) == 0) {
-            if (ld_acquire_agent(abortf)) break;
-            __builtin_amdgcn_s_sleep(2);
-            if (++spins > SPIN_LIMIT) {
-                __hip_atomic_store(abortf, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-        }
-        *s_flag = v;
-    }
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    const int v = *s_flag;
-    __syncthreads();
-    return v;
-}
-
-GP_DEV void wg_release(int *f, int v) {
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) st_release_agent(f, v);
-}
-
-__global__ __launch_bounds__(256, 1) void k_batch(const BProb *__restrict__ probs, const BTask *__restrict__ tasks,
-                                                  int64_t ntasks, int dim, const double *__restrict__ X,
-                                                  const double *__restrict__ y, double *C_pool, double *zbuf,
-                                                  double *wbuf, int *flags, int *ctl, double *out3, int32_t *info) {
-    __shared__ double As[T][T + 1];
-    __shared__ double Bs[T][T + 1];
-    __shared__ double red[4][T];
-    __shared__ int s_task, s_flag, s_fail;
-    int *abortf = &ctl[1];
+// acc = sum_{k < j} L_ik L_jk^T for one 64 x 64 tile (4 waves, 32 x 32 each,
+// f64 MFMA layout: row lane/16 + 4r, column lane%16).
+GP_DEV void tile_update(const double *L, int64_t ld, int64_t n, int64_t i0, int64_t j0, int j,
+                        double (*As)[T + 1], double (*Bs)[T + 1], v4d (&acc)[2][2]) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wm = w & 1, wn = w >> 1;  // 2 x 2 waves, 32 x 32 each
-
-    for (;;) {
-        if (tid == 0) s_task = atomicAdd(&ctl[0], 1);
+    const int wm = w & 1, wn = w >> 1;
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) acc[m][q] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < j; ++k) {
+        const int64_t k0 = (int64_t)k * T;  // block k < j is a full block
         __syncthreads();
-        const int64_t t = s_task;
+#pragma unroll
+        for (int r = 0; r < (T * T) / 256; ++r) {
+            const int e = r * 256 + tid;
+            const int ii = e & (T - 1), kk = e >> 6;
+            const int64_t gi = i0 + ii, gj = j0 + ii;
+            const double va = L[gi < n ? gi + (k0 + kk) * ld : 0];
+            const double vb = L[gj < n ? gj + (k0 + kk) * ld : 0];
+            As[kk][ii] = gi < n ? va : 0.0;
+            Bs[kk][ii] = gj < n ? vb : 0.0;
+        }
         __syncthreads();
-        if (t >= ntasks) break;
-        const BTask tk = tasks[t];
-        const BProb P = probs[tk.prob];
-        const int64_t n = P.n, ld = P.n;
-        double *L = C_pool + P.c_off;
-        int *tflag = flags + P.tflag_off;
-        int *zflag = flags + P.zflag_off;
-        const double *Xb = X + P.x_off * dim;
-
-        if (tk.type == 0) {
-            const int i = tk.i, j = tk.j;
-            const int64_t i0 = (int64_t)i * T, j0 = (int64_t)j * T;
-            bool ok = true;
-            v4d acc[2][2];
 #pragma unroll
-            for (int m = 0; m < 2; ++m)
+        for (int kk = 0; kk < T; kk += 4) {
+            double a[2], b[2];
 #pragma unroll
-                for (int q = 0; q < 2; ++q) acc[m][q] = v4d{0.0, 0.0, 0.0, 0.0};
-            for (int k = 0; k < j && ok; ++k) {
-                const int v1 = wg_wait(&tflag[tri_index(i, k)], abortf, &s_flag);
-                const int v2 = wg_wait(&tflag[tri_index(j, k)], abortf, &s_flag);
-                if (v1 != 1 || v2 != 1) {
-                    ok = false;
-                    break;
-                }
-                const int64_t k0 = (int64_t)k * T;  // block k < j is a full block
+            for (int m = 0; m < 2; ++m) a[m] = As[kk + (lane >> 4)][wm * 32 + m * 16 + (lane & 15)];
 #pragma unroll
-                for (int r = 0; r < (T * T) / 256; ++r) {
-                    const int e = r * 256 + tid;
-                    const int ii = e & (T - 1), kk = e >> 6;
-                    const int64_t gi = i0 + ii, gj = j0 + ii;
-                    const double va = L[gi < n ? gi + (k0 + kk) * ld : 0];
-                    const double vb = L[gj < n ? gj + (k0 + kk) * ld : 0];
-                    As[kk][ii] = gi < n ? va : 0.0;
-                    Bs[kk][ii] = gj < n ? vb : 0.0;
-                }
-                __syncthreads();
-#pragma unroll
-                for (int kk = 0; kk < T; kk += 4) {
-                    double a[2], b[2];
-#pragma unroll
-                    for (int m = 0; m < 2; ++m) a[m] = As[kk + (lane >> 4)][wm * 32 + m * 16 + (lane & 15)];
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) b[q] = Bs[kk + (lane >> 4)][wn * 32 + q * 16 + (lane & 15)];
-#pragma unroll
-                    for (int m = 0; m < 2; ++m)
-#pragma unroll
-                        for (int q = 0; q < 2; ++q)
-                            acc[m][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[q], acc[m][q], 0, 0, 0);
-                }
-                __syncthreads();
-            }
-            if (!ok) {
-                wg_release(&tflag[tri_index(i, j)], 2);
-                continue;
-            }
-            // S = C_ij - acc, in the f64 MFMA layout (row lane/16 + 4r, column lane%16)
-            double sv[2][2][4];
+            for (int q = 0; q < 2; ++q) b[q] = Bs[kk + (lane >> 4)][wn * 32 + q * 16 + (lane & 15)];
 #pragma unroll
             for (int m = 0; m < 2; ++m)
 #pragma unroll
                 for (int q = 0; q < 2; ++q)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = wm * 32 + m * 16 + (lane >> 4) + 4 * r;
-                        const int col = wn * 32 + q * 16 + (lane & 15);
-                        const int64_t gi = i0 + row, gj = j0 + col;
-                        double c;
-                        if (gi < n && gj < n) {
-                            const double d = point_dist(Xb + gi * dim, Xb + gj * dim, dim);
-                            c = P.s2 * cov_corr(P.kind, d * P.inv_rho) + (gi == gj ? P.t2 : 0.0);
-                        } else {
-                            c = (gi == gj) ? 1.0 : 0.0;  // identity padding of the last diagonal tile
-                        }
-                        sv[m][q][r] = c - acc[m][q][r];
-                    }
-            if (i == j) {
-#pragma unroll
-                for (int m = 0; m < 2; ++m)
-#pragma unroll
-                    for (int q = 0; q < 2; ++q)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            As[wm * 32 + m * 16 + (lane >> 4) + 4 * r][wn * 32 + q * 16 + (lane & 15)] = sv[m][q][r];
-                if (tid == 0) s_fail = 0;
-                __syncthreads();
-                const int tj = (int)((n - j0) < T ? (n - j0) : T);
-                if (w == 0) {
-                    double a[T];
-#pragma unroll
-                    for (int c = 0; c < T; ++c) a[c] = (c <= lane) ? As[lane][c] : 0.0;
-                    const int fail = wave_chol64(a, lane);
-                    if (fail) {
-                        if (lane == 0) s_fail = fail;
-                    } else {
-#pragma unroll
-                        for (int c = 0; c < T; ++c) {
-                            As[lane][c] = a[c];
-                            if (lane < tj && c <= lane) L[(j0 + lane) + (j0 + c) * ld] = a[c];
-                        }
-                    }
-                }
-                __syncthreads();
-                const int fail = s_fail;
-                if (fail) {
-                    if (tid == 0) info[tk.prob] = (int32_t)(j0 + fail);
-                    wg_release(&tflag[tri_index(i, j)], 2);
-                    continue;
-                }
-                if (w == 0) {
-                    double wv[T];
-                    wave_inv64(As, wv, lane);
-                    double *W = wbuf + P.w_off + (int64_t)j * T * T;
-#pragma unroll
-                    for (int r = 0; r < T; ++r) W[r + lane * T] = wv[r];
-                }
-                wg_release(&tflag[tri_index(i, j)], 1);
-            } else {
-                const int vd = wg_wait(&tflag[tri_index(j, j)], abortf, &s_flag);
-                if (vd != 1) {
-                    wg_release(&tflag[tri_index(i, j)], 2);
-                    continue;
-                }
-                // L_ij = S W_jj^T: A operand S staged k-major (As[kk][ii] = S[ii][kk]),
-                // B operand op(B)[kk][jj] = W_jj[jj][kk] = W[jj + kk T].
-                const double *W = wbuf + P.w_off + (int64_t)j * T * T;
-#pragma unroll
-                for (int m = 0; m < 2; ++m)
-#pragma unroll
-                    for (int q = 0; q < 2; ++q)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            As[wn * 32 + q * 16 + (lane & 15)][wm * 32 + m * 16 + (lane >> 4) + 4 * r] = sv[m][q][r];
-#pragma unroll
-                for (int r = 0; r < (T * T) / 256; ++r) {
-                    const int e = r * 256 + tid;
-                    Bs[e >> 6][e & (T - 1)] = W[e];
-                }
-                __syncthreads();
-                v4d o[2][2];
-#pragma unroll
-                for (int m = 0; m < 2; ++m)
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) o[m][q] = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int kk = 0; kk < T; kk += 4) {
-                    double a[2], b[2];
-#pragma unroll
-                    for (int m = 0; m < 2; ++m) a[m] = As[kk + (lane >> 4)][wm * 32 + m * 16 + (lane & 15)];
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) b[q] = Bs[kk + (lane >> 4)][wn * 32 + q * 16 + (lane & 15)];
-#pragma unroll
-                    for (int m = 0; m < 2; ++m)
-#pragma unroll
-                        for (int q = 0; q < 2; ++q)
-                            o[m][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[q], o[m][q], 0, 0, 0);
-                }
-#pragma unroll
-                for (int m = 0; m < 2; ++m)
-#pragma unroll
-                    for (int q = 0; q < 2; ++q)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int64_t gi = i0 + wm * 32 + m * 16 + (lane >> 4) + 4 * r;
-                            const int64_t gj = j0 + wn * 32 + q * 16 + (lane & 15);
-                            if (gi < n && gj < n) L[gi + gj * ld] = o[m][q][r];
-                        }
-                wg_release(&tflag[tri_index(i, j)], 1);
-            }
-        } else if (tk.type == 1) {
-            const int i = tk.i;
-            const int64_t i0 = (int64_t)i * T;
-            const int vd = wg_wait(&tflag[tri_index(i, i)], abortf, &s_flag);
-            const int vz = i > 0 ? wg_wait(&zflag[i - 1], abortf, &s_flag) : 1;
-            if (vd != 1 || vz != 1) {
-                wg_release(&zflag[i], 2);
-                continue;
-            }
-            double *z = zbuf + P.z_off;
-            const int64_t gi = i0 + lane;
-            const bool rv = gi < n;
-            double acc = 0.0;
-            for (int k = w; k < i; k += 4) {
-                const double *Lc = L + (rv ? gi : 0) + (int64_t)k * T * ld;
-                const double *zk = z + (int64_t)k * T;
-                if (rv) {
-#pragma unroll 16
-                    for (int c = 0; c < T; ++c) acc = fma(Lc[(int64_t)c * ld], zk[c], acc);
-                }
-            }
-            red[w][lane] = acc;
-            __syncthreads();
-            if (w == 0) {
-                const double yb = rv ? y[P.x_off + gi] : 0.0;
-                As[0][lane] = rv ? yb - (((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]) : 0.0;
-            }
-            __syncthreads();
-            const double *W = wbuf + P.w_off + (int64_t)i * T * T;
-            double sacc = 0.0;
-            for (int c = w * 16; c < w * 16 + 16; ++c) sacc = fma(W[lane + c * T], As[0][c], sacc);
-            red[w][lane] = sacc;
-            __syncthreads();
-            if (w == 0 && rv) z[gi] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
-            wg_release(&zflag[i], 1);
-        } else {
-            const int nt = P.nt;
-            const int vz = nt > 0 ? wg_wait(&zflag[nt - 1], abortf, &s_flag) : 1;
-            const bool bad = vz != 1 || info[tk.prob] != 0 || ld_acquire_agent(abortf);
-            CSum sl, sq;
-            if (!bad) {
-                const double *z = zbuf + P.z_off;
-                for (int64_t q = tid; q < n; q += 256) {
-                    sl.add(log(L[q + q * ld]));
-                    sq.add(z[q] * z[q]);
-                }
-            }
-            __shared__ double r2[4 * 256];
-            r2[tid * 4 + 0] = sl.s; r2[tid * 4 + 1] = sl.c; r2[tid * 4 + 2] = sq.s; r2[tid * 4 + 3] = sq.c;
-            __syncthreads();
-            for (int st = 128; st > 0; st >>= 1) {
-                if (tid < st) {
-                    for (int h = 0; h < 2; ++h) {
-                        CSum a, b;
-                        a.s = r2[tid * 4 + 2 * h]; a.c = r2[tid * 4 + 2 * h + 1];
-                        b.s = r2[(tid + st) * 4 + 2 * h]; b.c = r2[(tid + st) * 4 + 2 * h + 1];
-                        a.merge(b);
-                        r2[tid * 4 + 2 * h] = a.s; r2[tid * 4 + 2 * h + 1] = a.c;
-                    }
-                }
-                __syncthreads();
-            }
-            if (tid == 0) {
-                double *o = out3 + 3 * (int64_t)tk.prob;
-                if (bad) {
-                    o[0] = o[1] = o[2] = __builtin_nan("");
-                    if (info[tk.prob] == 0 && vz != 2) info[tk.prob] = -1;  // watchdog expired
-                } else {
-                    const double logdet = 2.0 * (r2[0] + r2[1]);
-                    const double q = r2[2] + r2[3];
-                    o[1] = logdet;
-                    o[2] = q;
-                    o[0] = -0.5 * (((double)n * 1.8378770664093453 + logdet) + q);
-                }
-            }
-            __syncthreads();
+                    acc[m][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[q], acc[m][q], 0, 0, 0);
         }
+    }
+    __syncthreads();
+}
+
+// S = C_ij - acc with C regenerated from the points; identity padding of the
+// last diagonal tile.
+GP_DEV void tile_residual(const BProb &P, const double *Xb, int dim, int64_t i0, int64_t j0,
+                          const v4d (&acc)[2][2], double (&sv)[2][2][4]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wm = w & 1, wn = w >> 1;
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gi = i0 + wm * 32 + m * 16 + (lane >> 4) + 4 * r;
+                const int64_t gj = j0 + wn * 32 + q * 16 + (lane & 15);
+                double c;
+                if (gi < P.n && gj < P.n) {
+                    const double d = point_dist(Xb + gi * dim, Xb + gj * dim, dim);
+                    c = P.s2 * cov_corr(P.kind, d * P.inv_rho) + (gi == gj ? P.t2 : 0.0);
+                } else {
+                    c = (gi == gj) ? 1.0 : 0.0;
+                }
+                sv[m][q][r] = c - acc[m][q][r];
+            }
+}
+
+__global__ __launch_bounds__(256, 1) void k_bdiag(const BProb *__restrict__ probs, const int32_t *__restrict__ plist,
+                                                  int j, int dim, const double *__restrict__ X, double *C_pool,
+                                                  double *wbuf, int32_t *info) {
+    __shared__ double As[T][T + 1];
+    __shared__ double Bs[T][T + 1];
+    __shared__ int s_fail;
+    const int b = plist[blockIdx.x];
+    if (info[b] != 0) return;
+    const BProb P = probs[b];
+    const int64_t ld = P.n, j0 = (int64_t)j * T;
+    double *L = C_pool + P.c_off;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w & 1, wn = w >> 1;
+    v4d acc[2][2];
+    tile_update(L, ld, P.n, j0, j0, j, As, Bs, acc);
+    double sv[2][2][4];
+    tile_residual(P, X + P.x_off * dim, dim, j0, j0, acc, sv);
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                As[wm * 32 + m * 16 + (lane >> 4) + 4 * r][wn * 32 + q * 16 + (lane & 15)] = sv[m][q][r];
+    if (tid == 0) s_fail = 0;
+    __syncthreads();
+    if (w != 0) return;  // one wave factors and inverts the tile
+    const int tj = (int)((P.n - j0) < T ? (P.n - j0) : T);
+    double a[T];
+#pragma unroll
+    for (int c = 0; c < T; ++c) a[c] = (c <= lane) ? As[lane][c] : 0.0;
+    const int fail = wave_chol64(a, lane);
+    if (fail) {
+        if (lane == 0) info[b] = (int32_t)(j0 + fail);
+        return;
+    }
+#pragma unroll
+    for (int c = 0; c < T; ++c) {
+        As[lane][c] = a[c];
+        if (lane < tj && c <= lane) L[(j0 + lane) + (j0 + c) * ld] = a[c];
+    }
+    double wv[T];
+    wave_inv64(As, wv, lane);
+    double *W = wbuf + P.w_off + (int64_t)j * T * T;
+#pragma unroll
+    for (int r = 0; r < T; ++r) W[r + lane * T] = wv[r];
+}
+
+__global__ __launch_bounds__(256, 2) void k_bpanel(const BProb *__restrict__ probs, const BTile *__restrict__ tlist,
+                                                   int j, int dim, const double *__restrict__ X, double *C_pool,
+                                                   const double *__restrict__ wbuf, const int32_t *__restrict__ info) {
+    __shared__ double As[T][T + 1];
+    __shared__ double Bs[T][T + 1];
+    const BTile tk = tlist[blockIdx.x];
+    if (info[tk.prob] != 0) return;
+    const BProb P = probs[tk.prob];
+    const int64_t ld = P.n, i0 = (int64_t)tk.i * T, j0 = (int64_t)j * T;
+    double *L = C_pool + P.c_off;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w & 1, wn = w >> 1;
+    v4d acc[2][2];
+    tile_update(L, ld, P.n, i0, j0, j, As, Bs, acc);
+    double sv[2][2][4];
+    tile_residual(P, X + P.x_off * dim, dim, i0, j0, acc, sv);
+    // L_ij = S W_jj^T: A operand S staged k-major (As[kk][ii] = S[ii][kk]),
+    // op(B)[kk][jj] = W_jj[jj][kk] = W[jj + kk T]
+    const double *W = wbuf + P.w_off + (int64_t)j * T * T;
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                As[wn * 32 + q * 16 + (lane & 15)][wm * 32 + m * 16 + (lane >> 4) + 4 * r] = sv[m][q][r];
+#pragma unroll
+    for (int r = 0; r < (T * T) / 256; ++r) {
+        const int e = r * 256 + tid;
+        Bs[e >> 6][e & (T - 1)] = W[e];
+    }
+    __syncthreads();
+    v4d o[2][2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) o[m][q] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < T; kk += 4) {
+        double a[2], bb[2];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) a[m] = As[kk + (lane >> 4)][wm * 32 + m * 16 + (lane & 15)];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) bb[q] = Bs[kk + (lane >> 4)][wn * 32 + q * 16 + (lane & 15)];
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+                o[m][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], bb[q], o[m][q], 0, 0, 0);
+    }
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gi = i0 + wm * 32 + m * 16 + (lane >> 4) + 4 * r;
+                const int64_t gj = j0 + wn * 32 + q * 16 + (lane & 15);
+                if (gi < P.n && gj < P.n) L[gi + gj * ld] = o[m][q][r];
+            }
+}
+
+// Per problem: z = L^{-1} y block by block (this workgroup only), then
+// log|C| = 2 sum log L_ii, q = z^T z and the log-likelihood.
+__global__ __launch_bounds__(256) void k_bsolve(const BProb *__restrict__ probs, const double *__restrict__ y,
+                                                const double *__restrict__ C_pool, double *zbuf,
+                                                const double *__restrict__ wbuf, double *out3, const int32_t *info) {
+    __shared__ double red[4][T];
+    __shared__ double rhs[T];
+    __shared__ double r2[4 * 256];
+    const int b = blockIdx.x;
+    const BProb P = probs[b];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    double *o = out3 + 3 * (int64_t)b;
+    if (info[b] != 0) {
+        if (tid == 0) o[0] = o[1] = o[2] = __builtin_nan("");
+        return;
+    }
+    const int64_t n = P.n, ld = P.n;
+    const double *L = C_pool + P.c_off;
+    double *z = zbuf + P.z_off;
+    for (int i = 0; i < P.nt; ++i) {
+        const int64_t gi = (int64_t)i * T + lane;
+        const bool rv = gi < n;
+        double acc = 0.0;
+        for (int k = w; k < i; k += 4) {
+            const double *Lc = L + (rv ? gi : 0) + (int64_t)k * T * ld;
+            const double *zk = z + (int64_t)k * T;
+            if (rv) {
+#pragma unroll 16
+                for (int c = 0; c < T; ++c) acc = fma(Lc[(int64_t)c * ld], zk[c], acc);
+            }
+        }
+        red[w][lane] = acc;
+        __syncthreads();
+        if (w == 0) rhs[lane] = rv ? y[P.x_off + gi] - (((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]) : 0.0;
+        __syncthreads();
+        const double *W = wbuf + P.w_off + (int64_t)i * T * T;
+        double sacc = 0.0;
+        for (int c = w * 16; c < w * 16 + 16; ++c) sacc = fma(W[lane + c * T], rhs[c], sacc);
+        red[w][lane] = sacc;
+        __syncthreads();
+        if (w == 0 && rv) z[gi] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+        __syncthreads();  // z_i (global, this workgroup) visible before the next block reads it
+    }
+    CSum sl, sq;
+    for (int64_t q = tid; q < n; q += 256) {
+        sl.add(log(L[q + q * ld]));
+        sq.add(z[q] * z[q]);
+    }
+    r2[tid * 4 + 0] = sl.s; r2[tid * 4 + 1] = sl.c; r2[tid * 4 + 2] = sq.s; r2[tid * 4 + 3] = sq.c;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (tid < st) {
+            for (int h = 0; h < 2; ++h) {
+                CSum a, c;
+                a.s = r2[tid * 4 + 2 * h]; a.c = r2[tid * 4 + 2 * h + 1];
+                c.s = r2[(tid + st) * 4 + 2 * h]; c.c = r2[(tid + st) * 4 + 2 * h + 1];
+                a.merge(c);
+                r2[tid * 4 + 2 * h] = a.s; r2[tid * 4 + 2 * h + 1] = a.c;
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const double logdet = 2.0 * (r2[0] + r2[1]);
+        const double q = r2[2] + r2[3];
+        o[1] = logdet;
+        o[2] = q;
+        o[0] = -0.5 * (((double)n * 1.8378770664093453 + logdet) + q);
     }
 }
 
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Host side: task table, workspace layout, launch.
+// Host side: per-step problem / tile lists, workspace layout, launches.
 // ---------------------------------------------------------------------------
 #include <algorithm>
 #include <cmath>
@@ -342,50 +292,48 @@ inline size_t al256b(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t batch_ws_bytes(int64_t nmax, int64_t nbatch) {
     const int64_t nt = (nmax + T - 1) / T;
-    const size_t per_tasks = (size_t)(nt * (nt + 1) / 2 + nt + 1);
     size_t b = 0;
     b += al256b(sizeof(BProb) * (size_t)nbatch);
-    b += al256b(sizeof(BTask) * per_tasks * (size_t)nbatch);
-    b += al256b(sizeof(int) * (per_tasks * (size_t)nbatch + 2));
-    b += al256b(sizeof(double) * (size_t)nmax * (size_t)nbatch);
-    b += al256b(sizeof(double) * (size_t)nt * T * T * (size_t)nbatch);
+    b += al256b(sizeof(int32_t) * (size_t)nt * (size_t)nbatch);                  // diag lists
+    b += al256b(sizeof(BTile) * (size_t)(nt * (nt + 1) / 2) * (size_t)nbatch);   // panel lists
+    b += al256b(sizeof(double) * (size_t)nmax * (size_t)nbatch);                 // z
+    b += al256b(sizeof(double) * (size_t)nt * T * T * (size_t)nbatch);           // diagonal inverses
     return b + 256;
 }
 
 struct BatchStaging {
     std::vector<BProb> probs;
-    std::vector<BTask> tasks;
+    std::vector<int32_t> dlist;
+    std::vector<BTile> tlist;
     hipEvent_t done = nullptr;
 };
 
 int batch_run(hipStream_t s, int num_cu, void *&staging_ptr, int32_t nb, const gp_theta_t *th, const int64_t *nh,
               const int64_t *xoff, const int64_t *coff, int32_t dim, const double *X, const double *y,
               double *C_pool, double *out3, int32_t *info, void *ws, size_t ws_bytes) {
+    (void)num_cu;
     BatchStaging *st = static_cast<BatchStaging *>(staging_ptr);
     if (!st) {
         st = new BatchStaging();
         staging_ptr = st;
     }
     if (st->done) {
-        if (hipEventSynchronize(st->done) != hipSuccess) return GP_ERR_HIP;  // host copy of the last call is consumed
+        if (hipEventSynchronize(st->done) != hipSuccess) return GP_ERR_HIP;  // host copy of the last call consumed
     } else if (hipEventCreateWithFlags(&st->done, hipEventDisableTiming) != hipSuccess) {
         return GP_ERR_HIP;
     }
     int64_t nmax = 1;
     for (int b = 0; b < nb; ++b) nmax = std::max(nmax, nh[b]);
     if (ws_bytes < batch_ws_bytes(nmax, nb)) return GP_ERR_WS_TOO_SMALL;
+    const int64_t ntmax = (nmax + T - 1) / T;
     st->probs.assign(nb, BProb{});
-    int64_t toff = 0, zoff = 0, woff = 0;
+    int64_t zoff = 0, woff = 0;
     for (int b = 0; b < nb; ++b) {
         BProb &p = st->probs[b];
         p.n = nh[b];
         p.x_off = xoff[b];
         p.c_off = coff[b];
         p.nt = (int32_t)((p.n + T - 1) / T);
-        p.tflag_off = toff;
-        toff += (int64_t)p.nt * (p.nt + 1) / 2;
-        p.zflag_off = toff;
-        toff += p.nt;
         p.z_off = zoff;
         zoff += p.n;
         p.w_off = woff;
@@ -395,37 +343,24 @@ int batch_run(hipStream_t s, int num_cu, void *&staging_ptr, int32_t nb, const g
         p.inv_rho = std::exp(-th[b].log_rho);
         p.t2 = std::exp(th[b].log_tau2);
     }
-    // order: level, then larger problems first, then row
-    std::vector<int> rank(nb);
-    for (int b = 0; b < nb; ++b) rank[b] = b;
-    std::stable_sort(rank.begin(), rank.end(), [&](int a, int c) { return nh[a] > nh[c]; });
-    std::vector<int> pos(nb);
-    for (int r = 0; r < nb; ++r) pos[rank[r]] = r;
-    struct Key {
-        int64_t level;
-        int32_t prank, i;
-        BTask t;
-    };
-    std::vector<Key> keys;
-    for (int b = 0; b < nb; ++b) {
-        const int nt = st->probs[b].nt;
-        if (nt == 0) {  // empty problem: only the reduce task (loglik 0)
-            keys.push_back({1, pos[b], 0, BTask{b, 0, 0, 2}});
-            continue;
-        }
-        for (int j = 0; j < nt; ++j)
-            for (int i = j; i < nt; ++i) keys.push_back({4LL * j + (i > j ? 2 : 0), pos[b], i, BTask{b, i, j, 0}});
-        for (int i = 0; i < nt; ++i) keys.push_back({4LL * i + 3, pos[b], i, BTask{b, i, i, 1}});
-        keys.push_back({4LL * nt + 1, pos[b], 0, BTask{b, 0, 0, 2}});
+    // step j: problems with nt > j (diagonal tile), tiles (b, i > j) (panel);
+    // larger problems first within a step
+    std::vector<int> order(nb);
+    for (int b = 0; b < nb; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return nh[a] > nh[c]; });
+    std::vector<int64_t> doff(ntmax + 1, 0), toff(ntmax + 1, 0);
+    st->dlist.clear();
+    st->tlist.clear();
+    for (int64_t j = 0; j < ntmax; ++j) {
+        doff[j] = (int64_t)st->dlist.size();
+        toff[j] = (int64_t)st->tlist.size();
+        for (int b : order)
+            if (st->probs[b].nt > j) st->dlist.push_back(b);
+        for (int b : order)
+            for (int i = (int)j + 1; i < st->probs[b].nt; ++i) st->tlist.push_back(BTile{b, i});
     }
-    std::stable_sort(keys.begin(), keys.end(), [](const Key &a, const Key &c) {
-        if (a.level != c.level) return a.level < c.level;
-        if (a.prank != c.prank) return a.prank < c.prank;
-        return a.i < c.i;
-    });
-    st->tasks.resize(keys.size());
-    for (size_t q = 0; q < keys.size(); ++q) st->tasks[q] = keys[q].t;
-    const int64_t ntasks = (int64_t)st->tasks.size();
+    doff[ntmax] = (int64_t)st->dlist.size();
+    toff[ntmax] = (int64_t)st->tlist.size();
 
     char *base = static_cast<char *>(ws);
     size_t off = 0;
@@ -434,27 +369,33 @@ int batch_run(hipStream_t s, int num_cu, void *&staging_ptr, int32_t nb, const g
         off += al256b(bytes);
         return p;
     };
-    const int64_t ntmax = (nmax + T - 1) / T;
-    const size_t per_tasks = (size_t)(ntmax * (ntmax + 1) / 2 + ntmax + 1);
     BProb *d_probs = reinterpret_cast<BProb *>(take(sizeof(BProb) * (size_t)nb));
-    BTask *d_tasks = reinterpret_cast<BTask *>(take(sizeof(BTask) * per_tasks * (size_t)nb));
-    int *d_flags = reinterpret_cast<int *>(take(sizeof(int) * (per_tasks * (size_t)nb + 2)));
+    int32_t *d_dl = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)ntmax * (size_t)nb));
+    BTile *d_tl = reinterpret_cast<BTile *>(take(sizeof(BTile) * (size_t)(ntmax * (ntmax + 1) / 2) * (size_t)nb));
     double *d_z = reinterpret_cast<double *>(take(sizeof(double) * (size_t)nmax * (size_t)nb));
     double *d_w = reinterpret_cast<double *>(take(sizeof(double) * (size_t)ntmax * T * T * (size_t)nb));
-    int *ctl = d_flags + toff;  // [ticket, abort] after the flags
 
     if (hipMemcpyAsync(d_probs, st->probs.data(), sizeof(BProb) * (size_t)nb, hipMemcpyHostToDevice, s) != hipSuccess)
         return GP_ERR_HIP;
-    if (ntasks > 0 && hipMemcpyAsync(d_tasks, st->tasks.data(), sizeof(BTask) * (size_t)ntasks, hipMemcpyHostToDevice,
-                                     s) != hipSuccess)
+    if (!st->dlist.empty() &&
+        hipMemcpyAsync(d_dl, st->dlist.data(), sizeof(int32_t) * st->dlist.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+        return GP_ERR_HIP;
+    if (!st->tlist.empty() &&
+        hipMemcpyAsync(d_tl, st->tlist.data(), sizeof(BTile) * st->tlist.size(), hipMemcpyHostToDevice, s) != hipSuccess)
         return GP_ERR_HIP;
     if (hipEventRecord(st->done, s) != hipSuccess) return GP_ERR_HIP;
-    if (launch_fill(s, d_flags, sizeof(int) * (size_t)(toff + 2)) != hipSuccess) return GP_ERR_HIP;
     if (launch_fill(s, info, sizeof(int32_t) * (size_t)nb) != hipSuccess) return GP_ERR_HIP;
-    if (ntasks == 0) return GP_OK;
-    const int64_t grid = std::min<int64_t>(ntasks, (int64_t)num_cu);
-    hipLaunchKernelGGL(k_batch, dim3((unsigned)grid), dim3(256), 0, s, d_probs, d_tasks, ntasks, dim, X, y, C_pool,
-                       d_z, d_w, d_flags, ctl, out3, info);
+    for (int64_t j = 0; j < ntmax; ++j) {
+        const int64_t nd = doff[j + 1] - doff[j], ntl = toff[j + 1] - toff[j];
+        if (nd > 0)
+            hipLaunchKernelGGL(k_bdiag, dim3((unsigned)nd), dim3(256), 0, s, d_probs, d_dl + doff[j], (int)j, dim, X,
+                               C_pool, d_w, info);
+        if (ntl > 0)
+            hipLaunchKernelGGL(k_bpanel, dim3((unsigned)ntl), dim3(256), 0, s, d_probs, d_tl + toff[j], (int)j, dim, X,
+                               C_pool, d_w, info);
+        if (hipGetLastError() != hipSuccess) return GP_ERR_HIP;
+    }
+    hipLaunchKernelGGL(k_bsolve, dim3((unsigned)nb), dim3(256), 0, s, d_probs, y, C_pool, d_z, d_w, out3, info);
     return hipGetLastError() == hipSuccess ? GP_OK : GP_ERR_HIP;
 }
 

@@ -105,6 +105,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmDesc d, TileMap tm) {
     if (t >= tm.ntiles) return;
     int64_t bi, bj;
     if (!decode_tile(tm, t, bi, bj)) return;
+    // tile indices are workgroup-uniform: keep them (and the slab base
+    // pointers derived from them) in scalar registers
+    bi = __builtin_amdgcn_readfirstlane((int)bi);
+    bj = __builtin_amdgcn_readfirstlane((int)bj);
     const int64_t i0 = bi * BM, j0 = bj * BN;
     const int64_t bz = blockIdx.y;
     const double *A = d.A + bz * d.sA;
@@ -126,32 +130,72 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmDesc d, TileMap tm) {
 #pragma unroll
         for (int n = 0; n < FN; ++n) acc[m][n] = v4d{0.0, 0.0, 0.0, 0.0};
 
+    // Loop-invariant load descriptors: element (ii, kk) of a K-slab sits at a
+    // 32-bit offset from the slab's uniform base pointer, so a K-step issues
+    // its 16 loads with no address arithmetic.  Rows/columns outside the
+    // matrix read the slab base (a valid element) and are zeroed.
+    uint32_t offA[LA], offB[LB];
+    bool okA[LA], okB[LB];
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+        const int e = r * 256 + tid;
+        const int ii = TA ? e / BK : e % BM;
+        const int kk = TA ? e % BK : e / BM;
+        okA[r] = i0 + ii < d.M;
+        offA[r] = okA[r] ? (uint32_t)(8 * (TA ? kk + (int64_t)ii * d.lda : ii + (int64_t)kk * d.lda)) : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+        const int e = r * 256 + tid;
+        const int jj = TB ? e % BN : e / BK;
+        const int kk = TB ? e / BN : e % BK;
+        okB[r] = j0 + jj < d.N;
+        offB[r] = okB[r] ? (uint32_t)(8 * (TB ? jj + (int64_t)kk * d.ldb : kk + (int64_t)jj * d.ldb)) : 0u;
+    }
+    const bool edge = (i0 + BM > d.M) || (j0 + BN > d.N);
     double ra[LA], rb[LB];
 
-    // Branch-free guarded loads: out-of-range elements read a clamped (valid)
-    // address and are replaced by zero, so all loads of a stage issue back to back.
     auto gload = [&](int64_t k0) {
+        const char *Ak = reinterpret_cast<const char *>(TA ? A + k0 + i0 * d.lda : A + i0 + k0 * d.lda);
+        const char *Bk = reinterpret_cast<const char *>(TB ? B + j0 + k0 * d.ldb : B + k0 + j0 * d.ldb);
+        auto ldA = [&](uint32_t o) { return *reinterpret_cast<const double *>(Ak + o); };
+        auto ldB = [&](uint32_t o) { return *reinterpret_cast<const double *>(Bk + o); };
+        if (k0 + BK <= khi) {
+            if (!edge) {
 #pragma unroll
-        for (int r = 0; r < LA; ++r) {
-            const int e = r * 256 + tid;
-            const int ii = TA ? e / BK : e % BM;
-            const int kk = TA ? e % BK : e / BM;
-            const int64_t gi = i0 + ii, gk = k0 + kk;
-            const bool ok = gi < d.M && gk < khi;
-            const int64_t off = ok ? (TA ? gk + gi * d.lda : gi + gk * d.lda) : 0;
-            const double v = A[off];
-            ra[r] = ok ? v : 0.0;
-        }
+                for (int r = 0; r < LA; ++r) ra[r] = ldA(offA[r]);
 #pragma unroll
-        for (int r = 0; r < LB; ++r) {
-            const int e = r * 256 + tid;
-            const int jj = TB ? e % BN : e / BK;
-            const int kk = TB ? e / BN : e % BK;
-            const int64_t gj = j0 + jj, gk = k0 + kk;
-            const bool ok = gj < d.N && gk < khi;
-            const int64_t off = ok ? (TB ? gj + gk * d.ldb : gk + gj * d.ldb) : 0;
-            const double v = B[off];
-            rb[r] = ok ? v : 0.0;
+                for (int r = 0; r < LB; ++r) rb[r] = ldB(offB[r]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < LA; ++r) {
+                    const double v = ldA(offA[r]);
+                    ra[r] = okA[r] ? v : 0.0;
+                }
+#pragma unroll
+                for (int r = 0; r < LB; ++r) {
+                    const double v = ldB(offB[r]);
+                    rb[r] = okB[r] ? v : 0.0;
+                }
+            }
+        } else {  // K tail: columns k >= khi are zero
+            const int kr = (int)(khi - k0);
+#pragma unroll
+            for (int r = 0; r < LA; ++r) {
+                const int e = r * 256 + tid;
+                const int kk = TA ? e % BK : e / BM;
+                const bool ok = okA[r] && kk < kr;
+                const double v = ldA(ok ? offA[r] : 0u);
+                ra[r] = ok ? v : 0.0;
+            }
+#pragma unroll
+            for (int r = 0; r < LB; ++r) {
+                const int e = r * 256 + tid;
+                const int kk = TB ? e / BN : e % BK;
+                const bool ok = okB[r] && kk < kr;
+                const double v = ldB(ok ? offB[r] : 0u);
+                rb[r] = ok ? v : 0.0;
+            }
         }
     };
     auto sstore = [&](int buf) {
@@ -249,6 +293,198 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmDesc d, TileMap tm) {
                     if (ok) C[gi + gj * d.ldc] = fma(d.beta, cv[n][r], d.alpha * acc[m][n][r]);
                 }
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Trailing update C -= P P^T (lower tiles) with direct-to-LDS loads.
+// Each K-slab (16 panel columns x 128 rows for each operand) is copied by
+// global_load_lds_dword straight into one of STAGES LDS buffers, so STAGES - 1
+// slabs are in flight while the matrix cores consume the current one and no
+// registers are spent on staging.  Wave w copies columns w, w + 4, w + 8,
+// w + 12 of both operands, 256 bytes per instruction.  Rows past the matrix
+// are clamped to its last row: they only feed output rows / columns that are
+// never stored.  Requires K % 16 == 0.
+// ---------------------------------------------------------------------------
+GP_DEV void wait_vmcnt_le(int n) {
+    // s_waitcnt vmcnt(n) leaving expcnt / lgkmcnt unconstrained (gfx9 encoding)
+    switch (n) {
+    case 0: __builtin_amdgcn_s_waitcnt((0 & 15) | (7 << 4) | (15 << 8) | ((0 >> 4) << 14)); break;
+    case 16: __builtin_amdgcn_s_waitcnt((16 & 15) | (7 << 4) | (15 << 8) | ((16 >> 4) << 14)); break;
+    case 32: __builtin_amdgcn_s_waitcnt((32 & 15) | (7 << 4) | (15 << 8) | ((32 >> 4) << 14)); break;
+    case 48: __builtin_amdgcn_s_waitcnt((48 & 15) | (7 << 4) | (15 << 8) | ((48 >> 4) << 14)); break;
+    default: __builtin_amdgcn_s_waitcnt((0 & 15) | (7 << 4) | (15 << 8)); break;
+    }
+}
+
+// One 256-byte LDS-DMA copy: each lane moves the dword at `g` to LDS address
+// lds + 4 * lane.  Written as inline assembly so the compiler's wait-count
+// pass, which cannot tell LDS-DMA targets apart, does not drain every copy in
+// flight before each LDS read; the kernel orders the copies itself with
+// explicit vmcnt waits and barriers.  m0 is restored for the compiler.
+GP_DEV void lds_dma_dword(const void *g, uint32_t lds_uniform) {
+    uint32_t saved;
+    asm volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dword %1, off\n\ts_mov_b32 m0, %0"
+                 : "=&s"(saved)
+                 : "v"(g), "s"(lds_uniform)
+                 : "memory");
+}
+
+// Multi-tile variant: a workgroup runs TPW consecutive tiles of its XCD's
+// range with a two-stage LDS pipeline that never drains between tiles.
+// During the last slab of a tile it issues the next tile's first slab and the
+// loads of the current C tile, so the HBM traffic of the epilogue overlaps the
+// matrix cores instead of stalling every workgroup at the same moment.
+// Workgroups still retire every TPW tiles, which leaves room for kernels on
+// other streams (the lookahead panel factorisation).  Requires K % 16 == 0.
+template <int TPW, int TAG>
+__global__ __launch_bounds__(256, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
+    constexpr int BM = 128, BN = 128, BKD = 16, WTM = 64, WTN = 64, FM = 4, FN = 4;
+    __shared__ double As0[BKD][BM], Bs0[BKD][BN];
+    __shared__ double As1[BKD][BM], Bs1[BKD][BN];
+
+    if (d.info && *d.info) return;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave & 1, wn = wave >> 1;
+    const double *P = d.A;
+    double *C = d.C;
+    const int64_t nk = d.K / BKD;
+    // this workgroup's tiles: [t_begin, t_end) of its XCD's contiguous range
+    const int64_t R = (tm.ntiles + 7) / 8;
+    const int64_t xcd = blockIdx.x & 7, widx = blockIdx.x >> 3;
+    const int64_t t_begin = xcd * R + widx * TPW;
+    int64_t t_end = t_begin + TPW;
+    if (t_end > (xcd + 1) * R) t_end = (xcd + 1) * R;
+    if (t_end > tm.ntiles) t_end = tm.ntiles;
+
+    auto next_valid = [&](int64_t t, int64_t &bi, int64_t &bj) -> int64_t {
+        for (; t < t_end; ++t)
+            if (decode_tile(tm, t, bi, bj)) return t;
+        return t_end;
+    };
+    int64_t bi, bj;
+    int64_t t = next_valid(t_begin, bi, bj);
+    if (t >= t_end) return;
+
+    uint32_t offA[4], offB[4];
+    auto set_offsets = [&](int64_t i0, int64_t j0) {
+        const int64_t rmaxA = d.M - 1 - i0, rmaxB = d.N - 1 - j0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t r = 32 * q + (lane >> 1);
+            offA[q] = (uint32_t)(8 * (r < rmaxA ? r : rmaxA) + 4 * (lane & 1));
+            offB[q] = (uint32_t)(8 * (r < rmaxB ? r : rmaxB) + 4 * (lane & 1));
+        }
+    };
+    auto issue = [&](int64_t i0, int64_t j0, int64_t k0, double (*Ad)[BM], double (*Bd)[BN]) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int kk = wave + 4 * c;
+            const char *colA = reinterpret_cast<const char *>(P + i0 + (k0 + kk) * d.lda);
+            const char *colB = reinterpret_cast<const char *>(P + j0 + (k0 + kk) * d.lda);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                lds_dma_dword(colA + offA[q],
+                              __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)&Ad[kk][32 * q]));
+                lds_dma_dword(colB + offB[q],
+                              __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)&Bd[kk][32 * q]));
+            }
+        }
+    };
+
+    bi = __builtin_amdgcn_readfirstlane((int)bi);
+    bj = __builtin_amdgcn_readfirstlane((int)bj);
+    int64_t i0 = bi * BM, j0 = bj * BN;
+    set_offsets(i0, j0);
+    int stage = 0;  // stage holding the slab about to be consumed
+    issue(i0, j0, 0, As0, Bs0);
+    bool first = true;
+
+    for (;;) {
+        int64_t nbi = 0, nbj = 0;
+        const int64_t tn = next_valid(t + 1, nbi, nbj);
+        const bool has_next = tn < t_end;
+        nbi = __builtin_amdgcn_readfirstlane((int)nbi);
+        nbj = __builtin_amdgcn_readfirstlane((int)nbj);
+        const int64_t ni0 = nbi * BM, nj0 = nbj * BN;
+
+        v4d acc[FM][FN];
+#pragma unroll
+        for (int m = 0; m < FM; ++m)
+#pragma unroll
+            for (int n = 0; n < FN; ++n) acc[m][n] = v4d{0.0, 0.0, 0.0, 0.0};
+        double cv[FM][FN][4];
+
+        const int64_t rb0 = i0 + wm * WTM + (lane >> 4);
+        const int64_t cb0 = j0 + wn * WTN + (lane & 15);
+        const bool interior = (i0 + BM <= d.M) && (j0 + BN <= d.N) && (i0 >= j0 + BN);
+
+        for (int64_t k = 0; k < nk; ++k) {
+            // the only copy in flight is this slab's (issued one step ago, or
+            // during the previous tile, whose C loads already waited for it)
+            if (k > 0 || first) wait_vmcnt_le(0);
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+            double (*Ar)[BM] = stage ? As1 : As0;
+            double (*Br)[BN] = stage ? Bs1 : Bs0;
+            double (*Ad)[BM] = stage ? As0 : As1;
+            double (*Bd)[BN] = stage ? Bs0 : Bs1;
+            if (k + 1 < nk) {
+                issue(i0, j0, (k + 1) * BKD, Ad, Bd);
+            } else {
+                if (has_next) {
+                    const uint32_t sa0 = offA[0], sa1 = offA[1], sa2 = offA[2], sa3 = offA[3];
+                    const uint32_t sb0 = offB[0], sb1 = offB[1], sb2 = offB[2], sb3 = offB[3];
+                    set_offsets(ni0, nj0);
+                    issue(ni0, nj0, 0, Ad, Bd);
+                    offA[0] = sa0; offA[1] = sa1; offA[2] = sa2; offA[3] = sa3;
+                    offB[0] = sb0; offB[1] = sb1; offB[2] = sb2; offB[3] = sb3;
+                }
+                // C loads for the epilogue, behind the copies above
+#pragma unroll
+                for (int m = 0; m < FM; ++m)
+#pragma unroll
+                    for (int n = 0; n < FN; ++n)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int64_t gi = rb0 + m * 16 + 4 * r, gj = cb0 + n * 16;
+                            const bool ok = interior || (gi < d.M && gj < d.N && gi >= gj);
+                            cv[m][n][r] = C[ok ? gi + gj * d.ldc : 0];
+                        }
+            }
+#pragma unroll
+            for (int kk = 0; kk < BKD; kk += 4) {
+                double a[FM], b[FN];
+#pragma unroll
+                for (int m = 0; m < FM; ++m) a[m] = Ar[kk + (lane >> 4)][wm * WTM + m * 16 + (lane & 15)];
+#pragma unroll
+                for (int n = 0; n < FN; ++n) b[n] = Br[kk + (lane >> 4)][wn * WTN + n * 16 + (lane & 15)];
+#pragma unroll
+                for (int m = 0; m < FM; ++m)
+#pragma unroll
+                    for (int n = 0; n < FN; ++n)
+                        acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[n], acc[m][n], 0, 0, 0);
+            }
+            stage ^= 1;
+        }
+#pragma unroll
+        for (int m = 0; m < FM; ++m)
+#pragma unroll
+            for (int n = 0; n < FN; ++n)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t gi = rb0 + m * 16 + 4 * r, gj = cb0 + n * 16;
+                    const bool ok = interior || (gi < d.M && gj < d.N && gi >= gj);
+                    if (ok) C[gi + gj * d.ldc] = cv[m][n][r] - acc[m][n][r];
+                }
+        if (!has_next) break;
+        t = tn;
+        i0 = ni0;
+        j0 = nj0;
+        set_offsets(i0, j0);
+        first = false;
     }
 }
 
