@@ -89,7 +89,9 @@ typedef struct {
     int32_t ir_max_iter; /* mixed modes: cap on iterative-refinement sweeps (0 = no refinement) */
     double ir_tol;       /* mixed modes: stop when |r - C x| / |r| <= ir_tol (FP64 residual) */
     int32_t reorder;     /* mixed modes: 1 = order the points along a Morton curve inside gp_loglik* */
-    int32_t reserved[3];
+    int32_t panel_cus;   /* compute units kept free of trailing updates for the lookahead chain
+                            (0 = none: one shared stream pair without CU masks) */
+    int32_t reserved[2];
 } gp_options_t;
 
 /* ---- handle ------------------------------------------------------------ */
@@ -114,7 +116,8 @@ int gp_profile_read(gp_handle_t h, double *out3);
 
 /* Bytes of workspace the call `op` needs for problem size n (and m new points
  * for GP_OP_KRIGE / right-hand sides for GP_OP_TRSM; for GP_OP_BATCHED, n is
- * the largest problem and m the number of problems). */
+ * the largest problem and m the number of problems).  The factorising calls
+ * size a panel buffer by the handle's panel width: query after gp_set_options. */
 int gp_workspace_size(gp_handle_t h, gp_op_t op, int64_t n, int64_t m, gp_prec_t prec,
                       size_t *bytes);
 
@@ -132,7 +135,11 @@ int gp_cross_cov_build(gp_handle_t h, gp_theta_t th, int64_t n, int64_t m, int32
 /* In place: the lower triangle of A [dev, lda >= n] is overwritten by L with
  * L L^T = A; the strict upper triangle is untouched.  *info_dev [dev] gets 0 or
  * the first failing 1-based column.  prec selects the trailing-update
- * arithmetic (gp_prec_t). */
+ * arithmetic (gp_prec_t).  Right-looking by panels of opt.nb columns: the
+ * panel's diagonal block is factored in 64-column steps and inverted, the rows
+ * below it are multiplied by that inverse, then the trailing matrix is
+ * updated; with opt.lookahead the next panel's diagonal block is factored on a
+ * second stream during that update. */
 int gp_potrf(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda,
              int32_t *info_dev, void *ws, size_t ws_bytes);
 

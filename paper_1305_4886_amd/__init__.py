@@ -42,7 +42,8 @@ class Theta(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("nb", ctypes.c_int32), ("lookahead", ctypes.c_int32), ("band", ctypes.c_int32),
                 ("ir_max_iter", ctypes.c_int32), ("ir_tol", ctypes.c_double),
-                ("reorder", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("reorder", ctypes.c_int32), ("panel_cus", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class GPError(RuntimeError):
@@ -276,7 +277,7 @@ def loglik(X, y, th, prec=GP_FP64, mu=None, S=None, want_alpha=False, ws=None):
     info = torch.zeros(1, dtype=torch.int32, device="cuda")
     ir = torch.zeros(3, dtype=torch.float64, device="cuda")
     alpha = torch.empty(n, dtype=torch.float64, device="cuda") if want_alpha else None
-    mu_t = None if mu is None else _f64(torch.as_tensor(mu, device="cuda").expand(n).contiguous())
+    mu_t = None if mu is None else _f64(torch.as_tensor(mu, dtype=torch.float64, device="cuda").expand(n).contiguous())
     ws = ws if ws is not None else h.workspace(GP_OP_LOGLIK, n, 0, prec)
     check(lib().gp_loglik(h.ptr, th, prec, n, d, _ptr(X), _ptr(y), _ptr(mu_t), _ptr(S), S.shape[1],
                           _ptr(out3), _ptr(alpha), _ptr(info), _ptr(ir), _ptr(ws), ws.numel()))
@@ -294,7 +295,7 @@ def loglik_grad(X, y, th, prec=GP_FP64, mu=None, S=None, want_alpha=False, ws=No
     info = torch.zeros(1, dtype=torch.int32, device="cuda")
     ir = torch.zeros(3, dtype=torch.float64, device="cuda")
     alpha = torch.empty(n, dtype=torch.float64, device="cuda") if want_alpha else None
-    mu_t = None if mu is None else _f64(torch.as_tensor(mu, device="cuda").expand(n).contiguous())
+    mu_t = None if mu is None else _f64(torch.as_tensor(mu, dtype=torch.float64, device="cuda").expand(n).contiguous())
     ws = ws if ws is not None else h.workspace(GP_OP_LOGLIK_GRAD, n, 0, prec)
     check(lib().gp_loglik_grad(h.ptr, th, prec, n, d, _ptr(X), _ptr(y), _ptr(mu_t), _ptr(S), S.shape[1],
                                _ptr(out3), _ptr(grad3), _ptr(alpha), _ptr(info), _ptr(ir), _ptr(ws),
@@ -349,3 +350,47 @@ def morton_order(X, ws=None):
     ws = ws if ws is not None else h.workspace(GP_OP_MORTON, n)
     check(lib().gp_morton_order(h.ptr, n, d, _ptr(X), _ptr(perm), _ptr(ws), ws.numel()))
     return perm
+
+
+def _loglik_function():
+    torch = _torch()
+
+    class LogLik(torch.autograd.Function):
+        """Marginal log-likelihood as a differentiable function of
+        log_theta = (log sigma^2, log rho, log tau^2).  The forward pass runs
+        gp_loglik, or gp_loglik_grad when log_theta needs a gradient (the
+        adjoint is formed in the same pass); backward scales that gradient."""
+
+        @staticmethod
+        def forward(ctx, log_theta, X, y, kind, prec, mu):
+            th = theta(kind, log=[float(v) for v in log_theta.detach().cpu()])
+            if ctx.needs_input_grad[0]:
+                r = loglik_grad(X, y, th, prec, mu)
+                g = r["grad"]
+            else:
+                r = loglik(X, y, th, prec, mu)
+                g = None
+            info = int(r["info"].item())
+            if info > 0:
+                raise NotPositiveDefinite(info)
+            ctx.save_for_backward(g if g is not None else torch.zeros(3, dtype=torch.float64, device="cuda"))
+            return r["out3"][0].clone().to(log_theta.device)
+
+        @staticmethod
+        def backward(ctx, gout):
+            (g,) = ctx.saved_tensors
+            return (gout * g).to(gout.device), None, None, None, None, None
+
+    return LogLik
+
+
+_LogLik = None
+
+
+def log_likelihood(X, y, log_theta, kernel=GP_EXP, prec=GP_FP64, mu=None):
+    """Differentiable loglik: a 0-d tensor whose backward gives d loglik / d log_theta."""
+    global _LogLik
+    if _LogLik is None:
+        _LogLik = _loglik_function()
+    k = KERNELS.get(kernel, kernel) if isinstance(kernel, str) else int(kernel)
+    return _LogLik.apply(log_theta, X, y, k, prec, mu)

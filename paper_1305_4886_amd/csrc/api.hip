@@ -51,8 +51,26 @@ CovParams cov_params(const gp_theta_t &th, int dim) {
 // ---- workspace layouts ------------------------------------------------------
 struct Layout {
     size_t dinv = 0, sync = 0, z = 0, vec2 = 0, vec3 = 0, vec4 = 0, vec5 = 0, part = 0, big1 = 0, big2 = 0,
-           big3 = 0, irst = 0, perm = 0, keys = 0, box = 0, xp = 0, yp = 0, mup = 0, total = 0;
+           big3 = 0, irst = 0, perm = 0, keys = 0, box = 0, xp = 0, yp = 0, mup = 0, pbuf = 0, vinv = 0,
+           vtmp = 0, total = 0;
 };
+
+// Buffers of the panel steps of the factorisation (null when n <= NB).
+struct PanelBufs {
+    double *pbuf = nullptr;  // copy of the rows below a diagonal block, (n - NB) x NB
+    double *vinv = nullptr;  // inverse of a diagonal block, NB x NB
+    double *vtmp = nullptr;  // products of the blocked inverse, trtri_tmp_elems(NB)
+};
+
+int64_t panel_width(gp_handle_t h) { return h->opt.nb > 0 ? h->opt.nb : 512; }
+
+// Reserved compute unit r of `reserve`: spaced ncu / reserve apart and offset
+// by r mod 8, which gives every XCD the same share whether mask bits are
+// numbered XCD by XCD or round-robin over the eight XCDs.
+int reserved_cu(int r, int reserve, int ncu) {
+    const int c = r * (ncu / reserve) + (r % 8);
+    return c < ncu ? c : ncu - 1;
+}
 
 inline int64_t next_pow2(int64_t n) {
     int64_t p = 1;
@@ -80,7 +98,7 @@ size_t trtri_tmp_elems(int64_t n) {
 
 constexpr int GRAD_PARTS = 2048;
 
-Layout layout(gp_op_t op, int64_t n, int64_t m, gp_prec_t prec) {
+Layout layout(gp_handle_t h, gp_op_t op, int64_t n, int64_t m, gp_prec_t prec) {
     Layout L;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -90,9 +108,17 @@ Layout layout(gp_op_t op, int64_t n, int64_t m, gp_prec_t prec) {
     };
     const int64_t nb = nblocks(n);
     const size_t vec = sizeof(double) * (size_t)(n > 0 ? n : 1);
+    const int64_t NB = panel_width(h);
+    auto take_panel = [&]() {
+        if (n <= NB) return;
+        L.pbuf = take(sizeof(double) * (size_t)(n - NB) * (size_t)NB);
+        L.vinv = take(sizeof(double) * (size_t)NB * (size_t)NB);
+        L.vtmp = take(sizeof(double) * trtri_tmp_elems(NB));
+    };
     switch (op) {
     case GP_OP_POTRF:
         L.dinv = take(sizeof(double) * DB * DB * (size_t)nb);
+        take_panel();
         break;
     case GP_OP_TRSV:
         L.dinv = take(sizeof(double) * DB * DB * (size_t)nb);
@@ -105,6 +131,7 @@ Layout layout(gp_op_t op, int64_t n, int64_t m, gp_prec_t prec) {
     case GP_OP_LOGLIK:
     case GP_OP_LOGLIK_GRAD:
         L.dinv = take(sizeof(double) * DB * DB * (size_t)nb);
+        take_panel();
         L.sync = take(sizeof(int) * (size_t)(nb + 2));
         L.z = take(vec);     // L^{-1} b
         L.vec2 = take(vec);  // x = C^{-1} b (evaluation order)
@@ -152,6 +179,16 @@ T *at(void *ws, size_t off) {
     return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
 }
 
+PanelBufs panel_bufs(void *ws, const Layout &L) {
+    PanelBufs p;
+    if (L.vinv) {  // never the first buffer of a layout
+        p.pbuf = at<double>(ws, L.pbuf);
+        p.vinv = at<double>(ws, L.vinv);
+        p.vtmp = at<double>(ws, L.vtmp);
+    }
+    return p;
+}
+
 #define HIPCHK(x)                                                                                  \
     do {                                                                                           \
         hipError_t e_ = (x);                                                                       \
@@ -183,45 +220,172 @@ hipError_t trailing(gp_handle_t h, hipStream_t s, gp_prec_t prec, const double *
 }
 
 // ---- blocked Cholesky -------------------------------------------------------
+// Blocked triangular inverse W = L^{-1} of an n x n lower factor whose 64 x 64
+// diagonal blocks are already inverted (dinv, consecutive blocks), by
+// recursive doubling (see trtri_tmp_elems).  W is dense n x n with ldw == n;
+// T holds trtri_tmp_elems(n) doubles.
+int trtri_lower(hipStream_t s, int64_t n, const double *L, int64_t ldl, const double *dinv, double *W,
+                double *T, const int32_t *info) {
+    const int64_t ldw = n;
+    HIPCHK(launch_fill(s, W, sizeof(double) * (size_t)n * (size_t)n));
+    HIPCHK(launch_place_dinv(s, n, dinv, W, ldw));
+    for (int64_t S = 2 * DB; S / 2 < n; S *= 2) {
+        const int64_t hh = S / 2;
+        const int64_t nfull = n / S;
+        if (nfull > 0) {
+            GemmDesc d{};
+            d.A = L + hh; d.lda = ldl; d.sA = S * (1 + ldl);           // L21 of node 0
+            d.B = W; d.ldb = ldw; d.sB = S * (1 + ldw);                 // W11
+            d.C = T; d.ldc = hh; d.sC = hh * hh;
+            d.M = hh; d.N = hh; d.K = hh; d.alpha = 1.0; d.beta = 0.0;
+            d.klo_j = 1; d.batch = nfull; d.info = info;
+            HIPCHK(launch_gemm_f64(s, d));
+            GemmDesc e{};
+            e.A = W + hh * (1 + ldw); e.lda = ldw; e.sA = S * (1 + ldw);  // W22
+            e.B = T; e.ldb = hh; e.sB = hh * hh;
+            e.C = W + hh; e.ldc = ldw; e.sC = S * (1 + ldw);              // W21
+            e.M = hh; e.N = hh; e.K = hh; e.alpha = -1.0; e.beta = 0.0;
+            e.khi_i = 1; e.batch = nfull; e.info = info;
+            HIPCHK(launch_gemm_f64(s, e));
+        }
+        const int64_t o = nfull * S;
+        const int64_t h2 = n - o - hh;
+        if (h2 > 0) {
+            GemmDesc d{};
+            d.A = L + (o + hh) + o * ldl; d.lda = ldl;
+            d.B = W + o * (1 + ldw); d.ldb = ldw;
+            d.C = T; d.ldc = h2;
+            d.M = h2; d.N = hh; d.K = hh; d.alpha = 1.0; d.beta = 0.0;
+            d.klo_j = 1; d.batch = 1; d.info = info;
+            HIPCHK(launch_gemm_f64(s, d));
+            GemmDesc e{};
+            e.A = W + (o + hh) * (1 + ldw); e.lda = ldw;
+            e.B = T; e.ldb = h2;
+            e.C = W + (o + hh) + o * ldw; e.ldc = ldw;
+            e.M = h2; e.N = hh; e.K = h2; e.alpha = -1.0; e.beta = 0.0;
+            e.khi_i = 1; e.batch = 1; e.info = info;
+            HIPCHK(launch_gemm_f64(s, e));
+        }
+    }
+    return GP_OK;
+}
+
+// CU masks: bit c of word c / 32 enables compute unit c.  The reserved units
+// are spread evenly over the index range so that each XCD keeps the same
+// number of units for the trailing update.
+static int make_masked_streams(gp_handle_t h, int reserve) {
+    if (h->masked_for == reserve && h->main_cu) return GP_OK;
+    if (h->main_cu) {
+        hipStreamSynchronize(h->main_cu);
+        hipStreamSynchronize(h->side_cu);
+        hipStreamDestroy(h->main_cu);
+        hipStreamDestroy(h->side_cu);
+        h->main_cu = h->side_cu = nullptr;
+        h->masked_for = 0;
+    }
+    const int ncu = h->num_cu;
+    if (reserve <= 0 || reserve >= ncu / 2) return GP_OK;
+    std::vector<uint32_t> all((size_t)(ncu + 31) / 32, 0u), rest;
+    for (int c = 0; c < ncu; ++c) all[(size_t)c / 32] |= 1u << (c % 32);
+    rest = all;
+    for (int r = 0; r < reserve; ++r) {
+        const int c = reserved_cu(r, reserve, ncu);
+        rest[(size_t)c / 32] &= ~(1u << (c % 32));
+    }
+    if (hipExtStreamCreateWithCUMask(&h->main_cu, (uint32_t)rest.size(), rest.data()) != hipSuccess)
+        return GP_ERR_HIP;
+    if (hipExtStreamCreateWithCUMask(&h->side_cu, (uint32_t)all.size(), all.data()) != hipSuccess) {
+        hipStreamDestroy(h->main_cu);
+        h->main_cu = nullptr;
+        return GP_ERR_HIP;
+    }
+    h->masked_for = reserve;
+    return GP_OK;
+}
+
+// Right-looking blocked Cholesky (Section 2.1): per panel of NB columns,
+// (1) the diagonal block A11 is factored in 64-column steps restricted to the
+// block (one-wave factor + inverse of each 64 x 64 block, the block's rows
+// below it multiplied by that inverse, update of the rest of the block), then
+// inverted, V = L11^{-1}; (2) the rows below get L21 = A21 V^T as one product
+// (A21 copied to pbuf first); (3) the trailing matrix gets A22 -= L21 L21^T.
+// With lookahead, step (3) is split: the columns of the next panel first,
+// then the next panel's step (1) on the side stream while the rest of (3)
+// runs on the main one.
 int potrf_impl(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda, int32_t *info,
-               double *dinv) {
-    hipStream_t s = h->stream;
-    const int64_t NB = h->opt.nb > 0 ? h->opt.nb : 256;
-    HIPCHK(launch_set_info(s, info));
+               double *dinv, const PanelBufs &pb) {
+    hipStream_t user = h->stream;
+    const int64_t NB = panel_width(h);
+    HIPCHK(launch_set_info(user, info));
     if (n <= 0) return GP_OK;
 
-    auto factor_panel = [&](hipStream_t st, int64_t c0) -> int {
-        const int64_t c1 = (c0 + NB < n) ? c0 + NB : n;
+    hipStream_t s = user, side = h->side;
+    const bool la = h->opt.lookahead && n > NB;
+    if (la && h->opt.panel_cus > 0) {
+        int rc = make_masked_streams(h, h->opt.panel_cus);
+        if (rc) return rc;
+        if (h->main_cu) {
+            s = h->main_cu;
+            side = h->side_cu;
+            HIPCHK(hipEventRecord(h->ev_in, user));
+            HIPCHK(hipStreamWaitEvent(s, h->ev_in, 0));
+        }
+    }
+
+    // (1) for the panel [c0, c1)
+    auto diag_block = [&](hipStream_t st, int64_t c0, int64_t c1) -> int {
         for (int64_t d = c0; d < c1; d += DB) {
             const int jb = (int)((n - d) < DB ? (n - d) : DB);
             double *W = dinv + (d / DB) * DB * DB;
             HIPCHK(launch_diag_potrf(st, A + d + d * lda, lda, jb, W, info, d));
-            const int64_t M = n - d - jb;
-            if (M > 0) HIPCHK(launch_panel_solve(st, A + (d + jb) + d * lda, lda, W, M, jb, info));
-            const int64_t nc = c1 - (d + jb);
-            if (nc > 0 && M > 0)
+            const int64_t Mi = c1 - d - jb;
+            if (Mi > 0) {
+                HIPCHK(launch_panel_solve(st, A + (d + jb) + d * lda, lda, W, Mi, jb, info));
                 HIPCHK(launch_syrk_lower(st, GP_FP64, -1, A + (d + jb) + d * lda, lda,
-                                         A + (d + jb) + (d + jb) * lda, lda, M, nc, jb, info, 2));
+                                         A + (d + jb) + (d + jb) * lda, lda, Mi, Mi, jb, info, 2));
+            }
+        }
+        if (c1 < n) {
+            int rc = trtri_lower(st, c1 - c0, A + c0 + c0 * lda, lda, dinv + (c0 / DB) * DB * DB, pb.vinv,
+                                 pb.vtmp, info);
+            if (rc) return rc;
         }
         return GP_OK;
     };
+    // (2) for the panel [c0, c1), c1 < n
+    auto below = [&](hipStream_t st, int64_t c0, int64_t c1) -> int {
+        const int64_t M = n - c1, K = c1 - c0;
+        HIPCHK(launch_copy2d(st, M, K, A + c1 + c0 * lda, lda, pb.pbuf, M));
+        GemmDesc g{};
+        g.A = pb.pbuf; g.lda = M;
+        g.B = pb.vinv; g.ldb = K; g.tb = 1;  // op(B)[k, j] = V[j, k], zero for k > j
+        g.khi_j = 1;
+        g.C = A + c1 + c0 * lda; g.ldc = lda;
+        g.M = M; g.N = K; g.K = K; g.alpha = 1.0; g.beta = 0.0;
+        g.batch = 1; g.info = info;
+        HIPCHK(launch_gemm_f64(st, g));
+        return GP_OK;
+    };
 
-    int rc = factor_panel(s, 0);
-    if (rc) return rc;
+    int rc = 0;
+    {
+        const int64_t c1 = NB < n ? NB : n;
+        if ((rc = diag_block(s, 0, c1))) return rc;
+        if (c1 < n && (rc = below(s, 0, c1))) return rc;
+    }
     for (int64_t c0 = 0; c0 < n; c0 += NB) {
         const int64_t c1 = (c0 + NB < n) ? c0 + NB : n;
         if (c1 >= n) break;
         const int64_t K = c1 - c0;
         const int64_t c2 = (c1 + NB < n) ? c1 + NB : n;
-        if (h->opt.lookahead) {
+        if (la) {
             // columns of the next panel first
             HIPCHK(trailing(h, s, prec, A + c1 + c0 * lda, lda, A + c1 + c1 * lda, lda, n - c1, c2 - c1, K,
                             info));
             HIPCHK(hipEventRecord(h->ev_cols, s));
-            HIPCHK(hipStreamWaitEvent(h->side, h->ev_cols, 0));
-            rc = factor_panel(h->side, c1);
-            if (rc) return rc;
-            HIPCHK(hipEventRecord(h->ev_panel, h->side));
+            HIPCHK(hipStreamWaitEvent(side, h->ev_cols, 0));
+            if ((rc = diag_block(side, c1, c2))) return rc;
+            HIPCHK(hipEventRecord(h->ev_panel, side));
             if (c2 < n)
                 HIPCHK(trailing(h, s, prec, A + c2 + c0 * lda, lda, A + c2 + c2 * lda, lda, n - c2, n - c2,
                                 K, info));
@@ -229,9 +393,13 @@ int potrf_impl(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda,
         } else {
             HIPCHK(trailing(h, s, prec, A + c1 + c0 * lda, lda, A + c1 + c1 * lda, lda, n - c1, n - c1, K,
                             info));
-            rc = factor_panel(s, c1);
-            if (rc) return rc;
+            if ((rc = diag_block(s, c1, c2))) return rc;
         }
+        if (c2 < n && (rc = below(s, c1, c2))) return rc;
+    }
+    if (s != user) {
+        HIPCHK(hipEventRecord(h->ev_out, s));
+        HIPCHK(hipStreamWaitEvent(user, h->ev_out, 0));
     }
     return GP_OK;
 }
@@ -301,46 +469,8 @@ int cinv_impl(gp_handle_t h, int64_t n, double *C, int64_t ldc, const double *di
               const int32_t *info) {
     hipStream_t s = h->stream;
     const int64_t ldw = n;
-    HIPCHK(launch_fill(s, W, sizeof(double) * (size_t)n * (size_t)n));
-    HIPCHK(launch_place_dinv(s, n, dinv, W, ldw));
-    for (int64_t S = 2 * DB; S / 2 < n; S *= 2) {
-        const int64_t hh = S / 2;
-        const int64_t nfull = n / S;
-        if (nfull > 0) {
-            GemmDesc d{};
-            d.A = C + hh; d.lda = ldc; d.sA = S * (1 + ldc);           // L21 of node 0
-            d.B = W; d.ldb = ldw; d.sB = S * (1 + ldw);                 // W11
-            d.C = T; d.ldc = hh; d.sC = hh * hh;
-            d.M = hh; d.N = hh; d.K = hh; d.alpha = 1.0; d.beta = 0.0;
-            d.klo_j = 1; d.batch = nfull; d.info = info;
-            HIPCHK(launch_gemm_f64(s, d));
-            GemmDesc e{};
-            e.A = W + hh * (1 + ldw); e.lda = ldw; e.sA = S * (1 + ldw);  // W22
-            e.B = T; e.ldb = hh; e.sB = hh * hh;
-            e.C = W + hh; e.ldc = ldw; e.sC = S * (1 + ldw);              // W21
-            e.M = hh; e.N = hh; e.K = hh; e.alpha = -1.0; e.beta = 0.0;
-            e.khi_i = 1; e.batch = nfull; e.info = info;
-            HIPCHK(launch_gemm_f64(s, e));
-        }
-        const int64_t o = nfull * S;
-        const int64_t h2 = n - o - hh;
-        if (h2 > 0) {
-            GemmDesc d{};
-            d.A = C + (o + hh) + o * ldc; d.lda = ldc;
-            d.B = W + o * (1 + ldw); d.ldb = ldw;
-            d.C = T; d.ldc = h2;
-            d.M = h2; d.N = hh; d.K = hh; d.alpha = 1.0; d.beta = 0.0;
-            d.klo_j = 1; d.batch = 1; d.info = info;
-            HIPCHK(launch_gemm_f64(s, d));
-            GemmDesc e{};
-            e.A = W + (o + hh) * (1 + ldw); e.lda = ldw;
-            e.B = T; e.ldb = h2;
-            e.C = W + (o + hh) + o * ldw; e.ldc = ldw;
-            e.M = h2; e.N = hh; e.K = h2; e.alpha = -1.0; e.beta = 0.0;
-            e.khi_i = 1; e.batch = 1; e.info = info;
-            HIPCHK(launch_gemm_f64(s, e));
-        }
-    }
+    int rc = trtri_lower(s, n, C, ldc, dinv, W, T, info);
+    if (rc) return rc;
     GemmDesc d{};
     d.A = W; d.lda = ldw; d.ta = 1;
     d.B = W; d.ldb = ldw; d.tb = 0;
@@ -361,7 +491,7 @@ int cinv_impl(gp_handle_t h, int64_t n, double *C, int64_t ldc, const double *di
 int loglik_core(gp_handle_t h, gp_op_t op, gp_theta_t th, gp_prec_t prec, int64_t n, int32_t dim,
                 const double *X, const double *y, const double *mu, double *C, int64_t ldc, double *out3,
                 double *grad3, double *alpha_dev, int32_t *info, double *ir, void *ws) {
-    const Layout lay = layout(op, n, 0, prec);
+    const Layout lay = layout(h, op, n, 0, prec);
     hipStream_t s = h->stream;
     const CovParams cp = cov_params(th, dim);
     double *dinv = at<double>(ws, lay.dinv);
@@ -382,7 +512,7 @@ int loglik_core(gp_handle_t h, gp_op_t op, gp_theta_t th, gp_prec_t prec, int64_
         mue = mu ? mp : nullptr;
     }
     HIPCHK(launch_cov_lower(s, cp, n, Xe, C, ldc, nullptr));
-    int rc = potrf_impl(h, prec, n, C, ldc, info, dinv);
+    int rc = potrf_impl(h, prec, n, C, ldc, info, dinv, panel_bufs(ws, lay));
     if (rc) return rc;
     HIPCHK(launch_sub_mu(s, n, ye, mue, b));
     HIPCHK(launch_copy_vec(s, n, b, z));
@@ -444,8 +574,9 @@ const char *gp_strerror(int code) {
 
 static void default_options(gp_options_t *o) {
     memset(o, 0, sizeof(*o));
-    o->nb = 256;
+    o->nb = 512;
     o->lookahead = 1;
+    o->panel_cus = 8;
     o->band = 2;
     o->ir_max_iter = 20;
     o->ir_tol = 1e-10;
@@ -463,10 +594,14 @@ int gp_create(gp_handle_t *h, void *stream) {
         hipDeviceGetAttribute(&p->num_cu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess ||
         hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_cols, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&p->ev_panel, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&p->ev_panel, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_out, hipEventDisableTiming) != hipSuccess) {
         if (p->side) hipStreamDestroy(p->side);
         if (p->ev_cols) hipEventDestroy(p->ev_cols);
         if (p->ev_panel) hipEventDestroy(p->ev_panel);
+        if (p->ev_in) hipEventDestroy(p->ev_in);
+        if (p->ev_out) hipEventDestroy(p->ev_out);
         delete p;
         return GP_ERR_HIP;
     }
@@ -505,8 +640,16 @@ int gp_destroy(gp_handle_t h) {
     batch_staging_free(h->batch_staging);
     hipStreamSynchronize(h->side);
     hipStreamDestroy(h->side);
+    if (h->main_cu) {
+        hipStreamSynchronize(h->main_cu);
+        hipStreamSynchronize(h->side_cu);
+        hipStreamDestroy(h->main_cu);
+        hipStreamDestroy(h->side_cu);
+    }
     hipEventDestroy(h->ev_cols);
     hipEventDestroy(h->ev_panel);
+    hipEventDestroy(h->ev_in);
+    hipEventDestroy(h->ev_out);
     h->magic = 0;
     delete h;
     return GP_OK;
@@ -525,7 +668,7 @@ int gp_set_options(gp_handle_t h, const gp_options_t *opt) {
         return GP_OK;
     }
     if (opt->nb < 0 || opt->nb % DB != 0) return -2;
-    if (opt->ir_max_iter < 0 || opt->band < -1) return -2;
+    if (opt->ir_max_iter < 0 || opt->band < -1 || opt->panel_cus < 0) return -2;
     if (!(opt->ir_tol >= 0.0) || isinf(opt->ir_tol)) return GP_ERR_NONFINITE;
     h->opt = *opt;
     return GP_OK;
@@ -545,7 +688,7 @@ int gp_workspace_size(gp_handle_t h, gp_op_t op, int64_t n, int64_t m, gp_prec_t
     if (m < 0) return -4;
     if ((int)prec < GP_FP64 || (int)prec > GP_BF16_TRAIL) return -5;
     if (!bytes) return -6;
-    *bytes = layout(op, n, m, prec).total;
+    *bytes = layout(h, op, n, m, prec).total;
     return GP_OK;
 }
 
@@ -585,10 +728,10 @@ int gp_potrf(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda, i
     if (n > 0 && !A) return -4;
     if (lda < (n > 1 ? n : 1)) return -5;
     if (!info_dev) return -6;
-    Layout L = layout(GP_OP_POTRF, n, 0, prec);
+    Layout L = layout(h, GP_OP_POTRF, n, 0, prec);
     if (!ws) return -7;
     if (ws_bytes < L.total) return GP_ERR_WS_TOO_SMALL;
-    return potrf_impl(h, prec, n, A, lda, info_dev, at<double>(ws, L.dinv));
+    return potrf_impl(h, prec, n, A, lda, info_dev, at<double>(ws, L.dinv), panel_bufs(ws, L));
 }
 
 int gp_trsv(gp_handle_t h, gp_trans_t trans, int64_t n, const double *L, int64_t ldl, double *x, void *ws,
@@ -599,7 +742,7 @@ int gp_trsv(gp_handle_t h, gp_trans_t trans, int64_t n, const double *L, int64_t
     if (n > 0 && !L) return -4;
     if (ldl < (n > 1 ? n : 1)) return -5;
     if (n > 0 && !x) return -6;
-    Layout lay = layout(GP_OP_TRSV, n, 0, GP_FP64);
+    Layout lay = layout(h, GP_OP_TRSV, n, 0, GP_FP64);
     if (!ws) return -7;
     if (ws_bytes < lay.total) return GP_ERR_WS_TOO_SMALL;
     if (n == 0) return GP_OK;
@@ -619,7 +762,7 @@ int gp_trsm(gp_handle_t h, gp_trans_t trans, int64_t n, int64_t nrhs, const doub
     if (ldl < (n > 1 ? n : 1)) return -6;
     if (n > 0 && nrhs > 0 && !B) return -7;
     if (ldb < (n > 1 ? n : 1)) return -8;
-    Layout lay = layout(GP_OP_TRSM, n, nrhs, GP_FP64);
+    Layout lay = layout(h, GP_OP_TRSM, n, nrhs, GP_FP64);
     if (!ws) return -9;
     if (ws_bytes < lay.total) return GP_ERR_WS_TOO_SMALL;
     if (n == 0 || nrhs == 0) return GP_OK;
@@ -642,7 +785,7 @@ int gp_loglik(gp_handle_t h, gp_theta_t th, gp_prec_t prec, int64_t n, int32_t d
     if (ldc < (n > 1 ? n : 1)) return -10;
     if (!out3_dev) return -11;
     if (!info_dev) return -13;
-    Layout lay = layout(GP_OP_LOGLIK, n, 0, prec);
+    Layout lay = layout(h, GP_OP_LOGLIK, n, 0, prec);
     if (!ws) return -15;
     if (ws_bytes < lay.total) return GP_ERR_WS_TOO_SMALL;
     return loglik_core(h, GP_OP_LOGLIK, th, prec, n, dim, X, y, mu, C, ldc, out3_dev, nullptr, alpha_dev,
@@ -665,7 +808,7 @@ int gp_loglik_grad(gp_handle_t h, gp_theta_t th, gp_prec_t prec, int64_t n, int3
     if (!out3_dev) return -11;
     if (!grad3_dev) return -12;
     if (!info_dev) return -14;
-    Layout lay = layout(GP_OP_LOGLIK_GRAD, n, 0, prec);
+    Layout lay = layout(h, GP_OP_LOGLIK_GRAD, n, 0, prec);
     if (!ws) return -16;
     if (ws_bytes < lay.total) return GP_ERR_WS_TOO_SMALL;
     return loglik_core(h, GP_OP_LOGLIK_GRAD, th, prec, n, dim, X, y, mu, C, ldc, out3_dev, grad3_dev, alpha_dev,
@@ -688,7 +831,7 @@ int gp_krige(gp_handle_t h, gp_theta_t th, int64_t n, int64_t m, int32_t dim, co
     if (!isfinite(mu)) return GP_ERR_NONFINITE;
     if (m > 0 && !mean_dev) return -12;
     if (m > 0 && !var_dev) return -13;
-    Layout lay = layout(GP_OP_KRIGE, n, m, GP_FP64);
+    Layout lay = layout(h, GP_OP_KRIGE, n, m, GP_FP64);
     if (!ws) return -15;
     if (ws_bytes < lay.total) return GP_ERR_WS_TOO_SMALL;
     if (m == 0) return GP_OK;
@@ -747,7 +890,7 @@ int gp_morton_order(gp_handle_t h, int64_t n, int32_t dim, const double *X, int6
     if (dim < 1 || dim > 16) return -3;
     if (n > 0 && !X) return -4;
     if (n > 0 && !perm_dev) return -5;
-    Layout lay = layout(GP_OP_MORTON, n, 0, GP_FP64);
+    Layout lay = layout(h, GP_OP_MORTON, n, 0, GP_FP64);
     if (!ws) return -6;
     if (ws_bytes < lay.total) return GP_ERR_WS_TOO_SMALL;
     HIPCHK(launch_morton(h->stream, n, dim, X, perm_dev, at<uint64_t>(ws, lay.keys), at<double>(ws, lay.box)));

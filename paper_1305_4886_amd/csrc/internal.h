@@ -24,6 +24,15 @@ struct gp_handle_s {
     hipStream_t side = nullptr;    // lookahead stream (default priority)
     hipEvent_t ev_cols = nullptr;  // main -> side: next panel's columns updated
     hipEvent_t ev_panel = nullptr; // side -> main: next panel factored
+    hipEvent_t ev_in = nullptr;    // caller's stream -> masked main stream
+    hipEvent_t ev_out = nullptr;   // masked main stream -> caller's stream
+    // With opt.panel_cus > 0 the factorisation runs on two streams of its own:
+    // main_cu, masked to every compute unit but panel_cus reserved ones, and
+    // side_cu, free to use all of them, so the lookahead chain always finds
+    // room next to the trailing update.
+    hipStream_t main_cu = nullptr;
+    hipStream_t side_cu = nullptr;
+    int masked_for = 0;            // panel_cus the masked streams were made for
     gp_options_t opt{};
     int device = 0;
     // optional timing of trailing updates (gp_profile)
@@ -141,43 +150,104 @@ GP_DEV double rdlane(double v, int l) {
     return __hiloint2double(hi, lo);
 }
 
-// Cholesky of a 64 x 64 block held by one wave, lane r = row r (a[c] = A[r][c],
-// zero above the diagonal), right-looking column by column: pivot
-// sqrt(A_jj), scale column j, rank-1 update of the trailing lower part.  The
-// column entries are broadcast with readlane, so no memory round trip or
-// barrier sits between the steps.  Returns 0 or the first failing 1-based
-// column (a non-positive or NaN pivot); later columns then hold garbage.
-GP_DEV int wave_chol64(double (&a)[DB], int lane) {
+// 1 / sqrt(x) to double precision: the hardware estimate (v_rsq_f64) refined
+// by two Newton-Raphson steps y <- y (3 - x y^2) / 2, each of which doubles the
+// number of correct bits.
+GP_DEV double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * fma(-hx * y, y, 1.5);
+    y = y * fma(-hx * y, y, 1.5);
+    return y;
+}
+
+// Orders LDS traffic between the lanes of one wave (LDS operations of a wave
+// complete in order; this keeps the compiler from moving them across).
+GP_DEV void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+typedef double gp_v4d __attribute__((ext_vector_type(4)));
+
+// Cholesky of a 64 x 64 block held by one wave, lane r = row r (a[c] = A[r][c]).
+// Right-looking in panels of 16 columns: inside a panel, column by column
+// (pivot, 1 / sqrt by rsqrt_nr, scale, rank-1 update of the panel's columns to
+// its right, with readlane broadcasts); then the columns right of the panel
+// get A -= P P^T on the matrix cores (v_mfma_f64_16x16x4 on 16 x 16 tiles,
+// operands from the panel staged in Pn, products returned through Us).  Only
+// the lower triangle is meaningful on return: entries above the diagonal are
+// updated without masks and hold garbage (they never feed a lower entry).
+// Returns 0 or the first failing 1-based column (a non-positive or NaN
+// pivot); later columns then hold garbage.  Us: 64 x 65, Pn: 64 x 17 doubles
+// of LDS, used by this wave only.
+GP_DEV int wave_chol64(double (&a)[DB], int lane, double (*Us)[DB + 1], double (*Pn)[17]) {
     int fail = 0;
 #pragma unroll
-    for (int j = 0; j < DB; ++j) {
-        const double piv = rdlane(a[j], j);
-        if (!(piv > 0.0) && fail == 0) fail = j + 1;
-        const double dj = sqrt(piv);
-        const double inv = 1.0 / dj;
-        a[j] = (lane == j) ? dj : ((lane > j) ? a[j] * inv : a[j]);
+    for (int p = 0; p < DB; p += 16) {
 #pragma unroll
-        for (int c = j + 1; c < DB; ++c) {
-            const double lcj = rdlane(a[j], c);
-            a[c] = (lane >= c) ? fma(-a[j], lcj, a[c]) : a[c];
+        for (int j = p; j < p + 16; ++j) {
+            const double piv = rdlane(a[j], j);
+            if (!(piv > 0.0) && fail == 0) fail = j + 1;
+            const double inv = rsqrt_nr(piv);
+            a[j] = (lane == j) ? piv * inv : a[j] * inv;
+#pragma unroll
+            for (int c = j + 1; c < p + 16; ++c) a[c] = fma(-a[j], rdlane(a[j], c), a[c]);
+        }
+        if (p + 16 < DB) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) Pn[lane][k] = a[p + k];
+            wave_lds_sync();
+            const int t0 = p + 16;
+#pragma unroll
+            for (int ti = 0; ti < (DB - p - 16) / 16; ++ti)
+#pragma unroll
+                for (int tj = 0; tj <= ti; ++tj) {
+                    // D layout of v_mfma_f64_16x16x4: lane l, register r holds
+                    // row l / 16 + 4 r, column l % 16
+                    gp_v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int k0 = 0; k0 < 16; k0 += 4) {
+                        const double av = Pn[t0 + 16 * ti + (lane & 15)][k0 + (lane >> 4)];
+                        const double bv = Pn[t0 + 16 * tj + (lane & 15)][k0 + (lane >> 4)];
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        Us[t0 + 16 * ti + (lane >> 4) + 4 * r][t0 + 16 * tj + (lane & 15)] = acc[r];
+                }
+            wave_lds_sync();
+#pragma unroll
+            for (int c = p + 16; c < DB; ++c) a[c] -= Us[lane][c];
+            wave_lds_sync();
         }
     }
     return fail;
 }
 
-// W = L^{-1} for the 64 x 64 lower factor in LDS (Ls[i][k] = L_ik), one wave,
-// lane c computes column c by forward substitution:
-//   W_ic = (delta_ic - sum_{c <= k < i} L_ik W_kc) / L_ii;
+// W = L^{-1} for the 64 x 64 lower factor in LDS (Ls[i][k] = L_ik for k <= i;
+// entries above the diagonal are not read), one wave, lane c computes column
+// c by forward substitution:
+//   W_ic = -(sum_{c <= k < i} L_ik W_kc) / L_ii,  W_cc = 1 / L_cc;
 // rows above c are zero, so the sum may run over all k < i.  Row i of L is a
-// broadcast LDS read (the same address for every lane).
+// broadcast LDS read (the same address for every lane); the sum is split over
+// four chains and the diagonal reciprocals are formed once, in parallel.
 GP_DEV void wave_inv64(const double (*Ls)[DB + 1], double (&w)[DB], int lane) {
+    const double rl = 1.0 / Ls[lane][lane];  // lane i: 1 / L_ii
 #pragma unroll
     for (int i = 0; i < DB; ++i) {
-        double s = 0.0;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-        for (int k = 0; k < i; ++k) s = fma(Ls[i][k], w[k], s);
-        const double lii = Ls[i][i];
-        w[i] = (lane == i) ? 1.0 / lii : ((lane < i) ? -s / lii : 0.0);
+        for (int k = 0; k + 3 < i; k += 4) {
+            s0 = fma(Ls[i][k], w[k], s0);
+            s1 = fma(Ls[i][k + 1], w[k + 1], s1);
+            s2 = fma(Ls[i][k + 2], w[k + 2], s2);
+            s3 = fma(Ls[i][k + 3], w[k + 3], s3);
+        }
+#pragma unroll
+        for (int k = i & ~3; k < i; ++k) s0 = fma(Ls[i][k], w[k], s0);
+        const double ri = rdlane(rl, i);
+        w[i] = (lane == i) ? ri : ((lane < i) ? -((s0 + s1) + (s2 + s3)) * ri : 0.0);
     }
 }
 
@@ -211,6 +281,7 @@ struct GemmDesc {
     int klo_i;     // skip k < tile row start (op(A) upper-zero structure)
     int klo_j;     // skip k < tile col start (op(B) lower-zero structure)
     int khi_i;     // skip k >= tile row end (op(A) lower-triangular)
+    int khi_j;     // skip k >= tile col end (op(B) upper-triangular)
     int64_t batch;  // number of independent products
     int64_t sA, sB, sC; // element strides between batch members
     const int32_t *info; // skip everything if *info != 0 (may be null)

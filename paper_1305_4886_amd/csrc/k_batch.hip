@@ -101,6 +101,7 @@ __global__ __launch_bounds__(256, 1) void k_bdiag(const BProb *__restrict__ prob
                                                   double *wbuf, int32_t *info) {
     __shared__ double As[T][T + 1];
     __shared__ double Bs[T][T + 1];
+    __shared__ double Pn[T][17];
     __shared__ int s_fail;
     const int b = plist[blockIdx.x];
     if (info[b] != 0) return;
@@ -127,7 +128,7 @@ __global__ __launch_bounds__(256, 1) void k_bdiag(const BProb *__restrict__ prob
     double a[T];
 #pragma unroll
     for (int c = 0; c < T; ++c) a[c] = (c <= lane) ? As[lane][c] : 0.0;
-    const int fail = wave_chol64(a, lane);
+    const int fail = wave_chol64(a, lane, As, Pn);
     if (fail) {
         if (lane == 0) info[b] = (int32_t)(j0 + fail);
         return;

@@ -26,7 +26,8 @@ namespace {
 // One wave per block.
 __global__ __launch_bounds__(64) void k_diag_potrf(double *A, int64_t lda, int jb, double *Winv,
                                                    int32_t *info, int64_t col0) {
-    __shared__ double Ls[DB][DB + 1];
+    __shared__ double Ls[DB][DB + 1];  // update buffer of the factorisation, then L
+    __shared__ double Pn[DB][17];
     if (*info) return;
     const int lane = threadIdx.x;
     double a[DB];
@@ -37,7 +38,7 @@ __global__ __launch_bounds__(64) void k_diag_potrf(double *A, int64_t lda, int j
         else v = (lane == c) ? 1.0 : 0.0;  // identity padding decouples unused rows
         a[c] = v;
     }
-    const int fail = wave_chol64(a, lane);
+    const int fail = wave_chol64(a, lane, Ls, Pn);
     if (fail) {
         if (lane == 0) *info = (int32_t)(col0 + fail);
         return;

@@ -119,6 +119,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmDesc d, TileMap tm) {
     if (d.klo_i && i0 > klo) klo = i0;
     if (d.klo_j && j0 > klo) klo = j0;
     if (d.khi_i && i0 + BM < khi) khi = i0 + BM;
+    if (d.khi_j && j0 + BN < khi) khi = j0 + BN;
     klo = (klo / BK) * BK;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -297,194 +298,153 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmDesc d, TileMap tm) {
 }
 
 // ---------------------------------------------------------------------------
-// Trailing update C -= P P^T (lower tiles) with direct-to-LDS loads.
-// Each K-slab (16 panel columns x 128 rows for each operand) is copied by
-// global_load_lds_dword straight into one of STAGES LDS buffers, so STAGES - 1
-// slabs are in flight while the matrix cores consume the current one and no
-// registers are spent on staging.  Wave w copies columns w, w + 4, w + 8,
-// w + 12 of both operands, 256 bytes per instruction.  Rows past the matrix
-// are clamped to its last row: they only feed output rows / columns that are
-// never stored.  Requires K % 16 == 0.
+// Trailing update C = beta C + alpha P P^T (lower tiles) with direct-to-LDS
+// loads and a STAGES-deep LDS ring.  Each K-slab (BKD panel columns, 128 rows
+// per operand) is copied by global_load_lds_dword straight into LDS, 256 bytes
+// per instruction, so STAGES - 1 slabs are in flight while the matrix cores
+// consume the current one and no registers hold staged data.  A copy address
+// is a scalar column base plus a 32-bit per-lane offset.  Rows past the matrix
+// are clamped to its last row: they feed only output rows / columns that are
+// never stored.  Requires K % BKD == 0.
 // ---------------------------------------------------------------------------
-GP_DEV void wait_vmcnt_le(int n) {
-    // s_waitcnt vmcnt(n) leaving expcnt / lgkmcnt unconstrained (gfx9 encoding)
-    switch (n) {
-    case 0: __builtin_amdgcn_s_waitcnt((0 & 15) | (7 << 4) | (15 << 8) | ((0 >> 4) << 14)); break;
-    case 16: __builtin_amdgcn_s_waitcnt((16 & 15) | (7 << 4) | (15 << 8) | ((16 >> 4) << 14)); break;
-    case 32: __builtin_amdgcn_s_waitcnt((32 & 15) | (7 << 4) | (15 << 8) | ((32 >> 4) << 14)); break;
-    case 48: __builtin_amdgcn_s_waitcnt((48 & 15) | (7 << 4) | (15 << 8) | ((48 >> 4) << 14)); break;
-    default: __builtin_amdgcn_s_waitcnt((0 & 15) | (7 << 4) | (15 << 8)); break;
+template <int N>
+GP_DEV void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt is a 6-bit field");
+    // s_waitcnt vmcnt(N), expcnt and lgkmcnt left unconstrained (gfx9 encoding)
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// Wait until at most j (0 <= j <= J) slabs of PER copies each are outstanding.
+template <int PER, int J>
+GP_DEV void wait_slabs(int j) {
+    if constexpr (J == 0) {
+        wait_vmcnt<0>();
+    } else {
+        if (j >= J)
+            wait_vmcnt<J * PER>();
+        else
+            wait_slabs<PER, J - 1>(j);
     }
 }
 
-// One 256-byte LDS-DMA copy: each lane moves the dword at `g` to LDS address
-// lds + 4 * lane.  Written as inline assembly so the compiler's wait-count
-// pass, which cannot tell LDS-DMA targets apart, does not drain every copy in
-// flight before each LDS read; the kernel orders the copies itself with
-// explicit vmcnt waits and barriers.  m0 is restored for the compiler.
-GP_DEV void lds_dma_dword(const void *g, uint32_t lds_uniform) {
+// One 256-byte LDS-DMA copy: lane l moves the dword at base + voff to LDS
+// address lds + 4 l.  Written as inline assembly so that the compiler's
+// wait-count pass, which cannot tell LDS-DMA targets apart, does not drain
+// every copy in flight before each LDS read; the kernel orders the copies
+// itself with explicit vmcnt waits and barriers.  m0 is restored afterwards.
+GP_DEV void lds_dma_dword(const double *base, uint32_t voff, uint32_t lds_uniform) {
     uint32_t saved;
-    asm volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dword %1, off\n\ts_mov_b32 m0, %0"
+    asm volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %3\n\ts_nop 0\n\tglobal_load_lds_dword %1, %2\n\ts_mov_b32 m0, %0"
                  : "=&s"(saved)
-                 : "v"(g), "s"(lds_uniform)
+                 : "v"(voff), "s"(base), "s"(lds_uniform)
                  : "memory");
 }
 
-// Multi-tile variant: a workgroup runs TPW consecutive tiles of its XCD's
-// range with a two-stage LDS pipeline that never drains between tiles.
-// During the last slab of a tile it issues the next tile's first slab and the
-// loads of the current C tile, so the HBM traffic of the epilogue overlaps the
-// matrix cores instead of stalling every workgroup at the same moment.
-// Workgroups still retire every TPW tiles, which leaves room for kernels on
-// other streams (the lookahead panel factorisation).  Requires K % 16 == 0.
-template <int TPW, int TAG>
-__global__ __launch_bounds__(256, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
-    constexpr int BM = 128, BN = 128, BKD = 16, WTM = 64, WTN = 64, FM = 4, FN = 4;
-    __shared__ double As0[BKD][BM], Bs0[BKD][BN];
-    __shared__ double As1[BKD][BM], Bs1[BKD][BN];
+template <int STAGES, int BKD, int TAG>
+__global__ __launch_bounds__(256, 2) void k_syrk_pipe(GemmDesc d, TileMap tm) {
+    constexpr int BM = 128, WTM = 64, FM = 4, FN = 4;
+    constexpr int CPW = BKD / 4;           // panel columns each wave copies per operand
+    constexpr int PER = CPW * 2 * 4;       // copies per wave per slab
+    static_assert(BKD % 4 == 0 && STAGES >= 2, "slab shape");
+    static_assert((STAGES - 2) * PER < 64, "outstanding copies exceed vmcnt");
+    __shared__ double Ls[STAGES][2][BKD][BM];  // [stage][operand][k][row]
 
     if (d.info && *d.info) return;
+    const int64_t t = xcd_remap();
+    if (t >= tm.ntiles) return;
+    int64_t bi, bj;
+    if (!decode_tile(tm, t, bi, bj)) return;
+    bi = __builtin_amdgcn_readfirstlane((int)bi);
+    bj = __builtin_amdgcn_readfirstlane((int)bj);
+    const int64_t i0 = bi * BM, j0 = bj * BM;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave & 1, wn = wave >> 1;
     const double *P = d.A;
     double *C = d.C;
-    const int64_t nk = d.K / BKD;
-    // this workgroup's tiles: [t_begin, t_end) of its XCD's contiguous range
-    const int64_t R = (tm.ntiles + 7) / 8;
-    const int64_t xcd = blockIdx.x & 7, widx = blockIdx.x >> 3;
-    const int64_t t_begin = xcd * R + widx * TPW;
-    int64_t t_end = t_begin + TPW;
-    if (t_end > (xcd + 1) * R) t_end = (xcd + 1) * R;
-    if (t_end > tm.ntiles) t_end = tm.ntiles;
-
-    auto next_valid = [&](int64_t t, int64_t &bi, int64_t &bj) -> int64_t {
-        for (; t < t_end; ++t)
-            if (decode_tile(tm, t, bi, bj)) return t;
-        return t_end;
-    };
-    int64_t bi, bj;
-    int64_t t = next_valid(t_begin, bi, bj);
-    if (t >= t_end) return;
+    const int nk = (int)(d.K / BKD);
 
     uint32_t offA[4], offB[4];
-    auto set_offsets = [&](int64_t i0, int64_t j0) {
-        const int64_t rmaxA = d.M - 1 - i0, rmaxB = d.N - 1 - j0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t r = 32 * q + (lane >> 1);
-            offA[q] = (uint32_t)(8 * (r < rmaxA ? r : rmaxA) + 4 * (lane & 1));
-            offB[q] = (uint32_t)(8 * (r < rmaxB ? r : rmaxB) + 4 * (lane & 1));
-        }
-    };
-    auto issue = [&](int64_t i0, int64_t j0, int64_t k0, double (*Ad)[BM], double (*Bd)[BN]) {
+    for (int q = 0; q < 4; ++q) {
+        const int64_t r = 32 * q + (lane >> 1);
+        const int64_t ra = i0 + r < d.M ? i0 + r : d.M - 1;
+        const int64_t rb = j0 + r < d.N ? j0 + r : d.N - 1;
+        offA[q] = (uint32_t)(8 * ra + 4 * (lane & 1));
+        offB[q] = (uint32_t)(8 * rb + 4 * (lane & 1));
+    }
+    auto issue = [&](int slab, int st) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < CPW; ++c) {
             const int kk = wave + 4 * c;
-            const char *colA = reinterpret_cast<const char *>(P + i0 + (k0 + kk) * d.lda);
-            const char *colB = reinterpret_cast<const char *>(P + j0 + (k0 + kk) * d.lda);
+            const double *col = P + ((int64_t)slab * BKD + kk) * d.lda;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                lds_dma_dword(colA + offA[q],
-                              __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)&Ad[kk][32 * q]));
-                lds_dma_dword(colB + offB[q],
-                              __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)&Bd[kk][32 * q]));
+                lds_dma_dword(col, offA[q], (uint32_t)(uintptr_t)&Ls[st][0][kk][32 * q]);
+                lds_dma_dword(col, offB[q], (uint32_t)(uintptr_t)&Ls[st][1][kk][32 * q]);
             }
         }
     };
 
-    bi = __builtin_amdgcn_readfirstlane((int)bi);
-    bj = __builtin_amdgcn_readfirstlane((int)bj);
-    int64_t i0 = bi * BM, j0 = bj * BN;
-    set_offsets(i0, j0);
-    int stage = 0;  // stage holding the slab about to be consumed
-    issue(i0, j0, 0, As0, Bs0);
-    bool first = true;
+#pragma unroll
+    for (int s = 0; s < STAGES - 1; ++s)
+        if (s < nk) issue(s, s);
 
-    for (;;) {
-        int64_t nbi = 0, nbj = 0;
-        const int64_t tn = next_valid(t + 1, nbi, nbj);
-        const bool has_next = tn < t_end;
-        nbi = __builtin_amdgcn_readfirstlane((int)nbi);
-        nbj = __builtin_amdgcn_readfirstlane((int)nbj);
-        const int64_t ni0 = nbi * BM, nj0 = nbj * BN;
+    v4d acc[FM][FN];
+#pragma unroll
+    for (int m = 0; m < FM; ++m)
+#pragma unroll
+        for (int n = 0; n < FN; ++n) acc[m][n] = v4d{0.0, 0.0, 0.0, 0.0};
 
-        v4d acc[FM][FN];
+    int st = 0;
+    for (int k = 0; k < nk; ++k) {
+        // slabs k .. min(k + STAGES - 2, nk - 1) are in flight: wait for slab k
+        const int later = nk - 1 - k;
+        wait_slabs<PER, STAGES - 2>(later < STAGES - 2 ? later : STAGES - 2);
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        // every wave is past its reads of the stage consumed last iteration
+        if (k + STAGES - 1 < nk) issue(k + STAGES - 1, st == 0 ? STAGES - 1 : st - 1);
 #pragma unroll
-        for (int m = 0; m < FM; ++m)
+        for (int kk = 0; kk < BKD; kk += 4) {
+            double a[FM], b[FN];
 #pragma unroll
-            for (int n = 0; n < FN; ++n) acc[m][n] = v4d{0.0, 0.0, 0.0, 0.0};
-        double cv[FM][FN][4];
-
-        const int64_t rb0 = i0 + wm * WTM + (lane >> 4);
-        const int64_t cb0 = j0 + wn * WTN + (lane & 15);
-        const bool interior = (i0 + BM <= d.M) && (j0 + BN <= d.N) && (i0 >= j0 + BN);
-
-        for (int64_t k = 0; k < nk; ++k) {
-            // the only copy in flight is this slab's (issued one step ago, or
-            // during the previous tile, whose C loads already waited for it)
-            if (k > 0 || first) wait_vmcnt_le(0);
-            asm volatile("" ::: "memory");
-            __builtin_amdgcn_s_barrier();
-            asm volatile("" ::: "memory");
-            double (*Ar)[BM] = stage ? As1 : As0;
-            double (*Br)[BN] = stage ? Bs1 : Bs0;
-            double (*Ad)[BM] = stage ? As0 : As1;
-            double (*Bd)[BN] = stage ? Bs0 : Bs1;
-            if (k + 1 < nk) {
-                issue(i0, j0, (k + 1) * BKD, Ad, Bd);
-            } else {
-                if (has_next) {
-                    const uint32_t sa0 = offA[0], sa1 = offA[1], sa2 = offA[2], sa3 = offA[3];
-                    const uint32_t sb0 = offB[0], sb1 = offB[1], sb2 = offB[2], sb3 = offB[3];
-                    set_offsets(ni0, nj0);
-                    issue(ni0, nj0, 0, Ad, Bd);
-                    offA[0] = sa0; offA[1] = sa1; offA[2] = sa2; offA[3] = sa3;
-                    offB[0] = sb0; offB[1] = sb1; offB[2] = sb2; offB[3] = sb3;
-                }
-                // C loads for the epilogue, behind the copies above
+            for (int m = 0; m < FM; ++m) a[m] = Ls[st][0][kk + (lane >> 4)][wm * WTM + m * 16 + (lane & 15)];
 #pragma unroll
-                for (int m = 0; m < FM; ++m)
+            for (int n = 0; n < FN; ++n) b[n] = Ls[st][1][kk + (lane >> 4)][wn * WTM + n * 16 + (lane & 15)];
 #pragma unroll
-                    for (int n = 0; n < FN; ++n)
+            for (int m = 0; m < FM; ++m)
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int64_t gi = rb0 + m * 16 + 4 * r, gj = cb0 + n * 16;
-                            const bool ok = interior || (gi < d.M && gj < d.N && gi >= gj);
-                            cv[m][n][r] = C[ok ? gi + gj * d.ldc : 0];
-                        }
-            }
-#pragma unroll
-            for (int kk = 0; kk < BKD; kk += 4) {
-                double a[FM], b[FN];
-#pragma unroll
-                for (int m = 0; m < FM; ++m) a[m] = Ar[kk + (lane >> 4)][wm * WTM + m * 16 + (lane & 15)];
-#pragma unroll
-                for (int n = 0; n < FN; ++n) b[n] = Br[kk + (lane >> 4)][wn * WTN + n * 16 + (lane & 15)];
-#pragma unroll
-                for (int m = 0; m < FM; ++m)
-#pragma unroll
-                    for (int n = 0; n < FN; ++n)
-                        acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[n], acc[m][n], 0, 0, 0);
-            }
-            stage ^= 1;
+                for (int n = 0; n < FN; ++n)
+                    acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[n], acc[m][n], 0, 0, 0);
         }
+        st = st + 1 == STAGES ? 0 : st + 1;
+    }
+
+    // D layout: lane l, register r holds row l / 16 + 4 r, column l % 16.
+    const int64_t rb0 = i0 + wm * WTM + (lane >> 4);
+    const int64_t cb0 = j0 + wn * WTM + (lane & 15);
+    const bool interior = (i0 + BM <= d.M) && (j0 + BM <= d.N) && (i0 >= j0 + BM);
 #pragma unroll
-        for (int m = 0; m < FM; ++m)
+    for (int m = 0; m < FM; ++m) {
+        double cv[FN][4];
 #pragma unroll
-            for (int n = 0; n < FN; ++n)
+        for (int n = 0; n < FN; ++n)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t gi = rb0 + m * 16 + 4 * r, gj = cb0 + n * 16;
-                    const bool ok = interior || (gi < d.M && gj < d.N && gi >= gj);
-                    if (ok) C[gi + gj * d.ldc] = cv[m][n][r] - acc[m][n][r];
-                }
-        if (!has_next) break;
-        t = tn;
-        i0 = ni0;
-        j0 = nj0;
-        set_offsets(i0, j0);
-        first = false;
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gi = rb0 + m * 16 + 4 * r, gj = cb0 + n * 16;
+                const bool ok = interior || (gi < d.M && gj < d.N && gi >= gj);
+                cv[n][r] = C[ok ? gi + gj * d.ldc : 0];
+            }
+#pragma unroll
+        for (int n = 0; n < FN; ++n)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gi = rb0 + m * 16 + 4 * r, gj = cb0 + n * 16;
+                const bool ok = interior || (gi < d.M && gj < d.N && gi >= gj);
+                if (ok) C[gi + gj * d.ldc] = fma(d.beta, cv[n][r], d.alpha * acc[m][n][r]);
+            }
     }
 }
 

@@ -68,15 +68,16 @@ def test_cross_cov(orc, n, m):
     np.testing.assert_allclose(M, orc.cross_cov(1, t, X, Xs), rtol=1e-14, atol=1e-300)
 
 
+# (n, panel width, lookahead, compute units reserved for the lookahead chain)
 POTRF_CASES = [
-    (1, 256, 1), (2, 256, 1), (63, 256, 1), (64, 256, 1), (65, 256, 1), (127, 64, 0),
-    (200, 128, 1), (257, 256, 1), (500, 64, 1), (1000, 256, 1), (1000, 256, 0), (1100, 128, 1),
-    (2048, 512, 1), (3001, 256, 1),
+    (1, 256, 1, 8), (2, 256, 1, 8), (63, 256, 1, 8), (64, 256, 1, 8), (65, 256, 1, 8), (127, 64, 0, 0),
+    (200, 128, 1, 8), (257, 256, 1, 0), (500, 64, 1, 8), (1000, 256, 1, 8), (1000, 256, 0, 8),
+    (1100, 128, 1, 0), (2048, 512, 1, 8), (3001, 256, 1, 16), (3001, 192, 1, 8), (4500, 512, 1, 8),
 ]
 
 
-@pytest.mark.parametrize("n,nb,la", POTRF_CASES)
-def test_potrf_parity(orc, n, nb, la):
+@pytest.mark.parametrize("n,nb,la,pc", POTRF_CASES)
+def test_potrf_parity(orc, n, nb, la, pc):
     X = synth.uniform_points(n, 100 + n)
     t = logth(1.0, 0.1, 0.1)
     C = orc.cov(0, t, X)
@@ -84,12 +85,13 @@ def test_potrf_parity(orc, n, nb, la):
     S.fill_(-3.25)
     gp.colmajor(S, n).copy_(torch.as_tensor(np.tril(C) + np.triu(np.full((n, n), -3.25), 1)))
     h = gp.handle()
-    h.set_options(nb=nb, lookahead=la)
+    saved = h.options()
+    h.set_options(nb=nb, lookahead=la, panel_cus=pc)
     try:
         info = gp.potrf(S, n)
         torch.cuda.synchronize()
     finally:
-        h.set_options(nb=256, lookahead=1)
+        h.set_options(nb=saved.nb, lookahead=saved.lookahead, panel_cus=saved.panel_cus)
     assert int(info.item()) == 0
     M = gp.colmajor(S, n).cpu().numpy()
     assert np.all(M[np.triu_indices(n, 1)] == -3.25), "upper triangle must stay untouched"
@@ -189,3 +191,17 @@ def test_compound_symmetry_n8192():
     q_ref = (yy - s2 * sy * sy / den) / t2
     assert abs(ld - ld_ref) <= 1e-11 * abs(ld_ref)
     assert abs(q - q_ref) <= 1e-10 * abs(q_ref)
+
+
+def test_loglik_scalar_mu_is_taken_in_fp64(orc):
+    """A Python float mean must reach the device as that double, not via float32."""
+    n = 300
+    X = synth.uniform_points(n, 31)
+    y = synth.smooth_field(X, 32, ell=0.1, t2=0.05)
+    t = logth(1.0, 0.1, 0.05)
+    mu = 0.2  # not representable in float32
+    ll_o, _, _ = orc.loglik(0, t, X, y, mu=np.full(n, mu))
+    a = gp.loglik(dev(X), dev(y), gp.theta(0, log=t), mu=mu)["out3"].cpu().numpy()
+    b = gp.loglik(dev(X), dev(y), gp.theta(0, log=t), mu=dev(np.full(n, mu)))["out3"].cpu().numpy()
+    assert np.array_equal(a, b)
+    assert abs(a[0] - ll_o) <= 1e-11 * abs(ll_o)

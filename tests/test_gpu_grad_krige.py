@@ -116,3 +116,34 @@ def test_grad_central_fd_and_scale_identity():
         fm = gp.loglik(dev(X), dev(y), gp.theta(1, log=tm))["out3"][0].item()
         fd = (fp - fm) / (2 * h)
         assert abs(g[k] - fd) <= 1e-6 * max(1.0, abs(fd)), (k, g[k], fd)
+
+
+def test_autograd_function_matches_oracle_gradient(orc):
+    """log_likelihood is a torch.autograd.Function: its backward is the adjoint."""
+    n = 500
+    X = synth.uniform_points(n, 650)
+    y = synth.smooth_field(X, 651, ell=0.1, t2=0.05)
+    t = logth(1.3, 0.1, 0.05)
+    (ll_o, _, _), g_o = orc.loglik_grad(2, t, X, y)
+    lt = torch.tensor(t, dtype=torch.float64, requires_grad=True)
+    ll = gp.log_likelihood(dev(X), dev(y), lt, kernel="matern52")
+    ll.backward()
+    assert abs(ll.item() - ll_o) <= 1e-11 * abs(ll_o)
+    g = lt.grad.numpy()
+    assert np.linalg.norm(g - g_o) <= 1e-9 * max(1.0, np.linalg.norm(g_o)), (g, g_o)
+    # chain rule through a function of log_theta
+    lt2 = torch.tensor(t, dtype=torch.float64, requires_grad=True)
+    (3.0 * gp.log_likelihood(dev(X), dev(y), lt2, kernel=2)).backward()
+    assert np.linalg.norm(lt2.grad.numpy() - 3.0 * g_o) <= 3e-9 * max(1.0, np.linalg.norm(g_o))
+    # no gradient requested: plain evaluation
+    with torch.no_grad():
+        v = gp.log_likelihood(dev(X), dev(y), torch.tensor(t, dtype=torch.float64), kernel=2)
+    assert abs(v.item() - ll_o) <= 1e-11 * abs(ll_o)
+
+
+def test_autograd_not_pd_raises():
+    X = np.zeros((5, 2))
+    y = np.ones(5)
+    lt = torch.tensor([0.0, math.log(0.1), -math.inf], dtype=torch.float64, requires_grad=True)
+    with pytest.raises(gp.NotPositiveDefinite):
+        gp.log_likelihood(dev(X), dev(y), lt)
