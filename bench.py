@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--m", type=int, default=4096)
     ap.add_argument("--parts", default="krige,grad,mixed,batch")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-n", type=int, default=6144, help="oracle sample size (leading block)")
+    ap.add_argument("--cpu-n", type=int, default=12288, help="oracle sample size (leading block)")
     return ap.parse_args()
 
 
@@ -225,7 +225,7 @@ def main():
                                    "all_finite": bool(torch.isfinite(last["batch"]["out3"]).all().item())}
     syrk_tflops = syrk[2] / (syrk[1] / 1e3) / 1e12 if syrk[1] > 0 else None
     syrk_per_launch_flops = syrk[2] / syrk[0] if syrk[0] else None
-    roofline = {"kernel": "trailing SYRK (k_gemm_f64 role 1)", "bound": "mfma",
+    roofline = {"kernel": "trailing SYRK (k_syrk_dma role 1)", "bound": "mfma",
                 "achieved": syrk_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": (syrk_tflops / FP64_PEAK_TFLOPS) if syrk_tflops else None,
                 "traffic": None, "launches": syrk[0],

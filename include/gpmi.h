@@ -143,6 +143,21 @@ int gp_cross_cov_build(gp_handle_t h, gp_theta_t th, int64_t n, int64_t m, int32
 int gp_potrf(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda,
              int32_t *info_dev, void *ws, size_t ws_bytes);
 
+/* Autotuner for gp_potrf's panel width and reserved compute units: for each
+ * pair (nb_cand[a], cu_cand[b]) [host arrays; nb a positive multiple of 64,
+ * panel_cus >= 0] it fills A [dev, lda >= n; overwritten] with a synthetic
+ * positive-definite matrix of order n (exp(-8 |i - j| / n) + I), times
+ * gp_potrf with lookahead on the handle's stream (HIP events, second of two
+ * runs) and writes the milliseconds to ms_out[a * n_cu + b] [host, may be
+ * NULL; -1 where the candidate's workspace exceeds ws_bytes].  The fastest
+ * pair is stored in the handle's options (nb, lookahead = 1, panel_cus);
+ * on error the options are left unchanged.  ws must hold
+ * gp_workspace_size(GP_OP_POTRF, n) for the candidates to be timed.
+ * Synchronises the handle's stream; info_dev [dev] is scratch. */
+int gp_tune_potrf(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda,
+                  const int32_t *nb_cand, int32_t n_nb, const int32_t *cu_cand, int32_t n_cu,
+                  int32_t *info_dev, double *ms_out, void *ws, size_t ws_bytes);
+
 /* ---- triangular solves with the lower factor (Section 1 "backsolve";
  *      the remoteForwardsolve / remoteBacksolve of Section 2.3.2) --------- */
 /* x [dev, n] <- L^{-1} x (GP_NOTRANS) or L^{-T} x (GP_TRANS), in place. */
@@ -191,12 +206,15 @@ int gp_krige(gp_handle_t h, gp_theta_t th, int64_t n, int64_t m, int32_t dim, co
              double *mean_dev, double *var_dev, int32_t include_nugget, void *ws,
              size_t ws_bytes);
 
-/* ---- many independent likelihoods in one persistent launch ---------------
+/* ---- many independent likelihoods in one call ------------------------------
  * Problem b has n_host[b] points starting at point x_off_host[b] of X [dev,
  * rows of dim doubles] and of y [dev]; its covariance/factor occupies
  * C_pool[c_off_host[b] + i + j * n_host[b]] (ld = n_b).  th_host[b] is its
  * parameter set.  Writes out3_dev[3 b + {0,1,2}] = {loglik, logdet, q} and
- * info_dev[b].  Same model and definitions as gp_loglik (FP64). */
+ * info_dev[b].  Same model and definitions as gp_loglik (FP64).  The
+ * problems are factored together in 64 x 64 tiles, one tile column per step
+ * for all problems at once (two launches per step plus one for the solves),
+ * largest problems first. */
 int gp_loglik_batched(gp_handle_t h, int32_t nbatch, const gp_theta_t *th_host,
                       const int64_t *n_host, const int64_t *x_off_host, const int64_t *c_off_host,
                       int32_t dim, const double *X, const double *y, double *C_pool,

@@ -31,7 +31,7 @@ PRECS = {"fp64": GP_FP64, "fp32": GP_FP32_TRAIL, "bf16": GP_BF16_TRAIL}
 EXPORTED = ["gp_create", "gp_destroy", "gp_set_stream", "gp_set_options", "gp_get_options",
             "gp_strerror", "gp_profile", "gp_profile_read", "gp_workspace_size", "gp_cov_build", "gp_cross_cov_build", "gp_potrf",
             "gp_trsv", "gp_trsm", "gp_loglik", "gp_loglik_grad", "gp_krige", "gp_loglik_batched",
-            "gp_morton_order"]
+            "gp_morton_order", "gp_tune_potrf"]
 
 
 class Theta(ctypes.Structure):
@@ -87,6 +87,8 @@ def lib():
         L.gp_cov_build.argtypes = [vp, Theta, i64, i32, vp, vp, i64]
         L.gp_cross_cov_build.argtypes = [vp, Theta, i64, i64, i32, vp, vp, vp, i64]
         L.gp_potrf.argtypes = [vp, ctypes.c_int, i64, vp, i64, vp, vp, sz]
+        L.gp_tune_potrf.argtypes = [vp, ctypes.c_int, i64, vp, i64, ctypes.POINTER(i32), i32, ctypes.POINTER(i32),
+                                    i32, vp, ctypes.POINTER(dbl), vp, sz]
         L.gp_trsv.argtypes = [vp, ctypes.c_int, i64, vp, i64, vp, vp, sz]
         L.gp_trsm.argtypes = [vp, ctypes.c_int, i64, i64, vp, i64, vp, i64, vp, sz]
         L.gp_loglik.argtypes = [vp, Theta, ctypes.c_int, i64, i32, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, sz]
@@ -173,6 +175,30 @@ class Handle:
         out = (ctypes.c_double * 3)()
         check(lib().gp_profile_read(self._h, out))
         return int(out[0]), float(out[1]), float(out[2])
+
+    def tune_potrf(self, n, prec=GP_FP64, nb=(256, 384, 512, 768, 1024), panel_cus=(0, 8, 16)):
+        """Time gp_potrf over (nb, panel_cus) on a synthetic matrix of order n and keep the fastest
+        in this handle's options.  Returns {(nb, panel_cus): ms} (-1: did not fit)."""
+        torch = _torch()
+        nb = [int(v) for v in nb]
+        cus = [int(v) for v in panel_cus]
+        saved = self.options()
+        need = 0
+        for v in nb:
+            self.set_options(nb=v)
+            b = ctypes.c_size_t()
+            check(lib().gp_workspace_size(self._h, GP_OP_POTRF, n, 0, prec, ctypes.byref(b)))
+            need = max(need, b.value)
+        self.set_options(nb=saved.nb)
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
+        A = colmajor_storage(n)
+        info = torch.zeros(1, dtype=torch.int32, device="cuda")
+        nb_a = (ctypes.c_int32 * len(nb))(*nb)
+        cu_a = (ctypes.c_int32 * len(cus))(*cus)
+        ms = (ctypes.c_double * (len(nb) * len(cus)))()
+        check(lib().gp_tune_potrf(self._h, prec, n, _ptr(A), A.shape[1], nb_a, len(nb), cu_a, len(cus),
+                                  _ptr(info), ms, _ptr(ws), ws.numel()))
+        return {(nb[a], cus[b]): ms[a * len(cus) + b] for a in range(len(nb)) for b in range(len(cus))}
 
     def workspace(self, op, n, m=0, prec=GP_FP64):
         torch = _torch()

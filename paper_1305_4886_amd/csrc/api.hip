@@ -576,7 +576,7 @@ static void default_options(gp_options_t *o) {
     memset(o, 0, sizeof(*o));
     o->nb = 512;
     o->lookahead = 1;
-    o->panel_cus = 8;
+    o->panel_cus = 0;
     o->band = 2;
     o->ir_max_iter = 20;
     o->ir_tol = 1e-10;
@@ -732,6 +732,86 @@ int gp_potrf(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda, i
     if (!ws) return -7;
     if (ws_bytes < L.total) return GP_ERR_WS_TOO_SMALL;
     return potrf_impl(h, prec, n, A, lda, info_dev, at<double>(ws, L.dinv), panel_bufs(ws, L));
+}
+
+int gp_tune_potrf(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda, const int32_t *nb_cand,
+                  int32_t n_nb, const int32_t *cu_cand, int32_t n_cu, int32_t *info_dev, double *ms_out, void *ws,
+                  size_t ws_bytes) {
+    if (!ok_handle(h)) return -1;
+    if ((int)prec < GP_FP64 || (int)prec > GP_BF16_TRAIL) return -2;
+    if (n < 1) return -3;
+    if (!A) return -4;
+    if (lda < n) return -5;
+    if (!nb_cand && n_nb > 0) return -6;
+    if (n_nb < 1) return -7;
+    for (int32_t i = 0; i < n_nb; ++i)
+        if (nb_cand[i] <= 0 || nb_cand[i] % DB != 0) return -6;
+    if (!cu_cand && n_cu > 0) return -8;
+    if (n_cu < 1) return -9;
+    for (int32_t i = 0; i < n_cu; ++i)
+        if (cu_cand[i] < 0) return -8;
+    if (!info_dev) return -10;
+    if (!ws) return -12;
+    hipStream_t s = h->stream;
+    const gp_options_t saved = h->opt;
+    double best = -1.0;
+    gp_options_t best_opt = saved;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) hipEventDestroy(e0);
+        return GP_ERR_HIP;
+    }
+    int rc = GP_OK;
+    for (int32_t a = 0; a < n_nb && rc == GP_OK; ++a) {
+        for (int32_t b = 0; b < n_cu && rc == GP_OK; ++b) {
+            double ms = -1.0;
+            h->opt = saved;
+            h->opt.nb = nb_cand[a];
+            h->opt.lookahead = 1;
+            h->opt.panel_cus = cu_cand[b];
+            const Layout L = layout(h, GP_OP_POTRF, n, 0, prec);
+            if (L.total <= ws_bytes) {
+                for (int rep = 0; rep < 2 && rc == GP_OK; ++rep) {  // the first run also creates streams
+                    if (launch_tune_fill(s, A, lda, n) != hipSuccess || hipEventRecord(e0, s) != hipSuccess) {
+                        rc = GP_ERR_HIP;
+                        break;
+                    }
+                    rc = potrf_impl(h, prec, n, A, lda, info_dev, at<double>(ws, L.dinv), panel_bufs(ws, L));
+                    if (rc) break;
+                    float t = 0.f;
+                    int32_t info = 0;
+                    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&t, e0, e1) != hipSuccess ||
+                        hipMemcpy(&info, info_dev, sizeof info, hipMemcpyDeviceToHost) != hipSuccess) {
+                        rc = GP_ERR_HIP;
+                        break;
+                    }
+                    if (info != 0) {  // the test matrix is positive definite
+                        rc = GP_ERR_HIP;
+                        break;
+                    }
+                    ms = t;
+                }
+            }
+            if (ms_out) ms_out[a * n_cu + b] = ms;
+            if (ms >= 0.0 && (best < 0.0 || ms < best)) {
+                best = ms;
+                best_opt = h->opt;
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) {
+        h->opt = saved;
+        return rc;
+    }
+    if (best < 0.0) {
+        h->opt = saved;
+        return GP_ERR_WS_TOO_SMALL;
+    }
+    h->opt = best_opt;
+    return GP_OK;
 }
 
 int gp_trsv(gp_handle_t h, gp_trans_t trans, int64_t n, const double *L, int64_t ldl, double *x, void *ws,

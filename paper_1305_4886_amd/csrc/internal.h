@@ -170,85 +170,133 @@ GP_DEV void wave_lds_sync() {
 
 typedef double gp_v4d __attribute__((ext_vector_type(4)));
 
-// Cholesky of a 64 x 64 block held by one wave, lane r = row r (a[c] = A[r][c]).
-// Right-looking in panels of 16 columns: inside a panel, column by column
-// (pivot, 1 / sqrt by rsqrt_nr, scale, rank-1 update of the panel's columns to
-// its right, with readlane broadcasts); then the columns right of the panel
-// get A -= P P^T on the matrix cores (v_mfma_f64_16x16x4 on 16 x 16 tiles,
-// operands from the panel staged in Pn, products returned through Us).  Only
-// the lower triangle is meaningful on return: entries above the diagonal are
-// updated without masks and hold garbage (they never feed a lower entry).
-// Returns 0 or the first failing 1-based column (a non-positive or NaN
-// pivot); later columns then hold garbage.  Us: 64 x 65, Pn: 64 x 17 doubles
-// of LDS, used by this wave only.
-GP_DEV int wave_chol64(double (&a)[DB], int lane, double (*Us)[DB + 1], double (*Pn)[17]) {
+// 16 x 16 x 16 product on the matrix cores, D = sum_k A(i, k) B(k, j) over
+// k in [kbeg, kend) (multiples of 4), operands read through the callables.
+// Operand layout of v_mfma_f64_16x16x4: lane l supplies A(l % 16, k0 + l / 16)
+// and B(k0 + l / 16, l % 16); D lane l, register r is (l / 16 + 4 r, l % 16).
+template <typename FA, typename FB>
+GP_DEV gp_v4d wave_mm16(FA fa, FB fb, int kbeg, int kend, int lane) {
+    gp_v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k0 = kbeg; k0 < kend; k0 += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fa(lane & 15, k0 + (lane >> 4)), fb(k0 + (lane >> 4), lane & 15),
+                                                   acc, 0, 0, 0);
+    return acc;
+}
+
+// The same factorisation with the block held in LDS (Us[r][c] = A_rc, lower
+// triangle; zeros or anything above it), for latency-bound single-wave
+// kernels: the 16-column panel step is one loop body run four times (small
+// code that stays in the instruction cache) and only the panel lives in
+// registers.  The trailing update is applied by the matrix cores in place in
+// Us.  On return the lower triangle of Us holds L.  Pn: 64 x 17 doubles of
+// LDS.  Returns 0 or the first failing 1-based column.
+GP_DEV int wave_potrf64_lds(double (*Us)[DB + 1], double (*Pn)[17], int lane) {
     int fail = 0;
-#pragma unroll
+#pragma unroll 1
     for (int p = 0; p < DB; p += 16) {
+        double a[16];
 #pragma unroll
-        for (int j = p; j < p + 16; ++j) {
-            const double piv = rdlane(a[j], j);
-            if (!(piv > 0.0) && fail == 0) fail = j + 1;
+        for (int k = 0; k < 16; ++k) a[k] = Us[lane][p + k];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const double piv = rdlane(a[j], p + j);
+            if (!(piv > 0.0) && fail == 0) fail = p + j + 1;
             const double inv = rsqrt_nr(piv);
-            a[j] = (lane == j) ? piv * inv : a[j] * inv;
+            a[j] = (lane == p + j) ? piv * inv : a[j] * inv;
 #pragma unroll
-            for (int c = j + 1; c < p + 16; ++c) a[c] = fma(-a[j], rdlane(a[j], c), a[c]);
+            for (int c = j + 1; c < 16; ++c) a[c] = fma(-a[j], rdlane(a[j], p + c), a[c]);
         }
-        if (p + 16 < DB) {
 #pragma unroll
-            for (int k = 0; k < 16; ++k) Pn[lane][k] = a[p + k];
-            wave_lds_sync();
-            const int t0 = p + 16;
-#pragma unroll
-            for (int ti = 0; ti < (DB - p - 16) / 16; ++ti)
-#pragma unroll
-                for (int tj = 0; tj <= ti; ++tj) {
-                    // D layout of v_mfma_f64_16x16x4: lane l, register r holds
-                    // row l / 16 + 4 r, column l % 16
-                    gp_v4d acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                    for (int k0 = 0; k0 < 16; k0 += 4) {
-                        const double av = Pn[t0 + 16 * ti + (lane & 15)][k0 + (lane >> 4)];
-                        const double bv = Pn[t0 + 16 * tj + (lane & 15)][k0 + (lane >> 4)];
-                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-                    }
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        Us[t0 + 16 * ti + (lane >> 4) + 4 * r][t0 + 16 * tj + (lane & 15)] = acc[r];
-                }
-            wave_lds_sync();
-#pragma unroll
-            for (int c = p + 16; c < DB; ++c) a[c] -= Us[lane][c];
-            wave_lds_sync();
+        for (int k = 0; k < 16; ++k) {
+            Pn[lane][k] = a[k];
+            Us[lane][p + k] = a[k];
         }
+        wave_lds_sync();
+        // tiles (ti, tj), ti >= tj, of rows / columns t0 .. 63: Us -= P P^T
+        const int t0 = p + 16, nt = (DB - t0) / 16;
+#pragma unroll 1
+        for (int ti = 0; ti < nt; ++ti)
+#pragma unroll 1
+            for (int tj = 0; tj <= ti; ++tj) {
+                const int r0 = t0 + 16 * ti, c0 = t0 + 16 * tj;
+                const gp_v4d acc = wave_mm16([&](int i, int k) { return Pn[r0 + i][k]; },
+                                             [&](int k, int j) { return Pn[c0 + j][k]; }, 0, 16, lane);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Us[r0 + (lane >> 4) + 4 * r][c0 + (lane & 15)] -= acc[r];
+            }
+        wave_lds_sync();
     }
     return fail;
 }
 
 // W = L^{-1} for the 64 x 64 lower factor in LDS (Ls[i][k] = L_ik for k <= i;
-// entries above the diagonal are not read), one wave, lane c computes column
-// c by forward substitution:
-//   W_ic = -(sum_{c <= k < i} L_ik W_kc) / L_ii,  W_cc = 1 / L_cc;
-// rows above c are zero, so the sum may run over all k < i.  Row i of L is a
-// broadcast LDS read (the same address for every lane); the sum is split over
-// four chains and the diagonal reciprocals are formed once, in parallel.
-GP_DEV void wave_inv64(const double (*Ls)[DB + 1], double (&w)[DB], int lane) {
-    const double rl = 1.0 / Ls[lane][lane];  // lane i: 1 / L_ii
+// entries above the diagonal are not read), one wave, blocked by 16:
+// (1) the four 16 x 16 diagonal blocks by forward substitution, lane 16 b + c
+//     solving column c of block b (W_cc = 1 / L_cc, W_ic = -(sum L_ik W_kc) / L_ii);
+// (2) recursive doubling on the matrix cores, W21 = -W22 (L21 W11): first the
+//     16-blocks (1,0) and (3,2), then the 32 x 32 block (rows 32.., cols ..31).
+// The result, zeros above the diagonal included, is left in Wl.
+// Scratch: T32 (32 x 33) and rd (64) doubles of LDS.
+GP_DEV void wave_inv64_blocked(const double (*Ls)[DB + 1], double (*Wl)[DB + 1], double (*T32)[33], double *rd,
+                               int lane) {
+    rd[lane] = 1.0 / Ls[lane][lane];
+    wave_lds_sync();
+    {
+        const int o = 16 * (lane >> 4), c = lane & 15;
+        double w[16];
 #pragma unroll
-    for (int i = 0; i < DB; ++i) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        for (int i = 0; i < 16; ++i) {
+            double s = (i == c) ? 1.0 : 0.0;
 #pragma unroll
-        for (int k = 0; k + 3 < i; k += 4) {
-            s0 = fma(Ls[i][k], w[k], s0);
-            s1 = fma(Ls[i][k + 1], w[k + 1], s1);
-            s2 = fma(Ls[i][k + 2], w[k + 2], s2);
-            s3 = fma(Ls[i][k + 3], w[k + 3], s3);
+            for (int k = 0; k < i; ++k) s = fma(-Ls[o + i][o + k], w[k], s);
+            w[i] = s * rd[o + i];
         }
 #pragma unroll
-        for (int k = i & ~3; k < i; ++k) s0 = fma(Ls[i][k], w[k], s0);
-        const double ri = rdlane(rl, i);
-        w[i] = (lane == i) ? ri : ((lane < i) ? -((s0 + s1) + (s2 + s3)) * ri : 0.0);
+        for (int i = 0; i < 16; ++i) Wl[o + i][o + c] = w[i];
+#pragma unroll
+        for (int i = 0; i < DB; ++i)
+            if ((i >> 4) != (lane >> 4)) Wl[i][lane] = 0.0;
     }
+    wave_lds_sync();
+#pragma unroll
+    for (int pr = 0; pr < 2; ++pr) {  // T = L(b1, b0) W(b0, b0)
+        const int o0 = 32 * pr, o1 = o0 + 16;
+        const gp_v4d t = wave_mm16([&](int i, int k) { return Ls[o1 + i][o0 + k]; },
+                                   [&](int k, int j) { return Wl[o0 + k][o0 + j]; }, 0, 16, lane);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) T32[16 * pr + (lane >> 4) + 4 * r][lane & 15] = t[r];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int pr = 0; pr < 2; ++pr) {  // W(b1, b0) = -W(b1, b1) T
+        const int o0 = 32 * pr, o1 = o0 + 16;
+        const gp_v4d u = wave_mm16([&](int i, int k) { return Wl[o1 + i][o1 + k]; },
+                                   [&](int k, int j) { return T32[16 * pr + k][j]; }, 0, 16, lane);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Wl[o1 + (lane >> 4) + 4 * r][o0 + (lane & 15)] = -u[r];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) {  // T = L21 W11; block (kb, tj) of W11 is zero for kb < tj
+            const gp_v4d t = wave_mm16([&](int i, int k) { return Ls[32 + 16 * ti + i][k]; },
+                                       [&](int k, int j) { return Wl[k][16 * tj + j]; }, 16 * tj, 32, lane);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) T32[16 * ti + (lane >> 4) + 4 * r][16 * tj + (lane & 15)] = t[r];
+        }
+    wave_lds_sync();
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) {  // W21 = -W22 T; block (ti, kb) of W22 is zero for kb > ti
+            const gp_v4d u = wave_mm16([&](int i, int k) { return Wl[32 + 16 * ti + i][32 + k]; },
+                                       [&](int k, int j) { return T32[k][16 * tj + j]; }, 0, 16 * ti + 16, lane);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Wl[32 + 16 * ti + (lane >> 4) + 4 * r][16 * tj + (lane & 15)] = -u[r];
+        }
+    wave_lds_sync();
 }
 
 // ---------------------------------------------------------------------------
@@ -341,6 +389,7 @@ hipError_t launch_gather_points(hipStream_t s, int64_t n, int dim, const int64_t
                                 const double *y, const double *mu, double *Xp, double *yp, double *mup);
 hipError_t launch_scatter_vec(hipStream_t s, int64_t n, const int64_t *perm, const double *src, double *dst);
 hipError_t launch_set_info(hipStream_t s, int32_t *info);
+hipError_t launch_tune_fill(hipStream_t s, double *A, int64_t lda, int64_t n);
 
 // k_batch.hip
 size_t batch_ws_bytes(int64_t nmax, int64_t nbatch);

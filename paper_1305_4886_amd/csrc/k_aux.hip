@@ -81,12 +81,30 @@ __global__ __launch_bounds__(64) void k_grad_finish(int nparts, const double *pa
     }
 }
 
+
+// Synthetic SPD test matrix for the autotuner: the exponential covariance of
+// n equispaced points on a line, exp(-8 |i - j| / n), plus the identity
+// (lower triangle only).
+__global__ void k_tune_fill(double *A, int64_t lda, int64_t n) {
+    const double sc = 8.0 / (double)n;
+    for (int64_t j = blockIdx.y; j < n; j += gridDim.y)
+        for (int64_t i = j + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+            A[i + j * lda] = exp(-sc * (double)(i - j)) + (i == j ? 1.0 : 0.0);
+}
+
 }  // namespace
 
 hipError_t launch_colreduce(hipStream_t s, int mode, int64_t n, int64_t m, const double *M, int64_t ld,
                             const double *v, double base, double *out) {
     if (m <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_colreduce, dim3((unsigned)m), dim3(256), 0, s, mode, n, m, M, ld, v, base, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_tune_fill(hipStream_t s, double *A, int64_t lda, int64_t n) {
+    if (n <= 0) return hipSuccess;
+    const int64_t gx = (n + 255) / 256 < 64 ? (n + 255) / 256 : 64;
+    hipLaunchKernelGGL(k_tune_fill, dim3((unsigned)gx, (unsigned)(n < 8192 ? n : 8192)), dim3(256), 0, s, A, lda, n);
     return hipGetLastError();
 }
 

@@ -100,8 +100,12 @@ __global__ __launch_bounds__(256, 1) void k_bdiag(const BProb *__restrict__ prob
                                                   int j, int dim, const double *__restrict__ X, double *C_pool,
                                                   double *wbuf, int32_t *info) {
     __shared__ double As[T][T + 1];
-    __shared__ double Bs[T][T + 1];
-    __shared__ double Pn[T][17];
+    __shared__ double Bs[T][T + 1];  // staging of the update, then the inverse
+    __shared__ union {
+        double pn[T][17];
+        double t32[32][33];
+    } U;
+    __shared__ double rd[T];
     __shared__ int s_fail;
     const int b = plist[blockIdx.x];
     if (info[b] != 0) return;
@@ -125,24 +129,18 @@ __global__ __launch_bounds__(256, 1) void k_bdiag(const BProb *__restrict__ prob
     __syncthreads();
     if (w != 0) return;  // one wave factors and inverts the tile
     const int tj = (int)((P.n - j0) < T ? (P.n - j0) : T);
-    double a[T];
-#pragma unroll
-    for (int c = 0; c < T; ++c) a[c] = (c <= lane) ? As[lane][c] : 0.0;
-    const int fail = wave_chol64(a, lane, As, Pn);
+    const int fail = wave_potrf64_lds(As, U.pn, lane);
     if (fail) {
         if (lane == 0) info[b] = (int32_t)(j0 + fail);
         return;
     }
-#pragma unroll
-    for (int c = 0; c < T; ++c) {
-        As[lane][c] = a[c];
-        if (lane < tj && c <= lane) L[(j0 + lane) + (j0 + c) * ld] = a[c];
-    }
-    double wv[T];
-    wave_inv64(As, wv, lane);
+#pragma unroll 4
+    for (int c = 0; c < T; ++c)
+        if (lane < tj && c <= lane) L[(j0 + lane) + (j0 + c) * ld] = As[lane][c];
+    wave_inv64_blocked(As, Bs, U.t32, rd, lane);
     double *W = wbuf + P.w_off + (int64_t)j * T * T;
-#pragma unroll
-    for (int r = 0; r < T; ++r) W[r + lane * T] = wv[r];
+#pragma unroll 4
+    for (int c = 0; c < T; ++c) W[lane + c * T] = Bs[lane][c];
 }
 
 __global__ __launch_bounds__(256, 2) void k_bpanel(const BProb *__restrict__ probs, const BTile *__restrict__ tlist,

@@ -23,57 +23,61 @@
 namespace {
 
 // Factor + invert one diagonal block (jb <= 64 valid rows, identity padding).
-// One wave per block.
+// One wave per block; the block lives in LDS (wave_potrf64_lds), the inverse
+// is formed on the matrix cores (wave_inv64_blocked).  Winv is column-major
+// 64 x 64.
 __global__ __launch_bounds__(64) void k_diag_potrf(double *A, int64_t lda, int jb, double *Winv,
                                                    int32_t *info, int64_t col0) {
-    __shared__ double Ls[DB][DB + 1];  // update buffer of the factorisation, then L
-    __shared__ double Pn[DB][17];
+    __shared__ double Us[DB][DB + 1];  // the block, then L
+    __shared__ double Wl[DB][DB + 1];  // L^{-1}
+    __shared__ union {
+        double pn[DB][17];
+        double t32[32][33];
+    } U;
+    __shared__ double rd[DB];
     if (*info) return;
     const int lane = threadIdx.x;
-    double a[DB];
-#pragma unroll
+#pragma unroll 4
     for (int c = 0; c < DB; ++c) {
         double v;
         if (lane < jb && c < jb) v = (c <= lane) ? A[lane + (int64_t)c * lda] : 0.0;
         else v = (lane == c) ? 1.0 : 0.0;  // identity padding decouples unused rows
-        a[c] = v;
+        Us[lane][c] = v;
     }
-    const int fail = wave_chol64(a, lane, Ls, Pn);
+    wave_lds_sync();
+    const int fail = wave_potrf64_lds(Us, U.pn, lane);
     if (fail) {
         if (lane == 0) *info = (int32_t)(col0 + fail);
         return;
     }
-#pragma unroll
-    for (int c = 0; c < DB; ++c) Ls[lane][c] = a[c];
-    __syncthreads();
-#pragma unroll
+#pragma unroll 4
     for (int c = 0; c < DB; ++c)
-        if (lane < jb && c < jb && c <= lane) A[lane + (int64_t)c * lda] = a[c];
-    double w[DB];
-    wave_inv64(Ls, w, lane);
-    // Winv column-major: W[i + c DB] = W_ic, lane = c
-#pragma unroll
-    for (int i = 0; i < DB; ++i) Winv[i + lane * DB] = w[i];
+        if (lane < jb && c < jb && c <= lane) A[lane + (int64_t)c * lda] = Us[lane][c];
+    wave_inv64_blocked(Us, Wl, U.t32, rd, lane);
+#pragma unroll 4
+    for (int c = 0; c < DB; ++c) Winv[lane + c * DB] = Wl[lane][c];
 }
 
 __global__ __launch_bounds__(64) void k_diag_inv(const double *L, int64_t ldl, int64_t n, double *dinv) {
     __shared__ double Ls[DB][DB + 1];
+    __shared__ double Wl[DB][DB + 1];
+    __shared__ double T32[32][33];
+    __shared__ double rd[DB];
     const int64_t b0 = (int64_t)blockIdx.x * DB;
     const int jb = (int)((n - b0) < DB ? (n - b0) : DB);
     const int lane = threadIdx.x;
-#pragma unroll
+#pragma unroll 4
     for (int c = 0; c < DB; ++c) {
         double v;
         if (lane < jb && c < jb) v = (c <= lane) ? L[(b0 + lane) + (b0 + c) * ldl] : 0.0;
         else v = (lane == c) ? 1.0 : 0.0;
         Ls[lane][c] = v;
     }
-    __syncthreads();
-    double w[DB];
-    wave_inv64(Ls, w, lane);
+    wave_lds_sync();
+    wave_inv64_blocked(Ls, Wl, T32, rd, lane);
     double *W = dinv + (int64_t)blockIdx.x * DB * DB;
-#pragma unroll
-    for (int i = 0; i < DB; ++i) W[i + lane * DB] = w[i];
+#pragma unroll 4
+    for (int c = 0; c < DB; ++c) W[lane + c * DB] = Wl[lane][c];
 }
 
 // Cross-lane reduction of H register values: lanes l and l ^ H exchange the

@@ -303,9 +303,12 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmDesc d, TileMap tm) {
 // per operand) is copied by global_load_lds_dword straight into LDS, 256 bytes
 // per instruction, so STAGES - 1 slabs are in flight while the matrix cores
 // consume the current one and no registers hold staged data.  A copy address
-// is a scalar column base plus a 32-bit per-lane offset.  Rows past the matrix
-// are clamped to its last row: they feed only output rows / columns that are
-// never stored.  Requires K % BKD == 0.
+// is a scalar column base plus a 32-bit per-lane offset.  The copies of the
+// next slab are spread between the matrix instructions (two MFMAs, one copy)
+// and the LDS reads of step kk + 1 are issued before the MFMAs of step kk, so
+// a wave keeps its matrix pipe busy while it feeds the ring.  Rows past the
+// matrix are clamped to its last row: they feed only output rows / columns
+// that are never stored.  Requires K % BKD == 0.
 // ---------------------------------------------------------------------------
 template <int N>
 GP_DEV void wait_vmcnt() {
@@ -341,10 +344,10 @@ GP_DEV void lds_dma_dword(const double *base, uint32_t voff, uint32_t lds_unifor
 }
 
 template <int STAGES, int BKD, int TAG>
-__global__ __launch_bounds__(256, 2) void k_syrk_pipe(GemmDesc d, TileMap tm) {
+__global__ __launch_bounds__(256, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
     constexpr int BM = 128, WTM = 64, FM = 4, FN = 4;
-    constexpr int CPW = BKD / 4;           // panel columns each wave copies per operand
-    constexpr int PER = CPW * 2 * 4;       // copies per wave per slab
+    constexpr int NKK = BKD / 4;           // MFMA K-steps per slab = panel columns each wave copies
+    constexpr int PER = NKK * 2 * 4;       // copies per wave per slab
     static_assert(BKD % 4 == 0 && STAGES >= 2, "slab shape");
     static_assert((STAGES - 2) * PER < 64, "outstanding copies exceed vmcnt");
     __shared__ double Ls[STAGES][2][BKD][BM];  // [stage][operand][k][row]
@@ -373,22 +376,24 @@ __global__ __launch_bounds__(256, 2) void k_syrk_pipe(GemmDesc d, TileMap tm) {
         offA[q] = (uint32_t)(8 * ra + 4 * (lane & 1));
         offB[q] = (uint32_t)(8 * rb + 4 * (lane & 1));
     }
-    auto issue = [&](int slab, int st) {
-#pragma unroll
-        for (int c = 0; c < CPW; ++c) {
-            const int kk = wave + 4 * c;
-            const double *col = P + ((int64_t)slab * BKD + kk) * d.lda;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                lds_dma_dword(col, offA[q], (uint32_t)(uintptr_t)&Ls[st][0][kk][32 * q]);
-                lds_dma_dword(col, offB[q], (uint32_t)(uintptr_t)&Ls[st][1][kk][32 * q]);
-            }
-        }
+    // copy q (0..7) of column `part` of slab `slab`: q < 4 operand A rows 32 q.., else B
+    auto copy1 = [&](int slab, int st, int part, int q) {
+        const int kk = wave + 4 * part;
+        const double *col = P + ((int64_t)slab * BKD + kk) * d.lda;
+        if (q < 4)
+            lds_dma_dword(col, offA[q], (uint32_t)(uintptr_t)&Ls[st][0][kk][32 * q]);
+        else
+            lds_dma_dword(col, offB[q - 4], (uint32_t)(uintptr_t)&Ls[st][1][kk][32 * (q - 4)]);
     };
 
 #pragma unroll
     for (int s = 0; s < STAGES - 1; ++s)
-        if (s < nk) issue(s, s);
+        if (s < nk) {
+#pragma unroll
+            for (int part = 0; part < NKK; ++part)
+#pragma unroll
+                for (int q = 0; q < 8; ++q) copy1(s, s, part, q);
+        }
 
     v4d acc[FM][FN];
 #pragma unroll
@@ -398,26 +403,45 @@ __global__ __launch_bounds__(256, 2) void k_syrk_pipe(GemmDesc d, TileMap tm) {
 
     int st = 0;
     for (int k = 0; k < nk; ++k) {
-        // slabs k .. min(k + STAGES - 2, nk - 1) are in flight: wait for slab k
         const int later = nk - 1 - k;
         wait_slabs<PER, STAGES - 2>(later < STAGES - 2 ? later : STAGES - 2);
         asm volatile("" ::: "memory");
         __builtin_amdgcn_s_barrier();
         asm volatile("" ::: "memory");
-        // every wave is past its reads of the stage consumed last iteration
-        if (k + STAGES - 1 < nk) issue(k + STAGES - 1, st == 0 ? STAGES - 1 : st - 1);
+        const bool more = k + STAGES - 1 < nk;
+        const int ns = k + STAGES - 1, nst = st == 0 ? STAGES - 1 : st - 1;
+        double a[FM], b[FN];
 #pragma unroll
-        for (int kk = 0; kk < BKD; kk += 4) {
-            double a[FM], b[FN];
+        for (int m = 0; m < FM; ++m) a[m] = Ls[st][0][(lane >> 4)][wm * WTM + m * 16 + (lane & 15)];
 #pragma unroll
-            for (int m = 0; m < FM; ++m) a[m] = Ls[st][0][kk + (lane >> 4)][wm * WTM + m * 16 + (lane & 15)];
+        for (int n = 0; n < FN; ++n) b[n] = Ls[st][1][(lane >> 4)][wn * WTM + n * 16 + (lane & 15)];
 #pragma unroll
-            for (int n = 0; n < FN; ++n) b[n] = Ls[st][1][kk + (lane >> 4)][wn * WTM + n * 16 + (lane & 15)];
+        for (int kk = 0; kk < NKK; ++kk) {
+            double an[FM], bn[FN];
+            if (kk + 1 < NKK) {
 #pragma unroll
-            for (int m = 0; m < FM; ++m)
+                for (int m = 0; m < FM; ++m)
+                    an[m] = Ls[st][0][4 * (kk + 1) + (lane >> 4)][wm * WTM + m * 16 + (lane & 15)];
 #pragma unroll
                 for (int n = 0; n < FN; ++n)
-                    acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[n], acc[m][n], 0, 0, 0);
+                    bn[n] = Ls[st][1][4 * (kk + 1) + (lane >> 4)][wn * WTM + n * 16 + (lane & 15)];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int m = q >> 1, n0 = (q & 1) * 2;
+                acc[m][n0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[n0], acc[m][n0], 0, 0, 0);
+                acc[m][n0 + 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[n0 + 1], acc[m][n0 + 1], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+                if (more) copy1(ns, nst, kk, q);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (kk + 1 < NKK) {
+#pragma unroll
+                for (int m = 0; m < FM; ++m) a[m] = an[m];
+#pragma unroll
+                for (int n = 0; n < FN; ++n) b[n] = bn[n];
+            }
         }
         st = st + 1 == STAGES ? 0 : st + 1;
     }
@@ -651,6 +675,23 @@ hipError_t run_band_f64(hipStream_t s, const GemmDesc &d, int64_t band) {
 
 }  // namespace
 
+namespace {
+
+// Lower trapezoid of 128 x 128 tiles in row-major order (no super-tiles), four
+// LDS stages of 8 panel columns (64 KB: two workgroups per CU).
+template <int TAG>
+hipError_t run_dma(hipStream_t s, const GemmDesc &d) {
+    if (d.M <= 0 || d.N <= 0 || d.K <= 0) return hipSuccess;
+    TileMap tm = make_map(d.M, d.N, 128, 128, 1);
+    tm.sgm = tm.sgn = 1;
+    tm.ntiles = tm.ntn * (tm.ntn + 1) / 2 + (tm.ntm - tm.ntn) * tm.ntn;
+    const int64_t g = ((tm.ntiles + 7) / 8) * 8;
+    hipLaunchKernelGGL((k_syrk_dma<4, 8, TAG>), dim3((unsigned)g), dim3(256), 0, s, d, tm);
+    return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_syrk_lower(hipStream_t s, gp_prec_t prec, int band, const double *P, int64_t ldp,
                              double *C, int64_t ldc, int64_t M, int64_t N, int64_t K,
                              const int32_t *info, int role) {
@@ -659,6 +700,7 @@ hipError_t launch_syrk_lower(hipStream_t s, gp_prec_t prec, int band, const doub
     d.M = M; d.N = N; d.K = K; d.alpha = -1.0; d.beta = 1.0;
     d.ta = 0; d.tb = 1; d.lower = 1; d.batch = 1; d.info = info;
     if (prec == GP_FP64) {
+        if (K % 8 == 0) return role == 1 ? run_dma<1>(s, d) : run_dma<2>(s, d);
         if (role == 1) return run_f64<128, 128, 2, 2, 0, 1, 1>(s, d);
         return run_f64<128, 128, 2, 2, 0, 1, 2>(s, d);
     }

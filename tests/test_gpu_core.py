@@ -205,3 +205,26 @@ def test_loglik_scalar_mu_is_taken_in_fp64(orc):
     b = gp.loglik(dev(X), dev(y), gp.theta(0, log=t), mu=dev(np.full(n, mu)))["out3"].cpu().numpy()
     assert np.array_equal(a, b)
     assert abs(a[0] - ll_o) <= 1e-11 * abs(ll_o)
+
+
+def test_tune_potrf_picks_a_candidate_and_factors_correctly(orc):
+    h = gp.handle()
+    saved = h.options()
+    try:
+        times = h.tune_potrf(1500, nb=(128, 256), panel_cus=(0, 8))
+        o = h.options()
+        assert set(times) == {(128, 0), (128, 8), (256, 0), (256, 8)}
+        assert all(t > 0 for t in times.values()), times
+        assert (o.nb, o.panel_cus) == min(times, key=times.get) and o.lookahead == 1
+        n = 1500
+        X = synth.uniform_points(n, 77)
+        t = logth(1.0, 0.1, 0.1)
+        C = orc.cov(0, t, X)
+        S = gp.colmajor_storage(n)
+        gp.colmajor(S, n).copy_(torch.as_tensor(np.tril(C)))
+        assert int(gp.potrf(S, n).item()) == 0
+        Lo, _ = orc.potrf(C)
+        L = lower_of(S, n)
+        assert np.linalg.norm(L - Lo) <= 1e-12 * np.linalg.norm(Lo)
+    finally:
+        h.set_options(nb=saved.nb, lookahead=saved.lookahead, panel_cus=saved.panel_cus)

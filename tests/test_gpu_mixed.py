@@ -88,6 +88,8 @@ def test_mixed_bf16_loglik(orc, n, kernel, rho, t2, seed):
     print("bf16 n=%d rel loglik err %.2e  logdet err %.2e  q err %.2e  ir=%s" % (
         n, err, abs(out[1] - ld) / abs(ld), abs(out[2] - q) / abs(q), ir))
     assert int(r["info"].item()) == 0
+    assert ir[2] == 1.0 and ir[1] <= 1e-10, ir
+    assert abs(out[2] - q) <= 1e-9 * abs(q)
     assert err <= 1e-3
 
 
