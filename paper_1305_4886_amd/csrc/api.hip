@@ -52,7 +52,7 @@ CovParams cov_params(const gp_theta_t &th, int dim) {
 struct Layout {
     size_t dinv = 0, sync = 0, z = 0, vec2 = 0, vec3 = 0, vec4 = 0, vec5 = 0, part = 0, big1 = 0, big2 = 0,
            big3 = 0, irst = 0, perm = 0, keys = 0, box = 0, xp = 0, yp = 0, mup = 0, pbuf = 0, vinv = 0,
-           vtmp = 0, total = 0;
+           vtmp = 0, qbuf = 0, total = 0;
 };
 
 // Buffers of the panel steps of the factorisation (null when n <= NB).
@@ -60,6 +60,7 @@ struct PanelBufs {
     double *pbuf = nullptr;  // copy of the rows below a diagonal block, (n - NB) x NB
     double *vinv = nullptr;  // inverse of a diagonal block, NB x NB
     double *vtmp = nullptr;  // products of the blocked inverse, trtri_tmp_elems(NB)
+    void *qbuf = nullptr;    // low-precision packed panel (mixed modes)
 };
 
 int64_t panel_width(gp_handle_t h) { return h->opt.nb > 0 ? h->opt.nb : 512; }
@@ -114,6 +115,7 @@ Layout layout(gp_handle_t h, gp_op_t op, int64_t n, int64_t m, gp_prec_t prec) {
         L.pbuf = take(sizeof(double) * (size_t)(n - NB) * (size_t)NB);
         L.vinv = take(sizeof(double) * (size_t)NB * (size_t)NB);
         L.vtmp = take(sizeof(double) * trtri_tmp_elems(NB));
+        if (prec != GP_FP64) L.qbuf = take(packed_panel_bytes(n - NB, NB));
     };
     switch (op) {
     case GP_OP_POTRF:
@@ -185,6 +187,7 @@ PanelBufs panel_bufs(void *ws, const Layout &L) {
         p.pbuf = at<double>(ws, L.pbuf);
         p.vinv = at<double>(ws, L.vinv);
         p.vtmp = at<double>(ws, L.vtmp);
+        if (L.qbuf) p.qbuf = at<char>(ws, L.qbuf);
     }
     return p;
 }
@@ -211,6 +214,31 @@ hipError_t trailing(gp_handle_t h, hipStream_t s, gp_prec_t prec, const double *
         hipEventRecord(e0, s);
     }
     hipError_t e = launch_syrk_lower(s, prec, h->opt.band, P, ldp, C, ldc, M, N, K, info, 1);
+    if (h->prof) {
+        hipEventRecord(e1, s);
+        h->prof_flops += syrk_flops(M, N, K);
+        h->prof_launches += 1;
+    }
+    return e;
+}
+
+// Low-precision trailing update from the packed panel, bracketed like trailing().
+hipError_t trailing_packed(gp_handle_t h, hipStream_t s, gp_prec_t prec, const double *P, int64_t ldp,
+                           const void *Q, int64_t Mpack, int64_t qrow0, double *C, int64_t ldc, int64_t M,
+                           int64_t N, int64_t K, const int32_t *info) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (h->prof) {
+        while (h->prof_ev.size() < h->prof_used + 2) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return hipErrorOutOfMemory;
+            h->prof_ev.push_back(e);
+        }
+        e0 = h->prof_ev[h->prof_used];
+        e1 = h->prof_ev[h->prof_used + 1];
+        h->prof_used += 2;
+        hipEventRecord(e0, s);
+    }
+    hipError_t e = launch_syrk_packed(s, prec, h->opt.band, P, ldp, Q, Mpack, qrow0, C, ldc, M, N, K, info);
     if (h->prof) {
         hipEventRecord(e1, s);
         h->prof_flops += syrk_flops(M, N, K);
@@ -378,21 +406,27 @@ int potrf_impl(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda,
         if (c1 >= n) break;
         const int64_t K = c1 - c0;
         const int64_t c2 = (c1 + NB < n) ? c1 + NB : n;
+        const bool packed = prec != GP_FP64 && pb.qbuf && K % 32 == 0;
+        if (packed) HIPCHK(launch_pack_panel(s, prec, A + c1 + c0 * lda, lda, n - c1, K, pb.qbuf));
+        // trailing update of rows / columns [r0, r1) x [r0, ...) from panel rows r0 ..
+        auto update = [&](int64_t r0, int64_t ncols) -> hipError_t {
+            const int64_t M = n - r0;
+            if (packed)
+                return trailing_packed(h, s, prec, A + r0 + c0 * lda, lda, pb.qbuf, n - c1, r0 - c1,
+                                       A + r0 + r0 * lda, lda, M, ncols, K, info);
+            return trailing(h, s, prec, A + r0 + c0 * lda, lda, A + r0 + r0 * lda, lda, M, ncols, K, info);
+        };
         if (la) {
             // columns of the next panel first
-            HIPCHK(trailing(h, s, prec, A + c1 + c0 * lda, lda, A + c1 + c1 * lda, lda, n - c1, c2 - c1, K,
-                            info));
+            HIPCHK(update(c1, c2 - c1));
             HIPCHK(hipEventRecord(h->ev_cols, s));
             HIPCHK(hipStreamWaitEvent(side, h->ev_cols, 0));
             if ((rc = diag_block(side, c1, c2))) return rc;
             HIPCHK(hipEventRecord(h->ev_panel, side));
-            if (c2 < n)
-                HIPCHK(trailing(h, s, prec, A + c2 + c0 * lda, lda, A + c2 + c2 * lda, lda, n - c2, n - c2,
-                                K, info));
+            if (c2 < n) HIPCHK(update(c2, n - c2));
             HIPCHK(hipStreamWaitEvent(s, h->ev_panel, 0));
         } else {
-            HIPCHK(trailing(h, s, prec, A + c1 + c0 * lda, lda, A + c1 + c1 * lda, lda, n - c1, n - c1, K,
-                            info));
+            HIPCHK(update(c1, n - c1));
             if ((rc = diag_block(s, c1, c2))) return rc;
         }
         if (c2 < n && (rc = below(s, c1, c2))) return rc;

@@ -184,48 +184,57 @@ GP_DEV gp_v4d wave_mm16(FA fa, FB fb, int kbeg, int kend, int lane) {
     return acc;
 }
 
-// The same factorisation with the block held in LDS (Us[r][c] = A_rc, lower
-// triangle; zeros or anything above it), for latency-bound single-wave
-// kernels: the 16-column panel step is one loop body run four times (small
-// code that stays in the instruction cache) and only the panel lives in
-// registers.  The trailing update is applied by the matrix cores in place in
-// Us.  On return the lower triangle of Us holds L.  Pn: 64 x 17 doubles of
-// LDS.  Returns 0 or the first failing 1-based column.
-GP_DEV int wave_potrf64_lds(double (*Us)[DB + 1], double (*Pn)[17], int lane) {
+// Cholesky of a 64 x 64 block held by one wave, lane r = row r (a[c] = A[r][c]).
+// Right-looking in panels of 16 columns: inside a panel, column by column
+// (pivot, 1 / sqrt by rsqrt_nr, scale, rank-1 update of the panel's columns to
+// its right, with readlane broadcasts); then the columns right of the panel
+// get A -= P P^T on the matrix cores (v_mfma_f64_16x16x4 on 16 x 16 tiles,
+// operands from the panel staged in Pn, products returned through Us).  Only
+// the lower triangle is meaningful on return: entries above the diagonal are
+// updated without masks and hold garbage (they never feed a lower entry).
+// Returns 0 or the first failing 1-based column (a non-positive or NaN
+// pivot); later columns then hold garbage.  Us: 64 x 65, Pn: 64 x 17 doubles
+// of LDS, used by this wave only.
+GP_DEV int wave_chol64(double (&a)[DB], int lane, double (*Us)[DB + 1], double (*Pn)[17]) {
     int fail = 0;
-#pragma unroll 1
+#pragma unroll
     for (int p = 0; p < DB; p += 16) {
-        double a[16];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) a[k] = Us[lane][p + k];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const double piv = rdlane(a[j], p + j);
-            if (!(piv > 0.0) && fail == 0) fail = p + j + 1;
+        for (int j = p; j < p + 16; ++j) {
+            const double piv = rdlane(a[j], j);
+            if (!(piv > 0.0) && fail == 0) fail = j + 1;
             const double inv = rsqrt_nr(piv);
-            a[j] = (lane == p + j) ? piv * inv : a[j] * inv;
+            a[j] = (lane == j) ? piv * inv : a[j] * inv;
 #pragma unroll
-            for (int c = j + 1; c < 16; ++c) a[c] = fma(-a[j], rdlane(a[j], p + c), a[c]);
+            for (int c = j + 1; c < p + 16; ++c) a[c] = fma(-a[j], rdlane(a[j], c), a[c]);
         }
+        if (p + 16 < DB) {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            Pn[lane][k] = a[k];
-            Us[lane][p + k] = a[k];
+            for (int k = 0; k < 16; ++k) Pn[lane][k] = a[p + k];
+            wave_lds_sync();
+            const int t0 = p + 16;
+#pragma unroll
+            for (int ti = 0; ti < (DB - p - 16) / 16; ++ti)
+#pragma unroll
+                for (int tj = 0; tj <= ti; ++tj) {
+                    // D layout of v_mfma_f64_16x16x4: lane l, register r holds
+                    // row l / 16 + 4 r, column l % 16
+                    gp_v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int k0 = 0; k0 < 16; k0 += 4) {
+                        const double av = Pn[t0 + 16 * ti + (lane & 15)][k0 + (lane >> 4)];
+                        const double bv = Pn[t0 + 16 * tj + (lane & 15)][k0 + (lane >> 4)];
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        Us[t0 + 16 * ti + (lane >> 4) + 4 * r][t0 + 16 * tj + (lane & 15)] = acc[r];
+                }
+            wave_lds_sync();
+#pragma unroll
+            for (int c = p + 16; c < DB; ++c) a[c] -= Us[lane][c];
+            wave_lds_sync();
         }
-        wave_lds_sync();
-        // tiles (ti, tj), ti >= tj, of rows / columns t0 .. 63: Us -= P P^T
-        const int t0 = p + 16, nt = (DB - t0) / 16;
-#pragma unroll 1
-        for (int ti = 0; ti < nt; ++ti)
-#pragma unroll 1
-            for (int tj = 0; tj <= ti; ++tj) {
-                const int r0 = t0 + 16 * ti, c0 = t0 + 16 * tj;
-                const gp_v4d acc = wave_mm16([&](int i, int k) { return Pn[r0 + i][k]; },
-                                             [&](int k, int j) { return Pn[c0 + j][k]; }, 0, 16, lane);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) Us[r0 + (lane >> 4) + 4 * r][c0 + (lane & 15)] -= acc[r];
-            }
-        wave_lds_sync();
     }
     return fail;
 }
@@ -342,6 +351,18 @@ hipError_t launch_gemm_f64(hipStream_t s, const GemmDesc &d);
 hipError_t launch_syrk_lower(hipStream_t s, gp_prec_t prec, int band, const double *P,
                              int64_t ldp, double *C, int64_t ldc, int64_t M, int64_t N, int64_t K,
                              const int32_t *info, int role);
+// Low-precision trailing updates from a packed copy of the panel: rows
+// 0 .. Mpack - 1 of P (FP64, ld ldp, K columns) rounded once into Q
+// (packed_panel_bytes(Mpack, K) bytes); a call then updates the M x N lower
+// trapezoid whose panel rows start at packed row qrow0 (P points at that row).
+// K must be a multiple of 32.
+int64_t packed_rows(int64_t M);
+size_t packed_panel_bytes(int64_t M, int64_t K);
+hipError_t launch_pack_panel(hipStream_t s, gp_prec_t prec, const double *P, int64_t ldp, int64_t M, int64_t K,
+                             void *Q);
+hipError_t launch_syrk_packed(hipStream_t s, gp_prec_t prec, int band, const double *P, int64_t ldp, const void *Q,
+                              int64_t Mpack, int64_t qrow0, double *C, int64_t ldc, int64_t M, int64_t N, int64_t K,
+                              const int32_t *info);
 // Algorithmic flops of a lower-trapezoid update of M rows x N columns (N <= M)
 // with inner dimension K: 2 K (N M - N (N - 1) / 2).
 inline double syrk_flops(int64_t M, int64_t N, int64_t K) {

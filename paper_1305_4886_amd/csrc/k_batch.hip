@@ -129,14 +129,20 @@ __global__ __launch_bounds__(256, 1) void k_bdiag(const BProb *__restrict__ prob
     __syncthreads();
     if (w != 0) return;  // one wave factors and inverts the tile
     const int tj = (int)((P.n - j0) < T ? (P.n - j0) : T);
-    const int fail = wave_potrf64_lds(As, U.pn, lane);
+    double a[T];
+#pragma unroll
+    for (int c = 0; c < T; ++c) a[c] = As[lane][c];
+    const int fail = wave_chol64(a, lane, As, U.pn);
     if (fail) {
         if (lane == 0) info[b] = (int32_t)(j0 + fail);
         return;
     }
-#pragma unroll 4
-    for (int c = 0; c < T; ++c)
-        if (lane < tj && c <= lane) L[(j0 + lane) + (j0 + c) * ld] = As[lane][c];
+#pragma unroll
+    for (int c = 0; c < T; ++c) {
+        As[lane][c] = a[c];
+        if (lane < tj && c <= lane) L[(j0 + lane) + (j0 + c) * ld] = a[c];
+    }
+    wave_lds_sync();
     wave_inv64_blocked(As, Bs, U.t32, rd, lane);
     double *W = wbuf + P.w_off + (int64_t)j * T * T;
 #pragma unroll 4

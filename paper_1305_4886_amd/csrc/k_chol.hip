@@ -23,12 +23,12 @@
 namespace {
 
 // Factor + invert one diagonal block (jb <= 64 valid rows, identity padding).
-// One wave per block; the block lives in LDS (wave_potrf64_lds), the inverse
-// is formed on the matrix cores (wave_inv64_blocked).  Winv is column-major
-// 64 x 64.
+// One wave per block: rows in registers, 16-column panels with MFMA updates
+// (wave_chol64), then the inverse on the matrix cores (wave_inv64_blocked).
+// Winv is column-major 64 x 64.
 __global__ __launch_bounds__(64) void k_diag_potrf(double *A, int64_t lda, int jb, double *Winv,
                                                    int32_t *info, int64_t col0) {
-    __shared__ double Us[DB][DB + 1];  // the block, then L
+    __shared__ double Ls[DB][DB + 1];  // update buffer of the factorisation, then L
     __shared__ double Wl[DB][DB + 1];  // L^{-1}
     __shared__ union {
         double pn[DB][17];
@@ -37,23 +37,26 @@ __global__ __launch_bounds__(64) void k_diag_potrf(double *A, int64_t lda, int j
     __shared__ double rd[DB];
     if (*info) return;
     const int lane = threadIdx.x;
-#pragma unroll 4
+    double a[DB];
+#pragma unroll
     for (int c = 0; c < DB; ++c) {
         double v;
         if (lane < jb && c < jb) v = (c <= lane) ? A[lane + (int64_t)c * lda] : 0.0;
         else v = (lane == c) ? 1.0 : 0.0;  // identity padding decouples unused rows
-        Us[lane][c] = v;
+        a[c] = v;
     }
-    wave_lds_sync();
-    const int fail = wave_potrf64_lds(Us, U.pn, lane);
+    const int fail = wave_chol64(a, lane, Ls, U.pn);
     if (fail) {
         if (lane == 0) *info = (int32_t)(col0 + fail);
         return;
     }
-#pragma unroll 4
+#pragma unroll
+    for (int c = 0; c < DB; ++c) Ls[lane][c] = a[c];
+    wave_lds_sync();
+#pragma unroll
     for (int c = 0; c < DB; ++c)
-        if (lane < jb && c < jb && c <= lane) A[lane + (int64_t)c * lda] = Us[lane][c];
-    wave_inv64_blocked(Us, Wl, U.t32, rd, lane);
+        if (lane < jb && c < jb && c <= lane) A[lane + (int64_t)c * lda] = a[c];
+    wave_inv64_blocked(Ls, Wl, U.t32, rd, lane);
 #pragma unroll 4
     for (int c = 0; c < DB; ++c) Winv[lane + c * DB] = Wl[lane][c];
 }

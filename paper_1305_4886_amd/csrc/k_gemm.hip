@@ -472,6 +472,170 @@ __global__ __launch_bounds__(256, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Low-precision trailing update from a packed copy of the panel.
+// k_pack_panel rounds the FP64 panel P (M x K, ld lda) once per panel into Q:
+//   FP32 (PREC 1): Q[k Mp + r]            (column-major, ld Mp)
+//   BF16 (PREC 2): Q[(k / 32) Mp 32 + 32 r + k % 32]  (32-column slabs, 64 B per row)
+// with rows M .. Mp - 1 zero (Mp a multiple of 128).  k_syrk_pk then runs the
+// same four-stage direct-to-LDS pipeline as the FP64 kernel on Q, with FP32
+// accumulation (v_mfma_f32_16x16x4_f32: one element per lane and operand, or
+// v_mfma_f32_16x16x32_bf16: 8 consecutive k per lane), and subtracts the
+// products from the FP64 tile.  D layout of both (checked with a probe):
+// lane l, register r holds row 4 (l / 16) + r, column l % 16.
+// ---------------------------------------------------------------------------
+template <int PREC>
+__global__ void k_pack_panel(const double *__restrict__ P, int64_t lda, int64_t M, int64_t Mp, int64_t K,
+                             void *__restrict__ Q) {
+    const int64_t total = Mp * K;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        if (PREC == 1) {  // e = k Mp + r: coalesced in r on both sides
+            const int64_t k = e / Mp, r = e - k * Mp;
+            static_cast<float *>(Q)[e] = r < M ? (float)P[r + k * lda] : 0.f;
+        } else {          // e = (s Mp + r) 32 + kk
+            const int64_t kk = e & 31, sr = e >> 5;
+            const int64_t sl = sr / Mp, r = sr - sl * Mp, k = 32 * sl + kk;
+            static_cast<__bf16 *>(Q)[e] = (r < M && k < K) ? (__bf16)P[r + k * lda] : (__bf16)0.f;
+        }
+    }
+}
+
+template <int PREC, int TAG>
+__global__ __launch_bounds__(256, 2) void k_syrk_pk(GemmDesc d, TileMap tm, const void *__restrict__ Qv, int64_t Mp,
+                                                    int64_t qrow0) {
+    constexpr int STAGES = 4, BM = 128, WTM = 64, FM = 4, FN = 4;
+    constexpr int BKD = PREC == 1 ? 16 : 32;                    // panel columns per slab
+    constexpr int EB = PREC == 1 ? 4 : 2;                       // bytes per element
+    constexpr int CHUNKS = 2 * BM * BKD * EB / 256;             // 256-byte copies per slab (both operands)
+    constexpr int PER = CHUNKS / 4;                             // per wave
+    constexpr int NKK = PREC == 1 ? BKD / 4 : 1;                // MFMA K-steps per slab
+    static_assert((STAGES - 2) * PER < 64, "outstanding copies exceed vmcnt");
+    static_assert(PER % NKK == 0, "copies per K-step");
+    __shared__ __attribute__((aligned(16))) char Ls[STAGES][2][BM * BKD * EB];
+
+    if (d.info && *d.info) return;
+    const int64_t t = xcd_remap();
+    if (t >= tm.ntiles) return;
+    int64_t bi, bj;
+    if (!decode_tile(tm, t, bi, bj)) return;
+    bi = __builtin_amdgcn_readfirstlane((int)bi);
+    bj = __builtin_amdgcn_readfirstlane((int)bj);
+    const int64_t i0 = bi * BM, j0 = bj * BM;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave & 1, wn = wave >> 1;
+    double *C = d.C;
+    const int nk = (int)((d.K + BKD - 1) / BKD);
+    const char *Q = static_cast<const char *>(Qv);
+    const uint32_t voff = 4u * (uint32_t)lane;
+
+    // copy q of this wave for slab `slab` into stage st: chunk c = wave + 4 q
+    auto copy1 = [&](int slab, int st, int q) {
+        const int c = wave + 4 * q;
+        const int op = c / (CHUNKS / 2), cc = c % (CHUNKS / 2);
+        const int64_t row0 = qrow0 + (op ? j0 : i0);
+        const char *src;
+        if (PREC == 1) {  // chunk cc: column cc / 2, rows 64 (cc % 2) ..
+            const int col = cc >> 1, half = cc & 1;
+            src = Q + 4 * ((int64_t)(slab * BKD + col) * Mp + row0 + 64 * half);
+        } else {          // chunk cc: rows 4 cc .. 4 cc + 3 of the 32-column slab
+            src = Q + 2 * (((int64_t)slab * Mp + row0) * 32 + 128 * (int64_t)cc);
+        }
+        lds_dma_dword(reinterpret_cast<const double *>(src), voff,
+                      (uint32_t)(uintptr_t)&Ls[st][op][256 * cc]);
+    };
+
+#pragma unroll
+    for (int s = 0; s < STAGES - 1; ++s)
+        if (s < nk) {
+#pragma unroll
+            for (int q = 0; q < PER; ++q) copy1(s, s, q);
+        }
+
+    v4f acc[FM][FN];
+#pragma unroll
+    for (int m = 0; m < FM; ++m)
+#pragma unroll
+        for (int n = 0; n < FN; ++n) acc[m][n] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    int st = 0;
+    for (int k = 0; k < nk; ++k) {
+        const int later = nk - 1 - k;
+        wait_slabs<PER, STAGES - 2>(later < STAGES - 2 ? later : STAGES - 2);
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        const bool more = k + STAGES - 1 < nk;
+        const int ns = k + STAGES - 1, nst = st == 0 ? STAGES - 1 : st - 1;
+#pragma unroll
+        for (int kk = 0; kk < NKK; ++kk) {
+            if (PREC == 1) {
+                const float *A = reinterpret_cast<const float *>(&Ls[st][0][0]);
+                const float *B = reinterpret_cast<const float *>(&Ls[st][1][0]);
+                float a[FM], b[FN];
+#pragma unroll
+                for (int m = 0; m < FM; ++m) a[m] = A[(4 * kk + (lane >> 4)) * BM + wm * WTM + m * 16 + (lane & 15)];
+#pragma unroll
+                for (int n = 0; n < FN; ++n) b[n] = B[(4 * kk + (lane >> 4)) * BM + wn * WTM + n * 16 + (lane & 15)];
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                    for (int n = 0; n < FN; ++n)
+                        acc[q][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b[n], acc[q][n], 0, 0, 0);
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (more) copy1(ns, nst, kk * 4 + q);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            } else {
+                const __bf16 *A = reinterpret_cast<const __bf16 *>(&Ls[st][0][0]);
+                const __bf16 *B = reinterpret_cast<const __bf16 *>(&Ls[st][1][0]);
+                v8bf a[FM], b[FN];
+#pragma unroll
+                for (int m = 0; m < FM; ++m)
+                    a[m] = *reinterpret_cast<const v8bf *>(&A[(wm * WTM + m * 16 + (lane & 15)) * 32 + 8 * (lane >> 4)]);
+#pragma unroll
+                for (int n = 0; n < FN; ++n)
+                    b[n] = *reinterpret_cast<const v8bf *>(&B[(wn * WTM + n * 16 + (lane & 15)) * 32 + 8 * (lane >> 4)]);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int q = 0; q < PER; ++q) {
+                    const int m = q >> 2, n = q & 3;
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[n], acc[m][n], 0, 0, 0);
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (more) copy1(ns, nst, q);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+        }
+        st = st + 1 == STAGES ? 0 : st + 1;
+    }
+
+    const int64_t rb0 = i0 + wm * WTM + 4 * (lane >> 4);
+    const int64_t cb0 = j0 + wn * WTM + (lane & 15);
+    const bool interior = (i0 + BM <= d.M) && (j0 + BM <= d.N) && (i0 >= j0 + BM);
+#pragma unroll
+    for (int m = 0; m < FM; ++m) {
+        double cv[FN][4];
+#pragma unroll
+        for (int n = 0; n < FN; ++n)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gi = rb0 + m * 16 + r, gj = cb0 + n * 16;
+                const bool ok = interior || (gi < d.M && gj < d.N && gi >= gj);
+                cv[n][r] = C[ok ? gi + gj * d.ldc : 0];
+            }
+#pragma unroll
+        for (int n = 0; n < FN; ++n)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gi = rb0 + m * 16 + r, gj = cb0 + n * 16;
+                const bool ok = interior || (gi < d.M && gj < d.N && gi >= gj);
+                if (ok) C[gi + gj * d.ldc] = cv[n][r] - (double)acc[m][n][r];
+            }
+    }
+}
+
 // Super-tiles are SG x SG tiles, narrowed to the grid when it has fewer than
 // SG tile columns.  A lower map needs square super-tiles unless a single
 // super-tile column covers every tile column.
@@ -710,6 +874,61 @@ hipError_t launch_syrk_lower(hipStream_t s, gp_prec_t prec, int band, const doub
         if (e != hipSuccess) return e;
     }
     return prec == GP_FP32_TRAIL ? run_lowp<1>(s, d, b) : run_lowp<2>(s, d, b);
+}
+
+int64_t packed_rows(int64_t M) { return ((M + 127) / 128 + 1) * 128; }
+
+size_t packed_panel_bytes(int64_t M, int64_t K) {
+    return (size_t)packed_rows(M) * (size_t)(((K + 31) / 32) * 32) * sizeof(float);
+}
+
+hipError_t launch_pack_panel(hipStream_t s, gp_prec_t prec, const double *P, int64_t ldp, int64_t M, int64_t K,
+                             void *Q) {
+    if (M <= 0 || K <= 0) return hipSuccess;
+    const int64_t Mp = packed_rows(M);
+    const int64_t total = prec == GP_FP32_TRAIL ? Mp * K : Mp * ((K + 31) / 32) * 32;
+    const int64_t g = (total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096;
+    if (prec == GP_FP32_TRAIL)
+        hipLaunchKernelGGL((k_pack_panel<1>), dim3((unsigned)g), dim3(256), 0, s, P, ldp, M, Mp, K, Q);
+    else
+        hipLaunchKernelGGL((k_pack_panel<2>), dim3((unsigned)g), dim3(256), 0, s, P, ldp, M, Mp, K, Q);
+    return hipGetLastError();
+}
+
+hipError_t launch_syrk_packed(hipStream_t s, gp_prec_t prec, int band, const double *P, int64_t ldp, const void *Q,
+                              int64_t Mpack, int64_t qrow0, double *C, int64_t ldc, int64_t M, int64_t N, int64_t K,
+                              const int32_t *info) {
+    if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+    GemmDesc d{};
+    d.A = P; d.lda = ldp; d.B = P; d.ldb = ldp; d.C = C; d.ldc = ldc;
+    d.M = M; d.N = N; d.K = K; d.alpha = -1.0; d.beta = 1.0;
+    d.ta = 0; d.tb = 1; d.lower = 1; d.batch = 1; d.info = info;
+    const int64_t b = band > 0 ? band : 0;
+    if (b > 0) {  // FP64 on the first `band` tile diagonals
+        TileMap tb = make_map(M, N, 128, 128, 1);
+        tb.bandmode = 1;
+        tb.band = b;
+        tb.ntiles = tb.ntn * b;
+        const int64_t g = ((tb.ntiles + 7) / 8) * 8;
+        if (K % 8 == 0)
+            hipLaunchKernelGGL((k_syrk_dma<4, 8, 1>), dim3((unsigned)g), dim3(256), 0, s, d, tb);
+        else
+            hipLaunchKernelGGL((k_gemm_f64<128, 128, 2, 2, 0, 1, 1>), dim3((unsigned)g), dim3(256), 0, s, d, tb);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    TileMap tm = make_map(M, N, 128, 128, 1);
+    tm.sgm = tm.sgn = 1;
+    tm.ntiles = tm.ntn * (tm.ntn + 1) / 2 + (tm.ntm - tm.ntn) * tm.ntn;
+    tm.bandmode = b > 0 ? 2 : 0;
+    tm.band = b;
+    const int64_t g = ((tm.ntiles + 7) / 8) * 8;
+    const int64_t Mp = packed_rows(Mpack);
+    if (prec == GP_FP32_TRAIL)
+        hipLaunchKernelGGL((k_syrk_pk<1, 1>), dim3((unsigned)g), dim3(256), 0, s, d, tm, Q, Mp, qrow0);
+    else
+        hipLaunchKernelGGL((k_syrk_pk<2, 1>), dim3((unsigned)g), dim3(256), 0, s, d, tm, Q, Mp, qrow0);
+    return hipGetLastError();
 }
 
 hipError_t launch_panel_solve(hipStream_t s, double *A, int64_t lda, const double *Winv, int64_t M,
