@@ -52,7 +52,7 @@ CovParams cov_params(const gp_theta_t &th, int dim) {
 struct Layout {
     size_t dinv = 0, sync = 0, z = 0, vec2 = 0, vec3 = 0, vec4 = 0, vec5 = 0, part = 0, big1 = 0, big2 = 0,
            big3 = 0, irst = 0, perm = 0, keys = 0, box = 0, xp = 0, yp = 0, mup = 0, pbuf = 0, vinv = 0,
-           vtmp = 0, qbuf = 0, total = 0;
+           vtmp = 0, qbuf = 0, big4 = 0, total = 0;
 };
 
 // Buffers of the panel steps of the factorisation (null when n <= NB).
@@ -152,8 +152,9 @@ Layout layout(gp_handle_t h, gp_op_t op, int64_t n, int64_t m, gp_prec_t prec) {
             L.mup = take(vec);
         }
         if (op == GP_OP_LOGLIK_GRAD) {
-            // W = L^{-1} (n x n, ld n) and the product buffer of the blocked inverse
+            // W = L^{-1} and V = W^T (n x n, ld n) and the product buffer of the blocked inverse
             L.big1 = take(sizeof(double) * (size_t)(n > 0 ? n : 1) * (size_t)(n > 0 ? n : 1));
+            L.big4 = take(sizeof(double) * (size_t)(n > 0 ? n : 1) * (size_t)(n > 0 ? n : 1));
             L.big3 = take(sizeof(double) * trtri_tmp_elems(n));
         }
         break;
@@ -298,6 +299,51 @@ int trtri_lower(hipStream_t s, int64_t n, const double *L, int64_t ldl, const do
     return GP_OK;
 }
 
+// W = L^{-1} (lower) and V = W^T (upper), both n x n with ld n, by recursive
+// doubling on the NT MFMA kernel (products of the form A B^T with both
+// operands column-major).  Per level and node, whose two halves are already
+// inverted (W11, W22 and their transposes V11, V22):
+//   Tt  = V11 L21^T      (= (L21 W11)^T, h x h2; V11 is zero left of its diagonal)
+//   W21 = -W22 Tt^T      (W22 is zero right of its diagonal)
+//   V12 = W21^T
+// T holds trtri_tmp_elems(n) doubles.
+int trtri_nt(hipStream_t s, int64_t n, const double *L, int64_t ldl, const double *dinv, double *W, double *V,
+             double *T, const int32_t *info) {
+    const int64_t ld = n;
+    HIPCHK(launch_fill(s, W, sizeof(double) * (size_t)n * (size_t)n));
+    HIPCHK(launch_fill(s, V, sizeof(double) * (size_t)n * (size_t)n));
+    HIPCHK(launch_place_dinv(s, n, dinv, W, ld, 0));
+    HIPCHK(launch_place_dinv(s, n, dinv, V, ld, 1));
+    for (int64_t S = 2 * DB; S / 2 < n; S *= 2) {
+        const int64_t h = S / 2;
+        auto level = [&](int64_t o, int64_t h2, int64_t batch) -> hipError_t {
+            GemmDesc a{};
+            a.A = V + o * (1 + ld); a.lda = ld; a.sA = S * (1 + ld);
+            a.B = L + (o + h) + o * ldl; a.ldb = ldl; a.sB = S * (1 + ldl);
+            a.C = T; a.ldc = h; a.sC = h * h2;
+            a.M = h; a.N = h2; a.K = h; a.alpha = 1.0; a.beta = 0.0;
+            a.klo_i = 1; a.batch = batch; a.info = info;
+            hipError_t e = launch_gemm_nt_dma(s, a);
+            if (e != hipSuccess) return e;
+            GemmDesc b{};
+            b.A = W + (o + h) * (1 + ld); b.lda = ld; b.sA = S * (1 + ld);
+            b.B = T; b.ldb = h; b.sB = h * h2;
+            b.C = W + (o + h) + o * ld; b.ldc = ld; b.sC = S * (1 + ld);
+            b.M = h2; b.N = h; b.K = h2; b.alpha = -1.0; b.beta = 0.0;
+            b.khi_i = 1; b.batch = batch; b.info = info;
+            e = launch_gemm_nt_dma(s, b);
+            if (e != hipSuccess) return e;
+            return launch_transpose_copy(s, h2, h, W + (o + h) + o * ld, ld, S * (1 + ld), V + o + (o + h) * ld, ld,
+                                         S * (1 + ld), batch);
+        };
+        const int64_t nfull = n / S;
+        if (nfull > 0) HIPCHK(level(0, h, nfull));
+        const int64_t o = nfull * S, h2 = n - o - h;
+        if (h2 > 0) HIPCHK(level(o, h2, 1));
+    }
+    return GP_OK;
+}
+
 // CU masks: bit c of word c / 32 enables compute unit c.  The reserved units
 // are spread evenly over the index range so that each XCD keeps the same
 // number of units for the trailing update.
@@ -391,7 +437,7 @@ int potrf_impl(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda,
         g.C = A + c1 + c0 * lda; g.ldc = lda;
         g.M = M; g.N = K; g.K = K; g.alpha = 1.0; g.beta = 0.0;
         g.batch = 1; g.info = info;
-        HIPCHK(launch_gemm_f64(st, g));
+        HIPCHK(launch_gemm_nt_dma(st, g));
         return GP_OK;
     };
 
@@ -499,19 +545,14 @@ int trsm_impl(gp_handle_t h, int trans, int64_t n, int64_t nrhs, const double *L
 // from the factorisation, then per level W21 = -W22 (L21 W11)), followed by
 // C^{-1} = W^T W restricted to the lower triangle (K runs from the tile row,
 // as rows of W above it are zero).  Both steps run on the matrix cores.
-int cinv_impl(gp_handle_t h, int64_t n, double *C, int64_t ldc, const double *dinv, double *W, double *T,
-              const int32_t *info) {
+int cinv_impl(gp_handle_t h, int64_t n, double *C, int64_t ldc, const double *dinv, double *W, double *V,
+              double *T, const int32_t *info) {
     hipStream_t s = h->stream;
-    const int64_t ldw = n;
-    int rc = trtri_lower(s, n, C, ldc, dinv, W, T, info);
+    int rc = trtri_nt(s, n, C, ldc, dinv, W, V, T, info);
     if (rc) return rc;
-    GemmDesc d{};
-    d.A = W; d.lda = ldw; d.ta = 1;
-    d.B = W; d.ldb = ldw; d.tb = 0;
-    d.C = C; d.ldc = ldc;
-    d.M = n; d.N = n; d.K = n; d.alpha = 1.0; d.beta = 0.0;
-    d.lower = 1; d.klo_i = 1; d.batch = 1; d.info = info;
-    HIPCHK(launch_gemm_f64(s, d));
+    // C^{-1} = W^T W = V V^T (lower triangle), V zero left of its diagonal:
+    // a SYRK whose tile rows i0.. start at k = i0
+    HIPCHK(launch_syrk_dma(s, V, n, C, ldc, n, n, 1.0, 0.0, 1, info));
     return GP_OK;
 }
 
@@ -580,7 +621,8 @@ int loglik_core(gp_handle_t h, gp_op_t op, gp_theta_t th, gp_prec_t prec, int64_
     }
     if (grad3) {
         if (n > 0) {
-            rc = cinv_impl(h, n, C, ldc, dinv, at<double>(ws, lay.big1), at<double>(ws, lay.big3), info);
+            rc = cinv_impl(h, n, C, ldc, dinv, at<double>(ws, lay.big1), at<double>(ws, lay.big4),
+                           at<double>(ws, lay.big3), info);
             if (rc) return rc;
         }
         double *part = at<double>(ws, lay.part);

@@ -363,6 +363,11 @@ hipError_t launch_pack_panel(hipStream_t s, gp_prec_t prec, const double *P, int
 hipError_t launch_syrk_packed(hipStream_t s, gp_prec_t prec, int band, const double *P, int64_t ldp, const void *Q,
                               int64_t Mpack, int64_t qrow0, double *C, int64_t ldc, int64_t M, int64_t N, int64_t K,
                               const int32_t *info);
+// C = beta C + alpha P P^T on the lower triangle of the M x M matrix C, P
+// M x K (ld ldp), on the direct-to-LDS MFMA kernel; klo_i: P is zero left of
+// its diagonal (P[i, k] = 0 for k < i), so tile rows i0.. start at k = i0.
+hipError_t launch_syrk_dma(hipStream_t s, const double *P, int64_t ldp, double *C, int64_t ldc, int64_t M, int64_t K,
+                           double alpha, double beta, int klo_i, const int32_t *info);
 // Algorithmic flops of a lower-trapezoid update of M rows x N columns (N <= M)
 // with inner dimension K: 2 K (N M - N (N - 1) / 2).
 inline double syrk_flops(int64_t M, int64_t N, int64_t K) {
@@ -391,7 +396,14 @@ hipError_t launch_colreduce(hipStream_t s, int mode, int64_t n, int64_t m, const
                             const double *v, double base, double *out);
 hipError_t launch_copy2d(hipStream_t s, int64_t rows, int64_t cols, const double *src, int64_t lds, double *dst,
                          int64_t ldd);
-hipError_t launch_place_dinv(hipStream_t s, int64_t n, const double *dinv, double *W, int64_t ldw);
+hipError_t launch_place_dinv(hipStream_t s, int64_t n, const double *dinv, double *W, int64_t ldw, int trans = 0);
+// dst = src^T for a rows x cols block (batch blocks at element strides sstr / dstr).
+hipError_t launch_transpose_copy(hipStream_t s, int64_t rows, int64_t cols, const double *src, int64_t lds,
+                                 int64_t sstr, double *dst, int64_t ldd, int64_t dstr, int64_t batch);
+// The FP64 direct-to-LDS MFMA kernel on a general product
+//   C = beta C + alpha A B^T  (A: M x K, B: N x K, both column-major),
+// with GemmDesc's lower / K-range / batch fields (ta = 0, tb = 1 form).
+hipError_t launch_gemm_nt_dma(hipStream_t s, const GemmDesc &d);
 hipError_t launch_grad_finish(hipStream_t s, int nparts, const double *partials, double *grad3,
                               const int32_t *info);
 // iterative refinement control (state: 8 doubles; done: int32 skip flag)

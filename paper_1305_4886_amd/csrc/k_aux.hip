@@ -50,13 +50,34 @@ __global__ __launch_bounds__(256) void k_copy2d(int64_t rows, int64_t cols, cons
 }
 
 // Diagonal 64-blocks of W from the stored block inverses (column-major, ld DB).
-__global__ __launch_bounds__(256) void k_place_dinv(int64_t n, const double *dinv, double *W, int64_t ldw) {
+__global__ __launch_bounds__(256) void k_place_dinv(int64_t n, const double *dinv, double *W, int64_t ldw,
+                                                    int trans) {
     const int64_t b = blockIdx.x;
     const int64_t b0 = b * DB;
     const double *src = dinv + b * DB * DB;
     for (int e = threadIdx.x; e < DB * DB; e += 256) {
         const int i = e & (DB - 1), j = e >> 6;
-        if (b0 + i < n && b0 + j < n) W[(b0 + i) + (b0 + j) * ldw] = src[i + j * DB];
+        if (b0 + i < n && b0 + j < n) W[(b0 + i) + (b0 + j) * ldw] = trans ? src[j + i * DB] : src[i + j * DB];
+    }
+}
+
+// dst[j + i ldd] = src[i + j lds] for i < rows, j < cols (batch z: strides
+// sstr, dstr), 64 x 64 tiles through LDS.
+__global__ __launch_bounds__(256) void k_transpose_copy(int64_t rows, int64_t cols, const double *src, int64_t lds,
+                                                        int64_t sstr, double *dst, int64_t ldd, int64_t dstr) {
+    __shared__ double Tt[64][65];
+    const double *S = src + (int64_t)blockIdx.z * sstr;
+    double *D = dst + (int64_t)blockIdx.z * dstr;
+    const int64_t r0 = (int64_t)blockIdx.x * 64, c0 = (int64_t)blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int c = ty; c < 64; c += 4) {
+        const int64_t i = r0 + tx, j = c0 + c;
+        Tt[c][tx] = (i < rows && j < cols) ? S[i + j * lds] : 0.0;
+    }
+    __syncthreads();
+    for (int c = ty; c < 64; c += 4) {  // D(c0 + tx, r0 + c) = S(r0 + c, c0 + tx)
+        const int64_t j = c0 + tx, i = r0 + c;
+        if (i < rows && j < cols) D[j + i * ldd] = Tt[tx][c];
     }
 }
 
@@ -92,6 +113,7 @@ __global__ void k_tune_fill(double *A, int64_t lda, int64_t n) {
             A[i + j * lda] = exp(-sc * (double)(i - j)) + (i == j ? 1.0 : 0.0);
 }
 
+
 }  // namespace
 
 hipError_t launch_colreduce(hipStream_t s, int mode, int64_t n, int64_t m, const double *M, int64_t ld,
@@ -116,9 +138,17 @@ hipError_t launch_copy2d(hipStream_t s, int64_t rows, int64_t cols, const double
     return hipGetLastError();
 }
 
-hipError_t launch_place_dinv(hipStream_t s, int64_t n, const double *dinv, double *W, int64_t ldw) {
+hipError_t launch_place_dinv(hipStream_t s, int64_t n, const double *dinv, double *W, int64_t ldw, int trans) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_place_dinv, dim3((unsigned)((n + DB - 1) / DB)), dim3(256), 0, s, n, dinv, W, ldw);
+    hipLaunchKernelGGL(k_place_dinv, dim3((unsigned)((n + DB - 1) / DB)), dim3(256), 0, s, n, dinv, W, ldw, trans);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_copy(hipStream_t s, int64_t rows, int64_t cols, const double *src, int64_t lds,
+                                 int64_t sstr, double *dst, int64_t ldd, int64_t dstr, int64_t batch) {
+    if (rows <= 0 || cols <= 0 || batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_transpose_copy, dim3((unsigned)((rows + 63) / 64), (unsigned)((cols + 63) / 64), (unsigned)batch),
+                       dim3(256), 0, s, rows, cols, src, lds, sstr, dst, ldd, dstr);
     return hipGetLastError();
 }
 

@@ -308,7 +308,9 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmDesc d, TileMap tm) {
 // and the LDS reads of step kk + 1 are issued before the MFMAs of step kk, so
 // a wave keeps its matrix pipe busy while it feeds the ring.  Rows past the
 // matrix are clamped to its last row: they feed only output rows / columns
-// that are never stored.  Requires K % BKD == 0.
+// that are never stored; columns past K are zeroed in LDS.  With d.klo_i the
+// K loop of a tile starts at its first row (an operand that is zero left of
+// its diagonal, such as the transpose of a lower-triangular matrix).
 // ---------------------------------------------------------------------------
 template <int N>
 GP_DEV void wait_vmcnt() {
@@ -363,9 +365,21 @@ __global__ __launch_bounds__(256, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave & 1, wn = wave >> 1;
-    const double *P = d.A;
-    double *C = d.C;
-    const int nk = (int)(d.K / BKD);
+    const int64_t bz = blockIdx.y;
+    const double *A = d.A + bz * d.sA;
+    const double *B = d.B + bz * d.sB;
+    double *C = d.C + bz * d.sC;
+    // K range of this tile (operands are zero outside it by structure):
+    // slabs kf .. kf + nk - 1; the last one holds ktail <= BKD columns below K
+    int64_t klo = 0, khi = d.K;
+    if (d.klo_i && i0 > klo) klo = i0;
+    if (d.klo_j && j0 > klo) klo = j0;
+    if (d.khi_i && i0 + BM < khi) khi = i0 + BM;
+    if (d.khi_j && j0 + BM < khi) khi = j0 + BM;
+    const int kf = (int)(klo / BKD);
+    const int kl = khi > klo ? (int)((khi + BKD - 1) / BKD) : kf;
+    const int nk = kl - kf;
+    const int ktail = (int)(d.K - (int64_t)(kl - 1) * BKD);
 
     uint32_t offA[4], offB[4];
 #pragma unroll
@@ -379,11 +393,12 @@ __global__ __launch_bounds__(256, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
     // copy q (0..7) of column `part` of slab `slab`: q < 4 operand A rows 32 q.., else B
     auto copy1 = [&](int slab, int st, int part, int q) {
         const int kk = wave + 4 * part;
-        const double *col = P + ((int64_t)slab * BKD + kk) * d.lda;
+        int64_t kc = (int64_t)(kf + slab) * BKD + kk;
+        if (kc >= d.K) kc = d.K - 1;  // tail columns: any valid address, zeroed in LDS below
         if (q < 4)
-            lds_dma_dword(col, offA[q], (uint32_t)(uintptr_t)&Ls[st][0][kk][32 * q]);
+            lds_dma_dword(A + kc * d.lda, offA[q], (uint32_t)(uintptr_t)&Ls[st][0][kk][32 * q]);
         else
-            lds_dma_dword(col, offB[q - 4], (uint32_t)(uintptr_t)&Ls[st][1][kk][32 * (q - 4)]);
+            lds_dma_dword(B + kc * d.ldb, offB[q - 4], (uint32_t)(uintptr_t)&Ls[st][1][kk][32 * (q - 4)]);
     };
 
 #pragma unroll
@@ -410,6 +425,14 @@ __global__ __launch_bounds__(256, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
         asm volatile("" ::: "memory");
         const bool more = k + STAGES - 1 < nk;
         const int ns = k + STAGES - 1, nst = st == 0 ? STAGES - 1 : st - 1;
+        if (k == nk - 1 && ktail < BKD) {  // columns past K contribute zero (uniform branch)
+            const int nz = (BKD - ktail) * BM;
+            for (int e = tid; e < 2 * nz; e += 256) {
+                const int op = e >= nz, r = e - op * nz;
+                Ls[st][op][ktail + r / BM][r % BM] = 0.0;
+            }
+            __syncthreads();
+        }
         double a[FM], b[FN];
 #pragma unroll
         for (int m = 0; m < FM; ++m) a[m] = Ls[st][0][(lane >> 4)][wm * WTM + m * 16 + (lane & 15)];
@@ -449,7 +472,8 @@ __global__ __launch_bounds__(256, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
     // D layout: lane l, register r holds row l / 16 + 4 r, column l % 16.
     const int64_t rb0 = i0 + wm * WTM + (lane >> 4);
     const int64_t cb0 = j0 + wn * WTM + (lane & 15);
-    const bool interior = (i0 + BM <= d.M) && (j0 + BM <= d.N) && (i0 >= j0 + BM);
+    const bool interior = (i0 + BM <= d.M) && (j0 + BM <= d.N) && (!d.lower || i0 >= j0 + BM);
+    const bool use_c = d.beta != 0.0;
 #pragma unroll
     for (int m = 0; m < FM; ++m) {
         double cv[FN][4];
@@ -458,15 +482,16 @@ __global__ __launch_bounds__(256, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t gi = rb0 + m * 16 + 4 * r, gj = cb0 + n * 16;
-                const bool ok = interior || (gi < d.M && gj < d.N && gi >= gj);
-                cv[n][r] = C[ok ? gi + gj * d.ldc : 0];
+                const bool ok = use_c && (interior || (gi < d.M && gj < d.N && (!d.lower || gi >= gj)));
+                const double v = C[ok ? gi + gj * d.ldc : 0];
+                cv[n][r] = ok ? v : 0.0;
             }
 #pragma unroll
         for (int n = 0; n < FN; ++n)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t gi = rb0 + m * 16 + 4 * r, gj = cb0 + n * 16;
-                const bool ok = interior || (gi < d.M && gj < d.N && gi >= gj);
+                const bool ok = interior || (gi < d.M && gj < d.N && (!d.lower || gi >= gj));
                 if (ok) C[gi + gj * d.ldc] = fma(d.beta, cv[n][r], d.alpha * acc[m][n][r]);
             }
     }
@@ -845,12 +870,12 @@ namespace {
 // LDS stages of 8 panel columns (64 KB: two workgroups per CU).
 template <int TAG>
 hipError_t run_dma(hipStream_t s, const GemmDesc &d) {
-    if (d.M <= 0 || d.N <= 0 || d.K <= 0) return hipSuccess;
-    TileMap tm = make_map(d.M, d.N, 128, 128, 1);
+    if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return hipSuccess;
+    TileMap tm = make_map(d.M, d.N, 128, 128, d.lower);
     tm.sgm = tm.sgn = 1;
-    tm.ntiles = tm.ntn * (tm.ntn + 1) / 2 + (tm.ntm - tm.ntn) * tm.ntn;
+    tm.ntiles = d.lower ? tm.ntn * (tm.ntn + 1) / 2 + (tm.ntm - tm.ntn) * tm.ntn : tm.ntm * tm.ntn;
     const int64_t g = ((tm.ntiles + 7) / 8) * 8;
-    hipLaunchKernelGGL((k_syrk_dma<4, 8, TAG>), dim3((unsigned)g), dim3(256), 0, s, d, tm);
+    hipLaunchKernelGGL((k_syrk_dma<4, 8, TAG>), dim3((unsigned)g, (unsigned)d.batch), dim3(256), 0, s, d, tm);
     return hipGetLastError();
 }
 
@@ -929,6 +954,17 @@ hipError_t launch_syrk_packed(hipStream_t s, gp_prec_t prec, int band, const dou
     else
         hipLaunchKernelGGL((k_syrk_pk<2, 1>), dim3((unsigned)g), dim3(256), 0, s, d, tm, Q, Mp, qrow0);
     return hipGetLastError();
+}
+
+hipError_t launch_gemm_nt_dma(hipStream_t s, const GemmDesc &d) { return run_dma<0>(s, d); }
+
+hipError_t launch_syrk_dma(hipStream_t s, const double *P, int64_t ldp, double *C, int64_t ldc, int64_t M, int64_t K,
+                           double alpha, double beta, int klo_i, const int32_t *info) {
+    GemmDesc d{};
+    d.A = P; d.lda = ldp; d.B = P; d.ldb = ldp; d.C = C; d.ldc = ldc;
+    d.M = M; d.N = M; d.K = K; d.alpha = alpha; d.beta = beta;
+    d.ta = 0; d.tb = 1; d.lower = 1; d.klo_i = klo_i; d.batch = 1; d.info = info;
+    return run_dma<0>(s, d);
 }
 
 hipError_t launch_panel_solve(hipStream_t s, double *A, int64_t lda, const double *Winv, int64_t M,
