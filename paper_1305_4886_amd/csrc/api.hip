@@ -124,7 +124,7 @@ Layout layout(gp_handle_t h, gp_op_t op, int64_t n, int64_t m, gp_prec_t prec) {
         break;
     case GP_OP_TRSV:
         L.dinv = take(sizeof(double) * DB * DB * (size_t)nb);
-        L.sync = take(sizeof(int) * (size_t)(nb + 2));
+        L.sync = take(trsv_work_bytes(n));
         break;
     case GP_OP_TRSM:
         L.dinv = take(sizeof(double) * DB * DB * (size_t)nb);
@@ -134,7 +134,7 @@ Layout layout(gp_handle_t h, gp_op_t op, int64_t n, int64_t m, gp_prec_t prec) {
     case GP_OP_LOGLIK_GRAD:
         L.dinv = take(sizeof(double) * DB * DB * (size_t)nb);
         take_panel();
-        L.sync = take(sizeof(int) * (size_t)(nb + 2));
+        L.sync = take(trsv_work_bytes(n));
         L.z = take(vec);     // L^{-1} b
         L.vec2 = take(vec);  // x = C^{-1} b (evaluation order)
         L.vec3 = take(vec);  // b = y - mu (evaluation order)

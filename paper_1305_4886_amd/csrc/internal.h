@@ -381,8 +381,11 @@ hipError_t launch_panel_solve(hipStream_t s, double *A, int64_t lda, const doubl
 hipError_t launch_diag_potrf(hipStream_t s, double *A, int64_t lda, int jb, double *Winv,
                              int32_t *info, int64_t col0);
 hipError_t launch_diag_inv(hipStream_t s, const double *L, int64_t ldl, int64_t n, double *dinv);
-hipError_t launch_trsv(hipStream_t s, int trans, const double *L, int64_t ldl, double *x,
-                       int64_t n, const double *dinv, int *sync, const int32_t *info);
+// Work area of a triangular solve: trsv_work_bytes(n) bytes (counters and a
+// mailbox of n doubles); the abort flag is its int [1].
+size_t trsv_work_bytes(int64_t n);
+hipError_t launch_trsv(hipStream_t s, int trans, const double *L, int64_t ldl, double *x, int64_t n,
+                       const double *dinv, void *work, const int32_t *info);
 hipError_t launch_sub_mu(hipStream_t s, int64_t n, const double *y, const double *mu, double *z);
 hipError_t launch_copy_vec(hipStream_t s, int64_t n, const double *a, double *b);
 hipError_t launch_loglik_reduce(hipStream_t s, int64_t n, const double *L, int64_t ldl,

@@ -116,20 +116,48 @@ GP_DEV double xr_reduce16(double *p, int lane) {
     return v;
 }
 
-// sync layout (ints): [0] ticket, [1] abort, [2 + b] flag of block b.
-//
+// Work area of the solves: ints [0] ticket, [1] abort, then (at byte 256) a
+// mailbox of one double per row.  A solved value is published by storing it
+// into its mailbox slot, which holds a signalling-NaN sentinel until then;
+// a reader polls the slots it needs (relaxed agent-scope atomics, which the
+// hardware keeps coherent across XCDs), so each value carries its own ready
+// signal and no flag or cache-wide fence sits on the dependency chain.
+constexpr uint64_t MBOX_EMPTY = 0x7FF4DEADBEEF0000ull;
+
+GP_DEV double mbox_poll(const double *slot, int *abortf) {
+    const uint64_t *p = reinterpret_cast<const uint64_t *>(slot);
+    uint64_t v;
+    int spins = 0;
+    while ((v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == MBOX_EMPTY) {
+        if (__hip_atomic_load(abortf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > SPIN_LIMIT) {
+            __hip_atomic_store(abortf, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+    }
+    return __longlong_as_double((long long)v);
+}
+
+GP_DEV void mbox_put(double *slot, double v) {
+    __hip_atomic_store(reinterpret_cast<uint64_t *>(slot), (uint64_t)__double_as_longlong(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Forward solve, block blk (rows i0 .. i0 + 63):
 //   x_blk = Winv_blk (b_blk - sum_{j < blk} L[blk, j] x_j).
-// Far blocks j < blk - 1 are split over the 4 waves (lane = row, 512-byte
-// column loads).  The nearest block j = blk - 1, which decides the critical
-// path, is prefetched into registers (16 columns per wave) together with the
-// wave's 16 columns of Winv before any waiting starts.
+// Each workgroup takes a ticket (so the blocks it depends on belong to
+// workgroups already running).  Waves 1-3 take the far blocks j < blk - 1
+// (lane = row, 512-byte column loads, x_j broadcast by readlane) as their
+// values appear; wave 0 has the nearest block's 64 x 64 tile and the rows of
+// Winv in registers, so once the far sums are in, the critical path is one
+// poll of x_{blk-1}, two 64-term dot products per lane and the store.
 __global__ __launch_bounds__(256) void k_trsv_fwd(const double *L, int64_t ldl, double *x, int64_t n,
-                                                  const double *dinv, int *sync, const int32_t *info) {
+                                                  const double *dinv, int *sync, double *mbox,
+                                                  const int32_t *info) {
     __shared__ int s_blk;
-    __shared__ double part[4][DB];
-    __shared__ double rhs[DB];
-    __shared__ double sol[4][DB];
+    __shared__ double part[3][DB];
+    __shared__ double Ws[DB][DB + 1];
     if (info && *info) return;
     const int nblk = (int)((n + DB - 1) / DB);
     if (threadIdx.x == 0) s_blk = atomicAdd(&sync[0], 1);
@@ -137,64 +165,69 @@ __global__ __launch_bounds__(256) void k_trsv_fwd(const double *L, int64_t ldl, 
     const int blk = s_blk;
     if (blk >= nblk) return;
     int *abortf = &sync[1];
-    int *flags = &sync[2];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t i0 = (int64_t)blk * DB;
     const int64_t i = i0 + lane;
     const bool rv = i < n;
-    const double *W = dinv + (int64_t)blk * DB * DB;
-    double wreg[16], lnear[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) wreg[q] = W[lane + (16 * w + q) * DB];
-#pragma unroll
-    for (int q = 0; q < 16; ++q)
-        lnear[q] = (rv && blk >= 1) ? L[i + ((int64_t)(blk - 1) * DB + 16 * w + q) * ldl] : 0.0;
-    const double b = (rv && w == 0) ? x[i] : 0.0;
-    double acc = 0.0;
-    for (int jb = w; jb < blk - 1; jb += 4) {
-        if (lane == 0) wait_flag(&flags[jb], abortf);
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const double *Lc = L + i + (int64_t)jb * DB * ldl;
-        const double *xj = x + (int64_t)jb * DB;
-        if (rv) {
+    if (w > 0) {
+        double acc = 0.0;
+        for (int jb = w - 1; jb < blk - 1; jb += 3) {
+            const double *Lc = L + i + (int64_t)jb * DB * ldl;
+            const double xv = mbox_poll(&mbox[(int64_t)jb * DB + lane], abortf);
+            if (rv) {
 #pragma unroll 16
-            for (int c = 0; c < DB; ++c) acc = fma(Lc[(int64_t)c * ldl], xj[c], acc);
+                for (int c = 0; c < DB; ++c) acc = fma(Lc[(int64_t)c * ldl], rdlane(xv, c), acc);
+            }
         }
+        part[w - 1][lane] = acc;
+        __syncthreads();
+        return;
     }
+    const double *W = dinv + (int64_t)blk * DB * DB;
+#pragma unroll 8
+    for (int c = 0; c < DB; ++c) Ws[lane][c] = W[lane + c * DB];  // Ws[a][b] = Winv(a, b)
+    double lnear[DB];
+#pragma unroll
+    for (int c = 0; c < DB; ++c)
+        lnear[c] = (rv && blk >= 1) ? L[i + ((int64_t)(blk - 1) * DB + c) * ldl] : 0.0;
+    const double b = rv ? x[i] : 0.0;
+    __syncthreads();
+    double rhs = b - ((part[0][lane] + part[1][lane]) + part[2][lane]);
     if (blk >= 1) {
-        if (lane == 0) wait_flag(&flags[blk - 1], abortf);
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const double *xj = x + (int64_t)(blk - 1) * DB + 16 * w;
+        const double xv = mbox_poll(&mbox[(int64_t)(blk - 1) * DB + lane], abortf);
+        double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc = fma(lnear[q], xj[q], acc);
+        for (int c = 0; c < DB; c += 2) {
+            a0 = fma(lnear[c], rdlane(xv, c), a0);
+            a1 = fma(lnear[c + 1], rdlane(xv, c + 1), a1);
+        }
+        rhs -= a0 + a1;
     }
-    part[w][lane] = acc;
-    __syncthreads();
-    if (w == 0) rhs[lane] = rv ? b - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]) : 0.0;
-    __syncthreads();
-    double s = 0.0;
+    double z0 = 0.0, z1 = 0.0;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) s = fma(wreg[q], rhs[16 * w + q], s);
-    sol[w][lane] = s;
-    __syncthreads();
-    if (w == 0 && rv) x[i] = ((sol[0][lane] + sol[1][lane]) + sol[2][lane]) + sol[3][lane];
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) st_release_agent(&flags[blk], 1);
+    for (int c = 0; c < DB; c += 2) {
+        z0 = fma(Ws[lane][c], rdlane(rhs, c), z0);
+        z1 = fma(Ws[lane][c + 1], rdlane(rhs, c + 1), z1);
+    }
+    const double z = z0 + z1;
+    if (rv) {
+        x[i] = z;
+        mbox_put(&mbox[i], z);
+    }
 }
 
 // Backward solve x <- L^{-T} x, block blk (columns c0 .. c0 + 63 of L):
 //   x_blk = Winv_blk^T (b_blk - sum_{j > blk} L[j, blk]^T x_j).
-// Lane = row of a row block j; each lane keeps 64 column partial sums, so
-// every load is 64 contiguous rows of one column; a cross-lane exchange
-// reduces them once per wave.  The nearest block j = blk + 1 is prefetched.
+// Waves 1-3: far row blocks j > blk + 1, last first (their completion order):
+// lane = row of block j, 64 column partial sums per lane, 512-byte loads,
+// one cross-lane exchange per wave at the end.  Wave 0 (lane = column) keeps
+// its column of the nearest row block and of Winv in registers.
 __global__ __launch_bounds__(256) void k_trsv_trans(const double *L, int64_t ldl, double *x, int64_t n,
-                                                    const double *dinv, int *sync, const int32_t *info) {
+                                                    const double *dinv, int *sync, double *mbox,
+                                                    const int32_t *info) {
     __shared__ int s_t;
-    __shared__ double part[4][DB];
-    __shared__ double nearp[DB];
-    __shared__ double rhs[DB];
-    __shared__ double sol[4][DB];
+    __shared__ double part[3][DB];
+    __shared__ double Ws[DB][DB + 1];
     if (info && *info) return;
     const int nblk = (int)((n + DB - 1) / DB);
     if (threadIdx.x == 0) s_t = atomicAdd(&sync[0], 1);
@@ -203,64 +236,69 @@ __global__ __launch_bounds__(256) void k_trsv_trans(const double *L, int64_t ldl
     if (tk >= nblk) return;
     const int blk = nblk - 1 - tk;
     int *abortf = &sync[1];
-    int *flags = &sync[2];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t c0 = (int64_t)blk * DB;
     const int64_t col = c0 + lane;
     const bool cv = col < n;
-    const double *W = dinv + (int64_t)blk * DB * DB;
-    double wreg[16], lnear[16];
+    if (w > 0) {
+        // far blocks: full row blocks strictly below blk + 1, so this block's
+        // columns are all < n
+        double p[DB];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) wreg[q] = W[(16 * w + q) + lane * DB];
-    const bool has_near = blk + 1 < nblk;
-    const int64_t rn = (int64_t)(blk + 1) * DB + lane;  // row of the nearest block held by this lane
-    const bool rnv = has_near && rn < n;
+        for (int c = 0; c < DB; ++c) p[c] = 0.0;
+        for (int jb = nblk - w; jb >= blk + 2; jb -= 3) {
+            const int64_t row = (int64_t)jb * DB + lane;
+            if (row < n) {
+                const double *Lr = L + row + c0 * ldl;
+                const double xv = mbox_poll(&mbox[row], abortf);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) lnear[q] = rnv ? L[rn + (c0 + 16 * w + q) * ldl] : 0.0;
-    const double b = (cv && w == 0) ? x[col] : 0.0;
-    // far blocks: full blocks of rows strictly below blk + 1; this block's
-    // columns are then all < n
-    double p[DB];
-#pragma unroll
-    for (int c = 0; c < DB; ++c) p[c] = 0.0;
-    // visit far blocks in the order they complete (last block first)
-    for (int jb = nblk - 1 - w; jb >= blk + 2; jb -= 4) {
-        if (lane == 0) wait_flag(&flags[jb], abortf);
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const int64_t row = (int64_t)jb * DB + lane;
-        if (row < n) {
-            const double xv = x[row];
-            const double *Lr = L + row + c0 * ldl;
-#pragma unroll
-            for (int c = 0; c < DB; ++c) p[c] = fma(Lr[(int64_t)c * ldl], xv, p[c]);
+                for (int c = 0; c < DB; ++c) p[c] = fma(Lr[(int64_t)c * ldl], xv, p[c]);
+            }
         }
+        part[w - 1][lane] = xr_reduce64(p, lane);
+        __syncthreads();
+        return;
     }
-    part[w][lane] = xr_reduce64(p, lane);
+    const double *W = dinv + (int64_t)blk * DB * DB;
+    const bool has_near = blk + 1 < nblk;
+#pragma unroll 8
+    for (int c = 0; c < DB; ++c) Ws[lane][c] = W[lane + c * DB];  // Ws[a][b] = Winv(a, b)
+    double lcol[DB];
+#pragma unroll
+    for (int r = 0; r < DB; ++r) {
+        const int64_t row = (int64_t)(blk + 1) * DB + r;
+        lcol[r] = (has_near && row < n && cv) ? L[row + col * ldl] : 0.0;
+    }
+    const double b = cv ? x[col] : 0.0;
+    __syncthreads();
+    double rhs = b - ((part[0][lane] + part[1][lane]) + part[2][lane]);
     if (has_near) {
-        if (lane == 0) wait_flag(&flags[blk + 1], abortf);
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const double xv = rnv ? x[rn] : 0.0;
-        double v[16];
+        const int64_t rn = (int64_t)(blk + 1) * DB + lane;
+        const double xv = rn < n ? mbox_poll(&mbox[rn], abortf) : 0.0;
+        double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) v[q] = lnear[q] * xv;
-        const double sv = xr_reduce16(v, lane);
-        if (lane < 16) nearp[16 * w + lane] = sv;
-    } else if (lane < 16) {
-        nearp[16 * w + lane] = 0.0;
+        for (int r = 0; r < DB; r += 2) {
+            a0 = fma(lcol[r], rdlane(xv, r), a0);
+            a1 = fma(lcol[r + 1], rdlane(xv, r + 1), a1);
+        }
+        rhs -= a0 + a1;
     }
-    __syncthreads();
-    if (w == 0)
-        rhs[lane] = cv ? b - ((((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]) + nearp[lane]) : 0.0;
-    __syncthreads();
-    double s = 0.0;
+    double z0 = 0.0, z1 = 0.0;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) s = fma(wreg[q], rhs[16 * w + q], s);
-    sol[w][lane] = s;
-    __syncthreads();
-    if (w == 0 && cv) x[col] = ((sol[0][lane] + sol[1][lane]) + sol[2][lane]) + sol[3][lane];
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) st_release_agent(&flags[blk], 1);
+    for (int r = 0; r < DB; r += 2) {  // (Winv^T rhs)[lane] = sum_r Winv(r, lane) rhs_r
+        z0 = fma(Ws[r][lane], rdlane(rhs, r), z0);
+        z1 = fma(Ws[r + 1][lane], rdlane(rhs, r + 1), z1);
+    }
+    const double z = z0 + z1;
+    if (cv) {
+        x[col] = z;
+        mbox_put(&mbox[col], z);
+    }
+}
+
+__global__ void k_fill_u64(uint64_t *p, int64_t cnt, uint64_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) p[i] = v;
 }
 
 __global__ void k_fill_u32(uint32_t *p, int64_t cnt) {
@@ -341,16 +379,23 @@ hipError_t launch_fill(hipStream_t s, void *p, size_t bytes) {
     return hipGetLastError();
 }
 
+size_t trsv_work_bytes(int64_t n) { return 256 + sizeof(double) * (size_t)((n + DB - 1) / DB) * DB; }
+
 hipError_t launch_trsv(hipStream_t s, int trans, const double *L, int64_t ldl, double *x, int64_t n,
-                       const double *dinv, int *sync, const int32_t *info) {
+                       const double *dinv, void *work, const int32_t *info) {
     if (n <= 0) return hipSuccess;
     const int nblk = (int)((n + DB - 1) / DB);
-    hipError_t e = launch_fill(s, sync, sizeof(int) * (size_t)(nblk + 2));
+    int *sync = static_cast<int *>(work);
+    double *mbox = reinterpret_cast<double *>(static_cast<char *>(work) + 256);
+    hipError_t e = launch_fill(s, sync, 256);
     if (e != hipSuccess) return e;
+    const int64_t cnt = (int64_t)nblk * DB;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
+                       reinterpret_cast<uint64_t *>(mbox), cnt, MBOX_EMPTY);
     if (trans)
-        hipLaunchKernelGGL(k_trsv_trans, dim3((unsigned)nblk), dim3(256), 0, s, L, ldl, x, n, dinv, sync, info);
+        hipLaunchKernelGGL(k_trsv_trans, dim3((unsigned)nblk), dim3(256), 0, s, L, ldl, x, n, dinv, sync, mbox, info);
     else
-        hipLaunchKernelGGL(k_trsv_fwd, dim3((unsigned)nblk), dim3(256), 0, s, L, ldl, x, n, dinv, sync, info);
+        hipLaunchKernelGGL(k_trsv_fwd, dim3((unsigned)nblk), dim3(256), 0, s, L, ldl, x, n, dinv, sync, mbox, info);
     return hipGetLastError();
 }
 
