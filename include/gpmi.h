@@ -200,7 +200,10 @@ int gp_loglik_grad(gp_handle_t h, gp_theta_t th, gp_prec_t prec, int64_t n, int3
  * points Xs [dev, m x dim]:
  *   mean_dev[j] = mu + c_j^T alpha,
  *   var_dev[j]  = sigma^2 - |L^{-1} c_j|^2 (+ tau^2 if include_nugget),
- * c_j the cross-covariance column.  var is not clamped at 0. */
+ * c_j the cross-covariance column.  var is not clamped at 0.  The m x n
+ * cross-covariance is built transposed in the workspace and solved from the
+ * right (C*^T L^{-T}) on the matrix cores; mean and variance are compensated
+ * row sums. */
 int gp_krige(gp_handle_t h, gp_theta_t th, int64_t n, int64_t m, int32_t dim, const double *X,
              const double *Xs, const double *L, int64_t ldl, const double *alpha, double mu,
              double *mean_dev, double *var_dev, int32_t include_nugget, void *ws,

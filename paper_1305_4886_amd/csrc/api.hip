@@ -167,8 +167,9 @@ Layout layout(gp_handle_t h, gp_op_t op, int64_t n, int64_t m, gp_prec_t prec) {
         break;
     case GP_OP_KRIGE:
         L.dinv = take(sizeof(double) * DB * DB * (size_t)nb);
-        L.big1 = take(sizeof(double) * (size_t)(n > 0 ? n : 1) * (size_t)(m > 0 ? m : 1));
-        L.part = take(sizeof(double) * DB * (size_t)(m > 0 ? m : 1));
+        L.big1 = take(sizeof(double) * (size_t)(n > 0 ? n : 1) * (size_t)(m > 0 ? m : 1));  // C*^T, m x n
+        L.part = take(sizeof(double) * DB * (size_t)(m > 0 ? m : 1));                        // m x 64
+        L.big2 = take(sizeof(double) * 2 * (size_t)(m > 0 ? m : 1) * (size_t)(n > 0 ? rowreduce_chunks(n) : 1));
         break;
     default:
         break;
@@ -536,6 +537,40 @@ int trsm_impl(gp_handle_t h, int trans, int64_t n, int64_t nrhs, const double *L
             kb1 = kb0;
             (void)nblk;
         }
+    }
+    return GP_OK;
+}
+
+// ---- right-side solve Y <- Y L^{-T} (Y: m x n, column-major, ld m) --------
+// Left-looking by 64-column blocks on the NT matrix-core kernel (both
+// operands column-major with contiguous rows, as its direct-to-LDS copies
+// need): block d becomes (Y_d - sum_{k<d} X_k L_dk^T) Winv_d^T, with the
+// updates gathered per 256-column band so the large product has K = 256.
+// tmp holds m x 64 doubles.
+int trsm_right_lt(hipStream_t s, int64_t n, int64_t m, const double *L, int64_t ldl, double *Y, const double *dinv,
+                  double *tmp, const int32_t *info) {
+    const int64_t NBT = 256;
+    auto nt = [&](const double *A, int64_t lda, const double *B, int64_t ldb, double *C, int64_t M, int64_t N,
+                  int64_t K, double alpha, double beta) -> hipError_t {
+        GemmDesc d{};
+        d.A = A; d.lda = lda; d.B = B; d.ldb = ldb; d.C = C; d.ldc = m;
+        d.M = M; d.N = N; d.K = K; d.alpha = alpha; d.beta = beta;
+        d.ta = 0; d.tb = 1; d.batch = 1; d.info = info;
+        return launch_gemm_nt_dma(s, d);
+    };
+    if (n <= 0 || m <= 0) return GP_OK;
+    for (int64_t kb0 = 0; kb0 < n; kb0 += NBT) {
+        const int64_t kb1 = (kb0 + NBT < n) ? kb0 + NBT : n;
+        for (int64_t d = kb0; d < kb1; d += DB) {
+            const int64_t jb = (n - d) < DB ? (n - d) : DB;
+            HIPCHK(launch_copy2d(s, m, jb, Y + d * m, m, tmp, m));
+            // X_d = tmp Winv_d^T
+            HIPCHK(nt(tmp, m, dinv + (d / DB) * DB * DB, DB, Y + d * m, m, jb, jb, 1.0, 0.0));
+            if (d + jb < kb1)
+                HIPCHK(nt(Y + d * m, m, L + (d + jb) + d * ldl, ldl, Y + (d + jb) * m, m, kb1 - d - jb, jb, -1.0, 1.0));
+        }
+        if (kb1 < n)
+            HIPCHK(nt(Y + kb0 * m, m, L + kb1 + kb0 * ldl, ldl, Y + kb1 * m, m, n - kb1, kb1 - kb0, -1.0, 1.0));
     }
     return GP_OK;
 }
@@ -994,20 +1029,20 @@ int gp_krige(gp_handle_t h, gp_theta_t th, int64_t n, int64_t m, int32_t dim, co
     hipStream_t s = h->stream;
     const CovParams cp = cov_params(th, dim);
     const double base_var = cp.s2 + (include_nugget ? cp.t2 : 0.0);
-    double *Cs = at<double>(ws, lay.big1);
-    const int64_t ldcs = n > 0 ? n : 1;
+    double *Y = at<double>(ws, lay.big1);  // Y = C*^T: m x n, ld m
+    double *partials = at<double>(ws, lay.big2);
     if (n == 0) {
-        HIPCHK(launch_colreduce(s, 0, 0, m, Cs, ldcs, nullptr, mu, mean_dev));
-        HIPCHK(launch_colreduce(s, 1, 0, m, Cs, ldcs, nullptr, base_var, var_dev));
+        HIPCHK(launch_rowreduce(s, 0, m, 0, Y, m, nullptr, mu, partials, mean_dev));
+        HIPCHK(launch_rowreduce(s, 1, m, 0, Y, m, nullptr, base_var, partials, var_dev));
         return GP_OK;
     }
     double *dinv = at<double>(ws, lay.dinv);
     HIPCHK(launch_diag_inv(s, L, ldl, n, dinv));
-    HIPCHK(launch_cross_cov(s, cp, n, m, X, Xs, Cs, ldcs));
-    HIPCHK(launch_colreduce(s, 0, n, m, Cs, ldcs, alpha, mu, mean_dev));
-    int rc = trsm_impl(h, 0, n, m, L, ldl, Cs, ldcs, dinv, at<double>(ws, lay.part), nullptr);
+    HIPCHK(launch_cross_cov(s, cp, m, n, Xs, X, Y, m));  // Y(j, i) = sigma^2 k(|s_j - x_i| / rho)
+    HIPCHK(launch_rowreduce(s, 0, m, n, Y, m, alpha, mu, partials, mean_dev));
+    int rc = trsm_right_lt(s, n, m, L, ldl, Y, dinv, at<double>(ws, lay.part), nullptr);  // rows of L^{-1} C*, transposed
     if (rc) return rc;
-    HIPCHK(launch_colreduce(s, 1, n, m, Cs, ldcs, nullptr, base_var, var_dev));
+    HIPCHK(launch_rowreduce(s, 1, m, n, Y, m, nullptr, base_var, partials, var_dev));
     return GP_OK;
 }
 

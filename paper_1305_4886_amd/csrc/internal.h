@@ -395,8 +395,6 @@ hipError_t launch_fill(hipStream_t s, void *p, size_t bytes);
 
 // k_aux.hip
 // mode 0: out[j] = base + sum_i M_ij v_i; mode 1: out[j] = base - sum_i M_ij^2.
-hipError_t launch_colreduce(hipStream_t s, int mode, int64_t n, int64_t m, const double *M, int64_t ld,
-                            const double *v, double base, double *out);
 hipError_t launch_copy2d(hipStream_t s, int64_t rows, int64_t cols, const double *src, int64_t lds, double *dst,
                          int64_t ldd);
 hipError_t launch_place_dinv(hipStream_t s, int64_t n, const double *dinv, double *W, int64_t ldw, int trans = 0);
@@ -426,6 +424,12 @@ hipError_t launch_gather_points(hipStream_t s, int64_t n, int dim, const int64_t
 hipError_t launch_scatter_vec(hipStream_t s, int64_t n, const int64_t *perm, const double *src, double *dst);
 hipError_t launch_set_info(hipStream_t s, int32_t *info);
 hipError_t launch_tune_fill(hipStream_t s, double *A, int64_t lda, int64_t n);
+// Row reductions of an m x n column-major matrix (compensated, two passes;
+// partials holds 2 m rowreduce_chunks(n) doubles):
+//   mode 0: out_j = base + sum_i Y(j, i) v_i      mode 1: out_j = base - sum_i Y(j, i)^2
+int64_t rowreduce_chunks(int64_t n);
+hipError_t launch_rowreduce(hipStream_t s, int mode, int64_t m, int64_t n, const double *Y, int64_t ldy,
+                            const double *v, double base, double *partials, double *out);
 
 // k_batch.hip
 size_t batch_ws_bytes(int64_t nmax, int64_t nbatch);

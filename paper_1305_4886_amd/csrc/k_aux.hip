@@ -1,45 +1,11 @@
 // k_aux.hip -- small streaming kernels around the matrix-core products:
-// column reductions for kriging (c_j^T alpha and |w_j|^2, Section 1's
-// prediction and its variance), block copies for the blocked triangular
-// solve with many right-hand sides, and the placement of diagonal-block
-// inverses into the blocked triangular inverse.
+// row reductions for kriging (c_j^T alpha and |w_j|^2, Section 1's
+// prediction and its variance), block copies and transposes, the placement
+// of diagonal-block inverses into the blocked triangular inverse, the
+// iterative-refinement bookkeeping and the Morton ordering.
 #include "internal.h"
 
 namespace {
-
-// One workgroup per column j of the n x m matrix M (ld):
-//   mode 0: out[j] = base + sum_i M_ij v_i        (kriging mean)
-//   mode 1: out[j] = base - sum_i M_ij^2          (kriging variance)
-// Compensated per-thread sums, then a fixed-order tree.
-__global__ __launch_bounds__(256) void k_colreduce(int mode, int64_t n, int64_t m, const double *M, int64_t ld,
-                                                   const double *v, double base, double *out) {
-    __shared__ double red[2 * 256];
-    const int64_t j = blockIdx.x;
-    if (j >= m) return;
-    const double *col = M + j * ld;
-    CSum s;
-    for (int64_t i = threadIdx.x; i < n; i += 256) {
-        const double x = col[i];
-        s.add(mode == 0 ? x * v[i] : x * x);
-    }
-    red[2 * threadIdx.x] = s.s;
-    red[2 * threadIdx.x + 1] = s.c;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if (threadIdx.x < st) {
-            CSum a, b;
-            a.s = red[2 * threadIdx.x]; a.c = red[2 * threadIdx.x + 1];
-            b.s = red[2 * (threadIdx.x + st)]; b.c = red[2 * (threadIdx.x + st) + 1];
-            a.merge(b);
-            red[2 * threadIdx.x] = a.s; red[2 * threadIdx.x + 1] = a.c;
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const double t = red[0] + red[1];
-        out[j] = mode == 0 ? base + t : base - t;
-    }
-}
 
 // dst[i + j ldd] = src[i + j lds], rows x cols.
 __global__ __launch_bounds__(256) void k_copy2d(int64_t rows, int64_t cols, const double *src, int64_t lds,
@@ -114,19 +80,63 @@ __global__ void k_tune_fill(double *A, int64_t lda, int64_t n) {
 }
 
 
-}  // namespace
 
-hipError_t launch_colreduce(hipStream_t s, int mode, int64_t n, int64_t m, const double *M, int64_t ld,
-                            const double *v, double base, double *out) {
-    if (m <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_colreduce, dim3((unsigned)m), dim3(256), 0, s, mode, n, m, M, ld, v, base, out);
-    return hipGetLastError();
+// Row reductions of an m x n column-major matrix Y (ld ldy), in two passes
+// with compensated sums: chunk c of RR_COLS columns gives partials
+// (s, e)[c][j] for each row j (threads run along j, so every load is a
+// contiguous run of a column); the finish pass adds the chunks in order.
+//   mode 0: out_j = base + sum_i Y(j, i) v_i      mode 1: out_j = base - sum_i Y(j, i)^2
+constexpr int RR_COLS = 512;
+__global__ __launch_bounds__(256) void k_rowreduce_partial(int mode, int64_t m, int64_t n, const double *Y, int64_t ldy,
+                                                           const double *v, double *partials) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t c = blockIdx.y;
+    if (j >= m) return;
+    const int64_t i1 = (c + 1) * RR_COLS < n ? (c + 1) * RR_COLS : n;
+    CSum acc;
+    for (int64_t i = c * RR_COLS; i < i1; ++i) {
+        const double y = Y[j + i * ldy];
+        acc.add(mode == 0 ? y * v[i] : y * y);
+    }
+    partials[2 * (c * m + j)] = acc.s;
+    partials[2 * (c * m + j) + 1] = acc.c;
 }
+
+__global__ __launch_bounds__(256) void k_rowreduce_finish(int mode, int64_t m, int64_t nchunk, const double *partials,
+                                                          double base, double *out) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= m) return;
+    CSum acc;
+    for (int64_t c = 0; c < nchunk; ++c) {
+        CSum b;
+        b.s = partials[2 * (c * m + j)];
+        b.c = partials[2 * (c * m + j) + 1];
+        acc.merge(b);
+    }
+    const double t = acc.value();
+    out[j] = mode == 0 ? base + t : base - t;
+}
+
+}  // namespace
 
 hipError_t launch_tune_fill(hipStream_t s, double *A, int64_t lda, int64_t n) {
     if (n <= 0) return hipSuccess;
     const int64_t gx = (n + 255) / 256 < 64 ? (n + 255) / 256 : 64;
     hipLaunchKernelGGL(k_tune_fill, dim3((unsigned)gx, (unsigned)(n < 8192 ? n : 8192)), dim3(256), 0, s, A, lda, n);
+    return hipGetLastError();
+}
+
+int64_t rowreduce_chunks(int64_t n) { return (n + RR_COLS - 1) / RR_COLS; }
+
+hipError_t launch_rowreduce(hipStream_t s, int mode, int64_t m, int64_t n, const double *Y, int64_t ldy,
+                            const double *v, double base, double *partials, double *out) {
+    if (m <= 0) return hipSuccess;
+    const int64_t nch = n > 0 ? rowreduce_chunks(n) : 0;
+    if (nch > 0)
+        hipLaunchKernelGGL(k_rowreduce_partial, dim3((unsigned)((m + 255) / 256), (unsigned)nch), dim3(256), 0, s, mode,
+                           m, n, Y, ldy, v, partials);
+    hipLaunchKernelGGL(k_rowreduce_finish, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, mode, m, nch, partials,
+                       base, out);
     return hipGetLastError();
 }
 
