@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--parts", default="krige,grad,mixed,batch")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-n", type=int, default=12288, help="oracle sample size (leading block)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy three times (scale for HBM counters)")
     return ap.parse_args()
 
 
@@ -83,6 +85,14 @@ def main():
     from paper_1305_4886_amd import synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if a.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": src.numel() * 8, "launches": 3}))
+        return
     dev = "cuda"
     n, m = a.n, a.m
     parts = set(a.parts.split(","))

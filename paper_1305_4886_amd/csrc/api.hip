@@ -688,7 +688,7 @@ static void default_options(gp_options_t *o) {
     o->nb = 512;
     o->lookahead = 1;
     o->panel_cus = 0;
-    o->band = 2;
+    o->band = 8;
     o->ir_max_iter = 20;
     o->ir_tol = 1e-10;
     o->reorder = 1;

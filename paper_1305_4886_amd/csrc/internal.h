@@ -339,6 +339,7 @@ struct GemmDesc {
     int klo_j;     // skip k < tile col start (op(B) lower-zero structure)
     int khi_i;     // skip k >= tile row end (op(A) lower-triangular)
     int khi_j;     // skip k >= tile col end (op(B) upper-triangular)
+    int64_t koff;   // absolute index of local k = 0 for the K-range flags (K split into chunks)
     int64_t batch;  // number of independent products
     int64_t sA, sB, sC; // element strides between batch members
     const int32_t *info; // skip everything if *info != 0 (may be null)

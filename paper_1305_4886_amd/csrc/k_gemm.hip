@@ -372,10 +372,11 @@ __global__ __launch_bounds__(256, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
     // K range of this tile (operands are zero outside it by structure):
     // slabs kf .. kf + nk - 1; the last one holds ktail <= BKD columns below K
     int64_t klo = 0, khi = d.K;
-    if (d.klo_i && i0 > klo) klo = i0;
-    if (d.klo_j && j0 > klo) klo = j0;
-    if (d.khi_i && i0 + BM < khi) khi = i0 + BM;
-    if (d.khi_j && j0 + BM < khi) khi = j0 + BM;
+    if (d.klo_i && i0 - d.koff > klo) klo = i0 - d.koff;
+    if (d.klo_j && j0 - d.koff > klo) klo = j0 - d.koff;
+    if (d.khi_i && i0 + BM - d.koff < khi) khi = i0 + BM - d.koff;
+    if (d.khi_j && j0 + BM - d.koff < khi) khi = j0 + BM - d.koff;
+    if (khi <= klo && d.beta == 1.0) return;  // nothing to add to this tile
     const int kf = (int)(klo / BKD);
     const int kl = khi > klo ? (int)((khi + BKD - 1) / BKD) : kf;
     const int nk = kl - kf;
@@ -956,7 +957,24 @@ hipError_t launch_syrk_packed(hipStream_t s, gp_prec_t prec, int band, const dou
     return hipGetLastError();
 }
 
-hipError_t launch_gemm_nt_dma(hipStream_t s, const GemmDesc &d) { return run_dma<0>(s, d); }
+hipError_t launch_gemm_nt_dma(hipStream_t s, const GemmDesc &d) {
+    // K in chunks of KC columns: every tile then streams a bounded slab of the
+    // operands (the working set of the concurrent tiles stays cache- and
+    // TLB-resident), at the cost of re-reading C once per chunk.
+    constexpr int64_t KC = 1024;
+    if (d.K <= KC) return run_dma<0>(s, d);
+    for (int64_t k0 = 0; k0 < d.K; k0 += KC) {
+        GemmDesc c = d;
+        c.A = d.A + k0 * d.lda;
+        c.B = d.B + k0 * d.ldb;
+        c.K = d.K - k0 < KC ? d.K - k0 : KC;
+        c.koff = d.koff + k0;
+        c.beta = k0 == 0 ? d.beta : 1.0;
+        hipError_t e = run_dma<0>(s, c);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
 
 hipError_t launch_syrk_dma(hipStream_t s, const double *P, int64_t ldp, double *C, int64_t ldc, int64_t M, int64_t K,
                            double alpha, double beta, int klo_i, const int32_t *info) {
@@ -964,7 +982,21 @@ hipError_t launch_syrk_dma(hipStream_t s, const double *P, int64_t ldp, double *
     d.A = P; d.lda = ldp; d.B = P; d.ldb = ldp; d.C = C; d.ldc = ldc;
     d.M = M; d.N = M; d.K = K; d.alpha = alpha; d.beta = beta;
     d.ta = 0; d.tb = 1; d.lower = 1; d.klo_i = klo_i; d.batch = 1; d.info = info;
-    return run_dma<0>(s, d);
+    constexpr int64_t KC = 1024;
+    if (K <= KC) return run_dma<0>(s, d);
+    // K in chunks; with klo_i, rows at or below a chunk's end get nothing from it
+    for (int64_t k0 = 0; k0 < K; k0 += KC) {
+        GemmDesc c = d;
+        c.A = d.A + k0 * ldp;
+        c.B = c.A;
+        c.K = K - k0 < KC ? K - k0 : KC;
+        c.koff = k0;
+        c.beta = k0 == 0 ? beta : 1.0;
+        if (klo_i && k0 > 0 && k0 + c.K < M) c.M = c.N = k0 + c.K;
+        hipError_t e = run_dma<0>(s, c);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_panel_solve(hipStream_t s, double *A, int64_t lda, const double *Winv, int64_t M,
