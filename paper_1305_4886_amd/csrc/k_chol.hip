@@ -83,9 +83,13 @@ __global__ __launch_bounds__(64) void k_diag_inv(const double *L, int64_t ldl, i
     for (int c = 0; c < DB; ++c) W[lane + c * DB] = Wl[lane][c];
 }
 
-// Cross-lane reduction of H register values: lanes l and l ^ H exchange the
-// halves they do not keep, so after the steps H = 32, 16, ..., 1 lane l holds
-// the sum over all lanes of the original p[l] (or p[l & 15] for 16 values).
+// Two doubles at 8-byte alignment (a column-major operand with odd leading
+// dimension), read as one 16-byte load.
+typedef double gp_d2u __attribute__((ext_vector_type(2), aligned(8)));
+
+// Cross-lane reduction step: lanes l and l ^ H exchange the halves of p[0..2H)
+// they do not keep.  After the steps H = 16, 8, 4, 2, 1 on 32 register values,
+// lane l holds the sum of p[l % 32] over the 32 lanes of its half-wave.
 template <int H>
 GP_DEV void xr_step(double *p, int lane) {
     const bool hi = (lane & H) != 0;
@@ -95,25 +99,6 @@ GP_DEV void xr_step(double *p, int lane) {
         const double send = hi ? p[c] : p[c + H];
         p[c] = keep + __shfl_xor(send, H, 64);
     }
-}
-GP_DEV double xr_reduce64(double *p, int lane) {
-    xr_step<32>(p, lane);
-    xr_step<16>(p, lane);
-    xr_step<8>(p, lane);
-    xr_step<4>(p, lane);
-    xr_step<2>(p, lane);
-    xr_step<1>(p, lane);
-    return p[0];
-}
-GP_DEV double xr_reduce16(double *p, int lane) {
-    xr_step<8>(p, lane);
-    xr_step<4>(p, lane);
-    xr_step<2>(p, lane);
-    xr_step<1>(p, lane);
-    double v = p[0];
-    v += __shfl_xor(v, 16, 64);
-    v += __shfl_xor(v, 32, 64);
-    return v;
 }
 
 // Work area of the solves: ints [0] ticket, [1] abort, then (at byte 256) a
@@ -152,7 +137,7 @@ GP_DEV void mbox_put(double *slot, double v) {
 // values appear; wave 0 has the nearest block's 64 x 64 tile and the rows of
 // Winv in registers, so once the far sums are in, the critical path is one
 // poll of x_{blk-1}, two 64-term dot products per lane and the store.
-__global__ __launch_bounds__(256) void k_trsv_fwd(const double *L, int64_t ldl, double *x, int64_t n,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_trsv_fwd(const double *L, int64_t ldl, double *x, int64_t n,
                                                   const double *dinv, int *sync, double *mbox,
                                                   const int32_t *info) {
     __shared__ int s_blk;
@@ -174,9 +159,17 @@ __global__ __launch_bounds__(256) void k_trsv_fwd(const double *L, int64_t ldl, 
         for (int jb = w - 1; jb < blk - 1; jb += 3) {
             const double *Lc = L + i + (int64_t)jb * DB * ldl;
             const double xv = mbox_poll(&mbox[(int64_t)jb * DB + lane], abortf);
-            if (rv) {
-#pragma unroll 16
-                for (int c = 0; c < DB; ++c) acc = fma(Lc[(int64_t)c * ldl], rdlane(xv, c), acc);
+            if (rv) {  // all 64 loads of the tile in flight before the first product
+                double v[DB];
+#pragma unroll
+                for (int c = 0; c < DB; ++c) v[c] = Lc[(int64_t)c * ldl];
+                double a1 = 0.0;
+#pragma unroll
+                for (int c = 0; c < DB; c += 2) {
+                    acc = fma(v[c], rdlane(xv, c), acc);
+                    a1 = fma(v[c + 1], rdlane(xv, c + 1), a1);
+                }
+                acc += a1;
             }
         }
         part[w - 1][lane] = acc;
@@ -218,10 +211,13 @@ __global__ __launch_bounds__(256) void k_trsv_fwd(const double *L, int64_t ldl, 
 
 // Backward solve x <- L^{-T} x, block blk (columns c0 .. c0 + 63 of L):
 //   x_blk = Winv_blk^T (b_blk - sum_{j > blk} L[j, blk]^T x_j).
-// Waves 1-3: far row blocks j > blk + 1, last first (their completion order):
-// lane = row of block j, 64 column partial sums per lane, 512-byte loads,
-// one cross-lane exchange per wave at the end.  Wave 0 (lane = column) keeps
-// its column of the nearest row block and of Winv in registers.
+// Waves 1-3: far row blocks j > blk + 1, last first (their completion order).
+// Lane (h, r) with h = lane / 32, r = lane % 32 reads rows 2r, 2r + 1 of block
+// j in columns 2q + h (q = 0..31) as 16-byte loads, so one instruction covers
+// two full 512-byte column segments and all 32 loads of a tile are in flight
+// before the products; 32 column partial sums per lane, one cross-lane
+// exchange over each half-wave at the end.  Wave 0 (lane = column) keeps its
+// column of the nearest row block and of Winv in registers.
 __global__ __launch_bounds__(256) void k_trsv_trans(const double *L, int64_t ldl, double *x, int64_t n,
                                                     const double *dinv, int *sync, double *mbox,
                                                     const int32_t *info) {
@@ -241,21 +237,36 @@ __global__ __launch_bounds__(256) void k_trsv_trans(const double *L, int64_t ldl
     const int64_t col = c0 + lane;
     const bool cv = col < n;
     if (w > 0) {
-        // far blocks: full row blocks strictly below blk + 1, so this block's
-        // columns are all < n
-        double p[DB];
+        // far blocks exist only when blk + 2 < nblk, so this block's 64
+        // columns are all < n; only the last row block can be partial
+        const int hh = lane >> 5, r2 = lane & 31;
+        double p[DB / 2];
 #pragma unroll
-        for (int c = 0; c < DB; ++c) p[c] = 0.0;
+        for (int q = 0; q < DB / 2; ++q) p[q] = 0.0;
         for (int jb = nblk - w; jb >= blk + 2; jb -= 3) {
-            const int64_t row = (int64_t)jb * DB + lane;
-            if (row < n) {
-                const double *Lr = L + row + c0 * ldl;
-                const double xv = mbox_poll(&mbox[row], abortf);
+            const int64_t row = (int64_t)jb * DB + 2 * r2;
+            const double *Lr = L + row + (c0 + hh) * ldl;
+            if (row + 1 < n) {
+                const double x0 = mbox_poll(&mbox[row], abortf);
+                const double x1 = mbox_poll(&mbox[row + 1], abortf);
+                gp_d2u v[DB / 2];
 #pragma unroll
-                for (int c = 0; c < DB; ++c) p[c] = fma(Lr[(int64_t)c * ldl], xv, p[c]);
+                for (int q = 0; q < DB / 2; ++q) v[q] = *reinterpret_cast<const gp_d2u *>(Lr + (int64_t)(2 * q) * ldl);
+#pragma unroll
+                for (int q = 0; q < DB / 2; ++q) p[q] = fma(v[q].y, x1, fma(v[q].x, x0, p[q]));
+            } else if (row < n) {
+                const double x0 = mbox_poll(&mbox[row], abortf);
+#pragma unroll
+                for (int q = 0; q < DB / 2; ++q) p[q] = fma(Lr[(int64_t)(2 * q) * ldl], x0, p[q]);
             }
         }
-        part[w - 1][lane] = xr_reduce64(p, lane);
+        // lane (h, r) ends with the half-wave sum of p[r]: column 2 r + h
+        xr_step<16>(p, lane);
+        xr_step<8>(p, lane);
+        xr_step<4>(p, lane);
+        xr_step<2>(p, lane);
+        xr_step<1>(p, lane);
+        part[w - 1][2 * r2 + hh] = p[0];
         __syncthreads();
         return;
     }
@@ -301,9 +312,19 @@ __global__ void k_fill_u64(uint64_t *p, int64_t cnt, uint64_t v) {
     if (i < cnt) p[i] = v;
 }
 
-__global__ void k_fill_u32(uint32_t *p, int64_t cnt) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < cnt) p[i] = 0u;
+// Zero fill, grid-stride: a dispatch holds fewer than 2^32 work-items, so a
+// buffer of n^2 doubles (n > 46341) cannot take one work-item per element.
+// 16-byte stores over the aligned bulk, 4-byte stores for the rest.
+__global__ void k_fill_zero(uint32_t *p, int64_t cnt) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t head = (int64_t)((16 - ((uintptr_t)p & 15)) & 15) / 4;  // u32 before 16-byte alignment
+    const int64_t h = head < cnt ? head : cnt;
+    const int64_t nv = (cnt - h) / 4;
+    uint4 *v = reinterpret_cast<uint4 *>(p + h);
+    for (int64_t i = t0; i < nv; i += stride) v[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (int64_t i = t0; i < h; i += stride) p[i] = 0u;
+    for (int64_t i = h + 4 * nv + t0; i < cnt; i += stride) p[i] = 0u;
 }
 
 __global__ void k_set_info(int32_t *info) { *info = 0; }
@@ -375,7 +396,9 @@ hipError_t launch_diag_inv(hipStream_t s, const double *L, int64_t ldl, int64_t 
 hipError_t launch_fill(hipStream_t s, void *p, size_t bytes) {
     const int64_t cnt = (int64_t)(bytes / 4);
     if (cnt <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, (uint32_t *)p, cnt);
+    const int64_t want = (cnt / 4 + 255) / 256;
+    const unsigned g = (unsigned)(want < 1 ? 1 : (want > 8192 ? 8192 : want));
+    hipLaunchKernelGGL(k_fill_zero, dim3(g), dim3(256), 0, s, (uint32_t *)p, cnt);
     return hipGetLastError();
 }
 
