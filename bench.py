@@ -51,6 +51,40 @@ def parse():
     return ap.parse_args()
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_syrk_dma_trailing_n32768_hbm_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1305_4886_amd", "csrc", f) for f in ("k_gemm.hip", "internal.h")]
+
+
+def kernel_sources_sha256():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per trailing-SYRK launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by its reading for a plain copy of
+    known size), or None when the kernel sources changed since it was taken."""
+    import re
+
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            txt = fh.read()
+    except OSError:
+        return None, "no counter summary"
+    b = re.search(r"^traffic_bytes_per_launch = (\d+)$", txt, re.M)
+    h = re.search(r"^kernel_sources_sha256 = ([0-9a-f]{64})$", txt, re.M)
+    if not b or not h:
+        return None, "counter summary unreadable"
+    if h.group(1) != kernel_sources_sha256():
+        return None, "kernel sources changed since the counters were taken"
+    return int(b.group(1)), "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, copy-calibrated"
+
+
 def cpu_baseline(n_s, seed=4):
     """Oracle Cholesky of the leading n_s x n_s block of the same covariance."""
     import numpy as np
@@ -235,10 +269,15 @@ def main():
                                    "all_finite": bool(torch.isfinite(last["batch"]["out3"]).all().item())}
     syrk_tflops = syrk[2] / (syrk[1] / 1e3) / 1e12 if syrk[1] > 0 else None
     syrk_per_launch_flops = syrk[2] / syrk[0] if syrk[0] else None
+    traffic, traffic_src = measured_traffic()
+    # algorithmic HBM bytes of the same launches: the lower-triangle C tile
+    # read and written once (8 B each way per flop pair / K) plus the panel
+    alg_bytes = (2 * 8 * syrk_per_launch_flops / (2 * h.options().nb)) if syrk_per_launch_flops else None
     roofline = {"kernel": "trailing SYRK (k_syrk_dma role 1)", "bound": "mfma",
                 "achieved": syrk_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": (syrk_tflops / FP64_PEAK_TFLOPS) if syrk_tflops else None,
-                "traffic": None, "launches": syrk[0],
+                "traffic": traffic, "traffic_unit": "B/launch", "traffic_source": traffic_src,
+                "algorithmic_c_bytes_per_launch": alg_bytes, "launches": syrk[0],
                 "avg_launch_ms": syrk[1] / syrk[0] if syrk[0] else None,
                 "flops_per_launch": syrk_per_launch_flops}
     cpu = None

@@ -90,7 +90,8 @@ GP_DEV int64_t xcd_remap() {
 // FP64 MFMA GEMM.  BM x BN tile, WM x WN waves.
 // ---------------------------------------------------------------------------
 // TAG only separates instantiations by role in kernel traces:
-// 0 generic product, 1 trailing update, 2 update inside a panel, 3 panel solve.
+// 0 generic product, 1 FP64 trailing update, 2 update inside a panel,
+// 3 panel solve, 4 FP64 band tiles of a mixed-precision trailing update.
 template <int BM, int BN, int WM, int WN, int TA, int TB, int TAG>
 __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmDesc d, TileMap tm) {
     constexpr int WTM = BM / WM, WTN = BN / WN;
@@ -937,9 +938,9 @@ hipError_t launch_syrk_packed(hipStream_t s, gp_prec_t prec, int band, const dou
         tb.ntiles = tb.ntn * b;
         const int64_t g = ((tb.ntiles + 7) / 8) * 8;
         if (K % 8 == 0)
-            hipLaunchKernelGGL((k_syrk_dma<4, 8, 1>), dim3((unsigned)g), dim3(256), 0, s, d, tb);
+            hipLaunchKernelGGL((k_syrk_dma<4, 8, 4>), dim3((unsigned)g), dim3(256), 0, s, d, tb);
         else
-            hipLaunchKernelGGL((k_gemm_f64<128, 128, 2, 2, 0, 1, 1>), dim3((unsigned)g), dim3(256), 0, s, d, tb);
+            hipLaunchKernelGGL((k_gemm_f64<128, 128, 2, 2, 0, 1, 4>), dim3((unsigned)g), dim3(256), 0, s, d, tb);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
