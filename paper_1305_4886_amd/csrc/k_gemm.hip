@@ -353,6 +353,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
     constexpr int PER = NKK * 2 * 4;       // copies per wave per slab
     static_assert(BKD % 4 == 0 && STAGES >= 2, "slab shape");
     static_assert((STAGES - 2) * PER < 64, "outstanding copies exceed vmcnt");
+    static_assert(STAGES * 2 * BKD * BM >= 4 * 2048, "the ring holds the epilogue's four wave regions");
     __shared__ double Ls[STAGES][2][BKD][BM];  // [stage][operand][k][row]
 
     if (d.info && *d.info) return;
@@ -471,11 +472,52 @@ __global__ __launch_bounds__(256, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
         st = st + 1 == STAGES ? 0 : st + 1;
     }
 
-    // D layout: lane l, register r holds row l / 16 + 4 r, column l % 16.
-    const int64_t rb0 = i0 + wm * WTM + (lane >> 4);
-    const int64_t cb0 = j0 + wn * WTM + (lane & 15);
+    // Epilogue through the (now idle) LDS ring: each wave writes its 64 x 64
+    // accumulator block in two halves of 32 rows into a private 16 KB region
+    // and reads it back with lane = row, so the C tile is read and written
+    // as 256-byte column segments (the MFMA D layout -- lane l, register r:
+    // row l / 16 + 4 r, column l % 16 -- would give 32-byte pieces of 16
+    // columns per instruction).  The C loads of a half are issued before the
+    // LDS exchange.  Region: element (row p, column g) at g 32 + (p ^ 2 (g % 16)),
+    // a swizzle that keeps both the writes and the reads free of bank conflicts.
+    // Tiles on the diagonal or the matrix edge keep the direct, guarded
+    // stores (a guarded LDS path would spill).
     const bool interior = (i0 + BM <= d.M) && (j0 + BM <= d.N) && (!d.lower || i0 >= j0 + BM);
     const bool use_c = d.beta != 0.0;
+    if (interior) {
+        double *R = &Ls[0][0][0][0] + wave * 2048;
+        const int p = lane & 31, hc = lane >> 5;
+        __syncthreads();  // every wave is past its last ring read
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int64_t gi = i0 + wm * WTM + 32 * h + p;
+            double *Cc = C + gi + (j0 + wn * WTM + hc) * d.ldc;
+            double cv[32];
+            if (use_c) {
+#pragma unroll
+                for (int q = 0; q < 32; ++q) cv[q] = Cc[(int64_t)(2 * q) * d.ldc];
+            }
+#pragma unroll
+            for (int mm = 0; mm < 2; ++mm)
+#pragma unroll
+                for (int n = 0; n < FN; ++n)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int rr = (lane >> 4) + 4 * r + 16 * mm, g = n * 16 + (lane & 15);
+                        R[g * 32 + (rr ^ (2 * (g & 15)))] = acc[2 * h + mm][n][r];
+                    }
+            // the wave reads back only its own region: its LDS operations complete in order
+#pragma unroll
+            for (int q = 0; q < 32; ++q) {
+                const int g = 2 * q + hc;
+                const double v = R[g * 32 + (p ^ (2 * (g & 15)))];
+                Cc[(int64_t)(2 * q) * d.ldc] = use_c ? fma(d.beta, cv[q], d.alpha * v) : d.alpha * v;
+            }
+        }
+        return;
+    }
+    const int64_t rb0 = i0 + wm * WTM + (lane >> 4);
+    const int64_t cb0 = j0 + wn * WTM + (lane & 15);
 #pragma unroll
     for (int m = 0; m < FM; ++m) {
         double cv[FN][4];
@@ -484,7 +526,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t gi = rb0 + m * 16 + 4 * r, gj = cb0 + n * 16;
-                const bool ok = use_c && (interior || (gi < d.M && gj < d.N && (!d.lower || gi >= gj)));
+                const bool ok = use_c && gi < d.M && gj < d.N && (!d.lower || gi >= gj);
                 const double v = C[ok ? gi + gj * d.ldc : 0];
                 cv[n][r] = ok ? v : 0.0;
             }
@@ -493,7 +535,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t gi = rb0 + m * 16 + 4 * r, gj = cb0 + n * 16;
-                const bool ok = interior || (gi < d.M && gj < d.N && (!d.lower || gi >= gj));
+                const bool ok = gi < d.M && gj < d.N && (!d.lower || gi >= gj);
                 if (ok) C[gi + gj * d.ldc] = fma(d.beta, cv[n][r], d.alpha * acc[m][n][r]);
             }
     }
