@@ -580,6 +580,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk_pk(GemmDesc d, TileMap tm, cons
     constexpr int NKK = PREC == 1 ? BKD / 4 : 1;                // MFMA K-steps per slab
     static_assert((STAGES - 2) * PER < 64, "outstanding copies exceed vmcnt");
     static_assert(PER % NKK == 0, "copies per K-step");
+    static_assert(STAGES * 2 * BM * BKD * EB >= 4 * 2048 * 8, "the ring holds the epilogue's four wave regions");
     __shared__ __attribute__((aligned(16))) char Ls[STAGES][2][BM * BKD * EB];
 
     if (d.info && *d.info) return;
@@ -680,9 +681,42 @@ __global__ __launch_bounds__(256, 2) void k_syrk_pk(GemmDesc d, TileMap tm, cons
         st = st + 1 == STAGES ? 0 : st + 1;
     }
 
+    // Interior tiles: the same LDS-transposed write-back as the FP64 kernel
+    // (D layout here: lane l, register r holds row 4 (l / 16) + r, column
+    // l % 16), with the region swizzle p ^ s(g), s(g) = (g % 4) + 16 ((g / 4) % 2),
+    // which spreads these writes over 32 distinct slots per instruction.
+    const bool interior = (i0 + BM <= d.M) && (j0 + BM <= d.N) && (i0 >= j0 + BM);
+    if (interior) {
+        double *R = reinterpret_cast<double *>(&Ls[0][0][0]) + wave * 2048;
+        const int p = lane & 31, hc = lane >> 5;
+        __syncthreads();  // every wave is past its last ring read
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int64_t gi = i0 + wm * WTM + 32 * h + p;
+            double *Cc = C + gi + (j0 + wn * WTM + hc) * d.ldc;
+            double cv[32];
+#pragma unroll
+            for (int q = 0; q < 32; ++q) cv[q] = Cc[(int64_t)(2 * q) * d.ldc];
+#pragma unroll
+            for (int mm = 0; mm < 2; ++mm)
+#pragma unroll
+                for (int n = 0; n < FN; ++n)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int rr = 4 * (lane >> 4) + r + 16 * mm, g = n * 16 + (lane & 15);
+                        R[g * 32 + (rr ^ ((g & 3) | ((g & 4) << 2)))] = (double)acc[2 * h + mm][n][r];
+                    }
+            // the wave reads back only its own region: its LDS operations complete in order
+#pragma unroll
+            for (int q = 0; q < 32; ++q) {
+                const int g = 2 * q + hc;
+                Cc[(int64_t)(2 * q) * d.ldc] = cv[q] - R[g * 32 + (p ^ ((g & 3) | ((g & 4) << 2)))];
+            }
+        }
+        return;
+    }
     const int64_t rb0 = i0 + wm * WTM + 4 * (lane >> 4);
     const int64_t cb0 = j0 + wn * WTM + (lane & 15);
-    const bool interior = (i0 + BM <= d.M) && (j0 + BM <= d.N) && (i0 >= j0 + BM);
 #pragma unroll
     for (int m = 0; m < FM; ++m) {
         double cv[FN][4];
@@ -691,7 +725,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk_pk(GemmDesc d, TileMap tm, cons
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t gi = rb0 + m * 16 + r, gj = cb0 + n * 16;
-                const bool ok = interior || (gi < d.M && gj < d.N && gi >= gj);
+                const bool ok = gi < d.M && gj < d.N && gi >= gj;
                 cv[n][r] = C[ok ? gi + gj * d.ldc : 0];
             }
 #pragma unroll
@@ -699,7 +733,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk_pk(GemmDesc d, TileMap tm, cons
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t gi = rb0 + m * 16 + r, gj = cb0 + n * 16;
-                const bool ok = interior || (gi < d.M && gj < d.N && gi >= gj);
+                const bool ok = gi < d.M && gj < d.N && gi >= gj;
                 if (ok) C[gi + gj * d.ldc] = cv[n][r] - (double)acc[m][n][r];
             }
     }
