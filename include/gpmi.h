@@ -91,7 +91,10 @@ typedef struct {
     int32_t reorder;     /* mixed modes: 1 = order the points along a Morton curve inside gp_loglik* */
     int32_t panel_cus;   /* compute units kept free of trailing updates for the lookahead chain
                             (0 = none: one shared stream pair without CU masks) */
-    int32_t reserved[2];
+    int32_t fused_panel; /* 1: each panel's diagonal block (factor, block inverses and, when rows
+                            follow, its full inverse) in one launch of concurrent workgroups
+                            (panels up to 1024 columns); 0: a chain of per-64-column launches */
+    int32_t reserved;
 } gp_options_t;
 
 /* ---- handle ------------------------------------------------------------ */

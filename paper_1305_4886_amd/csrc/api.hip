@@ -52,7 +52,7 @@ CovParams cov_params(const gp_theta_t &th, int dim) {
 struct Layout {
     size_t dinv = 0, sync = 0, z = 0, vec2 = 0, vec3 = 0, vec4 = 0, vec5 = 0, part = 0, big1 = 0, big2 = 0,
            big3 = 0, irst = 0, perm = 0, keys = 0, box = 0, xp = 0, yp = 0, mup = 0, pbuf = 0, vinv = 0,
-           vtmp = 0, qbuf = 0, big4 = 0, total = 0;
+           vtmp = 0, qbuf = 0, big4 = 0, pflags = 0, total = 0;
 };
 
 // Buffers of the panel steps of the factorisation (null when n <= NB).
@@ -61,6 +61,7 @@ struct PanelBufs {
     double *vinv = nullptr;  // inverse of a diagonal block, NB x NB
     double *vtmp = nullptr;  // products of the blocked inverse, trtri_tmp_elems(NB)
     void *qbuf = nullptr;    // low-precision packed panel (mixed modes)
+    int *pflags = nullptr;   // hand-over flags of the fused panel kernel
 };
 
 int64_t panel_width(gp_handle_t h) { return h->opt.nb > 0 ? h->opt.nb : 512; }
@@ -120,6 +121,7 @@ Layout layout(gp_handle_t h, gp_op_t op, int64_t n, int64_t m, gp_prec_t prec) {
     switch (op) {
     case GP_OP_POTRF:
         L.dinv = take(sizeof(double) * DB * DB * (size_t)nb);
+        L.pflags = take(panel_flags_bytes());
         take_panel();
         break;
     case GP_OP_TRSV:
@@ -133,6 +135,7 @@ Layout layout(gp_handle_t h, gp_op_t op, int64_t n, int64_t m, gp_prec_t prec) {
     case GP_OP_LOGLIK:
     case GP_OP_LOGLIK_GRAD:
         L.dinv = take(sizeof(double) * DB * DB * (size_t)nb);
+        L.pflags = take(panel_flags_bytes());
         take_panel();
         L.sync = take(trsv_work_bytes(n));
         L.z = take(vec);     // L^{-1} b
@@ -191,6 +194,7 @@ PanelBufs panel_bufs(void *ws, const Layout &L) {
         p.vtmp = at<double>(ws, L.vtmp);
         if (L.qbuf) p.qbuf = at<char>(ws, L.qbuf);
     }
+    if (L.pflags) p.pflags = at<int>(ws, L.pflags);
     return p;
 }
 
@@ -409,6 +413,11 @@ int potrf_impl(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda,
 
     // (1) for the panel [c0, c1)
     auto diag_block = [&](hipStream_t st, int64_t c0, int64_t c1) -> int {
+        if (h->opt.fused_panel && pb.pflags && c1 - c0 <= DB * PF_MAXB && (c1 == n || pb.vinv)) {
+            HIPCHK(launch_panel_chol(st, A + c0 + c0 * lda, lda, (int)(c1 - c0), dinv + (c0 / DB) * DB * DB,
+                                     c1 < n ? pb.vinv : nullptr, c1 - c0, pb.pflags, info, c0));
+            return GP_OK;
+        }
         for (int64_t d = c0; d < c1; d += DB) {
             const int jb = (int)((n - d) < DB ? (n - d) : DB);
             double *W = dinv + (d / DB) * DB * DB;
@@ -692,6 +701,7 @@ static void default_options(gp_options_t *o) {
     o->ir_max_iter = 20;
     o->ir_tol = 1e-10;
     o->reorder = 1;
+    o->fused_panel = 1;
 }
 
 int gp_create(gp_handle_t *h, void *stream) {
@@ -780,6 +790,7 @@ int gp_set_options(gp_handle_t h, const gp_options_t *opt) {
     }
     if (opt->nb < 0 || opt->nb % DB != 0) return -2;
     if (opt->ir_max_iter < 0 || opt->band < -1 || opt->panel_cus < 0) return -2;
+    if (opt->fused_panel != 0 && opt->fused_panel != 1) return -2;
     if (!(opt->ir_tol >= 0.0) || isinf(opt->ir_tol)) return GP_ERR_NONFINITE;
     h->opt = *opt;
     return GP_OK;

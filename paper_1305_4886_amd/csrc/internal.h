@@ -382,6 +382,15 @@ hipError_t launch_panel_solve(hipStream_t s, double *A, int64_t lda, const doubl
 hipError_t launch_diag_potrf(hipStream_t s, double *A, int64_t lda, int jb, double *Winv,
                              int32_t *info, int64_t col0);
 hipError_t launch_diag_inv(hipStream_t s, const double *L, int64_t ldl, int64_t n, double *dinv);
+// The diagonal K x K block of a panel (K <= 64 PF_MAXB) in one launch of
+// ceil(K / 64) concurrent workgroups: L in place (A, lda), the 64 x 64 block
+// inverses into dinv and, if W is non-null (K % 64 == 0), W = L^{-1} (ld ldw,
+// zeros above the diagonal).  flags: panel_flags_bytes() of workspace.
+// A non-positive pivot sets *info = col0 + its 1-based column in the block.
+constexpr int PF_MAXB = 16;
+constexpr size_t panel_flags_bytes() { return sizeof(int) * (PF_MAXB * PF_MAXB + 64); }
+hipError_t launch_panel_chol(hipStream_t s, double *A, int64_t lda, int K, double *dinv, double *W, int64_t ldw,
+                             int *flags, int32_t *info, int64_t col0);
 // Work area of a triangular solve: trsv_work_bytes(n) bytes (counters and a
 // mailbox of n doubles); the abort flag is its int [1].
 size_t trsv_work_bytes(int64_t n);

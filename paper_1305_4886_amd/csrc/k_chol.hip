@@ -61,6 +61,271 @@ __global__ __launch_bounds__(64) void k_diag_potrf(double *A, int64_t lda, int j
     for (int c = 0; c < DB; ++c) Winv[lane + c * DB] = Wl[lane][c];
 }
 
+// ---------------------------------------------------------------------------
+// k_panel_chol: the K x K diagonal block of one panel (K <= 64 PF_MAXB) in a
+// single launch of NB = ceil(K / 64) workgroups that run concurrently and
+// hand 64 x 64 blocks to each other through memory, instead of a chain of
+// ~4 launches per 64 columns (factor, solve, update) plus the launches of
+// the blocked inverse -- every one of which waits for a free slot behind the
+// trailing update and pays a dispatch latency on the critical path.
+//
+// Phase 1 (workgroup b owns block row b; right-looking by block columns k):
+//   when L_kk and W_k = L_kk^{-1} are published:
+//     L_bk = S_bk W_k^T, published;  S_bj -= L_bk L_jk^T for k < j <= b
+//     (L_jk from workgroup j as soon as it is published);
+//   after the last column: L_bb = chol(S_bb) and W_b (one wave, as in
+//   k_diag_potrf), published.  Critical path per 64 columns: two 64^3
+//   products, the 64 x 64 factor and inverse, and one flag round trip.
+// Phase 2 (only when the rows below the panel follow, K % 64 == 0;
+// workgroup b owns block column b of W = L^{-1}):
+//   W_bb = W_b;  for k = b, b + 1, ...: T_sb += L_sk W_kb for s > k (in the
+//   W buffer), then W_{k+1,b} = -W_{k+1} T_{k+1,b}.
+//
+// Every block another workgroup reads is written and read with relaxed
+// agent-scope atomic accesses (coherent across XCDs, no cache-wide fence);
+// a publisher waits for its stores (vmcnt 0, barrier) before it raises the
+// block's flag.  Waits are bounded: on a timeout or a failed pivot the abort
+// flag stops every workgroup.  Outputs: L in place, W_b into dinv (column-
+// major 64 x 64 per block), W (ld ldw, zeros above the diagonal) if non-null.
+// ---------------------------------------------------------------------------
+constexpr int PF_ABORT = PF_MAXB * PF_MAXB;
+
+GP_DEV double ld_coh(const double *p) {
+    return __longlong_as_double((long long)__hip_atomic_load(
+        reinterpret_cast<uint64_t *>(const_cast<double *>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+GP_DEV void st_coh(double *p, double v) {
+    __hip_atomic_store(reinterpret_cast<uint64_t *>(p), (uint64_t)__double_as_longlong(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0 waits for flags[idx] (bounded); every thread gets the outcome.
+GP_DEV bool pf_wait(int *flags, int idx, int *s_ok) {
+    if (threadIdx.x == 0) {
+        int ok = 1, spins = 0;
+        while (__hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+            if (__hip_atomic_load(&flags[PF_ABORT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > SPIN_LIMIT) {
+                __hip_atomic_store(&flags[PF_ABORT], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+        }
+        *s_ok = ok;
+    }
+    __syncthreads();
+    return *s_ok != 0;
+}
+
+// All of this workgroup's stores done, then flags[idx] = 1.
+GP_DEV void pf_publish(int *flags, int idx) {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(&flags[idx], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// dst[r][c] = M[r + c ld] (T: dst[c][r] = M[r + c ld]) for r < rows, c < cols; 0 elsewhere.
+template <bool T>
+GP_DEV void pf_load(double (*dst)[DB + 1], const double *M, int64_t ld, int rows, int cols) {
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int e = threadIdx.x + 256 * q, r = e & (DB - 1), c = e >> 6;
+        v[q] = (r < rows && c < cols) ? ld_coh(M + r + (int64_t)c * ld) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int e = threadIdx.x + 256 * q, r = e & (DB - 1), c = e >> 6;
+        if (T)
+            dst[c][r] = v[q];
+        else
+            dst[r][c] = v[q];
+    }
+}
+
+// acc[n][i] = sum_m X(row, m) Y[col][m] over m < 64, wave w: row = 16 w +
+// lane / 16 + 4 i, col = 16 n + lane % 16 (the D layout of
+// v_mfma_f64_16x16x4).  X from LDS (Xs[row][m]) or, with Xs null, from memory
+// (Xg[row + m ldx], rows >= xrows read as zero).
+GP_DEV void pf_gemm(const double (*Xs)[DB + 1], const double *Xg, int64_t ldx, int xrows, const double (*Y)[DB + 1],
+                    gp_v4d (&acc)[4], int w, int lane) {
+    const int row = 16 * w + (lane & 15);
+    double a[16];
+    if (Xs) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) a[q] = Xs[row][4 * q + (lane >> 4)];
+    } else {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) a[q] = row < xrows ? ld_coh(Xg + row + (int64_t)(4 * q + (lane >> 4)) * ldx) : 0.0;
+    }
+#pragma unroll
+    for (int n = 0; n < 4; ++n) acc[n] = gp_v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+            acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], Y[16 * n + (lane & 15)][4 * q + (lane >> 4)], acc[n], 0,
+                                                          0, 0);
+}
+
+// M(row, col) += sgn acc for the wave's rows < rows and cols < cols (and col <= row
+// if lower); loads first, then stores.
+GP_DEV void pf_accum(double *M, int64_t ld, const gp_v4d (&acc)[4], double sgn, int rows, int cols, bool lower, int w,
+                     int lane) {
+    double v[16];
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * w + (lane >> 4) + 4 * i, c = 16 * n + (lane & 15);
+            const bool ok = r < rows && c < cols && (!lower || c <= r);
+            v[4 * n + i] = ok ? ld_coh(M + r + (int64_t)c * ld) : 0.0;
+        }
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * w + (lane >> 4) + 4 * i, c = 16 * n + (lane & 15);
+            const bool ok = r < rows && c < cols && (!lower || c <= r);
+            if (ok) st_coh(M + r + (int64_t)c * ld, fma(sgn, acc[n][i], v[4 * n + i]));
+        }
+}
+
+__global__ __launch_bounds__(256, 1) void k_panel_chol(double *A, int64_t lda, int K, double *dinv, double *W,
+                                                       int64_t ldw, int *flags, int32_t *info, int64_t col0) {
+    // 74 KB, so that a workgroup fits beside one workgroup of the trailing update
+    __shared__ union {
+        struct {
+            double op[DB][DB + 1];  // B operand of the current product
+            double lb[DB][DB + 1];  // L_bk of the current column (phase 1), W_kb^T (phase 2)
+        } g;
+        struct {
+            double ls[DB][DB + 1];  // factor workspace, then L_bb
+            double wl[DB][DB + 1];  // W_b
+            union {
+                double pn[DB][17];
+                double t32[32][33];
+            } u;
+            double rd[DB];
+        } d;
+    } sm;
+    __shared__ int s_ok;
+    if (*info) return;
+    const int nb = (K + DB - 1) / DB;
+    const int b = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int rb = K - DB * b < DB ? K - DB * b : DB;  // rows (and columns) of block b
+    double *Ab = A + DB * b;                           // block row b: Ab[r + c lda]
+    gp_v4d acc[4];
+
+    // ---- phase 1 ----
+    for (int k = 0; k < b; ++k) {
+        if (!pf_wait(flags, k * PF_MAXB + k, &s_ok)) return;
+        pf_load<false>(sm.g.op, dinv + (int64_t)k * DB * DB, DB, DB, DB);  // W_k
+        __syncthreads();
+        pf_gemm(nullptr, Ab + (int64_t)DB * k * lda, lda, rb, sm.g.op, acc, w, lane);  // L_bk = S_bk W_k^T
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * w + (lane >> 4) + 4 * i, c = 16 * n + (lane & 15);
+                sm.g.lb[r][c] = acc[n][i];
+                if (r < rb) st_coh(Ab + r + (int64_t)(DB * k + c) * lda, acc[n][i]);
+            }
+        pf_publish(flags, b * PF_MAXB + k);  // its barrier also orders the lb writes
+        for (int j = k + 1; j <= b; ++j) {
+            const double (*Y)[DB + 1] = sm.g.lb;
+            if (j < b) {
+                if (!pf_wait(flags, j * PF_MAXB + k, &s_ok)) return;
+                pf_load<false>(sm.g.op, A + DB * j + (int64_t)DB * k * lda, lda, DB, DB);  // L_jk
+                __syncthreads();
+                Y = sm.g.op;
+            }
+            pf_gemm(sm.g.lb, nullptr, 0, 0, Y, acc, w, lane);  // L_bk L_jk^T
+            // S_bj -= L_bk L_jk^T (the diagonal block's lower triangle only)
+            pf_accum(Ab + (int64_t)DB * j * lda, lda, acc, -1.0, rb, j < b ? DB : rb, j == b, w, lane);
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();  // op is reloaded next; S_bj stores complete
+        }
+    }
+    // diagonal block: one wave factors and inverts it
+    if (w == 0) {
+        double a[DB];
+        double *D = Ab + (int64_t)DB * b * lda;
+#pragma unroll
+        for (int c = 0; c < DB; ++c) {
+            double v;
+            if (lane < rb && c < rb) v = (c <= lane) ? ld_coh(D + lane + (int64_t)c * lda) : 0.0;
+            else v = (lane == c) ? 1.0 : 0.0;
+            a[c] = v;
+        }
+        const int fail = wave_chol64(a, lane, sm.d.ls, sm.d.u.pn);
+        if (fail) {
+            if (lane == 0) {
+                *info = (int32_t)(col0 + DB * b + fail);
+                __hip_atomic_store(&flags[PF_ABORT], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_ok = 0;
+            }
+        } else {
+            if (lane == 0) s_ok = 1;
+#pragma unroll
+            for (int c = 0; c < DB; ++c) sm.d.ls[lane][c] = a[c];
+            wave_lds_sync();
+#pragma unroll
+            for (int c = 0; c < DB; ++c)
+                if (lane < rb && c < rb && c <= lane) st_coh(D + lane + (int64_t)c * lda, a[c]);
+            wave_inv64_blocked(sm.d.ls, sm.d.wl, sm.d.u.t32, sm.d.rd, lane);
+            double *Wb = dinv + (int64_t)b * DB * DB;
+#pragma unroll 4
+            for (int c = 0; c < DB; ++c) st_coh(Wb + lane + c * DB, sm.d.wl[lane][c]);
+        }
+    }
+    __syncthreads();
+    if (!s_ok) return;
+    // phase 2 starts from W_b; its block column of W is written before the
+    // publication, while W_b is still in LDS
+    double *Wc = W ? W + (int64_t)DB * b * ldw : nullptr;  // block column b: Wc[r + c ldw], r < K
+    if (W) {
+        for (int e = tid; e < DB * DB; e += 256) {
+            const int r = e & (DB - 1), c = e >> 6;
+            for (int s2 = 0; s2 < b; ++s2) Wc[DB * s2 + r + (int64_t)c * ldw] = 0.0;  // above the diagonal
+            st_coh(Wc + DB * b + r + (int64_t)c * ldw, sm.d.wl[r][c]);              // W_bb
+            for (int s2 = b + 1; s2 < nb; ++s2) st_coh(Wc + DB * s2 + r + (int64_t)c * ldw, 0.0);  // T_sb = 0
+        }
+    }
+    pf_publish(flags, b * PF_MAXB + b);
+    if (!W) return;
+
+    // ---- phase 2: block column b of W = L^{-1} ----
+    for (int k = b; k + 1 < nb; ++k) {
+        pf_load<true>(sm.g.lb, Wc + DB * k, ldw, DB, DB);  // lb[c][m] = W_kb(m, c)
+        __syncthreads();
+        for (int s2 = k + 1; s2 < nb; ++s2) {
+            if (!pf_wait(flags, s2 * PF_MAXB + k, &s_ok)) return;
+            pf_gemm(nullptr, A + DB * s2 + (int64_t)DB * k * lda, lda, DB, sm.g.lb, acc, w, lane);  // L_sk W_kb
+            pf_accum(Wc + DB * s2, ldw, acc, 1.0, DB, DB, false, w, lane);                       // T_sb +=
+        }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();  // T stores complete
+        if (!pf_wait(flags, (k + 1) * PF_MAXB + (k + 1), &s_ok)) return;
+        pf_load<true>(sm.g.op, Wc + DB * (k + 1), ldw, DB, DB);  // op[c][m] = T(m, c)
+        __syncthreads();
+        pf_gemm(nullptr, dinv + (int64_t)(k + 1) * DB * DB, DB, DB, sm.g.op, acc, w, lane);  // W_{k+1} T
+        double *Wk = Wc + DB * (k + 1);
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                st_coh(Wk + (16 * w + (lane >> 4) + 4 * i) + (int64_t)(16 * n + (lane & 15)) * ldw, -acc[n][i]);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();  // W_{k+1,b} complete before it is read as the next W_kb; lb and op free
+    }
+}
+
 __global__ __launch_bounds__(64) void k_diag_inv(const double *L, int64_t ldl, int64_t n, double *dinv) {
     __shared__ double Ls[DB][DB + 1];
     __shared__ double Wl[DB][DB + 1];
@@ -384,6 +649,17 @@ __global__ __launch_bounds__(256) void k_loglik_reduce(int64_t n, const double *
 hipError_t launch_diag_potrf(hipStream_t s, double *A, int64_t lda, int jb, double *Winv,
                              int32_t *info, int64_t col0) {
     hipLaunchKernelGGL(k_diag_potrf, dim3(1), dim3(64), 0, s, A, lda, jb, Winv, info, col0);
+    return hipGetLastError();
+}
+
+hipError_t launch_panel_chol(hipStream_t s, double *A, int64_t lda, int K, double *dinv, double *W, int64_t ldw,
+                             int *flags, int32_t *info, int64_t col0) {
+    if (K <= 0) return hipSuccess;
+    if (K > DB * PF_MAXB || (W && (K % DB != 0 || ldw < K))) return hipErrorInvalidValue;
+    hipError_t e = launch_fill(s, flags, panel_flags_bytes());
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_panel_chol, dim3((unsigned)((K + DB - 1) / DB)), dim3(256), 0, s, A, lda, K, dinv, W, ldw,
+                       flags, info, col0);
     return hipGetLastError();
 }
 

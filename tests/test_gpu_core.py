@@ -68,16 +68,20 @@ def test_cross_cov(orc, n, m):
     np.testing.assert_allclose(M, orc.cross_cov(1, t, X, Xs), rtol=1e-14, atol=1e-300)
 
 
-# (n, panel width, lookahead, compute units reserved for the lookahead chain)
+# (n, panel width, lookahead, compute units reserved for the lookahead chain,
+#  fused panel kernel or the per-64-column launch chain)
 POTRF_CASES = [
-    (1, 256, 1, 8), (2, 256, 1, 8), (63, 256, 1, 8), (64, 256, 1, 8), (65, 256, 1, 8), (127, 64, 0, 0),
-    (200, 128, 1, 8), (257, 256, 1, 0), (500, 64, 1, 8), (1000, 256, 1, 8), (1000, 256, 0, 8),
-    (1100, 128, 1, 0), (2048, 512, 1, 8), (3001, 256, 1, 16), (3001, 192, 1, 8), (4500, 512, 1, 8),
+    (1, 256, 1, 8, 1), (2, 256, 1, 8, 1), (63, 256, 1, 8, 1), (64, 256, 1, 8, 1), (65, 256, 1, 8, 1),
+    (127, 64, 0, 0, 1), (200, 128, 1, 8, 1), (257, 256, 1, 0, 1), (500, 64, 1, 8, 1), (1000, 256, 1, 8, 1),
+    (1000, 256, 0, 8, 1), (1100, 128, 1, 0, 1), (2048, 512, 1, 8, 1), (3001, 256, 1, 16, 1),
+    (3001, 192, 1, 8, 1), (4500, 512, 1, 8, 1), (3001, 768, 1, 0, 1), (2500, 1024, 1, 0, 1),
+    (2500, 1024, 0, 0, 1),
+    (127, 64, 0, 0, 0), (1000, 256, 1, 8, 0), (3001, 192, 1, 8, 0), (4500, 512, 1, 0, 0),
 ]
 
 
-@pytest.mark.parametrize("n,nb,la,pc", POTRF_CASES)
-def test_potrf_parity(orc, n, nb, la, pc):
+@pytest.mark.parametrize("n,nb,la,pc,fused", POTRF_CASES)
+def test_potrf_parity(orc, n, nb, la, pc, fused):
     X = synth.uniform_points(n, 100 + n)
     t = logth(1.0, 0.1, 0.1)
     C = orc.cov(0, t, X)
@@ -86,12 +90,13 @@ def test_potrf_parity(orc, n, nb, la, pc):
     gp.colmajor(S, n).copy_(torch.as_tensor(np.tril(C) + np.triu(np.full((n, n), -3.25), 1)))
     h = gp.handle()
     saved = h.options()
-    h.set_options(nb=nb, lookahead=la, panel_cus=pc)
+    h.set_options(nb=nb, lookahead=la, panel_cus=pc, fused_panel=fused)
     try:
         info = gp.potrf(S, n)
         torch.cuda.synchronize()
     finally:
-        h.set_options(nb=saved.nb, lookahead=saved.lookahead, panel_cus=saved.panel_cus)
+        h.set_options(nb=saved.nb, lookahead=saved.lookahead, panel_cus=saved.panel_cus,
+                      fused_panel=saved.fused_panel)
     assert int(info.item()) == 0
     M = gp.colmajor(S, n).cpu().numpy()
     assert np.all(M[np.triu_indices(n, 1)] == -3.25), "upper triangle must stay untouched"
