@@ -606,11 +606,11 @@ __global__ __launch_bounds__(256, 2) void k_syrk_pk(GemmDesc d, TileMap tm, cons
     constexpr int STAGES = 4, BM = 128, WTM = 64, FM = 4, FN = 4;
     constexpr int BKD = PREC == 1 ? 16 : 32;                    // panel columns per slab
     constexpr int EB = PREC == 1 ? 4 : 2;                       // bytes per element
-    constexpr int CHUNKS = 2 * BM * BKD * EB / 256;             // 256-byte copies per slab (both operands)
+    constexpr int CHUNKS = 2 * BM * BKD * EB / 1024;            // 1 KB copies per slab (both operands)
     constexpr int PER = CHUNKS / 4;                             // per wave
     constexpr int NKK = PREC == 1 ? BKD / 4 : 1;                // MFMA K-steps per slab
     static_assert((STAGES - 2) * PER < 64, "outstanding copies exceed vmcnt");
-    static_assert(PER % NKK == 0, "copies per K-step");
+    static_assert(PER == 4 && CHUNKS / 2 == 8, "slab = 8 chunks per operand");
     static_assert(STAGES * 2 * BM * BKD * EB >= 4 * 2048 * 8, "the ring holds the epilogue's four wave regions");
     __shared__ __attribute__((aligned(16))) char Ls[STAGES][2][BM * BKD * EB];
 
@@ -628,7 +628,11 @@ __global__ __launch_bounds__(256, 2) void k_syrk_pk(GemmDesc d, TileMap tm, cons
     double *C = d.C;
     const int nk = (int)((d.K + BKD - 1) / BKD);
     const char *Q = static_cast<const char *>(Qv);
-    const uint32_t voff = 4u * (uint32_t)lane;
+    // 16-byte copies (global_load_lds_dwordx4), lane l -> LDS bytes 16 l .. of
+    // a 1 KB chunk.  FP32 chunk cc: columns 2 cc (lanes 0-31) and 2 cc + 1
+    // (lanes 32-63), 4 rows per lane; BF16 chunk cc: rows 16 cc .. 16 cc + 15,
+    // contiguous in both layouts.
+    const uint32_t voff = PREC == 1 ? (uint32_t)(4 * ((lane >> 5) * Mp + 4 * (lane & 31))) : 16u * (uint32_t)lane;
 
     // copy q of this wave for slab `slab` into stage st: chunk c = wave + 4 q
     auto copy1 = [&](int slab, int st, int q) {
@@ -636,14 +640,11 @@ __global__ __launch_bounds__(256, 2) void k_syrk_pk(GemmDesc d, TileMap tm, cons
         const int op = c / (CHUNKS / 2), cc = c % (CHUNKS / 2);
         const int64_t row0 = qrow0 + (op ? j0 : i0);
         const char *src;
-        if (PREC == 1) {  // chunk cc: column cc / 2, rows 64 (cc % 2) ..
-            const int col = cc >> 1, half = cc & 1;
-            src = Q + 4 * ((int64_t)(slab * BKD + col) * Mp + row0 + 64 * half);
-        } else {          // chunk cc: rows 4 cc .. 4 cc + 3 of the 32-column slab
-            src = Q + 2 * (((int64_t)slab * Mp + row0) * 32 + 128 * (int64_t)cc);
-        }
-        lds_dma_dword(reinterpret_cast<const double *>(src), voff,
-                      (uint32_t)(uintptr_t)&Ls[st][op][256 * cc]);
+        if (PREC == 1)
+            src = Q + 4 * ((int64_t)(slab * BKD + 2 * cc) * Mp + row0);
+        else
+            src = Q + 2 * (((int64_t)slab * Mp + row0) * 32 + 512 * (int64_t)cc);
+        lds_dma_dwordx4(reinterpret_cast<const double *>(src), voff, (uint32_t)(uintptr_t)&Ls[st][op][1024 * cc]);
     };
 
 #pragma unroll
@@ -685,7 +686,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk_pk(GemmDesc d, TileMap tm, cons
                     for (int n = 0; n < FN; ++n)
                         acc[q][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b[n], acc[q][n], 0, 0, 0);
                     __builtin_amdgcn_sched_barrier(0);
-                    if (more) copy1(ns, nst, kk * 4 + q);
+                    if (more && q == 3) copy1(ns, nst, kk);
                     __builtin_amdgcn_sched_barrier(0);
                 }
             } else {
@@ -700,11 +701,11 @@ __global__ __launch_bounds__(256, 2) void k_syrk_pk(GemmDesc d, TileMap tm, cons
                     b[n] = *reinterpret_cast<const v8bf *>(&B[(wn * WTM + n * 16 + (lane & 15)) * 32 + 8 * (lane >> 4)]);
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int q = 0; q < PER; ++q) {
+                for (int q = 0; q < FM * FN; ++q) {
                     const int m = q >> 2, n = q & 3;
                     acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[n], acc[m][n], 0, 0, 0);
                     __builtin_amdgcn_sched_barrier(0);
-                    if (more) copy1(ns, nst, q);
+                    if (more && (q & 3) == 3) copy1(ns, nst, q >> 2);
                     __builtin_amdgcn_sched_barrier(0);
                 }
             }
@@ -1069,6 +1070,7 @@ hipError_t launch_syrk_packed(hipStream_t s, gp_prec_t prec, int band, const dou
     tm.band = b;
     const int64_t g = ((tm.ntiles + 7) / 8) * 8;
     const int64_t Mp = packed_rows(Mpack);
+    if (((uintptr_t)Q & 15) != 0 || qrow0 % 64 != 0) return hipErrorInvalidValue;  // 16-byte copies
     if (prec == GP_FP32_TRAIL)
         hipLaunchKernelGGL((k_syrk_pk<1, 1>), dim3((unsigned)g), dim3(256), 0, s, d, tm, Q, Mp, qrow0);
     else
