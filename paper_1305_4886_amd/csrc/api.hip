@@ -244,7 +244,17 @@ hipError_t trailing_packed(gp_handle_t h, hipStream_t s, gp_prec_t prec, const d
         h->prof_used += 2;
         hipEventRecord(e0, s);
     }
-    hipError_t e = launch_syrk_packed(s, prec, h->opt.band, P, ldp, Q, Mpack, qrow0, C, ldc, M, N, K, info);
+    // FP64 band tiles on their own stream, concurrent with the low-precision
+    // tiles (disjoint C tiles, same read-only panel)
+    hipError_t e = hipSuccess;
+    if (h->opt.band > 0) {
+        e = hipEventRecord(h->ev_band_in, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(h->band, h->ev_band_in, 0);
+        if (e == hipSuccess) e = launch_band_f64(h->band, h->opt.band, P, ldp, C, ldc, M, N, K, info);
+        if (e == hipSuccess) e = hipEventRecord(h->ev_band_out, h->band);
+    }
+    if (e == hipSuccess) e = launch_lowp_packed(s, prec, h->opt.band, P, ldp, Q, Mpack, qrow0, C, ldc, M, N, K, info);
+    if (e == hipSuccess && h->opt.band > 0) e = hipStreamWaitEvent(s, h->ev_band_out, 0);
     if (h->prof) {
         hipEventRecord(e1, s);
         h->prof_flops += syrk_flops(M, N, K);
@@ -714,11 +724,17 @@ int gp_create(gp_handle_t *h, void *stream) {
     if (hipGetDevice(&p->device) != hipSuccess ||
         hipDeviceGetAttribute(&p->num_cu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess ||
         hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&p->band, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_band_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_band_out, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_cols, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_panel, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_out, hipEventDisableTiming) != hipSuccess) {
         if (p->side) hipStreamDestroy(p->side);
+        if (p->band) hipStreamDestroy(p->band);
+        if (p->ev_band_in) hipEventDestroy(p->ev_band_in);
+        if (p->ev_band_out) hipEventDestroy(p->ev_band_out);
         if (p->ev_cols) hipEventDestroy(p->ev_cols);
         if (p->ev_panel) hipEventDestroy(p->ev_panel);
         if (p->ev_in) hipEventDestroy(p->ev_in);
@@ -761,6 +777,10 @@ int gp_destroy(gp_handle_t h) {
     batch_staging_free(h->batch_staging);
     hipStreamSynchronize(h->side);
     hipStreamDestroy(h->side);
+    hipStreamSynchronize(h->band);
+    hipStreamDestroy(h->band);
+    hipEventDestroy(h->ev_band_in);
+    hipEventDestroy(h->ev_band_out);
     if (h->main_cu) {
         hipStreamSynchronize(h->main_cu);
         hipStreamSynchronize(h->side_cu);

@@ -26,6 +26,11 @@ struct gp_handle_s {
     hipEvent_t ev_panel = nullptr; // side -> main: next panel factored
     hipEvent_t ev_in = nullptr;    // caller's stream -> masked main stream
     hipEvent_t ev_out = nullptr;   // masked main stream -> caller's stream
+    // mixed modes: the FP64 band tiles of a trailing update run on `band`
+    // (default priority) next to the low-precision tiles on the main stream
+    hipStream_t band = nullptr;
+    hipEvent_t ev_band_in = nullptr;   // main -> band: panel packed
+    hipEvent_t ev_band_out = nullptr;  // band -> main: band tiles updated
     // With opt.panel_cus > 0 the factorisation runs on two streams of its own:
     // main_cu, masked to every compute unit but panel_cus reserved ones, and
     // side_cu, free to use all of them, so the lookahead chain always finds
@@ -362,6 +367,13 @@ size_t packed_panel_bytes(int64_t M, int64_t K);
 hipError_t launch_pack_panel(hipStream_t s, gp_prec_t prec, const double *P, int64_t ldp, int64_t M, int64_t K,
                              void *Q);
 hipError_t launch_syrk_packed(hipStream_t s, gp_prec_t prec, int band, const double *P, int64_t ldp, const void *Q,
+                              int64_t Mpack, int64_t qrow0, double *C, int64_t ldc, int64_t M, int64_t N, int64_t K,
+                              const int32_t *info);
+// The two halves of launch_syrk_packed, for callers that overlap them: the FP64
+// tiles on the first `band` tile diagonals, and the low-precision rest.
+hipError_t launch_band_f64(hipStream_t s, int band, const double *P, int64_t ldp, double *C, int64_t ldc, int64_t M,
+                           int64_t N, int64_t K, const int32_t *info);
+hipError_t launch_lowp_packed(hipStream_t s, gp_prec_t prec, int band, const double *P, int64_t ldp, const void *Q,
                               int64_t Mpack, int64_t qrow0, double *C, int64_t ldc, int64_t M, int64_t N, int64_t K,
                               const int32_t *info);
 // C = beta C + alpha P P^T on the lower triangle of the M x M matrix C, P

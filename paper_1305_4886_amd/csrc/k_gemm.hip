@@ -1041,7 +1041,29 @@ hipError_t launch_pack_panel(hipStream_t s, gp_prec_t prec, const double *P, int
     return hipGetLastError();
 }
 
-hipError_t launch_syrk_packed(hipStream_t s, gp_prec_t prec, int band, const double *P, int64_t ldp, const void *Q,
+hipError_t launch_band_f64(hipStream_t s, int band, const double *P, int64_t ldp, double *C, int64_t ldc, int64_t M,
+                           int64_t N, int64_t K, const int32_t *info) {
+    if (M <= 0 || N <= 0 || K <= 0 || band <= 0) return hipSuccess;
+    GemmDesc d{};
+    d.A = P; d.lda = ldp; d.B = P; d.ldb = ldp; d.C = C; d.ldc = ldc;
+    d.M = M; d.N = N; d.K = K; d.alpha = -1.0; d.beta = 1.0;
+    d.ta = 0; d.tb = 1; d.lower = 1; d.batch = 1; d.info = info;
+    TileMap tb = make_map(M, N, 128, 128, 1);
+    tb.bandmode = 1;
+    tb.band = band;
+    tb.ntiles = tb.ntn * band;
+    const int64_t g = ((tb.ntiles + 7) / 8) * 8;
+    const bool x4 = M % 2 == 0 && N % 2 == 0 && M >= 2 && ldp % 2 == 0 && ((uintptr_t)P & 15) == 0;
+    if (K % 8 != 0)
+        hipLaunchKernelGGL((k_gemm_f64<128, 128, 2, 2, 0, 1, 4>), dim3((unsigned)g), dim3(256), 0, s, d, tb);
+    else if (x4)
+        hipLaunchKernelGGL((k_syrk_dma<2, 16, 4, true>), dim3((unsigned)g), dim3(256), 0, s, d, tb);
+    else
+        hipLaunchKernelGGL((k_syrk_dma<4, 8, 4, false>), dim3((unsigned)g), dim3(256), 0, s, d, tb);
+    return hipGetLastError();
+}
+
+hipError_t launch_lowp_packed(hipStream_t s, gp_prec_t prec, int band, const double *P, int64_t ldp, const void *Q,
                               int64_t Mpack, int64_t qrow0, double *C, int64_t ldc, int64_t M, int64_t N, int64_t K,
                               const int32_t *info) {
     if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
@@ -1050,19 +1072,6 @@ hipError_t launch_syrk_packed(hipStream_t s, gp_prec_t prec, int band, const dou
     d.M = M; d.N = N; d.K = K; d.alpha = -1.0; d.beta = 1.0;
     d.ta = 0; d.tb = 1; d.lower = 1; d.batch = 1; d.info = info;
     const int64_t b = band > 0 ? band : 0;
-    if (b > 0) {  // FP64 on the first `band` tile diagonals
-        TileMap tb = make_map(M, N, 128, 128, 1);
-        tb.bandmode = 1;
-        tb.band = b;
-        tb.ntiles = tb.ntn * b;
-        const int64_t g = ((tb.ntiles + 7) / 8) * 8;
-        if (K % 8 == 0)
-            hipLaunchKernelGGL((k_syrk_dma<4, 8, 4>), dim3((unsigned)g), dim3(256), 0, s, d, tb);
-        else
-            hipLaunchKernelGGL((k_gemm_f64<128, 128, 2, 2, 0, 1, 4>), dim3((unsigned)g), dim3(256), 0, s, d, tb);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
     TileMap tm = make_map(M, N, 128, 128, 1);
     tm.sgm = tm.sgn = 1;
     tm.ntiles = tm.ntn * (tm.ntn + 1) / 2 + (tm.ntm - tm.ntn) * tm.ntn;
@@ -1076,6 +1085,14 @@ hipError_t launch_syrk_packed(hipStream_t s, gp_prec_t prec, int band, const dou
     else
         hipLaunchKernelGGL((k_syrk_pk<2, 1>), dim3((unsigned)g), dim3(256), 0, s, d, tm, Q, Mp, qrow0);
     return hipGetLastError();
+}
+
+hipError_t launch_syrk_packed(hipStream_t s, gp_prec_t prec, int band, const double *P, int64_t ldp, const void *Q,
+                              int64_t Mpack, int64_t qrow0, double *C, int64_t ldc, int64_t M, int64_t N, int64_t K,
+                              const int32_t *info) {
+    hipError_t e = launch_band_f64(s, band, P, ldp, C, ldc, M, N, K, info);
+    if (e != hipSuccess) return e;
+    return launch_lowp_packed(s, prec, band, P, ldp, Q, Mpack, qrow0, C, ldc, M, N, K, info);
 }
 
 hipError_t launch_gemm_nt_dma(hipStream_t s, const GemmDesc &d) {
