@@ -32,6 +32,7 @@ struct TileMap {
     int sgm, sgn;   // super-tile shape in tiles
     int bandmode;   // 0 all tiles, 1 only 0 <= bi - bj < band (own enumeration), 2 only bi - bj >= band
     int64_t band;
+    int interleave; // 1: tile t = workgroup id (round-robin over the XCDs), 0: XCD-contiguous ranges
 };
 
 GP_DEV void tri_decode(int64_t t, int64_t &bi, int64_t &bj) {
@@ -80,8 +81,13 @@ GP_DEV bool decode_tile(const TileMap &tm, int64_t t, int64_t &bi, int64_t &bj) 
 }
 
 // Eight XCDs receive workgroups round-robin; give each XCD a contiguous range
-// of logical tiles.  gridDim.x is a multiple of 8.
-GP_DEV int64_t xcd_remap() {
+// of logical tiles (neighbouring tiles share panel rows in that XCD's L2).
+// gridDim.x is a multiple of 8.  Products whose tiles have K ranges cut by a
+// triangular operand keep the round-robin order instead: their busy tiles
+// cluster in a few rows, which contiguous ranges would hand to one or two
+// XCDs.
+GP_DEV int64_t xcd_remap(const TileMap &tm) {
+    if (tm.interleave) return blockIdx.x;
     const int64_t g8 = gridDim.x >> 3;
     return (int64_t)(blockIdx.x & 7) * g8 + (blockIdx.x >> 3);
 }
@@ -102,7 +108,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmDesc d, TileMap tm) {
     __shared__ double Bs[2][BK][BN + 1];
 
     if (d.info && *d.info) return;
-    const int64_t t = xcd_remap();
+    const int64_t t = xcd_remap(tm);
     if (t >= tm.ntiles) return;
     int64_t bi, bj;
     if (!decode_tile(tm, t, bi, bj)) return;
@@ -373,7 +379,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
     __shared__ double Ls[STAGES][2][BKD][BM];  // [stage][operand][k][row]
 
     if (d.info && *d.info) return;
-    const int64_t t = xcd_remap();
+    const int64_t t = xcd_remap(tm);
     if (t >= tm.ntiles) return;
     int64_t bi, bj;
     if (!decode_tile(tm, t, bi, bj)) return;
@@ -615,7 +621,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk_pk(GemmDesc d, TileMap tm, cons
     __shared__ __attribute__((aligned(16))) char Ls[STAGES][2][BM * BKD * EB];
 
     if (d.info && *d.info) return;
-    const int64_t t = xcd_remap();
+    const int64_t t = xcd_remap(tm);
     if (t >= tm.ntiles) return;
     int64_t bi, bj;
     if (!decode_tile(tm, t, bi, bj)) return;
@@ -779,6 +785,7 @@ TileMap make_map(int64_t M, int64_t N, int BM, int BN, int lower) {
     tm.lower = lower;
     tm.bandmode = 0;
     tm.band = 0;
+    tm.interleave = 0;
     tm.ntm = (M + BM - 1) / BM;
     tm.ntn = (N + BN - 1) / BN;
     if (lower && tm.ntn > tm.ntm) tm.ntn = tm.ntm;
@@ -794,6 +801,7 @@ template <int BM, int BN, int WM, int WN, int TA, int TB, int TAG = 0>
 hipError_t run_f64(hipStream_t s, const GemmDesc &d) {
     if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return hipSuccess;
     TileMap tm = make_map(d.M, d.N, BM, BN, d.lower);
+    tm.interleave = (d.klo_i || d.klo_j || d.khi_i || d.khi_j) ? 1 : 0;
     const int64_t g = ((tm.ntiles + 7) / 8) * 8;
     hipLaunchKernelGGL((k_gemm_f64<BM, BN, WM, WN, TA, TB, TAG>), dim3((unsigned)g, (unsigned)d.batch), dim3(256),
                        0, s, d, tm);
@@ -834,7 +842,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk_lowp(GemmDesc d, TileMap tm) {
     __shared__ ET Bs[2][ROWS][COLS];
 
     if (d.info && *d.info) return;
-    const int64_t t = xcd_remap();
+    const int64_t t = xcd_remap(tm);
     if (t >= tm.ntiles) return;
     int64_t bi, bj;
     if (!decode_tile(tm, t, bi, bj)) return;
@@ -988,6 +996,7 @@ hipError_t run_dma(hipStream_t s, const GemmDesc &d) {
     TileMap tm = make_map(d.M, d.N, 128, 128, d.lower);
     tm.sgm = tm.sgn = 1;
     tm.ntiles = d.lower ? tm.ntn * (tm.ntn + 1) / 2 + (tm.ntm - tm.ntn) * tm.ntn : tm.ntm * tm.ntn;
+    tm.interleave = (d.klo_i || d.klo_j || d.khi_i || d.khi_j) ? 1 : 0;
     const int64_t g = ((tm.ntiles + 7) / 8) * 8;
     const bool x4 = d.M >= 2 && d.N >= 2 && d.M % 2 == 0 && d.N % 2 == 0 && d.lda % 2 == 0 && d.ldb % 2 == 0 &&
                     ((uintptr_t)d.A & 15) == 0 && ((uintptr_t)d.B & 15) == 0 &&
