@@ -568,7 +568,7 @@ int trsm_impl(gp_handle_t h, int trans, int64_t n, int64_t nrhs, const double *L
 // tmp holds m x 64 doubles.
 int trsm_right_lt(hipStream_t s, int64_t n, int64_t m, const double *L, int64_t ldl, double *Y, const double *dinv,
                   double *tmp, const int32_t *info) {
-    const int64_t NBT = 256;
+    const int64_t NBT = 512;
     auto nt = [&](const double *A, int64_t lda, const double *B, int64_t ldb, double *C, int64_t M, int64_t N,
                   int64_t K, double alpha, double beta) -> hipError_t {
         GemmDesc d{};
