@@ -219,7 +219,7 @@ int gp_krige(gp_handle_t h, gp_theta_t th, int64_t n, int64_t m, int32_t dim, co
  * parameter set.  Writes out3_dev[3 b + {0,1,2}] = {loglik, logdet, q} and
  * info_dev[b].  Same model and definitions as gp_loglik (FP64).  The
  * problems are factored together in 64 x 64 tiles, one tile column per step
- * for all problems at once (two launches per step plus one for the solves),
+ * for all problems at once (three launches per step plus one for the solves),
  * largest problems first. */
 int gp_loglik_batched(gp_handle_t h, int32_t nbatch, const gp_theta_t *th_host,
                       const int64_t *n_host, const int64_t *x_off_host, const int64_t *c_off_host,

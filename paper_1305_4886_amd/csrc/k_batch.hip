@@ -2,17 +2,22 @@
 // (the same model and quantities as the single-problem path: C(theta),
 // L L^T = C, L^{-1} y, log|C|, loglik; Section 1).
 //
-// Level-synchronous tile Cholesky over the whole batch on 64 x 64 tiles.  For
-// tile column j = 0, 1, ... two launches cover every problem at once:
-//   diag(j):  C_jj - sum_{k<j} L_jk L_jk^T (left-looking, matrix cores), then
-//             factor + invert it in one wave's registers (the diagonal-block
-//             Cholesky of Section 2.1 / Fig. 1);
-//   panel(j): for every tile i > j of every problem,
-//             L_ij = (C_ij - sum_{k<j} L_ik L_jk^T) Winv_jj^T.
-// Covariance tiles are generated from the points inside these kernels (C is
-// never written as a whole).  A final launch runs, per problem, the forward
-// solve z = L^{-1} y and the log-determinant / quadratic-form reductions.
-// No workgroup ever waits on another: kernel boundaries order the steps.
+// Level-synchronous right-looking tile Cholesky over the whole batch on
+// 64 x 64 tiles.  The covariance tiles of every problem are written once
+// (lower triangle), then for tile column j = 0, 1, ... three launches cover
+// every problem at once:
+//   diag(j):   factor the (already updated) tile A_jj in one wave's registers
+//              and invert it (the diagonal-block Cholesky of Section 2.1 /
+//              Fig. 1);
+//   panel(j):  L_ij = A_ij W_jj^T for every tile i > j;
+//   update(j): A_ik -= L_ij L_kj^T for every tile j < k <= i (rank-64 on the
+//              matrix cores).
+// Every launch of a level has the same short K, so a level costs the same
+// whatever the problem sizes; problems are ordered largest first and each
+// workgroup finds its problem and tile from per-level prefix counts.  A final
+// launch runs, per problem, the forward solve z = L^{-1} y and the
+// log-determinant / quadratic-form reductions.  No workgroup ever waits on
+// another: kernel boundaries order the steps.
 #include "internal.h"
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -30,184 +35,194 @@ struct BTile {
 
 constexpr int T = 64;
 
-// acc = sum_{k < j} L_ik L_jk^T for one 64 x 64 tile (4 waves, 32 x 32 each,
-// f64 MFMA layout: row lane/16 + 4r, column lane%16).
-GP_DEV void tile_update(const double *L, int64_t ld, int64_t n, int64_t i0, int64_t j0, int j,
-                        double (*As)[T + 1], double (*Bs)[T + 1], v4d (&acc)[2][2]) {
+GP_DEV void btri_decode(int64_t t, int64_t &r, int64_t &c) {  // t = r (r + 1) / 2 + c, c <= r
+    double f = (sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5;
+    r = (int64_t)f;
+    while (r * (r + 1) / 2 > t) --r;
+    while ((r + 1) * (r + 2) / 2 <= t) ++r;
+    c = t - r * (r + 1) / 2;
+}
+
+// Largest q < cnt with off[q] <= t (off non-decreasing, off[0] = 0).
+GP_DEV int find_prob(const int64_t *off, int cnt, int64_t t) {
+    int lo = 0, hi = cnt - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// acc = X Y^T for two 64 x 64 blocks (rows past xr / yr read as zero): both
+// staged k-major in LDS, 4 waves of 32 x 32 (f64 MFMA layout: row lane / 16 +
+// 4 r, column lane % 16 within each 16 x 16 block).
+GP_DEV void tile_nt(const double *X, int64_t ldx, int xr, const double *Y, int64_t ldy, int yr, double (*As)[T + 1],
+                    double (*Bs)[T + 1], v4d (&acc)[2][2]) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w & 1, wn = w >> 1;
+    double va[(T * T) / 256], vb[(T * T) / 256];
+#pragma unroll
+    for (int r = 0; r < (T * T) / 256; ++r) {
+        const int e = r * 256 + tid, ii = e & (T - 1), kk = e >> 6;
+        va[r] = ii < xr ? X[ii + (int64_t)kk * ldx] : 0.0;
+        vb[r] = ii < yr ? Y[ii + (int64_t)kk * ldy] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < (T * T) / 256; ++r) {
+        const int e = r * 256 + tid, ii = e & (T - 1), kk = e >> 6;
+        As[kk][ii] = va[r];
+        Bs[kk][ii] = vb[r];
+    }
+    __syncthreads();
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
         for (int q = 0; q < 2; ++q) acc[m][q] = v4d{0.0, 0.0, 0.0, 0.0};
-    for (int k = 0; k < j; ++k) {
-        const int64_t k0 = (int64_t)k * T;  // block k < j is a full block
-        __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < T; kk += 4) {
+        double a[2], b[2];
 #pragma unroll
-        for (int r = 0; r < (T * T) / 256; ++r) {
-            const int e = r * 256 + tid;
-            const int ii = e & (T - 1), kk = e >> 6;
-            const int64_t gi = i0 + ii, gj = j0 + ii;
-            const double va = L[gi < n ? gi + (k0 + kk) * ld : 0];
-            const double vb = L[gj < n ? gj + (k0 + kk) * ld : 0];
-            As[kk][ii] = gi < n ? va : 0.0;
-            Bs[kk][ii] = gj < n ? vb : 0.0;
-        }
-        __syncthreads();
+        for (int m = 0; m < 2; ++m) a[m] = As[kk + (lane >> 4)][wm * 32 + m * 16 + (lane & 15)];
 #pragma unroll
-        for (int kk = 0; kk < T; kk += 4) {
-            double a[2], b[2];
+        for (int q = 0; q < 2; ++q) b[q] = Bs[kk + (lane >> 4)][wn * 32 + q * 16 + (lane & 15)];
 #pragma unroll
-            for (int m = 0; m < 2; ++m) a[m] = As[kk + (lane >> 4)][wm * 32 + m * 16 + (lane & 15)];
+        for (int m = 0; m < 2; ++m)
 #pragma unroll
-            for (int q = 0; q < 2; ++q) b[q] = Bs[kk + (lane >> 4)][wn * 32 + q * 16 + (lane & 15)];
-#pragma unroll
-            for (int m = 0; m < 2; ++m)
-#pragma unroll
-                for (int q = 0; q < 2; ++q)
-                    acc[m][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[q], acc[m][q], 0, 0, 0);
+            for (int q = 0; q < 2; ++q)
+                acc[m][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[q], acc[m][q], 0, 0, 0);
+    }
+}
+
+// Covariance tiles (i, k), k <= i, of every problem (full 64 x 64 squares,
+// clipped to the problem).
+__global__ __launch_bounds__(256) void k_bcov(const BProb *__restrict__ probs, const int32_t *__restrict__ order,
+                                              const int64_t *__restrict__ off, int cnt, int dim,
+                                              const double *__restrict__ X, double *C_pool) {
+    const int q = find_prob(off, cnt, blockIdx.x);
+    const BProb P = probs[order[q]];
+    int64_t ti, tk;
+    btri_decode(blockIdx.x - off[q], ti, tk);
+    const int64_t i0 = ti * T, k0 = tk * T;
+    double *C = C_pool + P.c_off;
+    const double *Xb = X + P.x_off * dim;
+    for (int e = threadIdx.x; e < T * T; e += 256) {
+        const int64_t gi = i0 + (e & (T - 1)), gk = k0 + (e >> 6);
+        if (gi < P.n && gk < P.n) {
+            const double d = point_dist(Xb + gi * dim, Xb + gk * dim, dim);
+            C[gi + gk * P.n] = P.s2 * cov_corr(P.kind, d * P.inv_rho) + (gi == gk ? P.t2 : 0.0);
         }
     }
-    __syncthreads();
 }
 
-// S = C_ij - acc with C regenerated from the points; identity padding of the
-// last diagonal tile.
-GP_DEV void tile_residual(const BProb &P, const double *Xb, int dim, int64_t i0, int64_t j0,
-                          const v4d (&acc)[2][2], double (&sv)[2][2][4]) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int wm = w & 1, wn = w >> 1;
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-        for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t gi = i0 + wm * 32 + m * 16 + (lane >> 4) + 4 * r;
-                const int64_t gj = j0 + wn * 32 + q * 16 + (lane & 15);
-                double c;
-                if (gi < P.n && gj < P.n) {
-                    const double d = point_dist(Xb + gi * dim, Xb + gj * dim, dim);
-                    c = P.s2 * cov_corr(P.kind, d * P.inv_rho) + (gi == gj ? P.t2 : 0.0);
-                } else {
-                    c = (gi == gj) ? 1.0 : 0.0;
-                }
-                sv[m][q][r] = c - acc[m][q][r];
-            }
-}
-
-__global__ __launch_bounds__(256, 1) void k_bdiag(const BProb *__restrict__ probs, const int32_t *__restrict__ plist,
-                                                  int j, int dim, const double *__restrict__ X, double *C_pool,
-                                                  double *wbuf, int32_t *info) {
-    __shared__ double As[T][T + 1];
-    __shared__ double Bs[T][T + 1];  // staging of the update, then the inverse
+// Factor + invert the diagonal tile j of problem order[blockIdx.x] (one wave).
+__global__ __launch_bounds__(64) void k_bdiag(const BProb *__restrict__ probs, const int32_t *__restrict__ order,
+                                              int j, double *C_pool, double *wbuf, int32_t *info) {
+    __shared__ double Ls[T][T + 1];
+    __shared__ double Wl[T][T + 1];
     __shared__ union {
         double pn[T][17];
         double t32[32][33];
     } U;
     __shared__ double rd[T];
-    __shared__ int s_fail;
-    const int b = plist[blockIdx.x];
+    const int b = order[blockIdx.x];
     if (info[b] != 0) return;
     const BProb P = probs[b];
     const int64_t ld = P.n, j0 = (int64_t)j * T;
-    double *L = C_pool + P.c_off;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wm = w & 1, wn = w >> 1;
-    v4d acc[2][2];
-    tile_update(L, ld, P.n, j0, j0, j, As, Bs, acc);
-    double sv[2][2][4];
-    tile_residual(P, X + P.x_off * dim, dim, j0, j0, acc, sv);
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-        for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                As[wm * 32 + m * 16 + (lane >> 4) + 4 * r][wn * 32 + q * 16 + (lane & 15)] = sv[m][q][r];
-    if (tid == 0) s_fail = 0;
-    __syncthreads();
-    if (w != 0) return;  // one wave factors and inverts the tile
     const int tj = (int)((P.n - j0) < T ? (P.n - j0) : T);
+    double *D = C_pool + P.c_off + j0 + j0 * ld;
+    const int lane = threadIdx.x;
     double a[T];
 #pragma unroll
-    for (int c = 0; c < T; ++c) a[c] = As[lane][c];
-    const int fail = wave_chol64(a, lane, As, U.pn);
+    for (int c = 0; c < T; ++c) {
+        double v;
+        if (lane < tj && c < tj) v = (c <= lane) ? D[lane + (int64_t)c * ld] : 0.0;
+        else v = (lane == c) ? 1.0 : 0.0;  // identity padding decouples unused rows
+        a[c] = v;
+    }
+    const int fail = wave_chol64(a, lane, Ls, U.pn);
     if (fail) {
         if (lane == 0) info[b] = (int32_t)(j0 + fail);
         return;
     }
 #pragma unroll
     for (int c = 0; c < T; ++c) {
-        As[lane][c] = a[c];
-        if (lane < tj && c <= lane) L[(j0 + lane) + (j0 + c) * ld] = a[c];
+        Ls[lane][c] = a[c];
+        if (lane < tj && c < tj && c <= lane) D[lane + (int64_t)c * ld] = a[c];
     }
     wave_lds_sync();
-    wave_inv64_blocked(As, Bs, U.t32, rd, lane);
+    wave_inv64_blocked(Ls, Wl, U.t32, rd, lane);
     double *W = wbuf + P.w_off + (int64_t)j * T * T;
 #pragma unroll 4
-    for (int c = 0; c < T; ++c) W[lane + c * T] = Bs[lane][c];
+    for (int c = 0; c < T; ++c) W[lane + c * T] = Wl[lane][c];
 }
 
-__global__ __launch_bounds__(256, 2) void k_bpanel(const BProb *__restrict__ probs, const BTile *__restrict__ tlist,
-                                                   int j, int dim, const double *__restrict__ X, double *C_pool,
+// L_ij = A_ij W_jj^T for tile i = j + 1 + (t - off[q]) of problem order[q].
+__global__ __launch_bounds__(256, 2) void k_bpanel(const BProb *__restrict__ probs, const int32_t *__restrict__ order,
+                                                   const int64_t *__restrict__ off, int cnt, int j, double *C_pool,
                                                    const double *__restrict__ wbuf, const int32_t *__restrict__ info) {
     __shared__ double As[T][T + 1];
     __shared__ double Bs[T][T + 1];
-    const BTile tk = tlist[blockIdx.x];
-    if (info[tk.prob] != 0) return;
-    const BProb P = probs[tk.prob];
-    const int64_t ld = P.n, i0 = (int64_t)tk.i * T, j0 = (int64_t)j * T;
-    double *L = C_pool + P.c_off;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wm = w & 1, wn = w >> 1;
+    const int q = find_prob(off, cnt, blockIdx.x);
+    const int b = order[q];
+    if (info[b] != 0) return;
+    const BProb P = probs[b];
+    const int64_t ld = P.n, i0 = (j + 1 + (blockIdx.x - off[q])) * (int64_t)T, j0 = (int64_t)j * T;
+    const int ri = (int)((P.n - i0) < T ? (P.n - i0) : T);
+    double *A = C_pool + P.c_off + i0 + j0 * ld;
     v4d acc[2][2];
-    tile_update(L, ld, P.n, i0, j0, j, As, Bs, acc);
-    double sv[2][2][4];
-    tile_residual(P, X + P.x_off * dim, dim, i0, j0, acc, sv);
-    // L_ij = S W_jj^T: A operand S staged k-major (As[kk][ii] = S[ii][kk]),
-    // op(B)[kk][jj] = W_jj[jj][kk] = W[jj + kk T]
-    const double *W = wbuf + P.w_off + (int64_t)j * T * T;
+    tile_nt(A, ld, ri, wbuf + P.w_off + (int64_t)j * T * T, T, T, As, Bs, acc);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wm = w & 1, wn = w >> 1;
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                As[wn * 32 + q * 16 + (lane & 15)][wm * 32 + m * 16 + (lane >> 4) + 4 * r] = sv[m][q][r];
-#pragma unroll
-    for (int r = 0; r < (T * T) / 256; ++r) {
-        const int e = r * 256 + tid;
-        Bs[e >> 6][e & (T - 1)] = W[e];
-    }
-    __syncthreads();
-    v4d o[2][2];
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-        for (int q = 0; q < 2; ++q) o[m][q] = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int kk = 0; kk < T; kk += 4) {
-        double a[2], bb[2];
-#pragma unroll
-        for (int m = 0; m < 2; ++m) a[m] = As[kk + (lane >> 4)][wm * 32 + m * 16 + (lane & 15)];
-#pragma unroll
-        for (int q = 0; q < 2; ++q) bb[q] = Bs[kk + (lane >> 4)][wn * 32 + q * 16 + (lane & 15)];
-#pragma unroll
-        for (int m = 0; m < 2; ++m)
-#pragma unroll
-            for (int q = 0; q < 2; ++q)
-                o[m][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], bb[q], o[m][q], 0, 0, 0);
-    }
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-        for (int q = 0; q < 2; ++q)
+        for (int qq = 0; qq < 2; ++qq)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t gi = i0 + wm * 32 + m * 16 + (lane >> 4) + 4 * r;
-                const int64_t gj = j0 + wn * 32 + q * 16 + (lane & 15);
-                if (gi < P.n && gj < P.n) L[gi + gj * ld] = o[m][q][r];
+                const int row = wm * 32 + m * 16 + (lane >> 4) + 4 * r, col = wn * 32 + qq * 16 + (lane & 15);
+                if (row < ri) A[row + (int64_t)col * ld] = acc[m][qq][r];
+            }
+}
+
+// A_ik -= L_ij L_kj^T for tile (i, k), j < k <= i, decoded from t - off[q]
+// within problem order[q]'s triangle of trailing tiles.
+__global__ __launch_bounds__(256, 2) void k_bupdate(const BProb *__restrict__ probs, const int32_t *__restrict__ order,
+                                                    const int64_t *__restrict__ off, int cnt, int j, double *C_pool,
+                                                    const int32_t *__restrict__ info) {
+    __shared__ double As[T][T + 1];
+    __shared__ double Bs[T][T + 1];
+    const int q = find_prob(off, cnt, blockIdx.x);
+    const int b = order[q];
+    if (info[b] != 0) return;
+    const BProb P = probs[b];
+    int64_t ti, tk;
+    btri_decode(blockIdx.x - off[q], ti, tk);
+    const int64_t ld = P.n, j0 = (int64_t)j * T;
+    const int64_t i0 = (j + 1 + ti) * (int64_t)T, k0 = (j + 1 + tk) * (int64_t)T;
+    const int ri = (int)((P.n - i0) < T ? (P.n - i0) : T), rk = (int)((P.n - k0) < T ? (P.n - k0) : T);
+    double *L = C_pool + P.c_off;
+    v4d acc[2][2];
+    tile_nt(L + i0 + j0 * ld, ld, ri, L + k0 + j0 * ld, ld, rk, As, Bs, acc);
+    double *A = L + i0 + k0 * ld;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wm = w & 1, wn = w >> 1;
+    double cv[2][2][4];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int qq = 0; qq < 2; ++qq)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = wm * 32 + m * 16 + (lane >> 4) + 4 * r, col = wn * 32 + qq * 16 + (lane & 15);
+                cv[m][qq][r] = (row < ri && col < rk) ? A[row + (int64_t)col * ld] : 0.0;
+            }
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int qq = 0; qq < 2; ++qq)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = wm * 32 + m * 16 + (lane >> 4) + 4 * r, col = wn * 32 + qq * 16 + (lane & 15);
+                if (row < ri && col < rk) A[row + (int64_t)col * ld] = cv[m][qq][r] - acc[m][qq][r];
             }
 }
 
@@ -299,8 +314,8 @@ size_t batch_ws_bytes(int64_t nmax, int64_t nbatch) {
     const int64_t nt = (nmax + T - 1) / T;
     size_t b = 0;
     b += al256b(sizeof(BProb) * (size_t)nbatch);
-    b += al256b(sizeof(int32_t) * (size_t)nt * (size_t)nbatch);                  // diag lists
-    b += al256b(sizeof(BTile) * (size_t)(nt * (nt + 1) / 2) * (size_t)nbatch);   // panel lists
+    b += al256b(sizeof(int32_t) * (size_t)nbatch);                              // size order
+    b += al256b(sizeof(int64_t) * (size_t)(2 * nt + 1) * (size_t)(nbatch + 1));  // per-level prefix counts
     b += al256b(sizeof(double) * (size_t)nmax * (size_t)nbatch);                 // z
     b += al256b(sizeof(double) * (size_t)nt * T * T * (size_t)nbatch);           // diagonal inverses
     return b + 256;
@@ -308,8 +323,8 @@ size_t batch_ws_bytes(int64_t nmax, int64_t nbatch) {
 
 struct BatchStaging {
     std::vector<BProb> probs;
-    std::vector<int32_t> dlist;
-    std::vector<BTile> tlist;
+    std::vector<int32_t> order;
+    std::vector<int64_t> offs;  // [level block][nb + 1]: covariance, then per level panel and update counts
     hipEvent_t done = nullptr;
 };
 
@@ -348,24 +363,27 @@ int batch_run(hipStream_t s, int num_cu, void *&staging_ptr, int32_t nb, const g
         p.inv_rho = std::exp(-th[b].log_rho);
         p.t2 = std::exp(th[b].log_tau2);
     }
-    // step j: problems with nt > j (diagonal tile), tiles (b, i > j) (panel);
-    // larger problems first within a step
-    std::vector<int> order(nb);
-    for (int b = 0; b < nb; ++b) order[b] = b;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return nh[a] > nh[c]; });
-    std::vector<int64_t> doff(ntmax + 1, 0), toff(ntmax + 1, 0);
-    st->dlist.clear();
-    st->tlist.clear();
+    // problems largest first: at level j the first cnt[j] of them have a
+    // diagonal tile; prefix counts of their covariance / panel / update tiles
+    st->order.resize(nb);
+    for (int b = 0; b < nb; ++b) st->order[b] = b;
+    std::stable_sort(st->order.begin(), st->order.end(), [&](int a, int c) { return nh[a] > nh[c]; });
+    const int64_t W = nb + 1;
+    st->offs.assign((size_t)(2 * ntmax + 1) * (size_t)W, 0);
+    std::vector<int> cnt(ntmax + 1, 0);
+    auto tri = [](int64_t m) { return m > 0 ? m * (m + 1) / 2 : 0; };
+    for (int q = 0; q < nb; ++q) st->offs[q + 1] = st->offs[q] + tri(st->probs[st->order[q]].nt);
     for (int64_t j = 0; j < ntmax; ++j) {
-        doff[j] = (int64_t)st->dlist.size();
-        toff[j] = (int64_t)st->tlist.size();
-        for (int b : order)
-            if (st->probs[b].nt > j) st->dlist.push_back(b);
-        for (int b : order)
-            for (int i = (int)j + 1; i < st->probs[b].nt; ++i) st->tlist.push_back(BTile{b, i});
+        int c = 0;
+        while (c < nb && st->probs[st->order[c]].nt > j) ++c;
+        cnt[j] = c;
+        int64_t *po = &st->offs[(size_t)(1 + 2 * j) * W], *uo = &st->offs[(size_t)(2 + 2 * j) * W];
+        for (int q = 0; q < c; ++q) {
+            const int64_t m = st->probs[st->order[q]].nt - j - 1;
+            po[q + 1] = po[q] + (m > 0 ? m : 0);
+            uo[q + 1] = uo[q] + tri(m);
+        }
     }
-    doff[ntmax] = (int64_t)st->dlist.size();
-    toff[ntmax] = (int64_t)st->tlist.size();
 
     char *base = static_cast<char *>(ws);
     size_t off = 0;
@@ -375,29 +393,34 @@ int batch_run(hipStream_t s, int num_cu, void *&staging_ptr, int32_t nb, const g
         return p;
     };
     BProb *d_probs = reinterpret_cast<BProb *>(take(sizeof(BProb) * (size_t)nb));
-    int32_t *d_dl = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)ntmax * (size_t)nb));
-    BTile *d_tl = reinterpret_cast<BTile *>(take(sizeof(BTile) * (size_t)(ntmax * (ntmax + 1) / 2) * (size_t)nb));
+    int32_t *d_order = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)nb));
+    int64_t *d_offs = reinterpret_cast<int64_t *>(take(sizeof(int64_t) * st->offs.size()));
     double *d_z = reinterpret_cast<double *>(take(sizeof(double) * (size_t)nmax * (size_t)nb));
     double *d_w = reinterpret_cast<double *>(take(sizeof(double) * (size_t)ntmax * T * T * (size_t)nb));
 
     if (hipMemcpyAsync(d_probs, st->probs.data(), sizeof(BProb) * (size_t)nb, hipMemcpyHostToDevice, s) != hipSuccess)
         return GP_ERR_HIP;
-    if (!st->dlist.empty() &&
-        hipMemcpyAsync(d_dl, st->dlist.data(), sizeof(int32_t) * st->dlist.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+    if (hipMemcpyAsync(d_order, st->order.data(), sizeof(int32_t) * (size_t)nb, hipMemcpyHostToDevice, s) != hipSuccess)
         return GP_ERR_HIP;
-    if (!st->tlist.empty() &&
-        hipMemcpyAsync(d_tl, st->tlist.data(), sizeof(BTile) * st->tlist.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+    if (hipMemcpyAsync(d_offs, st->offs.data(), sizeof(int64_t) * st->offs.size(), hipMemcpyHostToDevice, s) !=
+        hipSuccess)
         return GP_ERR_HIP;
     if (hipEventRecord(st->done, s) != hipSuccess) return GP_ERR_HIP;
     if (launch_fill(s, info, sizeof(int32_t) * (size_t)nb) != hipSuccess) return GP_ERR_HIP;
+    const int64_t ncov = st->offs[nb];
+    if (ncov > 0)
+        hipLaunchKernelGGL(k_bcov, dim3((unsigned)ncov), dim3(256), 0, s, d_probs, d_order, d_offs, nb, dim, X, C_pool);
     for (int64_t j = 0; j < ntmax; ++j) {
-        const int64_t nd = doff[j + 1] - doff[j], ntl = toff[j + 1] - toff[j];
-        if (nd > 0)
-            hipLaunchKernelGGL(k_bdiag, dim3((unsigned)nd), dim3(256), 0, s, d_probs, d_dl + doff[j], (int)j, dim, X,
-                               C_pool, d_w, info);
-        if (ntl > 0)
-            hipLaunchKernelGGL(k_bpanel, dim3((unsigned)ntl), dim3(256), 0, s, d_probs, d_tl + toff[j], (int)j, dim, X,
-                               C_pool, d_w, info);
+        const int c = cnt[j];
+        const int64_t np = st->offs[(size_t)(1 + 2 * j) * W + c], nu = st->offs[(size_t)(2 + 2 * j) * W + c];
+        if (c > 0)
+            hipLaunchKernelGGL(k_bdiag, dim3((unsigned)c), dim3(64), 0, s, d_probs, d_order, (int)j, C_pool, d_w, info);
+        if (np > 0)
+            hipLaunchKernelGGL(k_bpanel, dim3((unsigned)np), dim3(256), 0, s, d_probs, d_order,
+                               d_offs + (size_t)(1 + 2 * j) * W, c, (int)j, C_pool, d_w, info);
+        if (nu > 0)
+            hipLaunchKernelGGL(k_bupdate, dim3((unsigned)nu), dim3(256), 0, s, d_probs, d_order,
+                               d_offs + (size_t)(2 + 2 * j) * W, c, (int)j, C_pool, info);
         if (hipGetLastError() != hipSuccess) return GP_ERR_HIP;
     }
     hipLaunchKernelGGL(k_bsolve, dim3((unsigned)nb), dim3(256), 0, s, d_probs, y, C_pool, d_z, d_w, out3, info);
