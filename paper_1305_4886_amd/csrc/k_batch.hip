@@ -14,9 +14,10 @@
 //              matrix cores).
 // Every launch of a level has the same short K, so a level costs the same
 // whatever the problem sizes; problems are ordered largest first and each
-// workgroup finds its problem and tile from per-level prefix counts.  A final
-// launch runs, per problem, the forward solve z = L^{-1} y and the
-// log-determinant / quadratic-form reductions.  No workgroup ever waits on
+// workgroup finds its problem and tile from per-level prefix counts.  The
+// forward solve z = L^{-1} y rides along (diag: z_j = W_j y'_j; panel:
+// y'_i -= L_ij z_j); a final launch forms, per problem, the log-determinant /
+// quadratic-form reductions.  No workgroup ever waits on
 // another: kernel boundaries order the steps.
 #include "internal.h"
 
@@ -98,7 +99,8 @@ GP_DEV void tile_nt(const double *X, int64_t ldx, int xr, const double *Y, int64
 // clipped to the problem).
 __global__ __launch_bounds__(256) void k_bcov(const BProb *__restrict__ probs, const int32_t *__restrict__ order,
                                               const int64_t *__restrict__ off, int cnt, int dim,
-                                              const double *__restrict__ X, double *C_pool) {
+                                              const double *__restrict__ X, const double *__restrict__ y,
+                                              double *C_pool, double *zbuf) {
     const int q = find_prob(off, cnt, blockIdx.x);
     const BProb P = probs[order[q]];
     int64_t ti, tk;
@@ -106,6 +108,8 @@ __global__ __launch_bounds__(256) void k_bcov(const BProb *__restrict__ probs, c
     const int64_t i0 = ti * T, k0 = tk * T;
     double *C = C_pool + P.c_off;
     const double *Xb = X + P.x_off * dim;
+    if (ti == 0 && tk == 0)  // the forward solve's right-hand side, updated in place by the levels
+        for (int64_t e = threadIdx.x; e < P.n; e += 256) zbuf[P.z_off + e] = y[P.x_off + e];
     for (int e = threadIdx.x; e < T * T; e += 256) {
         const int64_t gi = i0 + (e & (T - 1)), gk = k0 + (e >> 6);
         if (gi < P.n && gk < P.n) {
@@ -117,7 +121,7 @@ __global__ __launch_bounds__(256) void k_bcov(const BProb *__restrict__ probs, c
 
 // Factor + invert the diagonal tile j of problem order[blockIdx.x] (one wave).
 __global__ __launch_bounds__(64) void k_bdiag(const BProb *__restrict__ probs, const int32_t *__restrict__ order,
-                                              int j, double *C_pool, double *wbuf, int32_t *info) {
+                                              int j, double *C_pool, double *wbuf, double *zbuf, int32_t *info) {
     __shared__ double Ls[T][T + 1];
     __shared__ double Wl[T][T + 1];
     __shared__ union {
@@ -155,12 +159,22 @@ __global__ __launch_bounds__(64) void k_bdiag(const BProb *__restrict__ probs, c
     double *W = wbuf + P.w_off + (int64_t)j * T * T;
 #pragma unroll 4
     for (int c = 0; c < T; ++c) W[lane + c * T] = Wl[lane][c];
+    // forward solve of this block: z_j = W_j y'_j (y'_j holds y_j minus the
+    // products of the earlier blocks, subtracted by the panel steps)
+    double *z = zbuf + P.z_off + j0;
+    rd[lane] = lane < tj ? z[lane] : 0.0;
+    wave_lds_sync();
+    double zr = 0.0;
+#pragma unroll 8
+    for (int c = 0; c < T; ++c) zr = fma(Wl[lane][c], rd[c], zr);
+    if (lane < tj) z[lane] = zr;
 }
 
 // L_ij = A_ij W_jj^T for tile i = j + 1 + (t - off[q]) of problem order[q].
 __global__ __launch_bounds__(256, 2) void k_bpanel(const BProb *__restrict__ probs, const int32_t *__restrict__ order,
                                                    const int64_t *__restrict__ off, int cnt, int j, double *C_pool,
-                                                   const double *__restrict__ wbuf, const int32_t *__restrict__ info) {
+                                                   const double *__restrict__ wbuf, double *zbuf,
+                                                   const int32_t *__restrict__ info) {
     __shared__ double As[T][T + 1];
     __shared__ double Bs[T][T + 1];
     const int q = find_prob(off, cnt, blockIdx.x);
@@ -173,6 +187,7 @@ __global__ __launch_bounds__(256, 2) void k_bpanel(const BProb *__restrict__ pro
     v4d acc[2][2];
     tile_nt(A, ld, ri, wbuf + P.w_off + (int64_t)j * T * T, T, T, As, Bs, acc);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wm = w & 1, wn = w >> 1;
+    __syncthreads();  // As is reused for L_ij below
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
@@ -180,8 +195,18 @@ __global__ __launch_bounds__(256, 2) void k_bpanel(const BProb *__restrict__ pro
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = wm * 32 + m * 16 + (lane >> 4) + 4 * r, col = wn * 32 + qq * 16 + (lane & 15);
+                As[row][col] = acc[m][qq][r];
                 if (row < ri) A[row + (int64_t)col * ld] = acc[m][qq][r];
             }
+    __syncthreads();
+    // forward solve: y'_i -= L_ij z_j (this tile is the only writer of y'_i at this level)
+    if (w == 0) {
+        const double *zj = zbuf + P.z_off + j0;
+        double u = 0.0;
+#pragma unroll 8
+        for (int c = 0; c < T; ++c) u = fma(As[lane][c], zj[c], u);
+        if (lane < ri) zbuf[P.z_off + i0 + lane] -= u;
+    }
 }
 
 // A_ik -= L_ij L_kj^T for tile (i, k), j < k <= i, decoded from t - off[q]
@@ -201,10 +226,9 @@ __global__ __launch_bounds__(256, 2) void k_bupdate(const BProb *__restrict__ pr
     const int64_t i0 = (j + 1 + ti) * (int64_t)T, k0 = (j + 1 + tk) * (int64_t)T;
     const int ri = (int)((P.n - i0) < T ? (P.n - i0) : T), rk = (int)((P.n - k0) < T ? (P.n - k0) : T);
     double *L = C_pool + P.c_off;
-    v4d acc[2][2];
-    tile_nt(L + i0 + j0 * ld, ld, ri, L + k0 + j0 * ld, ld, rk, As, Bs, acc);
     double *A = L + i0 + k0 * ld;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wm = w & 1, wn = w >> 1;
+    // the C tile's loads first, so their latency overlaps the operand product
     double cv[2][2][4];
 #pragma unroll
     for (int m = 0; m < 2; ++m)
@@ -215,6 +239,8 @@ __global__ __launch_bounds__(256, 2) void k_bupdate(const BProb *__restrict__ pr
                 const int row = wm * 32 + m * 16 + (lane >> 4) + 4 * r, col = wn * 32 + qq * 16 + (lane & 15);
                 cv[m][qq][r] = (row < ri && col < rk) ? A[row + (int64_t)col * ld] : 0.0;
             }
+    v4d acc[2][2];
+    tile_nt(L + i0 + j0 * ld, ld, ri, L + k0 + j0 * ld, ld, rk, As, Bs, acc);
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
@@ -226,17 +252,14 @@ __global__ __launch_bounds__(256, 2) void k_bupdate(const BProb *__restrict__ pr
             }
 }
 
-// Per problem: z = L^{-1} y block by block (this workgroup only), then
-// log|C| = 2 sum log L_ii, q = z^T z and the log-likelihood.
-__global__ __launch_bounds__(256) void k_bsolve(const BProb *__restrict__ probs, const double *__restrict__ y,
-                                                const double *__restrict__ C_pool, double *zbuf,
-                                                const double *__restrict__ wbuf, double *out3, const int32_t *info) {
-    __shared__ double red[4][T];
-    __shared__ double rhs[T];
+// Per problem: log|C| = 2 sum log L_ii, q = z^T z (z = L^{-1} y, formed by
+// the levels) and the log-likelihood.
+__global__ __launch_bounds__(256) void k_bsolve(const BProb *__restrict__ probs, const double *__restrict__ C_pool,
+                                                const double *__restrict__ zbuf, double *out3, const int32_t *info) {
     __shared__ double r2[4 * 256];
     const int b = blockIdx.x;
     const BProb P = probs[b];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x;
     double *o = out3 + 3 * (int64_t)b;
     if (info[b] != 0) {
         if (tid == 0) o[0] = o[1] = o[2] = __builtin_nan("");
@@ -244,31 +267,7 @@ __global__ __launch_bounds__(256) void k_bsolve(const BProb *__restrict__ probs,
     }
     const int64_t n = P.n, ld = P.n;
     const double *L = C_pool + P.c_off;
-    double *z = zbuf + P.z_off;
-    for (int i = 0; i < P.nt; ++i) {
-        const int64_t gi = (int64_t)i * T + lane;
-        const bool rv = gi < n;
-        double acc = 0.0;
-        for (int k = w; k < i; k += 4) {
-            const double *Lc = L + (rv ? gi : 0) + (int64_t)k * T * ld;
-            const double *zk = z + (int64_t)k * T;
-            if (rv) {
-#pragma unroll 16
-                for (int c = 0; c < T; ++c) acc = fma(Lc[(int64_t)c * ld], zk[c], acc);
-            }
-        }
-        red[w][lane] = acc;
-        __syncthreads();
-        if (w == 0) rhs[lane] = rv ? y[P.x_off + gi] - (((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]) : 0.0;
-        __syncthreads();
-        const double *W = wbuf + P.w_off + (int64_t)i * T * T;
-        double sacc = 0.0;
-        for (int c = w * 16; c < w * 16 + 16; ++c) sacc = fma(W[lane + c * T], rhs[c], sacc);
-        red[w][lane] = sacc;
-        __syncthreads();
-        if (w == 0 && rv) z[gi] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
-        __syncthreads();  // z_i (global, this workgroup) visible before the next block reads it
-    }
+    const double *z = zbuf + P.z_off;
     CSum sl, sq;
     for (int64_t q = tid; q < n; q += 256) {
         sl.add(log(L[q + q * ld]));
@@ -409,21 +408,23 @@ int batch_run(hipStream_t s, int num_cu, void *&staging_ptr, int32_t nb, const g
     if (launch_fill(s, info, sizeof(int32_t) * (size_t)nb) != hipSuccess) return GP_ERR_HIP;
     const int64_t ncov = st->offs[nb];
     if (ncov > 0)
-        hipLaunchKernelGGL(k_bcov, dim3((unsigned)ncov), dim3(256), 0, s, d_probs, d_order, d_offs, nb, dim, X, C_pool);
+        hipLaunchKernelGGL(k_bcov, dim3((unsigned)ncov), dim3(256), 0, s, d_probs, d_order, d_offs, nb, dim, X, y, C_pool,
+                           d_z);
     for (int64_t j = 0; j < ntmax; ++j) {
         const int c = cnt[j];
         const int64_t np = st->offs[(size_t)(1 + 2 * j) * W + c], nu = st->offs[(size_t)(2 + 2 * j) * W + c];
         if (c > 0)
-            hipLaunchKernelGGL(k_bdiag, dim3((unsigned)c), dim3(64), 0, s, d_probs, d_order, (int)j, C_pool, d_w, info);
+            hipLaunchKernelGGL(k_bdiag, dim3((unsigned)c), dim3(64), 0, s, d_probs, d_order, (int)j, C_pool, d_w, d_z,
+                               info);
         if (np > 0)
             hipLaunchKernelGGL(k_bpanel, dim3((unsigned)np), dim3(256), 0, s, d_probs, d_order,
-                               d_offs + (size_t)(1 + 2 * j) * W, c, (int)j, C_pool, d_w, info);
+                               d_offs + (size_t)(1 + 2 * j) * W, c, (int)j, C_pool, d_w, d_z, info);
         if (nu > 0)
             hipLaunchKernelGGL(k_bupdate, dim3((unsigned)nu), dim3(256), 0, s, d_probs, d_order,
                                d_offs + (size_t)(2 + 2 * j) * W, c, (int)j, C_pool, info);
         if (hipGetLastError() != hipSuccess) return GP_ERR_HIP;
     }
-    hipLaunchKernelGGL(k_bsolve, dim3((unsigned)nb), dim3(256), 0, s, d_probs, y, C_pool, d_z, d_w, out3, info);
+    hipLaunchKernelGGL(k_bsolve, dim3((unsigned)nb), dim3(256), 0, s, d_probs, C_pool, d_z, out3, info);
     return hipGetLastError() == hipSuccess ? GP_OK : GP_ERR_HIP;
 }
 
