@@ -10,8 +10,9 @@
 //              and invert it (the diagonal-block Cholesky of Section 2.1 /
 //              Fig. 1);
 //   panel(j):  L_ij = A_ij W_jj^T for every tile i > j;
-//   update(j): A_ik -= L_ij L_kj^T for every tile j < k <= i (rank-64 on the
-//              matrix cores).
+//   update:    A_ik -= L_ij L_kj^T on the matrix cores, taken for two tile
+//              columns at once (rank 128) after the column j + 1 alone has
+//              been brought up to date for diag / panel(j + 1).
 // Every launch of a level has the same short K, so a level costs the same
 // whatever the problem sizes; problems are ordered largest first and each
 // workgroup finds its problem and tile from per-level prefix counts.  The
@@ -55,14 +56,15 @@ GP_DEV int find_prob(const int64_t *off, int cnt, int64_t t) {
     return lo;
 }
 
-// acc = X Y^T for two 64 x 64 blocks (rows past xr / yr read as zero): both
+// acc (+)= X Y^T for two 64 x 64 blocks (rows past xr / yr read as zero): both
 // staged k-major in LDS, 4 waves of 32 x 32 (f64 MFMA layout: row lane / 16 +
 // 4 r, column lane % 16 within each 16 x 16 block).
 GP_DEV void tile_nt(const double *X, int64_t ldx, int xr, const double *Y, int64_t ldy, int yr, double (*As)[T + 1],
-                    double (*Bs)[T + 1], v4d (&acc)[2][2]) {
+                    double (*Bs)[T + 1], v4d (&acc)[2][2], bool accumulate = false) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w & 1, wn = w >> 1;
     double va[(T * T) / 256], vb[(T * T) / 256];
+    if (accumulate) __syncthreads();  // the previous product's LDS reads are done
 #pragma unroll
     for (int r = 0; r < (T * T) / 256; ++r) {
         const int e = r * 256 + tid, ii = e & (T - 1), kk = e >> 6;
@@ -76,10 +78,12 @@ GP_DEV void tile_nt(const double *X, int64_t ldx, int xr, const double *Y, int64
         Bs[kk][ii] = vb[r];
     }
     __syncthreads();
+    if (!accumulate) {
 #pragma unroll
-    for (int m = 0; m < 2; ++m)
+        for (int m = 0; m < 2; ++m)
 #pragma unroll
-        for (int q = 0; q < 2; ++q) acc[m][q] = v4d{0.0, 0.0, 0.0, 0.0};
+            for (int q = 0; q < 2; ++q) acc[m][q] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
 #pragma unroll 4
     for (int kk = 0; kk < T; kk += 4) {
         double a[2], b[2];
@@ -209,11 +213,14 @@ __global__ __launch_bounds__(256, 2) void k_bpanel(const BProb *__restrict__ pro
     }
 }
 
-// A_ik -= L_ij L_kj^T for tile (i, k), j < k <= i, decoded from t - off[q]
-// within problem order[q]'s triangle of trailing tiles.
+// A_ik -= sum_{c < nk} L_{i,j+c} L_{k,j+c}^T for one trailing tile of problem
+// order[q], u = t - off[q]: column mode (k = base, i = base + u) or triangle
+// mode (base <= k <= i, (i - base, k - base) the u-th pair of the lower
+// triangle).  nk = 2 applies two panel columns at once (rank 128), which
+// halves the C traffic of the update.
 __global__ __launch_bounds__(256, 2) void k_bupdate(const BProb *__restrict__ probs, const int32_t *__restrict__ order,
-                                                    const int64_t *__restrict__ off, int cnt, int j, double *C_pool,
-                                                    const int32_t *__restrict__ info) {
+                                                    const int64_t *__restrict__ off, int cnt, int j, int nk, int base,
+                                                    int column, double *C_pool, const int32_t *__restrict__ info) {
     __shared__ double As[T][T + 1];
     __shared__ double Bs[T][T + 1];
     const int q = find_prob(off, cnt, blockIdx.x);
@@ -221,9 +228,15 @@ __global__ __launch_bounds__(256, 2) void k_bupdate(const BProb *__restrict__ pr
     if (info[b] != 0) return;
     const BProb P = probs[b];
     int64_t ti, tk;
-    btri_decode(blockIdx.x - off[q], ti, tk);
+    const int64_t u = blockIdx.x - off[q];
+    if (column) {
+        ti = u;
+        tk = 0;
+    } else {
+        btri_decode(u, ti, tk);
+    }
     const int64_t ld = P.n, j0 = (int64_t)j * T;
-    const int64_t i0 = (j + 1 + ti) * (int64_t)T, k0 = (j + 1 + tk) * (int64_t)T;
+    const int64_t i0 = (base + ti) * (int64_t)T, k0 = (base + tk) * (int64_t)T;
     const int ri = (int)((P.n - i0) < T ? (P.n - i0) : T), rk = (int)((P.n - k0) < T ? (P.n - k0) : T);
     double *L = C_pool + P.c_off;
     double *A = L + i0 + k0 * ld;
@@ -241,6 +254,7 @@ __global__ __launch_bounds__(256, 2) void k_bupdate(const BProb *__restrict__ pr
             }
     v4d acc[2][2];
     tile_nt(L + i0 + j0 * ld, ld, ri, L + k0 + j0 * ld, ld, rk, As, Bs, acc);
+    if (nk == 2) tile_nt(L + i0 + (j0 + T) * ld, ld, ri, L + k0 + (j0 + T) * ld, ld, rk, As, Bs, acc, true);
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
@@ -410,18 +424,39 @@ int batch_run(hipStream_t s, int num_cu, void *&staging_ptr, int32_t nb, const g
     if (ncov > 0)
         hipLaunchKernelGGL(k_bcov, dim3((unsigned)ncov), dim3(256), 0, s, d_probs, d_order, d_offs, nb, dim, X, y, C_pool,
                            d_z);
-    for (int64_t j = 0; j < ntmax; ++j) {
+    auto poff = [&](int64_t j) { return (size_t)(1 + 2 * j) * W; };
+    auto uoff = [&](int64_t j) { return (size_t)(2 + 2 * j) * W; };
+    auto diag_panel = [&](int64_t j) {
         const int c = cnt[j];
-        const int64_t np = st->offs[(size_t)(1 + 2 * j) * W + c], nu = st->offs[(size_t)(2 + 2 * j) * W + c];
+        const int64_t np = st->offs[poff(j) + c];
         if (c > 0)
             hipLaunchKernelGGL(k_bdiag, dim3((unsigned)c), dim3(64), 0, s, d_probs, d_order, (int)j, C_pool, d_w, d_z,
                                info);
         if (np > 0)
-            hipLaunchKernelGGL(k_bpanel, dim3((unsigned)np), dim3(256), 0, s, d_probs, d_order,
-                               d_offs + (size_t)(1 + 2 * j) * W, c, (int)j, C_pool, d_w, d_z, info);
-        if (nu > 0)
-            hipLaunchKernelGGL(k_bupdate, dim3((unsigned)nu), dim3(256), 0, s, d_probs, d_order,
-                               d_offs + (size_t)(2 + 2 * j) * W, c, (int)j, C_pool, info);
+            hipLaunchKernelGGL(k_bpanel, dim3((unsigned)np), dim3(256), 0, s, d_probs, d_order, d_offs + poff(j), c,
+                               (int)j, C_pool, d_w, d_z, info);
+    };
+    // Tile columns in pairs (j, j + 1): diag / panel of j, the update of
+    // column j + 1 alone, diag / panel of j + 1, then one rank-128 update of
+    // the tiles right of both (counts of those = the update counts of j + 1).
+    for (int64_t j = 0; j < ntmax;) {
+        diag_panel(j);
+        if (j + 1 < ntmax) {
+            const int c = cnt[j];
+            const int64_t ncol = st->offs[poff(j) + c];  // tiles (i, j + 1), i > j: one per panel tile
+            if (ncol > 0)
+                hipLaunchKernelGGL(k_bupdate, dim3((unsigned)ncol), dim3(256), 0, s, d_probs, d_order, d_offs + poff(j),
+                                   c, (int)j, 1, (int)j + 1, 1, C_pool, info);
+            diag_panel(j + 1);
+            const int c1 = cnt[j + 1];
+            const int64_t nu = c1 > 0 ? st->offs[uoff(j + 1) + c1] : 0;
+            if (nu > 0)
+                hipLaunchKernelGGL(k_bupdate, dim3((unsigned)nu), dim3(256), 0, s, d_probs, d_order, d_offs + uoff(j + 1),
+                                   c1, (int)j, 2, (int)j + 2, 0, C_pool, info);
+            j += 2;
+        } else {
+            j += 1;  // the last tile column has nothing to its right
+        }
         if (hipGetLastError() != hipSuccess) return GP_ERR_HIP;
     }
     hipLaunchKernelGGL(k_bsolve, dim3((unsigned)nb), dim3(256), 0, s, d_probs, C_pool, d_z, out3, info);
