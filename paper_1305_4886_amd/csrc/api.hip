@@ -483,19 +483,22 @@ int potrf_impl(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda,
             return trailing(h, s, prec, A + r0 + c0 * lda, lda, A + r0 + r0 * lda, lda, M, ncols, K, info);
         };
         if (la) {
-            // columns of the next panel first
+            // columns of the next panel first; then, on the side stream, its
+            // diagonal block and the rows below it (columns c1 .. c2, which
+            // the rest of this trailing update does not touch)
             HIPCHK(update(c1, c2 - c1));
             HIPCHK(hipEventRecord(h->ev_cols, s));
             HIPCHK(hipStreamWaitEvent(side, h->ev_cols, 0));
             if ((rc = diag_block(side, c1, c2))) return rc;
+            if (c2 < n && (rc = below(side, c1, c2))) return rc;
             HIPCHK(hipEventRecord(h->ev_panel, side));
             if (c2 < n) HIPCHK(update(c2, n - c2));
             HIPCHK(hipStreamWaitEvent(s, h->ev_panel, 0));
         } else {
             HIPCHK(update(c1, n - c1));
             if ((rc = diag_block(s, c1, c2))) return rc;
+            if (c2 < n && (rc = below(s, c1, c2))) return rc;
         }
-        if (c2 < n && (rc = below(s, c1, c2))) return rc;
     }
     if (s != user) {
         HIPCHK(hipEventRecord(h->ev_out, s));
