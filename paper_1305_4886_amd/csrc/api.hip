@@ -64,7 +64,7 @@ struct PanelBufs {
     int *pflags = nullptr;   // hand-over flags of the fused panel kernel
 };
 
-int64_t panel_width(gp_handle_t h) { return h->opt.nb > 0 ? h->opt.nb : 512; }
+int64_t panel_width(gp_handle_t h) { return h->opt.nb > 0 ? h->opt.nb : 768; }
 
 // Reserved compute unit r of `reserve`: spaced ncu / reserve apart and offset
 // by r mod 8, which gives every XCD the same share whether mask bits are
@@ -707,7 +707,7 @@ const char *gp_strerror(int code) {
 
 static void default_options(gp_options_t *o) {
     memset(o, 0, sizeof(*o));
-    o->nb = 512;
+    o->nb = 768;
     o->lookahead = 1;
     o->panel_cus = 0;
     o->band = 8;
