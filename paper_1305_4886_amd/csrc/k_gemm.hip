@@ -606,17 +606,17 @@ __global__ void k_pack_panel(const double *__restrict__ P, int64_t lda, int64_t 
     }
 }
 
-template <int PREC, int TAG>
+template <int PREC, int TAG, int STAGES = 4, int BKD = (PREC == 1 ? 16 : 32)>
 __global__ __launch_bounds__(256, 2) void k_syrk_pk(GemmDesc d, TileMap tm, const void *__restrict__ Qv, int64_t Mp,
                                                     int64_t qrow0) {
-    constexpr int STAGES = 4, BM = 128, WTM = 64, FM = 4, FN = 4;
-    constexpr int BKD = PREC == 1 ? 16 : 32;                    // panel columns per slab
+    constexpr int BM = 128, WTM = 64, FM = 4, FN = 4;
     constexpr int EB = PREC == 1 ? 4 : 2;                       // bytes per element
     constexpr int CHUNKS = 2 * BM * BKD * EB / 1024;            // 1 KB copies per slab (both operands)
+    constexpr int CPO = CHUNKS / 2;                             // per operand
     constexpr int PER = CHUNKS / 4;                             // per wave
-    constexpr int NKK = PREC == 1 ? BKD / 4 : 1;                // MFMA K-steps per slab
+    constexpr int NKK = PREC == 1 ? BKD / 4 : BKD / 32;         // MFMA K-steps per slab
     static_assert((STAGES - 2) * PER < 64, "outstanding copies exceed vmcnt");
-    static_assert(PER == 4 && CHUNKS / 2 == 8, "slab = 8 chunks per operand");
+    static_assert(PER % NKK == 0 && (PREC == 1 ? BKD % 16 == 0 : BKD % 32 == 0), "slab shape");
     static_assert(STAGES * 2 * BM * BKD * EB >= 4 * 2048 * 8, "the ring holds the epilogue's four wave regions");
     __shared__ __attribute__((aligned(16))) char Ls[STAGES][2][BM * BKD * EB];
 
@@ -640,16 +640,17 @@ __global__ __launch_bounds__(256, 2) void k_syrk_pk(GemmDesc d, TileMap tm, cons
     // contiguous in both layouts.
     const uint32_t voff = PREC == 1 ? (uint32_t)(4 * ((lane >> 5) * Mp + 4 * (lane & 31))) : 16u * (uint32_t)lane;
 
-    // copy q of this wave for slab `slab` into stage st: chunk c = wave + 4 q
+    // copy q of this wave for slab `slab` into stage st: chunk c = wave + 4 q;
+    // BF16 chunk cc is rows 16 (cc % 8) .. of the (cc / 8)-th 32-column slab
     auto copy1 = [&](int slab, int st, int q) {
         const int c = wave + 4 * q;
-        const int op = c / (CHUNKS / 2), cc = c % (CHUNKS / 2);
+        const int op = c / CPO, cc = c % CPO;
         const int64_t row0 = qrow0 + (op ? j0 : i0);
         const char *src;
         if (PREC == 1)
             src = Q + 4 * ((int64_t)(slab * BKD + 2 * cc) * Mp + row0);
         else
-            src = Q + 2 * (((int64_t)slab * Mp + row0) * 32 + 512 * (int64_t)cc);
+            src = Q + 2 * (((int64_t)(slab * (BKD / 32) + cc / 8) * Mp + row0) * 32 + 512 * (int64_t)(cc % 8));
         lds_dma_dwordx4(reinterpret_cast<const double *>(src), voff, (uint32_t)(uintptr_t)&Ls[st][op][1024 * cc]);
     };
 
@@ -692,12 +693,12 @@ __global__ __launch_bounds__(256, 2) void k_syrk_pk(GemmDesc d, TileMap tm, cons
                     for (int n = 0; n < FN; ++n)
                         acc[q][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b[n], acc[q][n], 0, 0, 0);
                     __builtin_amdgcn_sched_barrier(0);
-                    if (more && q == 3) copy1(ns, nst, kk);
+                    if (more && q == 3) copy1(ns, nst, kk);  // PER == NKK: one copy per K-step
                     __builtin_amdgcn_sched_barrier(0);
                 }
             } else {
-                const __bf16 *A = reinterpret_cast<const __bf16 *>(&Ls[st][0][0]);
-                const __bf16 *B = reinterpret_cast<const __bf16 *>(&Ls[st][1][0]);
+                const __bf16 *A = reinterpret_cast<const __bf16 *>(&Ls[st][0][8192 * kk]);
+                const __bf16 *B = reinterpret_cast<const __bf16 *>(&Ls[st][1][8192 * kk]);
                 v8bf a[FM], b[FN];
 #pragma unroll
                 for (int m = 0; m < FM; ++m)
@@ -711,7 +712,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk_pk(GemmDesc d, TileMap tm, cons
                     const int m = q >> 2, n = q & 3;
                     acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[n], acc[m][n], 0, 0, 0);
                     __builtin_amdgcn_sched_barrier(0);
-                    if (more && (q & 3) == 3) copy1(ns, nst, q >> 2);
+                    if (more && (q & 3) == 3) copy1(ns, nst, kk * 4 + (q >> 2));
                     __builtin_amdgcn_sched_barrier(0);
                 }
             }
@@ -1090,9 +1091,12 @@ hipError_t launch_lowp_packed(hipStream_t s, gp_prec_t prec, int band, const dou
     const int64_t Mp = packed_rows(Mpack);
     if (((uintptr_t)Q & 15) != 0 || qrow0 % 64 != 0) return hipErrorInvalidValue;  // 16-byte copies
     if (prec == GP_FP32_TRAIL)
-        hipLaunchKernelGGL((k_syrk_pk<1, 1>), dim3((unsigned)g), dim3(256), 0, s, d, tm, Q, Mp, qrow0);
+        hipLaunchKernelGGL((k_syrk_pk<1, 1, 2, 32>), dim3((unsigned)g), dim3(256), 0, s, d, tm, Q, Mp, qrow0);
     else
-        hipLaunchKernelGGL((k_syrk_pk<2, 1>), dim3((unsigned)g), dim3(256), 0, s, d, tm, Q, Mp, qrow0);
+        if (K % 64 == 0)  // two 32-column packed slabs per LDS stage
+            hipLaunchKernelGGL((k_syrk_pk<2, 1, 2, 64>), dim3((unsigned)g), dim3(256), 0, s, d, tm, Q, Mp, qrow0);
+        else
+            hipLaunchKernelGGL((k_syrk_pk<2, 1>), dim3((unsigned)g), dim3(256), 0, s, d, tm, Q, Mp, qrow0);
     return hipGetLastError();
 }
 
