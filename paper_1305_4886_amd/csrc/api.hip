@@ -52,7 +52,7 @@ CovParams cov_params(const gp_theta_t &th, int dim) {
 struct Layout {
     size_t dinv = 0, sync = 0, z = 0, vec2 = 0, vec3 = 0, vec4 = 0, vec5 = 0, part = 0, big1 = 0, big2 = 0,
            big3 = 0, irst = 0, perm = 0, keys = 0, box = 0, xp = 0, yp = 0, mup = 0, pbuf = 0, vinv = 0,
-           vtmp = 0, qbuf = 0, big4 = 0, pflags = 0, total = 0;
+           vtmp = 0, qbuf = 0, big4 = 0, pflags = 0, kw = 0, total = 0;
 };
 
 // Buffers of the panel steps of the factorisation (null when n <= NB).
@@ -105,6 +105,11 @@ size_t trtri_tmp_elems(int64_t n) {
 }
 
 constexpr int GRAD_PARTS = 2048;
+
+// Column band of the kriging solve C*^T L^{-T}: each band is solved by one
+// product with the inverse of its diagonal block, then the columns right of
+// it are updated with K = KRIGE_BAND.
+constexpr int64_t KRIGE_BAND = 512;
 
 Layout layout(gp_handle_t h, gp_op_t op, int64_t n, int64_t m, gp_prec_t prec) {
     Layout L;
@@ -177,7 +182,10 @@ Layout layout(gp_handle_t h, gp_op_t op, int64_t n, int64_t m, gp_prec_t prec) {
     case GP_OP_KRIGE:
         L.dinv = take(sizeof(double) * DB * DB * (size_t)nb);
         L.big1 = take(sizeof(double) * (size_t)(n > 0 ? n : 1) * (size_t)(m > 0 ? m : 1));  // C*^T, m x n
-        L.part = take(sizeof(double) * DB * (size_t)(m > 0 ? m : 1));                        // m x 64
+        L.part = take(sizeof(double) * KRIGE_BAND * (size_t)(m > 0 ? m : 1));                // m x band copy
+        L.pflags = take(panel_flags_bytes());
+        if (n >= KRIGE_BAND)  // inverses of the full KRIGE_BAND diagonal blocks
+            L.kw = take(sizeof(double) * (size_t)(n / KRIGE_BAND) * KRIGE_BAND * KRIGE_BAND);
         L.big2 = take(sizeof(double) * 2 * (size_t)(m > 0 ? m : 1) * (size_t)(n > 0 ? rowreduce_chunks(n) : 1));
         break;
     default:
@@ -576,29 +584,38 @@ int trsm_impl(gp_handle_t h, int trans, int64_t n, int64_t nrhs, const double *L
 // updates gathered per 256-column band so the large product has K = 256.
 // tmp holds m x 64 doubles.
 int trsm_right_lt(hipStream_t s, int64_t n, int64_t m, const double *L, int64_t ldl, double *Y, const double *dinv,
-                  double *tmp, const int32_t *info) {
-    const int64_t NBT = 512;
+                  double *tmp, double *Wb, int *flags, const int32_t *info) {
+    const int64_t NBT = KRIGE_BAND;
     auto nt = [&](const double *A, int64_t lda, const double *B, int64_t ldb, double *C, int64_t M, int64_t N,
-                  int64_t K, double alpha, double beta) -> hipError_t {
+                  int64_t K, double alpha, double beta, int khi_j) -> hipError_t {
         GemmDesc d{};
         d.A = A; d.lda = lda; d.B = B; d.ldb = ldb; d.C = C; d.ldc = m;
         d.M = M; d.N = N; d.K = K; d.alpha = alpha; d.beta = beta;
-        d.ta = 0; d.tb = 1; d.batch = 1; d.info = info;
+        d.ta = 0; d.tb = 1; d.khi_j = khi_j; d.batch = 1; d.info = info;
         return launch_gemm_nt_dma(s, d);
     };
     if (n <= 0 || m <= 0) return GP_OK;
+    // inverses of all full diagonal bands in one launch
+    if (Wb && n >= NBT) HIPCHK(launch_block_trtri(s, L, ldl, (int)NBT, n / NBT, dinv, Wb, flags, info));
     for (int64_t kb0 = 0; kb0 < n; kb0 += NBT) {
         const int64_t kb1 = (kb0 + NBT < n) ? kb0 + NBT : n;
-        for (int64_t d = kb0; d < kb1; d += DB) {
-            const int64_t jb = (n - d) < DB ? (n - d) : DB;
-            HIPCHK(launch_copy2d(s, m, jb, Y + d * m, m, tmp, m));
-            // X_d = tmp Winv_d^T
-            HIPCHK(nt(tmp, m, dinv + (d / DB) * DB * DB, DB, Y + d * m, m, jb, jb, 1.0, 0.0));
-            if (d + jb < kb1)
-                HIPCHK(nt(Y + d * m, m, L + (d + jb) + d * ldl, ldl, Y + (d + jb) * m, m, kb1 - d - jb, jb, -1.0, 1.0));
+        if (Wb && kb1 - kb0 == NBT) {
+            // Y_B = Y_B W_B^T (W_B lower: op(B)[k, j] = W_B[j, k], zero for k > j)
+            HIPCHK(launch_copy2d(s, m, NBT, Y + kb0 * m, m, tmp, m));
+            HIPCHK(nt(tmp, m, Wb + (kb0 / NBT) * NBT * NBT, NBT, Y + kb0 * m, m, NBT, NBT, 1.0, 0.0, 1));
+        } else {
+            for (int64_t d = kb0; d < kb1; d += DB) {
+                const int64_t jb = (n - d) < DB ? (n - d) : DB;
+                HIPCHK(launch_copy2d(s, m, jb, Y + d * m, m, tmp, m));
+                // X_d = tmp Winv_d^T
+                HIPCHK(nt(tmp, m, dinv + (d / DB) * DB * DB, DB, Y + d * m, m, jb, jb, 1.0, 0.0, 0));
+                if (d + jb < kb1)
+                    HIPCHK(nt(Y + d * m, m, L + (d + jb) + d * ldl, ldl, Y + (d + jb) * m, m, kb1 - d - jb, jb, -1.0,
+                              1.0, 0));
+            }
         }
         if (kb1 < n)
-            HIPCHK(nt(Y + kb0 * m, m, L + kb1 + kb0 * ldl, ldl, Y + kb1 * m, m, n - kb1, kb1 - kb0, -1.0, 1.0));
+            HIPCHK(nt(Y + kb0 * m, m, L + kb1 + kb0 * ldl, ldl, Y + kb1 * m, m, n - kb1, kb1 - kb0, -1.0, 1.0, 0));
     }
     return GP_OK;
 }
@@ -1080,7 +1097,8 @@ int gp_krige(gp_handle_t h, gp_theta_t th, int64_t n, int64_t m, int32_t dim, co
     HIPCHK(launch_diag_inv(s, L, ldl, n, dinv));
     HIPCHK(launch_cross_cov(s, cp, m, n, Xs, X, Y, m));  // Y(j, i) = sigma^2 k(|s_j - x_i| / rho)
     HIPCHK(launch_rowreduce(s, 0, m, n, Y, m, alpha, mu, partials, mean_dev));
-    int rc = trsm_right_lt(s, n, m, L, ldl, Y, dinv, at<double>(ws, lay.part), nullptr);  // rows of L^{-1} C*, transposed
+    int rc = trsm_right_lt(s, n, m, L, ldl, Y, dinv, at<double>(ws, lay.part), lay.kw ? at<double>(ws, lay.kw) : nullptr,
+                           at<int>(ws, lay.pflags), nullptr);  // rows of L^{-1} C*, transposed
     if (rc) return rc;
     HIPCHK(launch_rowreduce(s, 1, m, n, Y, m, nullptr, base_var, partials, var_dev));
     return GP_OK;

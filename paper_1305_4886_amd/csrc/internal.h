@@ -403,6 +403,12 @@ constexpr int PF_MAXB = 16;
 constexpr size_t panel_flags_bytes() { return sizeof(int) * (PF_MAXB * PF_MAXB + 64); }
 hipError_t launch_panel_chol(hipStream_t s, double *A, int64_t lda, int K, double *dinv, double *W, int64_t ldw,
                              int *flags, int32_t *info, int64_t col0);
+// W_b = L_bb^{-1} (K x K, ld K, zeros above the diagonal, at W + b K^2) for the
+// nblocks consecutive K x K diagonal blocks b of a factored L (K % 64 == 0,
+// K <= 64 PF_MAXB), from their 64 x 64 block inverses (dinv, consecutive).  One
+// launch; flags: any valid pointer (nothing is waited for).
+hipError_t launch_block_trtri(hipStream_t s, const double *L, int64_t ldl, int K, int64_t nblocks, const double *dinv,
+                              double *W, int *flags, const int32_t *info);
 // Work area of a triangular solve: trsv_work_bytes(n) bytes (counters and a
 // mailbox of n doubles); the abort flag is its int [1].
 size_t trsv_work_bytes(int64_t n);

@@ -195,8 +195,13 @@ GP_DEV void pf_accum(double *M, int64_t ld, const gp_v4d (&acc)[4], double sgn, 
         }
 }
 
+// With factor == 0 the block is already factored (L, and its 64 x 64 block
+// inverses in dinv): only phase 2 runs, with nothing to wait for.  Launch
+// dimension y batches independent blocks at strides sA (A), sD (dinv), sW (W)
+// and sF (flags).
 __global__ __launch_bounds__(256, 1) void k_panel_chol(double *A, int64_t lda, int K, double *dinv, double *W,
-                                                       int64_t ldw, int *flags, int32_t *info, int64_t col0) {
+                                                       int64_t ldw, int *flags, int32_t *info, int64_t col0,
+                                                       int factor, int64_t sA, int64_t sD, int64_t sW, int64_t sF) {
     // 74 KB, so that a workgroup fits beside one workgroup of the trailing update
     __shared__ union {
         struct {
@@ -214,7 +219,11 @@ __global__ __launch_bounds__(256, 1) void k_panel_chol(double *A, int64_t lda, i
         } d;
     } sm;
     __shared__ int s_ok;
-    if (*info) return;
+    if (info && *info) return;
+    A += (int64_t)blockIdx.y * sA;
+    dinv += (int64_t)blockIdx.y * sD;
+    if (W) W += (int64_t)blockIdx.y * sW;
+    flags += (int64_t)blockIdx.y * sF;
     const int nb = (K + DB - 1) / DB;
     const int b = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -223,7 +232,7 @@ __global__ __launch_bounds__(256, 1) void k_panel_chol(double *A, int64_t lda, i
     gp_v4d acc[4];
 
     // ---- phase 1 ----
-    for (int k = 0; k < b; ++k) {
+    for (int k = 0; factor && k < b; ++k) {
         if (!pf_wait(flags, k * PF_MAXB + k, &s_ok)) return;
         pf_load<false>(sm.g.op, dinv + (int64_t)k * DB * DB, DB, DB, DB);  // W_k
         __syncthreads();
@@ -252,8 +261,12 @@ __global__ __launch_bounds__(256, 1) void k_panel_chol(double *A, int64_t lda, i
             __syncthreads();  // op is reloaded next; S_bj stores complete
         }
     }
-    // diagonal block: one wave factors and inverts it
-    if (w == 0) {
+    // diagonal block: one wave factors and inverts it (or, when it is
+    // factored already, W_b is read back)
+    if (!factor) {
+        for (int e = tid; e < DB * DB; e += 256) sm.d.wl[e & (DB - 1)][e >> 6] = dinv[(int64_t)b * DB * DB + e];
+        if (tid == 0) s_ok = 1;
+    } else if (w == 0) {
         double a[DB];
         double *D = Ab + (int64_t)DB * b * lda;
 #pragma unroll
@@ -305,7 +318,7 @@ __global__ __launch_bounds__(256, 1) void k_panel_chol(double *A, int64_t lda, i
         pf_load<true>(sm.g.lb, Wc + DB * k, ldw, DB, DB);  // lb[c][m] = W_kb(m, c)
         __syncthreads();
         for (int s2 = k + 1; s2 < nb; ++s2) {
-            if (!pf_wait(flags, s2 * PF_MAXB + k, &s_ok)) return;
+            if (factor && !pf_wait(flags, s2 * PF_MAXB + k, &s_ok)) return;
             pf_gemm(nullptr, A + DB * s2 + (int64_t)DB * k * lda, lda, DB, sm.g.lb, acc, w, lane);  // L_sk W_kb
             pf_accum(Wc + DB * s2, ldw, acc, 1.0, DB, DB, false, w, lane);                       // T_sb +=
         }
@@ -659,7 +672,18 @@ hipError_t launch_panel_chol(hipStream_t s, double *A, int64_t lda, int K, doubl
     hipError_t e = launch_fill(s, flags, panel_flags_bytes());
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_panel_chol, dim3((unsigned)((K + DB - 1) / DB)), dim3(256), 0, s, A, lda, K, dinv, W, ldw,
-                       flags, info, col0);
+                       flags, info, col0, 1, (int64_t)0, (int64_t)0, (int64_t)0, (int64_t)0);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_trtri(hipStream_t s, const double *L, int64_t ldl, int K, int64_t nblocks, const double *dinv,
+                              double *W, int *flags, const int32_t *info) {
+    if (K <= 0 || nblocks <= 0) return hipSuccess;
+    if (K > DB * PF_MAXB || K % DB != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_panel_chol, dim3((unsigned)(K / DB), (unsigned)nblocks), dim3(256), 0, s,
+                       const_cast<double *>(L), ldl, K, const_cast<double *>(dinv), W, (int64_t)K, flags,
+                       const_cast<int32_t *>(info), (int64_t)0, 0, (int64_t)K * (ldl + 1), (int64_t)(K / DB) * DB * DB,
+                       (int64_t)K * K, (int64_t)0);
     return hipGetLastError();
 }
 
