@@ -578,11 +578,14 @@ int trsm_impl(gp_handle_t h, int trans, int64_t n, int64_t nrhs, const double *L
 }
 
 // ---- right-side solve Y <- Y L^{-T} (Y: m x n, column-major, ld m) --------
-// Left-looking by 64-column blocks on the NT matrix-core kernel (both
+// Right-looking by KRIGE_BAND-column bands on the NT matrix-core kernel (both
 // operands column-major with contiguous rows, as its direct-to-LDS copies
-// need): block d becomes (Y_d - sum_{k<d} X_k L_dk^T) Winv_d^T, with the
-// updates gathered per 256-column band so the large product has K = 256.
-// tmp holds m x 64 doubles.
+// need).  The inverses W_B of all full diagonal bands come from one batched
+// launch (Wb, (n / KRIGE_BAND) * KRIGE_BAND^2 doubles; flags as for the
+// panel kernel); band B then becomes Y_B W_B^T in one product (triangular
+// K-range skipped) and every band to its right takes Y_R -= Y_B L_RB^T.  A
+// partial last band (or Wb == nullptr) is solved by 64-column blocks with
+// the diagonal-block inverses in dinv.  tmp holds m x KRIGE_BAND doubles.
 int trsm_right_lt(hipStream_t s, int64_t n, int64_t m, const double *L, int64_t ldl, double *Y, const double *dinv,
                   double *tmp, double *Wb, int *flags, const int32_t *info) {
     const int64_t NBT = KRIGE_BAND;
