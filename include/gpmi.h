@@ -95,7 +95,9 @@ typedef struct {
     int32_t fused_panel; /* 1: each panel's diagonal block (factor, block inverses and, when rows
                             follow, its full inverse) in one launch of concurrent workgroups
                             (panels up to 1024 columns); 0: a chain of per-64-column launches */
-    int32_t reserved;
+    int32_t batch_grid;  /* gp_loglik_batched: 0 = one persistent launch with one workgroup per compute
+                            unit; > 0 = a persistent launch of that many workgroups; -1 = level-synchronous
+                            launches (three per tile column) */
 } gp_options_t;
 
 /* ---- handle ------------------------------------------------------------ */
@@ -219,9 +221,17 @@ int gp_krige(gp_handle_t h, gp_theta_t th, int64_t n, int64_t m, int32_t dim, co
  * C_pool[c_off_host[b] + i + j * n_host[b]] (ld = n_b).  th_host[b] is its
  * parameter set.  Writes out3_dev[3 b + {0,1,2}] = {loglik, logdet, q} and
  * info_dev[b].  Same model and definitions as gp_loglik (FP64).  The
- * problems are factored together in 64 x 64 tiles, one tile column per step
- * for all problems at once (three launches per step plus one for the solves),
- * largest problems first. */
+ * problems are factored together in 64 x 64 tiles.  By default (options
+ * batch_grid >= 0) one persistent launch takes every tile of every problem
+ * as a task (covariance tile, left-looking update, then factor + inverse or
+ * the product with the diagonal inverse), ordered so that each task's inputs
+ * come from earlier tasks, with the forward solve and the reductions folded
+ * into the diagonal tasks; a small launch before it resets the task flags.
+ * batch_grid = -1 instead runs one tile column per step for all problems at
+ * once (three launches per step plus one for the solves).  A stall of the
+ * persistent launch (never expected) sets info_dev[b] = -1 and leaves NaN.
+ * The workspace size depends on batch_grid (the persistent launch keeps a
+ * tile-major copy of the factors). */
 int gp_loglik_batched(gp_handle_t h, int32_t nbatch, const gp_theta_t *th_host,
                       const int64_t *n_host, const int64_t *x_off_host, const int64_t *c_off_host,
                       int32_t dim, const double *X, const double *y, double *C_pool,

@@ -173,7 +173,7 @@ Layout layout(gp_handle_t h, gp_op_t op, int64_t n, int64_t m, gp_prec_t prec) {
         }
         break;
     case GP_OP_BATCHED:
-        L.total = batch_ws_bytes(n > 0 ? n : 1, m > 0 ? m : 1);
+        L.total = batch_ws_bytes(n > 0 ? n : 1, m > 0 ? m : 1, h->opt.batch_grid >= 0);
         return L;
     case GP_OP_MORTON:
         L.keys = take(sizeof(uint64_t) * (size_t)next_pow2(n > 0 ? n : 1));
@@ -741,6 +741,7 @@ static void default_options(gp_options_t *o) {
     o->ir_tol = 1e-10;
     o->reorder = 1;
     o->fused_panel = 1;
+    o->batch_grid = 0;
 }
 
 int gp_create(gp_handle_t *h, void *stream) {
@@ -840,6 +841,7 @@ int gp_set_options(gp_handle_t h, const gp_options_t *opt) {
     if (opt->nb < 0 || opt->nb % DB != 0) return -2;
     if (opt->ir_max_iter < 0 || opt->band < -1 || opt->panel_cus < 0) return -2;
     if (opt->fused_panel != 0 && opt->fused_panel != 1) return -2;
+    if (opt->batch_grid < -1) return -2;
     if (!(opt->ir_tol >= 0.0) || isinf(opt->ir_tol)) return GP_ERR_NONFINITE;
     h->opt = *opt;
     return GP_OK;
@@ -1131,7 +1133,7 @@ int gp_loglik_batched(gp_handle_t h, int32_t nbatch, const gp_theta_t *th_host, 
     if (nbatch > 0 && !info_dev) return -12;
     if (!ws) return -13;
     if (nbatch == 0) return GP_OK;
-    return batch_run(h->stream, h->num_cu, h->batch_staging, nbatch, th_host, n_host, x_off_host, c_off_host, dim,
+    return batch_run(h->stream, h->num_cu, h->opt.batch_grid, h->batch_staging, nbatch, th_host, n_host, x_off_host, c_off_host, dim,
                      X, y, C_pool, out3_dev, info_dev, ws, ws_bytes);
 }
 

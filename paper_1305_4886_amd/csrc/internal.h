@@ -460,8 +460,8 @@ hipError_t launch_rowreduce(hipStream_t s, int mode, int64_t m, int64_t n, const
                             const double *v, double base, double *partials, double *out);
 
 // k_batch.hip
-size_t batch_ws_bytes(int64_t nmax, int64_t nbatch);
-int batch_run(hipStream_t s, int num_cu, void *&staging, int32_t nb, const gp_theta_t *th, const int64_t *nh,
+size_t batch_ws_bytes(int64_t nmax, int64_t nbatch, bool persistent);
+int batch_run(hipStream_t s, int num_cu, int grid, void *&staging, int32_t nb, const gp_theta_t *th, const int64_t *nh,
               const int64_t *xoff, const int64_t *coff, int32_t dim, const double *X, const double *y,
               double *C_pool, double *out3, int32_t *info, void *ws, size_t ws_bytes);
 void batch_staging_free(void *p);

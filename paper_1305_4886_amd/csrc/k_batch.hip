@@ -23,11 +23,13 @@
 #include "internal.h"
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 
 namespace {
 
 struct BProb {
     int64_t n, x_off, c_off, z_off, w_off;
+    int64_t f_off, p_off;  // persistent launch: first tile flag, first per-tile partial pair
     double s2, inv_rho, t2;
     int32_t kind, nt;
 };
@@ -310,6 +312,502 @@ __global__ __launch_bounds__(256) void k_bsolve(const BProb *__restrict__ probs,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Persistent dataflow variant: the whole batch in one launch.
+//
+// Task (p, i, k), i >= k, owns tile (i, k) of problem p.  It builds C_ik in
+// registers (no covariance pass through memory), subtracts L_ij L_kj^T for
+// j < k as those tiles become available (left-looking, the accumulator never
+// leaves the registers), and then either factors and inverts the tile
+// (i == k: L_kk, W_k = L_kk^{-1}, z_k = W_k (y_k - sum_j L_kj z_j) and the
+// tile's log-determinant / quadratic-form partials) or forms L_ik = A_ik W_k^T
+// once W_k is there.  The last diagonal task of a problem reduces its partials
+// into (loglik, log|C|, q).  Workgroups take tasks through an atomic ticket in
+// an order where every dependency has a smaller ticket, so the smallest
+// unfinished ticket never waits and the launch always drains: tile column k of
+// every problem (largest problems first) before column k + 1, and within a
+// problem's column the tiles below the diagonal top-down, with the next
+// diagonal tile (k + 1, k + 1) placed right after (k + 1, k), its last input.
+// A diagonal task thus starts a column ahead of the tiles that wait for its
+// inverse.  A workgroup takes its next ticket while it works on the current
+// one (the smallest unfinished ticket is still always being worked on).
+//
+// Data that other workgroups read back (each L_ik in a tile-major copy, W_k,
+// z_k, the partials) is written through to memory (agent-scope atomic
+// stores), and a tile's flag is raised only after its publisher's stores have
+// drained: 1 = ready, 2 = the problem failed (dependents skip their work and
+// pass the 2 on).  The tile-major copy and W_k are then read with ordinary
+// (cached, 16-byte) loads: each tile is written once per launch, occupies its
+// own 32 KB, and is first read after its flag, so no XCD's caches can hold a
+// line of it from before it was written (the caches start each launch clean
+// of the previous one's data); z_k and the partials share cache lines across
+// tiles and are read with agent-scope atomic loads.  Every wait
+// is bounded: a stall raises the abort flag, every workgroup then leaves, and
+// the problem that saw it reports info = -1 (its outputs stay NaN).
+// ---------------------------------------------------------------------------
+constexpr int BF_TICKET = 0, BF_ABORT = 1, BF_TILES = 64;
+
+GP_DEV double bld(const double *p) {
+    return __longlong_as_double((long long)__hip_atomic_load(
+        reinterpret_cast<uint64_t *>(const_cast<double *>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+GP_DEV void bst(double *p, double v) {
+    __hip_atomic_store(reinterpret_cast<uint64_t *>(p), (uint64_t)__double_as_longlong(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+GP_DEV int bflag(const int *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+GP_DEV int64_t tri64(int64_t r) { return r * (r + 1) / 2; }
+
+struct alignas(16) PersistSmem {
+    union {
+        struct {  // operand ring: two stages of L_ij / L_kj (column-major, 16-byte aligned rows)
+            double A[2][T][T + 2];
+            double B[2][T][T + 2];
+        } r;
+        struct {  // diagonal task: the factor and its inverse
+            double L[T][T + 1];
+            double W[T][T + 1];
+        } d;
+    } u;
+    union {
+        double pn[T][17];
+        double t32[32][33];
+    } U;
+    double rd[T];
+    double zs[2][T];
+    double tp[4][T];
+    int64_t ticket;
+    int ready, state;
+};
+
+// Wave 0 polls the flags of tile columns j .. j + 63 (those below k) of tile
+// rows i and k until column j is published; returns the first column not yet
+// published (the caller may take every column below it without waiting) and
+// the state (1 ready, 2 the problem failed, 0 abort).  Block-uniform: every
+// exit test of the poll loop is wave-uniform (ballots, readfirstlane).
+GP_DEV void bensure(PersistSmem &sm, int *flags, const int *fl, int64_t ri_base, int64_t rk_base, int j, int k,
+                    int &ready, int &state) {
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x, c = j + lane;
+        const int cend = (k - j) < 64 ? k : j + 64;
+        int r = cend, st = 1, spins = 0;
+        for (;;) {
+            int v = 1;
+            if (c < cend) {
+                const int a = bflag(fl + ri_base + c), d = bflag(fl + rk_base + c);
+                v = (a == 0 || d == 0) ? 0 : ((a == 2 || d == 2) ? 2 : 1);
+            }
+            const uint64_t nr = __ballot(v == 0), fl2 = __ballot(v == 2);
+            if (fl2) {
+                st = 2;
+                break;
+            }
+            r = nr ? j + (int)__builtin_ctzll(nr) : cend;
+            if (r > j) break;
+            if (__builtin_amdgcn_readfirstlane(bflag(flags + BF_ABORT))) {
+                st = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > SPIN_LIMIT) {
+                if (lane == 0) __hip_atomic_store(flags + BF_ABORT, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                st = 0;
+                break;
+            }
+        }
+        if (lane == 0) {
+            sm.ready = r;
+            sm.state = st;
+        }
+    }
+    __syncthreads();
+    ready = sm.ready;
+    state = sm.state;
+}
+
+// Thread 0 waits for one flag; returns its value (1 / 2) or 0 on abort.  Block-uniform.
+GP_DEV int bwait1(PersistSmem &sm, int *flags, const int *f) {
+    if (threadIdx.x == 0) {
+        int v, spins = 0;
+        while ((v = bflag(f)) == 0) {
+            if (bflag(flags + BF_ABORT)) break;
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > SPIN_LIMIT) {
+                __hip_atomic_store(flags + BF_ABORT, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+        sm.state = v;
+    }
+    __syncthreads();
+    return sm.state;
+}
+
+// Flags, info and outputs of a persistent launch to their initial state:
+// flags (ticket, abort and one per tile) zero, info 0, out3 NaN (0 for an
+// empty problem, whose log-likelihood is the empty sum).
+// Also decodes every ticket t into its task (problem, tile row, tile column):
+// colstart[c] is the first ticket of tile column c, cofs[c][q] the first
+// ticket of problem order[q] within it (relative to colstart[c]).
+__global__ __launch_bounds__(256) void k_binit(int *flags, int64_t nflags, const BProb *__restrict__ probs, int nb,
+                                               const int32_t *__restrict__ order, const int64_t *__restrict__ colstart,
+                                               const int64_t *__restrict__ cofs, int ncol, int4 *tasks,
+                                               double *out3, int32_t *info) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nflags; e += stride) flags[e] = 0;
+    const int64_t total = colstart[ncol];
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+        int lo = 0, hi = ncol - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (colstart[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const int k = lo;
+        const int64_t u = t - colstart[k];
+        const int64_t *co = cofs + (int64_t)k * (nb + 1);
+        const int q = find_prob(co, nb, u);
+        int64_t v = u - co[q];
+        int ti, tk = k;
+        if (k == 0 && v == 0) {
+            ti = 0;  // the first diagonal tile opens column 0
+        } else {
+            if (k == 0) --v;
+            // (k + 1, k), (k + 1, k + 1), (k + 2, k), (k + 3, k), ...
+            if (v == 1) {
+                ti = k + 1;
+                tk = k + 1;
+            } else {
+                ti = k + (v == 0 ? 1 : (int)v);
+            }
+        }
+        tasks[t] = make_int4(order[q], ti, tk, 0);
+    }
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += stride) {
+        info[b] = 0;
+        const double v = probs[b].n == 0 ? -0.0 : __builtin_nan("");
+        out3[3 * b] = v;
+        out3[3 * b + 1] = probs[b].n == 0 ? 0.0 : v;
+        out3[3 * b + 2] = probs[b].n == 0 ? 0.0 : v;
+    }
+}
+
+__global__ __launch_bounds__(256, 1) void k_bpersist(const BProb *__restrict__ probs, const int4 *__restrict__ tasks,
+                                                     int64_t total, int dim, const double *__restrict__ X,
+                                                     const double *__restrict__ y, double *C_pool, double *lt,
+                                                     double *wbuf, double *zbuf, double *part, int *flags,
+                                                     double *out3, int32_t *info) {
+    __shared__ PersistSmem sm;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wm = w & 1, wn = w >> 1;
+    if (tid == 0) sm.ticket = atomicAdd(flags + BF_TICKET, 1);
+    __syncthreads();
+    int64_t t = sm.ticket;  // < 2^31: the ticket counter is a 32-bit int
+    for (;; t = sm.ticket) {
+        if (t >= total) break;
+        const int4 task = tasks[t];
+        int nxt = 0;  // thread 0: the next ticket, taken now and handed over at the end of this task
+        if (tid == 0) nxt = atomicAdd(flags + BF_TICKET, 1);
+        const int b = task.x, i = task.y, k = task.z;
+        const BProb P = probs[b];
+        const bool diag = (i == k);
+        const int64_t ld = P.n, i0 = (int64_t)i * T, k0 = (int64_t)k * T;
+        const int ri = (int)((P.n - i0) < T ? (P.n - i0) : T), rk = (int)((P.n - k0) < T ? (P.n - k0) : T);
+        double *L = C_pool + P.c_off;
+        int *fl = flags + BF_TILES + P.f_off;  // flag of tile (r, c): fl[r (r + 1) / 2 + c]
+        const int64_t fi = tri64(i), fk = tri64(k);
+        const bool idle_wave = diag && wm == 0 && wn == 1;  // upper-right quarter of a diagonal tile: unused
+
+        // 1. the covariance tile, in the D layout of v_mfma_f64_16x16x4 (built
+        //    after the first operand loads are issued)
+        v4d acc[2][2];
+        auto gen_cov = [&]() {
+            const double *Xb = X + P.x_off * dim;
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int qq = 0; qq < 2; ++qq)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = wm * 32 + m * 16 + (lane >> 4) + 4 * r, col = wn * 32 + qq * 16 + (lane & 15);
+                        double v = 0.0;
+                        if (!idle_wave && row < ri && col < rk) {
+                            const int64_t gi = i0 + row, gk = k0 + col;
+                            const double d = point_dist(Xb + gi * dim, Xb + gk * dim, dim);
+                            v = P.s2 * cov_corr(P.kind, d * P.inv_rho) + (gi == gk ? P.t2 : 0.0);
+                        }
+                        acc[m][qq][r] = v;
+                    }
+        };
+        // 2. A_ik -= sum_{j < k} L_ij L_kj^T, operands staged through registers
+        //    (next column's loads in flight during this column's products)
+        int ready = 0, state = 1;
+        double tpart = 0.0;  // diagonal task: this wave's share of (sum_j L_kj z_j)[lane]
+        if (k > 0) {
+            // element pairs (rows 2 rp, 2 rp + 1 of column c) of the tile-major
+            // copies of L_ij and L_kj (rows past the problem are stored as zeros)
+            d2 va[(T * T) / 512], vb[(T * T) / 512];
+            double zv = 0.0;
+            auto stage = [&](int buf) {  // registers -> LDS stage buf
+#pragma unroll
+                for (int r = 0; r < (T * T) / 512; ++r) {
+                    const int e = r * 256 + tid, rp = e & 31, kk = e >> 5;
+                    *reinterpret_cast<d2 *>(&sm.u.r.A[buf][kk][2 * rp]) = va[r];
+                    if (!diag) *reinterpret_cast<d2 *>(&sm.u.r.B[buf][kk][2 * rp]) = vb[r];
+                }
+                if (diag && tid < T) sm.zs[buf][tid] = zv;
+            };
+            bensure(sm, flags, fl, fi, fk, 0, k, ready, state);
+            if (state == 1) {
+                const d2 *Ai = reinterpret_cast<const d2 *>(lt + (P.f_off + fi) * (T * T));
+                const d2 *Bk = reinterpret_cast<const d2 *>(lt + (P.f_off + fk) * (T * T));
+#pragma unroll
+                for (int r = 0; r < (T * T) / 512; ++r) {
+                    va[r] = Ai[r * 256 + tid];
+                    if (!diag) vb[r] = Bk[r * 256 + tid];
+                }
+                if (diag && tid < T) zv = bld(zbuf + P.z_off + tid);
+            }
+            gen_cov();  // overlaps the first operand loads
+            if (state == 1) stage(0);
+            __syncthreads();
+            // One barrier per column: stage j & 1 is read while the registers
+            // take column j + 1, which then goes to the other stage (last read
+            // in column j - 1, before the previous barrier).
+            for (int j = 0; j < k && state == 1; ++j) {
+                const int cb = j & 1;
+                const bool more = j + 1 < k;
+                if (more) {
+                    if (j + 1 >= ready) bensure(sm, flags, fl, fi, fk, j + 1, k, ready, state);
+                    if (state != 1) break;
+                }
+                // The next column's loads go out one per step of the products
+                // (a burst of them would hold up the matrix instructions); at the
+                // last column the current tiles are fetched again (cached, unused).
+                const int jn = more ? j + 1 : j;
+                const d2 *An = reinterpret_cast<const d2 *>(lt + (P.f_off + fi + jn) * (T * T));
+                const d2 *Bn = reinterpret_cast<const d2 *>(lt + (P.f_off + fk + jn) * (T * T));
+                double(*Ao)[T + 2] = sm.u.r.A[cb];
+                double(*Bo)[T + 2] = diag ? sm.u.r.A[cb] : sm.u.r.B[cb];
+                double a[2], bb[2];
+                if (!idle_wave) {
+#pragma unroll
+                    for (int m = 0; m < 2; ++m) a[m] = -Ao[lane >> 4][wm * 32 + m * 16 + (lane & 15)];
+#pragma unroll
+                    for (int qq = 0; qq < 2; ++qq) bb[qq] = Bo[lane >> 4][wn * 32 + qq * 16 + (lane & 15)];
+                }
+#pragma unroll
+                for (int st = 0; st < T / 4; ++st) {
+                    if (!idle_wave) {
+                        // operands of the next step first: their LDS latency hides under these products
+                        double an[2], bn[2];
+                        if (st + 1 < T / 4) {
+                            const int kn = 4 * (st + 1) + (lane >> 4);
+#pragma unroll
+                            for (int m = 0; m < 2; ++m) an[m] = -Ao[kn][wm * 32 + m * 16 + (lane & 15)];
+#pragma unroll
+                            for (int qq = 0; qq < 2; ++qq) bn[qq] = Bo[kn][wn * 32 + qq * 16 + (lane & 15)];
+                        }
+#pragma unroll
+                        for (int m = 0; m < 2; ++m)
+#pragma unroll
+                            for (int qq = 0; qq < 2; ++qq)
+                                acc[m][qq] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], bb[qq], acc[m][qq], 0, 0, 0);
+                        if (st + 1 < T / 4) {
+                            a[0] = an[0];
+                            a[1] = an[1];
+                            bb[0] = bn[0];
+                            bb[1] = bn[1];
+                        }
+                    }
+                    if ((st & 1) == 0) va[st >> 1] = An[(st >> 1) * 256 + tid];
+                    else if (!diag) vb[st >> 1] = Bn[(st >> 1) * 256 + tid];
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                if (diag) {
+                    if (more && tid < T) zv = bld(zbuf + P.z_off + (int64_t)jn * T + tid);
+#pragma unroll
+                    for (int c = 16 * w; c < 16 * w + 16; ++c) tpart = fma(Ao[c][lane], sm.zs[cb][c], tpart);
+                }
+                if (more) stage(cb ^ 1);
+                __syncthreads();
+            }
+        } else {
+            gen_cov();
+        }
+        if (state == 0) {  // stalled: leave (the abort flag stops every workgroup)
+            if (tid == 0) info[b] = -1;
+            return;
+        }
+
+        if (!diag) {
+            // 3a. L_ik = A_ik W_k^T once the diagonal task of column k has published W_k
+            if (state == 1) state = bwait1(sm, flags, fl + fk + k);
+            if (state == 0) {
+                if (tid == 0) info[b] = -1;
+                return;
+            }
+            if (state == 1) {
+                // W_k's loads first, so their latency overlaps moving A_ik to LDS
+                const d2 *Wk = reinterpret_cast<const d2 *>(wbuf + P.w_off + k0 * T);
+                d2 wv[(T * T) / 512];
+#pragma unroll
+                for (int r = 0; r < (T * T) / 512; ++r) wv[r] = Wk[r * 256 + tid];
+                __syncthreads();
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+#pragma unroll
+                    for (int qq = 0; qq < 2; ++qq)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int row = wm * 32 + m * 16 + (lane >> 4) + 4 * r, col = wn * 32 + qq * 16 + (lane & 15);
+                            sm.u.r.A[0][col][row] = acc[m][qq][r];
+                        }
+#pragma unroll
+                for (int r = 0; r < (T * T) / 512; ++r) {
+                    const int e = r * 256 + tid, rp = e & 31, kk = e >> 5;
+                    *reinterpret_cast<d2 *>(&sm.u.r.B[0][kk][2 * rp]) = wv[r];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+#pragma unroll
+                    for (int qq = 0; qq < 2; ++qq) acc[m][qq] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+                for (int kk = 0; kk < T; kk += 4) {
+                    double a[2], bb[2];
+#pragma unroll
+                    for (int m = 0; m < 2; ++m) a[m] = sm.u.r.A[0][kk + (lane >> 4)][wm * 32 + m * 16 + (lane & 15)];
+#pragma unroll
+                    for (int qq = 0; qq < 2; ++qq) bb[qq] = sm.u.r.B[0][kk + (lane >> 4)][wn * 32 + qq * 16 + (lane & 15)];
+#pragma unroll
+                    for (int m = 0; m < 2; ++m)
+#pragma unroll
+                        for (int qq = 0; qq < 2; ++qq)
+                            acc[m][qq] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], bb[qq], acc[m][qq], 0, 0, 0);
+                }
+                __syncthreads();  // As / Bs reads of the product are done
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+#pragma unroll
+                    for (int qq = 0; qq < 2; ++qq)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int row = wm * 32 + m * 16 + (lane >> 4) + 4 * r, col = wn * 32 + qq * 16 + (lane & 15);
+                            sm.u.r.A[0][col][row] = acc[m][qq][r];
+                        }
+                __syncthreads();
+                double *Lik = L + i0 + k0 * ld;
+                double *Lt = lt + (P.f_off + fi + k) * (T * T);
+#pragma unroll
+                for (int r = 0; r < (T * T) / 512; ++r) {
+                    const int e = r * 256 + tid, rp = e & 31, c = e >> 5;
+                    const double v0 = sm.u.r.A[0][c][2 * rp], v1 = sm.u.r.A[0][c][2 * rp + 1];
+                    bst(Lt + 2 * rp + c * T, v0);
+                    bst(Lt + 2 * rp + 1 + c * T, v1);
+                    if (2 * rp < ri) Lik[2 * rp + (int64_t)c * ld] = v0;
+                    if (2 * rp + 1 < ri) Lik[2 * rp + 1 + (int64_t)c * ld] = v1;
+                }
+            }
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            if (tid == 0) {
+                __hip_atomic_store(fl + fi + k, state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                sm.ticket = bflag(flags + BF_ABORT) ? total : nxt;
+            }
+            __syncthreads();
+            continue;
+        }
+
+        // 3b. diagonal tile: factor, invert, forward-solve block k, partials
+        if (state == 1) {
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int qq = 0; qq < 2; ++qq)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = wm * 32 + m * 16 + (lane >> 4) + 4 * r, col = wn * 32 + qq * 16 + (lane & 15);
+                        if (!idle_wave) sm.u.d.L[row][col] = acc[m][qq][r];
+                    }
+            sm.tp[w][lane] = tpart;
+            __syncthreads();
+            if (w == 0) {
+                double a[T];
+#pragma unroll
+                for (int c = 0; c < T; ++c) {
+                    double v;
+                    if (lane < rk && c < rk) v = (c <= lane) ? sm.u.d.L[lane][c] : 0.0;
+                    else v = (lane == c) ? 1.0 : 0.0;  // identity padding decouples unused rows
+                    a[c] = v;
+                }
+                const int fail = wave_chol64(a, lane, sm.u.d.W, sm.U.pn);
+                if (fail) {
+                    if (lane == 0) {
+                        info[b] = (int32_t)(k0 + fail);
+                        sm.state = 2;
+                    }
+                } else {
+                    double *Lkk = L + k0 + k0 * ld;
+#pragma unroll
+                    for (int c = 0; c < T; ++c) {
+                        sm.u.d.L[lane][c] = a[c];
+                        if (lane < rk && c < rk && c <= lane) Lkk[lane + (int64_t)c * ld] = a[c];
+                    }
+                    wave_lds_sync();
+                    wave_inv64_blocked(sm.u.d.L, sm.u.d.W, sm.U.t32, sm.rd, lane);
+                    double *Wk = wbuf + P.w_off + k0 * T;
+#pragma unroll 4
+                    for (int c = 0; c < T; ++c) bst(Wk + lane + c * T, sm.u.d.W[lane][c]);
+                    const double tsum = (sm.tp[0][lane] + sm.tp[1][lane]) + (sm.tp[2][lane] + sm.tp[3][lane]);
+                    sm.zs[0][lane] = lane < rk ? y[P.x_off + k0 + lane] - tsum : 0.0;
+                    wave_lds_sync();
+                    double zr = 0.0;
+#pragma unroll 8
+                    for (int c = 0; c < T; ++c) zr = fma(sm.u.d.W[lane][c], sm.zs[0][c], zr);
+                    if (lane < rk) bst(zbuf + P.z_off + k0 + lane, zr);
+                    sm.tp[0][lane] = lane < rk ? log(sm.u.d.L[lane][lane]) : 0.0;
+                    sm.tp[1][lane] = lane < rk ? zr * zr : 0.0;
+                    wave_lds_sync();
+                    if (lane == 0) {
+                        CSum sl, sq;
+                        for (int c = 0; c < T; ++c) {
+                            sl.add(sm.tp[0][c]);
+                            sq.add(sm.tp[1][c]);
+                        }
+                        bst(part + P.p_off + 2 * k, sl.value());
+                        bst(part + P.p_off + 2 * k + 1, sq.value());
+                        sm.state = 1;
+                    }
+                }
+            }
+            __syncthreads();
+            state = sm.state;
+        }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (tid == 0) {
+            __hip_atomic_store(fl + fk + k, state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (k == P.nt - 1) {  // the last diagonal tile: every partial of the problem is published
+                double *o = out3 + 3 * (int64_t)b;
+                if (state == 1) {
+                    CSum sl, sq;
+                    for (int j = 0; j < P.nt; ++j) {
+                        sl.add(bld(part + P.p_off + 2 * j));
+                        sq.add(bld(part + P.p_off + 2 * j + 1));
+                    }
+                    const double logdet = 2.0 * sl.value(), qf = sq.value();
+                    o[1] = logdet;
+                    o[2] = qf;
+                    o[0] = -0.5 * (((double)P.n * 1.8378770664093453 + logdet) + qf);
+                }  // failed: the NaNs written at the start stay
+            }
+            sm.ticket = bflag(flags + BF_ABORT) ? total : nxt;
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -323,7 +821,7 @@ namespace {
 inline size_t al256b(size_t x) { return (x + 255) & ~(size_t)255; }
 }
 
-size_t batch_ws_bytes(int64_t nmax, int64_t nbatch) {
+size_t batch_ws_bytes(int64_t nmax, int64_t nbatch, bool persistent) {
     const int64_t nt = (nmax + T - 1) / T;
     size_t b = 0;
     b += al256b(sizeof(BProb) * (size_t)nbatch);
@@ -331,6 +829,12 @@ size_t batch_ws_bytes(int64_t nmax, int64_t nbatch) {
     b += al256b(sizeof(int64_t) * (size_t)(2 * nt + 1) * (size_t)(nbatch + 1));  // per-level prefix counts
     b += al256b(sizeof(double) * (size_t)nmax * (size_t)nbatch);                 // z
     b += al256b(sizeof(double) * (size_t)nt * T * T * (size_t)nbatch);           // diagonal inverses
+    b += al256b(sizeof(int64_t) * ((size_t)nt * (size_t)(nbatch + 1) + (size_t)nt + 1));  // persistent schedule
+    b += al256b(sizeof(int) * ((size_t)BF_TILES + (size_t)(nt * (nt + 1) / 2) * (size_t)nbatch));  // tile flags
+    b += al256b(sizeof(double) * 2 * (size_t)nt * (size_t)nbatch);               // per-tile partials
+    b += al256b(16 * (size_t)(nt * (nt + 1) / 2) * (size_t)nbatch);              // decoded tasks
+    if (persistent)  // tile-major copy of the factor's tiles, read back inside the launch
+        b += al256b(sizeof(double) * T * T * (size_t)(nt * (nt + 1) / 2) * (size_t)nbatch);
     return b + 256;
 }
 
@@ -338,13 +842,13 @@ struct BatchStaging {
     std::vector<BProb> probs;
     std::vector<int32_t> order;
     std::vector<int64_t> offs;  // [level block][nb + 1]: covariance, then per level panel and update counts
+    std::vector<int64_t> sched;  // persistent launch: colstart[ncol + 1], then cofs[ncol][nb + 1]
     hipEvent_t done = nullptr;
 };
 
-int batch_run(hipStream_t s, int num_cu, void *&staging_ptr, int32_t nb, const gp_theta_t *th, const int64_t *nh,
-              const int64_t *xoff, const int64_t *coff, int32_t dim, const double *X, const double *y,
-              double *C_pool, double *out3, int32_t *info, void *ws, size_t ws_bytes) {
-    (void)num_cu;
+int batch_run(hipStream_t s, int num_cu, int grid, void *&staging_ptr, int32_t nb, const gp_theta_t *th,
+              const int64_t *nh, const int64_t *xoff, const int64_t *coff, int32_t dim, const double *X,
+              const double *y, double *C_pool, double *out3, int32_t *info, void *ws, size_t ws_bytes) {
     BatchStaging *st = static_cast<BatchStaging *>(staging_ptr);
     if (!st) {
         st = new BatchStaging();
@@ -357,10 +861,10 @@ int batch_run(hipStream_t s, int num_cu, void *&staging_ptr, int32_t nb, const g
     }
     int64_t nmax = 1;
     for (int b = 0; b < nb; ++b) nmax = std::max(nmax, nh[b]);
-    if (ws_bytes < batch_ws_bytes(nmax, nb)) return GP_ERR_WS_TOO_SMALL;
+    if (ws_bytes < batch_ws_bytes(nmax, nb, grid >= 0)) return GP_ERR_WS_TOO_SMALL;
     const int64_t ntmax = (nmax + T - 1) / T;
     st->probs.assign(nb, BProb{});
-    int64_t zoff = 0, woff = 0;
+    int64_t zoff = 0, woff = 0, foff = 0, poff_ = 0;
     for (int b = 0; b < nb; ++b) {
         BProb &p = st->probs[b];
         p.n = nh[b];
@@ -371,6 +875,10 @@ int batch_run(hipStream_t s, int num_cu, void *&staging_ptr, int32_t nb, const g
         zoff += p.n;
         p.w_off = woff;
         woff += (int64_t)p.nt * T * T;
+        p.f_off = foff;
+        foff += (int64_t)p.nt * (p.nt + 1) / 2;
+        p.p_off = poff_;
+        poff_ += 2 * (int64_t)p.nt;
         p.kind = th[b].kind;
         p.s2 = std::exp(th[b].log_sigma2);
         p.inv_rho = std::exp(-th[b].log_rho);
@@ -410,6 +918,52 @@ int batch_run(hipStream_t s, int num_cu, void *&staging_ptr, int32_t nb, const g
     int64_t *d_offs = reinterpret_cast<int64_t *>(take(sizeof(int64_t) * st->offs.size()));
     double *d_z = reinterpret_cast<double *>(take(sizeof(double) * (size_t)nmax * (size_t)nb));
     double *d_w = reinterpret_cast<double *>(take(sizeof(double) * (size_t)ntmax * T * T * (size_t)nb));
+
+    if (grid >= 0) {
+        // Persistent launch.  Ticket order: tile column k of every problem
+        // (largest first), the diagonal tile first within a problem.
+        // Per tile column k and problem: k = 0 holds (0, 0), the tiles below
+        // it and (1, 1); 1 <= k <= nt - 2 holds the nt - k - 1 tiles below
+        // (k, k) and (k + 1, k + 1).
+        const int64_t W1 = nb + 1;
+        st->sched.assign((size_t)(ntmax + 1) + (size_t)ntmax * (size_t)W1, 0);
+        int64_t *colstart = st->sched.data(), *cofs = colstart + (ntmax + 1);
+        for (int64_t k = 0; k < ntmax; ++k) {
+            int64_t *co = cofs + k * W1;
+            for (int q = 0; q < nb; ++q) {
+                const int64_t ntq = st->probs[st->order[q]].nt;
+                const int64_t m = k == 0 ? ntq + (ntq >= 2 ? 1 : 0) : (k <= ntq - 2 ? ntq - k : 0);
+                co[q + 1] = co[q] + m;
+            }
+            colstart[k + 1] = colstart[k] + co[nb];
+        }
+        const int64_t total = colstart[ntmax];
+        int64_t *d_sched = reinterpret_cast<int64_t *>(take(sizeof(int64_t) * st->sched.size()));
+        const int64_t nflags = BF_TILES + foff;
+        int *d_flags = reinterpret_cast<int *>(take(sizeof(int) * (size_t)nflags));
+        double *d_part = reinterpret_cast<double *>(take(sizeof(double) * (size_t)(poff_ > 0 ? poff_ : 1)));
+        int4 *d_tasks = reinterpret_cast<int4 *>(take(sizeof(int4) * (size_t)(total > 0 ? total : 1)));
+        double *d_lt = reinterpret_cast<double *>(take(sizeof(double) * T * T * (size_t)(foff > 0 ? foff : 1)));
+        if (off > ws_bytes) return GP_ERR_WS_TOO_SMALL;
+        if (hipMemcpyAsync(d_probs, st->probs.data(), sizeof(BProb) * (size_t)nb, hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            hipMemcpyAsync(d_order, st->order.data(), sizeof(int32_t) * (size_t)nb, hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            hipMemcpyAsync(d_sched, st->sched.data(), sizeof(int64_t) * st->sched.size(), hipMemcpyHostToDevice, s) !=
+                hipSuccess)
+            return GP_ERR_HIP;
+        if (hipEventRecord(st->done, s) != hipSuccess) return GP_ERR_HIP;
+        const int64_t init_blocks = std::min<int64_t>(1024, std::max<int64_t>(std::max<int64_t>(nflags, total), nb) / 256 + 1);
+        hipLaunchKernelGGL(k_binit, dim3((unsigned)init_blocks), dim3(256), 0, s, d_flags, nflags, d_probs, nb, d_order,
+                           d_sched, d_sched + (ntmax + 1), (int)ntmax, d_tasks, out3, info);
+        if (total > 0) {
+            int64_t g = grid > 0 ? grid : (int64_t)(num_cu > 0 ? num_cu : 1);
+            if (g > total) g = total;
+            hipLaunchKernelGGL(k_bpersist, dim3((unsigned)g), dim3(256), 0, s, d_probs, d_tasks, total, (int)dim, X, y,
+                               C_pool, d_lt, d_w, d_z, d_part, d_flags, out3, info);
+        }
+        return hipGetLastError() == hipSuccess ? GP_OK : GP_ERR_HIP;
+    }
 
     if (hipMemcpyAsync(d_probs, st->probs.data(), sizeof(BProb) * (size_t)nb, hipMemcpyHostToDevice, s) != hipSuccess)
         return GP_ERR_HIP;

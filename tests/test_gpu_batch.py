@@ -1,6 +1,9 @@
-"""Batched likelihoods in one persistent launch: each problem of a ragged batch
-must match the single-problem CPU oracle (same model and definitions,
-Section 1), including per-problem failure reporting."""
+"""Batched likelihoods: each problem of a ragged batch must match the
+single-problem CPU oracle (same model and definitions, Section 1), including
+per-problem failure reporting.  Every schedule is covered: the persistent
+launch with its automatic grid, with one workgroup (every task in ticket
+order on one workgroup) and with a small odd grid, and the level-synchronous
+launches."""
 import math
 
 import numpy as np
@@ -38,8 +41,20 @@ def make_batch(sizes, seed, kernels=None):
     return Xs, ys, ths
 
 
+GRIDS = [0, 1, 7, -1]  # persistent (automatic, one workgroup, seven workgroups), level-synchronous
+
+
+@pytest.fixture(params=GRIDS, ids=lambda g: "grid%d" % g)
+def grid(request):
+    h = gp.handle()
+    saved = h.options()
+    h.set_options(batch_grid=request.param)
+    yield request.param
+    h.set_options(batch_grid=saved.batch_grid)
+
+
 @pytest.mark.parametrize("sizes", [[1], [64], [65, 3, 200], [300, 0, 129, 1000, 64, 777, 511, 2]])
-def test_batched_matches_oracle(orc, sizes):
+def test_batched_matches_oracle(orc, sizes, grid):
     Xs, ys, ths = make_batch(sizes, 70)
     X = np.concatenate([x for x in Xs if len(x)] or [np.zeros((0, 2))])
     y = np.concatenate([v for v in ys if len(v)] or [np.zeros(0)])
@@ -55,6 +70,38 @@ def test_batched_matches_oracle(orc, sizes):
         ll, ld, q = orc.loglik(k, t, Xs[b], ys[b])
         assert abs(out[b, 0] - ll) <= 1e-11 * abs(ll), (b, n, out[b], ll)
         assert abs(out[b, 1] - ld) <= 1e-11 * max(1.0, abs(ld))
+
+
+def test_batched_factor_in_pool(orc, grid):
+    """On return each problem's slice of the pool holds its lower factor."""
+    sizes = [200, 64, 131]
+    Xs, ys, ths = make_batch(sizes, 80)
+    r = gp.loglik_batched(dev(np.concatenate(Xs)), dev(np.concatenate(ys)),
+                          [gp.theta(k, log=t) for k, t in ths], sizes)
+    pool = r["C_pool"].cpu().numpy()
+    off = 0
+    for b, n in enumerate(sizes):
+        k, t = ths[b]
+        Lg = np.tril(pool[off:off + n * n].reshape(n, n).T)
+        Lo, oinfo = orc.potrf(orc.cov(k, t, Xs[b]))
+        assert oinfo == 0
+        assert np.linalg.norm(Lg - Lo) <= 1e-12 * np.linalg.norm(Lo), b
+        off += n * n
+
+
+def test_batched_more_than_64_tile_columns(orc, grid):
+    """n = 4200 has 66 tile columns: the dependency polls span more than one wave's width."""
+    sizes = [4200, 100]
+    Xs, ys, ths = make_batch(sizes, 85, kernels=[1, 0])
+    r = gp.loglik_batched(dev(np.concatenate(Xs)), dev(np.concatenate(ys)),
+                          [gp.theta(k, log=t) for k, t in ths], sizes)
+    out = r["out3"].cpu().numpy()
+    assert np.all(r["info"].cpu().numpy() == 0)
+    for b in range(2):
+        k, t = ths[b]
+        ll, ld, q = orc.loglik(k, t, Xs[b], ys[b])
+        assert abs(out[b, 0] - ll) <= 1e-11 * abs(ll), (b, out[b], ll)
+        assert abs(out[b, 2] - q) <= 1e-11 * abs(q)
 
 
 def test_batched_workload_64_problems(orc):
@@ -74,7 +121,7 @@ def test_batched_workload_64_problems(orc):
     assert np.all(np.isfinite(out))
 
 
-def test_batched_failure_is_per_problem():
+def test_batched_failure_is_per_problem(grid):
     sizes = [100, 150, 80]
     Xs, ys, ths = make_batch(sizes, 90, kernels=[0, 0, 0])
     Xs[1][120] = Xs[1][30]  # duplicate point, no nugget -> not PD
