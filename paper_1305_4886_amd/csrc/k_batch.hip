@@ -517,11 +517,34 @@ __global__ __launch_bounds__(256, 1) void k_bpersist(const BProb *__restrict__ p
         const int64_t fi = tri64(i), fk = tri64(k);
         const bool idle_wave = diag && wm == 0 && wn == 1;  // upper-right quarter of a diagonal tile: unused
 
-        // 1. the covariance tile, in the D layout of v_mfma_f64_16x16x4 (built
-        //    after the first operand loads are issued)
+        // 1. the covariance tile, in the D layout of v_mfma_f64_16x16x4.  For
+        //    points in the plane the coordinates of this thread's 8 rows and
+        //    2 columns are loaded first, before the operand tiles (the load
+        //    counter drains in issue order), and the tile is built once the
+        //    operand loads are on their way.
         v4d acc[2][2];
+        const double *Xb = X + P.x_off * dim;
+        double xr[8][2], xc[2][2];
+        const bool planar = dim <= 2;
+        if (planar) {
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = wm * 32 + m * 16 + (lane >> 4) + 4 * r;
+                    const double *p = Xb + (i0 + (row < ri ? row : 0)) * dim;
+                    xr[4 * m + r][0] = p[0];
+                    xr[4 * m + r][1] = dim == 2 ? p[1] : 0.0;
+                }
+#pragma unroll
+            for (int qq = 0; qq < 2; ++qq) {
+                const int col = wn * 32 + qq * 16 + (lane & 15);
+                const double *p = Xb + (k0 + (col < rk ? col : 0)) * dim;
+                xc[qq][0] = p[0];
+                xc[qq][1] = dim == 2 ? p[1] : 0.0;
+            }
+        }
         auto gen_cov = [&]() {
-            const double *Xb = X + P.x_off * dim;
 #pragma unroll
             for (int m = 0; m < 2; ++m)
 #pragma unroll
@@ -532,7 +555,13 @@ __global__ __launch_bounds__(256, 1) void k_bpersist(const BProb *__restrict__ p
                         double v = 0.0;
                         if (!idle_wave && row < ri && col < rk) {
                             const int64_t gi = i0 + row, gk = k0 + col;
-                            const double d = point_dist(Xb + gi * dim, Xb + gk * dim, dim);
+                            double d;
+                            if (planar) {
+                                const double d0 = xr[4 * m + r][0] - xc[qq][0], d1 = xr[4 * m + r][1] - xc[qq][1];
+                                d = sqrt(fma(d1, d1, d0 * d0));  // the rounding of point_dist
+                            } else {
+                                d = point_dist(Xb + gi * dim, Xb + gk * dim, dim);
+                            }
                             v = P.s2 * cov_corr(P.kind, d * P.inv_rho) + (gi == gk ? P.t2 : 0.0);
                         }
                         acc[m][qq][r] = v;
