@@ -237,6 +237,21 @@ int gp_loglik_batched(gp_handle_t h, int32_t nbatch, const gp_theta_t *th_host,
                       int32_t dim, const double *X, const double *y, double *C_pool,
                       double *out3_dev, int32_t *info_dev, void *ws, size_t ws_bytes);
 
+/* Autotuner for gp_loglik_batched's schedule: for each candidate batch_grid
+ * grid_cand[c] [host; -1 = level-synchronous launches, 0 = one persistent
+ * workgroup per compute unit, > 0 = that many persistent workgroups] it runs
+ * the batch given by the same arguments as gp_loglik_batched twice on the
+ * handle's stream and writes the milliseconds of the second run to ms_out[c]
+ * [host, may be NULL; -1 where the candidate's workspace exceeds ws_bytes].
+ * The fastest candidate is stored in the handle's options (batch_grid); on
+ * error the options are left unchanged.  C_pool, out3_dev and info_dev are
+ * written as by gp_loglik_batched (they hold the last candidate's results).
+ * Synchronises the handle's stream. */
+int gp_tune_batched(gp_handle_t h, int32_t nbatch, const gp_theta_t *th_host, const int64_t *n_host,
+                    const int64_t *x_off_host, const int64_t *c_off_host, int32_t dim, const double *X,
+                    const double *y, double *C_pool, double *out3_dev, int32_t *info_dev, const int32_t *grid_cand,
+                    int32_t n_cand, double *ms_out, void *ws, size_t ws_bytes);
+
 /* ---- spatial ordering ----------------------------------------------------
  * perm_dev [dev, n] <- the permutation that sorts the points X [dev, n x 2]
  * by their 2 x 21-bit Morton (Z-order) code on the bounding box, ties broken

@@ -31,7 +31,7 @@ PRECS = {"fp64": GP_FP64, "fp32": GP_FP32_TRAIL, "bf16": GP_BF16_TRAIL}
 EXPORTED = ["gp_create", "gp_destroy", "gp_set_stream", "gp_set_options", "gp_get_options",
             "gp_strerror", "gp_profile", "gp_profile_read", "gp_workspace_size", "gp_cov_build", "gp_cross_cov_build", "gp_potrf",
             "gp_trsv", "gp_trsm", "gp_loglik", "gp_loglik_grad", "gp_krige", "gp_loglik_batched",
-            "gp_morton_order", "gp_tune_potrf"]
+            "gp_morton_order", "gp_tune_potrf", "gp_tune_batched"]
 
 
 class Theta(ctypes.Structure):
@@ -97,6 +97,8 @@ def lib():
         L.gp_krige.argtypes = [vp, Theta, i64, i64, i32, vp, vp, vp, i64, vp, dbl, vp, vp, i32, vp, sz]
         L.gp_loglik_batched.argtypes = [vp, i32, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, sz]
         L.gp_morton_order.argtypes = [vp, i64, i32, vp, vp, vp, sz]
+        L.gp_tune_batched.argtypes = [vp, i32, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, ctypes.POINTER(i32), i32,
+                                      ctypes.POINTER(dbl), vp, sz]
         _lib = L
     return _lib
 
@@ -199,6 +201,38 @@ class Handle:
         check(lib().gp_tune_potrf(self._h, prec, n, _ptr(A), A.shape[1], nb_a, len(nb), cu_a, len(cus),
                                   _ptr(info), ms, _ptr(ws), ws.numel()))
         return {(nb[a], cus[b]): ms[a * len(cus) + b] for a in range(len(nb)) for b in range(len(cus))}
+
+    def tune_batched(self, X, y, thetas, sizes, grids=None):
+        """Time gp_loglik_batched over candidate schedules (batch_grid: -1 level-synchronous,
+        0 one persistent workgroup per compute unit, > 0 that many) and keep the fastest in this
+        handle's options.  Returns {batch_grid: ms} (-1: did not fit)."""
+        torch = _torch()
+        import numpy as np
+        X, y = _f64(X), _f64(y)
+        nb = len(sizes)
+        sizes = np.asarray(sizes, dtype=np.int64)
+        if grids is None:
+            ncu = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+            grids = (-1, 0, ncu // 2, 2 * ncu)
+        grids = [int(g) for g in grids]
+        x_off = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+        c_off = np.concatenate([[0], np.cumsum(sizes * sizes)[:-1]]).astype(np.int64)
+        th_arr = (Theta * nb)(*thetas)
+        saved = self.options()
+        self.set_options(batch_grid=0)  # the persistent workspace is the larger one
+        ws = self.workspace(GP_OP_BATCHED, int(sizes.max()), nb)
+        self.set_options(batch_grid=saved.batch_grid)
+        C_pool = torch.empty(max(int((sizes * sizes).sum()), 1), dtype=torch.float64, device="cuda")
+        out3 = torch.empty(3 * nb, dtype=torch.float64, device="cuda")
+        info = torch.zeros(nb, dtype=torch.int32, device="cuda")
+        cand = (ctypes.c_int32 * len(grids))(*grids)
+        ms = (ctypes.c_double * len(grids))()
+        check(lib().gp_tune_batched(self._h, nb, ctypes.cast(th_arr, ctypes.c_void_p),
+                                    sizes.ctypes.data_as(ctypes.c_void_p), x_off.ctypes.data_as(ctypes.c_void_p),
+                                    c_off.ctypes.data_as(ctypes.c_void_p), X.shape[1], _ptr(X), _ptr(y),
+                                    _ptr(C_pool), _ptr(out3), _ptr(info), cand, len(grids), ms, _ptr(ws),
+                                    ws.numel()))
+        return {grids[c]: ms[c] for c in range(len(grids))}
 
     def workspace(self, op, n, m=0, prec=GP_FP64):
         torch = _torch()

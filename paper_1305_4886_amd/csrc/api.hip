@@ -1137,6 +1137,67 @@ int gp_loglik_batched(gp_handle_t h, int32_t nbatch, const gp_theta_t *th_host, 
                      X, y, C_pool, out3_dev, info_dev, ws, ws_bytes);
 }
 
+int gp_tune_batched(gp_handle_t h, int32_t nbatch, const gp_theta_t *th_host, const int64_t *n_host,
+                    const int64_t *x_off_host, const int64_t *c_off_host, int32_t dim, const double *X,
+                    const double *y, double *C_pool, double *out3_dev, int32_t *info_dev, const int32_t *grid_cand,
+                    int32_t n_cand, double *ms_out, void *ws, size_t ws_bytes) {
+    if (!ok_handle(h)) return -1;
+    if (nbatch < 1) return -2;
+    if (!grid_cand) return -13;
+    if (n_cand < 1) return -14;
+    for (int32_t c = 0; c < n_cand; ++c)
+        if (grid_cand[c] < -1) return -13;
+    if (!ws) return -16;
+    int64_t nmax = 1;
+    if (n_host)
+        for (int32_t b = 0; b < nbatch; ++b) nmax = n_host[b] > nmax ? n_host[b] : nmax;
+    hipStream_t s = h->stream;
+    const gp_options_t saved = h->opt;
+    double best = -1.0;
+    int32_t best_grid = saved.batch_grid;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) hipEventDestroy(e0);
+        return GP_ERR_HIP;
+    }
+    int rc = GP_OK;
+    for (int32_t c = 0; c < n_cand && rc == GP_OK; ++c) {
+        double ms = -1.0;
+        h->opt = saved;
+        h->opt.batch_grid = grid_cand[c];
+        if (batch_ws_bytes(nmax, nbatch, grid_cand[c] >= 0) <= ws_bytes) {
+            for (int rep = 0; rep < 2 && rc == GP_OK; ++rep) {  // the first run warms the staging
+                if (hipEventRecord(e0, s) != hipSuccess) {
+                    rc = GP_ERR_HIP;
+                    break;
+                }
+                rc = gp_loglik_batched(h, nbatch, th_host, n_host, x_off_host, c_off_host, dim, X, y, C_pool, out3_dev,
+                                       info_dev, ws, ws_bytes);
+                if (rc) break;
+                float t = 0.f;
+                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+                    rc = GP_ERR_HIP;
+                    break;
+                }
+                ms = t;
+            }
+        }
+        if (ms_out) ms_out[c] = ms;
+        if (ms >= 0.0 && (best < 0.0 || ms < best)) {
+            best = ms;
+            best_grid = grid_cand[c];
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    h->opt = saved;
+    if (rc) return rc;
+    if (best < 0.0) return GP_ERR_WS_TOO_SMALL;
+    h->opt.batch_grid = best_grid;
+    return GP_OK;
+}
+
 int gp_morton_order(gp_handle_t h, int64_t n, int32_t dim, const double *X, int64_t *perm_dev, void *ws,
                     size_t ws_bytes) {
     if (!ok_handle(h)) return -1;

@@ -135,3 +135,26 @@ def test_batched_failure_is_per_problem(grid):
     assert np.all(np.isfinite(out[0])) and np.all(np.isfinite(out[2]))
     if info[1] != 0:
         assert info[1] >= 121 and np.all(np.isnan(out[1]))
+
+
+def test_tune_batched_picks_a_candidate(orc):
+    """The schedule autotuner times every candidate, keeps the fastest, and the
+    kept schedule still matches the oracle."""
+    sizes = [300, 129, 64, 700]
+    Xs, ys, ths = make_batch(sizes, 95, kernels=[0, 1, 2, 0])
+    X, y = dev(np.concatenate(Xs)), dev(np.concatenate(ys))
+    thetas = [gp.theta(k, log=t) for k, t in ths]
+    h = gp.handle()
+    saved = h.options()
+    try:
+        ms = h.tune_batched(X, y, thetas, sizes, grids=(-1, 0, 5))
+        assert set(ms) == {-1, 0, 5} and all(v > 0 for v in ms.values()), ms
+        best = min(ms, key=ms.get)
+        assert h.options().batch_grid == best
+        out = gp.loglik_batched(X, y, thetas, sizes)["out3"].cpu().numpy()
+        for b in range(len(sizes)):
+            k, t = ths[b]
+            ll, _, _ = orc.loglik(k, t, Xs[b], ys[b])
+            assert abs(out[b, 0] - ll) <= 1e-11 * abs(ll)
+    finally:
+        h.set_options(batch_grid=saved.batch_grid)
