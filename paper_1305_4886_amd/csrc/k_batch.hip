@@ -322,15 +322,22 @@ __global__ __launch_bounds__(256) void k_bsolve(const BProb *__restrict__ probs,
 // (i == k: L_kk, W_k = L_kk^{-1}, z_k = W_k (y_k - sum_j L_kj z_j) and the
 // tile's log-determinant / quadratic-form partials) or forms L_ik = A_ik W_k^T
 // once W_k is there.  The last diagonal task of a problem reduces its partials
-// into (loglik, log|C|, q).  Workgroups take tasks through an atomic ticket in
-// an order where every dependency has a smaller ticket, so the smallest
-// unfinished ticket never waits and the launch always drains: tile column k of
-// every problem (largest problems first) before column k + 1, and within a
-// problem's column the tiles below the diagonal top-down, with the next
-// diagonal tile (k + 1, k + 1) placed right after (k + 1, k), its last input.
-// A diagonal task thus starts a column ahead of the tiles that wait for its
-// inverse.  A workgroup takes its next ticket while it works on the current
-// one (the smallest unfinished ticket is still always being worked on).
+// into (loglik, log|C|, q).
+//
+// Scheduling: the problems are spread over BQ task queues (one per XCD, by
+// cost), each an ordered task list in which every task's inputs come earlier:
+// tile column k of each of the queue's problems (largest first) before column
+// k + 1, and within a problem's column the tiles below the diagonal top-down,
+// with the next diagonal tile (k + 1, k + 1) right after (k + 1, k), its last
+// input, so that it runs a column ahead of the tiles that wait for its
+// inverse.  Workgroup w drains queue w mod BQ first (workgroups are dispatched
+// to the XCDs round-robin, so a queue's problems share one L2), then takes
+// from the other queues in turn.  A queue hands out its tasks in order
+// through an atomic ticket, and a workgroup takes its next task while it
+// works on the current one.  The launch always drains: of the tasks taken and
+// not finished, the one taken first is being worked on (a prefetched task's
+// holder took its current task earlier) and its inputs, taken earlier still
+// from the same queue, are finished.
 //
 // Data that other workgroups read back (each L_ik in a tile-major copy, W_k,
 // z_k, the partials) is written through to memory (agent-scope atomic
@@ -345,7 +352,10 @@ __global__ __launch_bounds__(256) void k_bsolve(const BProb *__restrict__ probs,
 // is bounded: a stall raises the abort flag, every workgroup then leaves, and
 // the problem that saw it reports info = -1 (its outputs stay NaN).
 // ---------------------------------------------------------------------------
-constexpr int BF_TICKET = 0, BF_ABORT = 1, BF_TILES = 64;
+constexpr int BQ = 8;  // task queues
+// flags: queue q's ticket at BF_TICKET + 32 q (own cache lines), the abort
+// flag, then one flag per tile
+constexpr int BF_TICKET = 0, BF_ABORT = 32 * BQ, BF_TILES = 32 * BQ + 32;
 
 GP_DEV double bld(const double *p) {
     return __longlong_as_double((long long)__hip_atomic_load(
@@ -446,43 +456,10 @@ GP_DEV int bwait1(PersistSmem &sm, int *flags, const int *f) {
 // Flags, info and outputs of a persistent launch to their initial state:
 // flags (ticket, abort and one per tile) zero, info 0, out3 NaN (0 for an
 // empty problem, whose log-likelihood is the empty sum).
-// Also decodes every ticket t into its task (problem, tile row, tile column):
-// colstart[c] is the first ticket of tile column c, cofs[c][q] the first
-// ticket of problem order[q] within it (relative to colstart[c]).
 __global__ __launch_bounds__(256) void k_binit(int *flags, int64_t nflags, const BProb *__restrict__ probs, int nb,
-                                               const int32_t *__restrict__ order, const int64_t *__restrict__ colstart,
-                                               const int64_t *__restrict__ cofs, int ncol, int4 *tasks,
                                                double *out3, int32_t *info) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nflags; e += stride) flags[e] = 0;
-    const int64_t total = colstart[ncol];
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
-        int lo = 0, hi = ncol - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (colstart[mid] <= t) lo = mid;
-            else hi = mid - 1;
-        }
-        const int k = lo;
-        const int64_t u = t - colstart[k];
-        const int64_t *co = cofs + (int64_t)k * (nb + 1);
-        const int q = find_prob(co, nb, u);
-        int64_t v = u - co[q];
-        int ti, tk = k;
-        if (k == 0 && v == 0) {
-            ti = 0;  // the first diagonal tile opens column 0
-        } else {
-            if (k == 0) --v;
-            // (k + 1, k), (k + 1, k + 1), (k + 2, k), (k + 3, k), ...
-            if (v == 1) {
-                ti = k + 1;
-                tk = k + 1;
-            } else {
-                ti = k + (v == 0 ? 1 : (int)v);
-            }
-        }
-        tasks[t] = make_int4(order[q], ti, tk, 0);
-    }
     for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += stride) {
         info[b] = 0;
         const double v = probs[b].n == 0 ? -0.0 : __builtin_nan("");
@@ -492,22 +469,37 @@ __global__ __launch_bounds__(256) void k_binit(int *flags, int64_t nflags, const
     }
 }
 
-__global__ __launch_bounds__(256, 1) void k_bpersist(const BProb *__restrict__ probs, const int4 *__restrict__ tasks,
-                                                     int64_t total, int dim, const double *__restrict__ X,
+// tasks[t] = (problem, tile row | tile column << 16); queue q holds tasks
+// qstart[q] .. qstart[q + 1] - 1.
+__global__ __launch_bounds__(256, 1) void k_bpersist(const BProb *__restrict__ probs, const uint2 *__restrict__ tasks,
+                                                     const int64_t *__restrict__ qstart, int dim,
+                                                     const double *__restrict__ X,
                                                      const double *__restrict__ y, double *C_pool, double *lt,
                                                      double *wbuf, double *zbuf, double *part, int *flags,
                                                      double *out3, int32_t *info) {
     __shared__ PersistSmem sm;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wm = w & 1, wn = w >> 1;
-    if (tid == 0) sm.ticket = atomicAdd(flags + BF_TICKET, 1);
+    const int64_t total = qstart[BQ];
+    // thread 0: the queue it takes from and how many queues it has left behind
+    int qx = blockIdx.x % BQ, qleft = 0;
+    auto take = [&]() -> int64_t {
+        while (qleft < BQ) {
+            const int64_t a = atomicAdd(flags + BF_TICKET + 32 * qx, 1);
+            if (a < qstart[qx + 1] - qstart[qx]) return qstart[qx] + a;
+            qx = (qx + 1) % BQ;
+            ++qleft;
+        }
+        return total;
+    };
+    if (tid == 0) sm.ticket = take();
     __syncthreads();
-    int64_t t = sm.ticket;  // < 2^31: the ticket counter is a 32-bit int
+    int64_t t = sm.ticket;
     for (;; t = sm.ticket) {
         if (t >= total) break;
-        const int4 task = tasks[t];
-        int nxt = 0;  // thread 0: the next ticket, taken now and handed over at the end of this task
-        if (tid == 0) nxt = atomicAdd(flags + BF_TICKET, 1);
-        const int b = task.x, i = task.y, k = task.z;
+        const uint2 task = tasks[t];
+        int64_t nxt = 0;  // thread 0: the next task, taken now and handed over at the end of this one
+        if (tid == 0) nxt = take();
+        const int b = (int)task.x, i = (int)(task.y & 0xffffu), k = (int)(task.y >> 16);
         const BProb P = probs[b];
         const bool diag = (i == k);
         const int64_t ld = P.n, i0 = (int64_t)i * T, k0 = (int64_t)k * T;
@@ -858,10 +850,9 @@ size_t batch_ws_bytes(int64_t nmax, int64_t nbatch, bool persistent) {
     b += al256b(sizeof(int64_t) * (size_t)(2 * nt + 1) * (size_t)(nbatch + 1));  // per-level prefix counts
     b += al256b(sizeof(double) * (size_t)nmax * (size_t)nbatch);                 // z
     b += al256b(sizeof(double) * (size_t)nt * T * T * (size_t)nbatch);           // diagonal inverses
-    b += al256b(sizeof(int64_t) * ((size_t)nt * (size_t)(nbatch + 1) + (size_t)nt + 1));  // persistent schedule
     b += al256b(sizeof(int) * ((size_t)BF_TILES + (size_t)(nt * (nt + 1) / 2) * (size_t)nbatch));  // tile flags
     b += al256b(sizeof(double) * 2 * (size_t)nt * (size_t)nbatch);               // per-tile partials
-    b += al256b(16 * (size_t)(nt * (nt + 1) / 2) * (size_t)nbatch);              // decoded tasks
+    b += al256b(8 * (size_t)(nt * (nt + 1) / 2) * (size_t)nbatch + 8 * (BQ + 1));  // task list, queue starts
     if (persistent)  // tile-major copy of the factor's tiles, read back inside the launch
         b += al256b(sizeof(double) * T * T * (size_t)(nt * (nt + 1) / 2) * (size_t)nbatch);
     return b + 256;
@@ -871,7 +862,8 @@ struct BatchStaging {
     std::vector<BProb> probs;
     std::vector<int32_t> order;
     std::vector<int64_t> offs;  // [level block][nb + 1]: covariance, then per level panel and update counts
-    std::vector<int64_t> sched;  // persistent launch: colstart[ncol + 1], then cofs[ncol][nb + 1]
+    void *pinned = nullptr;  // persistent launch: task list + queue starts (pinned host memory)
+    size_t pinned_bytes = 0;
     hipEvent_t done = nullptr;
 };
 
@@ -949,46 +941,82 @@ int batch_run(hipStream_t s, int num_cu, int grid, void *&staging_ptr, int32_t n
     double *d_w = reinterpret_cast<double *>(take(sizeof(double) * (size_t)ntmax * T * T * (size_t)nb));
 
     if (grid >= 0) {
-        // Persistent launch.  Ticket order: tile column k of every problem
-        // (largest first), the diagonal tile first within a problem.
-        // Per tile column k and problem: k = 0 holds (0, 0), the tiles below
-        // it and (1, 1); 1 <= k <= nt - 2 holds the nt - k - 1 tiles below
-        // (k, k) and (k + 1, k + 1).
-        const int64_t W1 = nb + 1;
-        st->sched.assign((size_t)(ntmax + 1) + (size_t)ntmax * (size_t)W1, 0);
-        int64_t *colstart = st->sched.data(), *cofs = colstart + (ntmax + 1);
-        for (int64_t k = 0; k < ntmax; ++k) {
-            int64_t *co = cofs + k * W1;
-            for (int q = 0; q < nb; ++q) {
-                const int64_t ntq = st->probs[st->order[q]].nt;
-                const int64_t m = k == 0 ? ntq + (ntq >= 2 ? 1 : 0) : (k <= ntq - 2 ? ntq - k : 0);
-                co[q + 1] = co[q] + m;
-            }
-            colstart[k + 1] = colstart[k] + co[nb];
+        // Persistent launch.  Problems go to the BQ queues largest first, each
+        // to the queue with the least work so far (nt^3); a queue's task list
+        // is, per tile column k and problem (largest first): for k = 0 the
+        // tile (0, 0), then (1, 0), (1, 1), (2, 0), (3, 0), ...; for
+        // 1 <= k <= nt - 2: (k + 1, k), (k + 1, k + 1), (k + 2, k), ....
+        std::vector<int> qof(nb, 0);
+        double qload[BQ] = {0.0};
+        for (int q = 0; q < nb; ++q) {
+            const int b = st->order[q];
+            int x = 0;
+            for (int c = 1; c < BQ; ++c)
+                if (qload[c] < qload[x]) x = c;
+            qof[b] = x;
+            const double c3 = (double)st->probs[b].nt;
+            qload[x] += c3 * c3 * c3;
+            if (st->probs[b].nt >= 65536) return -4;  // tile indices are packed in 16 bits
         }
-        const int64_t total = colstart[ntmax];
-        int64_t *d_sched = reinterpret_cast<int64_t *>(take(sizeof(int64_t) * st->sched.size()));
+        const int64_t total = foff;  // one task per tile of the lower triangles
+        const size_t tbytes = sizeof(uint2) * (size_t)(total > 0 ? total : 1), qbytes = sizeof(int64_t) * (BQ + 1);
+        if (st->pinned_bytes < tbytes + qbytes) {
+            if (st->pinned) (void)hipHostFree(st->pinned);
+            st->pinned = nullptr;
+            st->pinned_bytes = 0;
+            if (hipHostMalloc(&st->pinned, tbytes + qbytes) != hipSuccess) return GP_ERR_HIP;
+            st->pinned_bytes = tbytes + qbytes;
+        }
+        uint2 *tl = static_cast<uint2 *>(st->pinned);
+        int64_t *qs = reinterpret_cast<int64_t *>(static_cast<char *>(st->pinned) + tbytes);
+        int64_t nt_ = 0;
+        auto emit = [&](int b, int64_t ti, int64_t tk) { tl[nt_++] = make_uint2((unsigned)b, (unsigned)(ti | (tk << 16))); };
+        for (int x = 0; x < BQ; ++x) {
+            qs[x] = nt_;
+            int64_t ncol = 0;
+            for (int q = 0; q < nb; ++q)
+                if (qof[st->order[q]] == x) ncol = std::max<int64_t>(ncol, st->probs[st->order[q]].nt);
+            for (int64_t k = 0; k < ncol; ++k)
+                for (int q = 0; q < nb; ++q) {
+                    const int b = st->order[q];
+                    const int64_t ntq = st->probs[b].nt;
+                    if (qof[b] != x || ntq == 0) continue;
+                    if (k == 0) {
+                        emit(b, 0, 0);
+                        if (ntq >= 2) {
+                            emit(b, 1, 0);
+                            emit(b, 1, 1);
+                        }
+                        for (int64_t r = 2; r < ntq; ++r) emit(b, r, 0);
+                    } else if (k <= ntq - 2) {
+                        emit(b, k + 1, k);
+                        emit(b, k + 1, k + 1);
+                        for (int64_t r = k + 2; r < ntq; ++r) emit(b, r, k);
+                    }
+                }
+        }
+        qs[BQ] = nt_;
+        if (nt_ != total) return GP_ERR_HIP;  // internal consistency
         const int64_t nflags = BF_TILES + foff;
         int *d_flags = reinterpret_cast<int *>(take(sizeof(int) * (size_t)nflags));
         double *d_part = reinterpret_cast<double *>(take(sizeof(double) * (size_t)(poff_ > 0 ? poff_ : 1)));
-        int4 *d_tasks = reinterpret_cast<int4 *>(take(sizeof(int4) * (size_t)(total > 0 ? total : 1)));
+        uint2 *d_tasks = reinterpret_cast<uint2 *>(take(tbytes));
+        int64_t *d_qs = reinterpret_cast<int64_t *>(take(qbytes));
         double *d_lt = reinterpret_cast<double *>(take(sizeof(double) * T * T * (size_t)(foff > 0 ? foff : 1)));
         if (off > ws_bytes) return GP_ERR_WS_TOO_SMALL;
         if (hipMemcpyAsync(d_probs, st->probs.data(), sizeof(BProb) * (size_t)nb, hipMemcpyHostToDevice, s) !=
                 hipSuccess ||
-            hipMemcpyAsync(d_order, st->order.data(), sizeof(int32_t) * (size_t)nb, hipMemcpyHostToDevice, s) !=
-                hipSuccess ||
-            hipMemcpyAsync(d_sched, st->sched.data(), sizeof(int64_t) * st->sched.size(), hipMemcpyHostToDevice, s) !=
-                hipSuccess)
+            hipMemcpyAsync(d_tasks, tl, tbytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(d_qs, qs, qbytes, hipMemcpyHostToDevice, s) != hipSuccess)
             return GP_ERR_HIP;
         if (hipEventRecord(st->done, s) != hipSuccess) return GP_ERR_HIP;
-        const int64_t init_blocks = std::min<int64_t>(1024, std::max<int64_t>(std::max<int64_t>(nflags, total), nb) / 256 + 1);
-        hipLaunchKernelGGL(k_binit, dim3((unsigned)init_blocks), dim3(256), 0, s, d_flags, nflags, d_probs, nb, d_order,
-                           d_sched, d_sched + (ntmax + 1), (int)ntmax, d_tasks, out3, info);
+        const int64_t init_blocks = std::min<int64_t>(1024, std::max<int64_t>(nflags, nb) / 256 + 1);
+        hipLaunchKernelGGL(k_binit, dim3((unsigned)init_blocks), dim3(256), 0, s, d_flags, nflags, d_probs, nb, out3,
+                           info);
         if (total > 0) {
             int64_t g = grid > 0 ? grid : (int64_t)(num_cu > 0 ? num_cu : 1);
             if (g > total) g = total;
-            hipLaunchKernelGGL(k_bpersist, dim3((unsigned)g), dim3(256), 0, s, d_probs, d_tasks, total, (int)dim, X, y,
+            hipLaunchKernelGGL(k_bpersist, dim3((unsigned)g), dim3(256), 0, s, d_probs, d_tasks, d_qs, (int)dim, X, y,
                                C_pool, d_lt, d_w, d_z, d_part, d_flags, out3, info);
         }
         return hipGetLastError() == hipSuccess ? GP_OK : GP_ERR_HIP;
@@ -1053,5 +1081,6 @@ void batch_staging_free(void *p) {
         (void)hipEventSynchronize(st->done);
         (void)hipEventDestroy(st->done);
     }
+    if (st->pinned) (void)hipHostFree(st->pinned);
     delete st;
 }
