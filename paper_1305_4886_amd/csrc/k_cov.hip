@@ -7,6 +7,7 @@
 //   * gradient contraction sum_ij (a_i a_j - Cinv_ij) dC_ij/dtheta over the
 //     lower triangle of C^{-1}, regenerating dC/dtheta from the points.
 #include "internal.h"
+#include <type_traits>
 
 namespace {
 
@@ -80,21 +81,25 @@ __global__ __launch_bounds__(256) void k_cross_cov(CovParams p, int64_t n, int64
 
 // Matrix-free residual, pass 1: partials[chunk][i] = sum_{j in chunk} C_ij x_j
 // for a 256-row block and a 2048-column chunk (C regenerated from X, FP64).
+// D > 0: the point dimension fixed at compile time (the distance loop fully
+// unrolled); D = 0: any dimension up to MAXDIM.  K: the covariance family.
 constexpr int RES_ROWS = 256, RES_COLS = 2048, RES_STAGE = 256;
+template <int D, int K>
 __global__ __launch_bounds__(256) void k_resid_partial(CovParams p, int64_t n,
                                                        const double *__restrict__ X,
                                                        const double *__restrict__ x,
                                                        double *__restrict__ partials,
                                                        const int32_t *skip) {
     if (skip && *skip) return;
-    __shared__ double sp[RES_STAGE * MAXDIM];
+    constexpr int ND = D > 0 ? D : MAXDIM;
+    __shared__ double sp[RES_STAGE * ND];
     __shared__ double sx[RES_STAGE];
-    const int dim = p.dim;
+    const int dim = D > 0 ? D : p.dim;
     const int64_t i = (int64_t)blockIdx.x * RES_ROWS + threadIdx.x;
     const int64_t jc0 = (int64_t)blockIdx.y * RES_COLS;
-    double xi[MAXDIM];
+    double xi[ND];
 #pragma unroll
-    for (int d = 0; d < MAXDIM; ++d) xi[d] = (d < dim && i < n) ? X[i * dim + d] : 0.0;
+    for (int d = 0; d < ND; ++d) xi[d] = (d < dim && i < n) ? X[i * dim + d] : 0.0;
     double acc = 0.0;
     for (int64_t js = jc0; js < jc0 + RES_COLS && js < n; js += RES_STAGE) {
         __syncthreads();
@@ -106,13 +111,13 @@ __global__ __launch_bounds__(256) void k_resid_partial(CovParams p, int64_t n,
         for (int c = 0; c < cnt; ++c) {
             double s = 0.0;
 #pragma unroll
-            for (int d = 0; d < MAXDIM; ++d) {
-                if (d < dim) {
+            for (int d = 0; d < ND; ++d) {
+                if (D > 0 || d < dim) {
                     double t = xi[d] - sp[c * dim + d];
                     s = fma(t, t, s);
                 }
             }
-            double v = p.s2 * cov_corr(p.kind, sqrt(s) * p.inv_rho);
+            double v = p.s2 * cov_corr(K, sqrt(s) * p.inv_rho);
             if (js + c == i) v += p.t2;
             acc = fma(v, sx[c], acc);
         }
@@ -227,7 +232,19 @@ hipError_t launch_resid_matfree(hipStream_t s, CovParams p, int64_t n, const dou
     if (n <= 0) return hipSuccess;
     const int nch = resid_chunks(n);
     dim3 g1((unsigned)((n + RES_ROWS - 1) / RES_ROWS), (unsigned)nch);
-    hipLaunchKernelGGL(k_resid_partial, g1, dim3(256), 0, s, p, n, X, x, partials, skip);
+    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, g1, dim3(256), 0, s, p, n, X, x, partials, skip); };
+    auto by_kind = [&](auto d) {
+        constexpr int D = decltype(d)::value;
+        if (p.kind == GP_EXP) go(k_resid_partial<D, GP_EXP>);
+        else if (p.kind == GP_MATERN32) go(k_resid_partial<D, GP_MATERN32>);
+        else go(k_resid_partial<D, GP_MATERN52>);
+    };
+    switch (p.dim) {
+    case 1: by_kind(std::integral_constant<int, 1>{}); break;
+    case 2: by_kind(std::integral_constant<int, 2>{}); break;
+    case 3: by_kind(std::integral_constant<int, 3>{}); break;
+    default: by_kind(std::integral_constant<int, 0>{}); break;
+    }
     hipLaunchKernelGGL(k_resid_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, nch, r0,
                        partials, res, skip);
     return hipGetLastError();
