@@ -24,16 +24,48 @@ GP_DEV void tri_decode(int64_t t, int64_t &bi, int64_t &bj) {
     bj = t - r * (r + 1) / 2;
 }
 
+// |xi - xj| with the point dimension fixed at compile time (D > 0, the loop
+// unrolled) or given at run time (D = 0); the same operations as point_dist.
+template <int D>
+GP_DEV double pdist(const double *xi, const double *xj, int dim) {
+    if (D == 0) return point_dist(xi, xj, dim);
+    double s = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const double t = xi[d] - xj[d];
+        s = fma(t, t, s);
+    }
+    return sqrt(s);
+}
+
+// Calls f(std::integral_constant<int, D>, std::integral_constant<int, K>) for
+// the point dimension (1, 2, 3, else 0 = any) and covariance family of p.
+template <typename F>
+void by_dim_kind(const CovParams &p, F f) {
+    auto k = [&](auto d) {
+        if (p.kind == GP_EXP) f(d, std::integral_constant<int, GP_EXP>{});
+        else if (p.kind == GP_MATERN32) f(d, std::integral_constant<int, GP_MATERN32>{});
+        else f(d, std::integral_constant<int, GP_MATERN52>{});
+    };
+    switch (p.dim) {
+    case 1: k(std::integral_constant<int, 1>{}); break;
+    case 2: k(std::integral_constant<int, 2>{}); break;
+    case 3: k(std::integral_constant<int, 3>{}); break;
+    default: k(std::integral_constant<int, 0>{}); break;
+    }
+}
+
 // One 64 x 64 tile of the lower triangle per workgroup of 256 threads.  Thread
 // (row = tid % 64, cg = tid / 64) writes column entries j = cg, cg + 4, ...:
 // each wave stores 64 consecutive rows of one column (512 B, coalesced).
+template <int D, int K>
 __global__ __launch_bounds__(256) void k_cov_lower(CovParams p, int64_t n, const double *__restrict__ X,
                                                    double *__restrict__ C, int64_t ldc) {
     __shared__ double sr[CT * MAXDIM];
     __shared__ double sc[CT * MAXDIM];
     int64_t bi, bj;
     tri_decode(blockIdx.x, bi, bj);
-    const int dim = p.dim;
+    const int dim = D > 0 ? D : p.dim;
     const int64_t i0 = bi * CT, j0 = bj * CT;
     for (int e = threadIdx.x; e < CT * dim; e += 256) {
         int64_t pi = i0 + e / dim, pj = j0 + e / dim;
@@ -48,20 +80,21 @@ __global__ __launch_bounds__(256) void k_cov_lower(CovParams p, int64_t n, const
     for (int c = cg; c < CT; c += 4) {
         const int64_t j = j0 + c;
         if (j > i) break;
-        double d = point_dist(xi, sc + c * dim, dim);
-        double v = p.s2 * cov_corr(p.kind, d * p.inv_rho);
+        double d = pdist<D>(xi, sc + c * dim, dim);
+        double v = p.s2 * cov_corr(K, d * p.inv_rho);
         if (i == j) v += p.t2;
         C[i + j * ldc] = v;
     }
 }
 
+template <int D, int K>
 __global__ __launch_bounds__(256) void k_cross_cov(CovParams p, int64_t n, int64_t m,
                                                    const double *__restrict__ X,
                                                    const double *__restrict__ Xs,
                                                    double *__restrict__ Cs, int64_t ld) {
     __shared__ double sr[CT * MAXDIM];
     __shared__ double sc[CT * MAXDIM];
-    const int dim = p.dim;
+    const int dim = D > 0 ? D : p.dim;
     const int64_t i0 = (int64_t)blockIdx.x * CT, j0 = (int64_t)blockIdx.y * CT;
     for (int e = threadIdx.x; e < CT * dim; e += 256) {
         sr[e] = i0 + e / dim < n ? X[i0 * dim + e] : 0.0;
@@ -74,8 +107,8 @@ __global__ __launch_bounds__(256) void k_cross_cov(CovParams p, int64_t n, int64
     for (int c = cg; c < CT; c += 4) {
         const int64_t j = j0 + c;
         if (j >= m) break;
-        double d = point_dist(sr + r * dim, sc + c * dim, dim);
-        Cs[i + j * ld] = p.s2 * cov_corr(p.kind, d * p.inv_rho);
+        double d = pdist<D>(sr + r * dim, sc + c * dim, dim);
+        Cs[i + j * ld] = p.s2 * cov_corr(K, d * p.inv_rho);
     }
 }
 
@@ -212,7 +245,10 @@ hipError_t launch_cov_lower(hipStream_t s, CovParams p, int64_t n, const double 
                             int64_t ldc, const int32_t *) {
     if (n <= 0) return hipSuccess;
     const int64_t T = (n + CT - 1) / CT;
-    hipLaunchKernelGGL(k_cov_lower, dim3((unsigned)(T * (T + 1) / 2)), dim3(256), 0, s, p, n, X, C, ldc);
+    by_dim_kind(p, [&](auto d, auto k) {
+        hipLaunchKernelGGL((k_cov_lower<decltype(d)::value, decltype(k)::value>), dim3((unsigned)(T * (T + 1) / 2)),
+                           dim3(256), 0, s, p, n, X, C, ldc);
+    });
     return hipGetLastError();
 }
 
@@ -220,7 +256,10 @@ hipError_t launch_cross_cov(hipStream_t s, CovParams p, int64_t n, int64_t m, co
                             const double *Xs, double *Cs, int64_t ld) {
     if (n <= 0 || m <= 0) return hipSuccess;
     dim3 grid((unsigned)((n + CT - 1) / CT), (unsigned)((m + CT - 1) / CT));
-    hipLaunchKernelGGL(k_cross_cov, grid, dim3(256), 0, s, p, n, m, X, Xs, Cs, ld);
+    by_dim_kind(p, [&](auto d, auto k) {
+        hipLaunchKernelGGL((k_cross_cov<decltype(d)::value, decltype(k)::value>), grid, dim3(256), 0, s, p, n, m, X,
+                           Xs, Cs, ld);
+    });
     return hipGetLastError();
 }
 
