@@ -109,7 +109,7 @@ def cpu_baseline(n_s, seed=4):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py measures one GPU; this build has no multi-GPU path (requested --gpus %d)" % a.gpus,
+        print("bench.py measures one GPU; the library has no multi-GPU path (requested --gpus %d)" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
