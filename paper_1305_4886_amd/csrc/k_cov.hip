@@ -112,50 +112,81 @@ __global__ __launch_bounds__(256) void k_cross_cov(CovParams p, int64_t n, int64
     }
 }
 
-// Matrix-free residual, pass 1: partials[chunk][i] = sum_{j in chunk} C_ij x_j
-// for a 256-row block and a 2048-column chunk (C regenerated from X, FP64).
-// D > 0: the point dimension fixed at compile time (the distance loop fully
-// unrolled); D = 0: any dimension up to MAXDIM.  K: the covariance family.
-constexpr int RES_ROWS = 256, RES_COLS = 2048, RES_STAGE = 256;
+// Matrix-free residual, pass 1 (C regenerated from X in FP64, each entry of
+// the lower triangle once, used for its row and its column).  Workgroup-tile
+// (I, J), I >= J, of 64 x 64: thread (tr, tc) = (tid % 16, tid / 16) takes
+// rows 4 tr .. 4 tr + 3 and columns 4 tc .. 4 tc + 3.  The row sums
+// sum_c C_rc x_c go to partial slot J of rows in block I, the column sums
+// sum_r C_rc x_r to slot I of rows in block J; a diagonal tile puts both
+// (entries strictly below its diagonal counted in each, the diagonal once)
+// into slot I.  Every (row block, slot) pair is written by exactly one tile,
+// and pass 2 adds the slots in a fixed order.  D > 0: the point dimension
+// fixed at compile time; D = 0: any up to MAXDIM.  K: the covariance family.
+constexpr int RT = 64;
 template <int D, int K>
-__global__ __launch_bounds__(256) void k_resid_partial(CovParams p, int64_t n,
-                                                       const double *__restrict__ X,
-                                                       const double *__restrict__ x,
-                                                       double *__restrict__ partials,
-                                                       const int32_t *skip) {
+__global__ __launch_bounds__(256) void k_resid_sym(CovParams p, int64_t n, const double *__restrict__ X,
+                                                   const double *__restrict__ x, double *__restrict__ partials,
+                                                   const int32_t *skip) {
     if (skip && *skip) return;
     constexpr int ND = D > 0 ? D : MAXDIM;
-    __shared__ double sp[RES_STAGE * ND];
-    __shared__ double sx[RES_STAGE];
+    __shared__ double sr[RT * ND], sc[RT * ND], xr[RT], xc[RT];
+    __shared__ double red_r[16][RT + 1], red_c[16][RT + 1];
     const int dim = D > 0 ? D : p.dim;
-    const int64_t i = (int64_t)blockIdx.x * RES_ROWS + threadIdx.x;
-    const int64_t jc0 = (int64_t)blockIdx.y * RES_COLS;
-    double xi[ND];
-#pragma unroll
-    for (int d = 0; d < ND; ++d) xi[d] = (d < dim && i < n) ? X[i * dim + d] : 0.0;
-    double acc = 0.0;
-    for (int64_t js = jc0; js < jc0 + RES_COLS && js < n; js += RES_STAGE) {
+    const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
+    const int64_t nb = (n + RT - 1) / RT, ntiles = nb * (nb + 1) / 2;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        int64_t bi, bj;
+        tri_decode(t, bi, bj);
+        const int64_t i0 = bi * RT, j0 = bj * RT;
+        const bool dg = bi == bj;
+        __syncthreads();  // the previous tile's LDS reads are done
+        for (int e = tid; e < RT * dim; e += 256) {
+            sr[e] = i0 + e / dim < n ? X[i0 * dim + e] : 0.0;
+            sc[e] = j0 + e / dim < n ? X[j0 * dim + e] : 0.0;
+        }
+        if (tid < RT) {
+            xr[tid] = i0 + tid < n ? x[i0 + tid] : 0.0;
+            xc[tid] = j0 + tid < n ? x[j0 + tid] : 0.0;
+        }
         __syncthreads();
-        for (int e = threadIdx.x; e < RES_STAGE * dim; e += 256)
-            sp[e] = js + e / dim < n ? X[js * dim + e] : 0.0;
-        sx[threadIdx.x] = js + threadIdx.x < n ? x[js + threadIdx.x] : 0.0;
-        __syncthreads();
-        const int cnt = (int)((n - js) < RES_STAGE ? (n - js) : RES_STAGE);
-        for (int c = 0; c < cnt; ++c) {
-            double s = 0.0;
+        double rs[4] = {0.0, 0.0, 0.0, 0.0}, cs[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int d = 0; d < ND; ++d) {
-                if (D > 0 || d < dim) {
-                    double t = xi[d] - sp[c * dim + d];
-                    s = fma(t, t, s);
+        for (int a = 0; a < 4; ++a) {
+            const int r = 4 * tr + a;
+            const int64_t gi = i0 + r;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int c = 4 * tc + b;
+                const int64_t gj = j0 + c;
+                if (gi >= n || gj >= n || (dg && c > r)) continue;
+                double v = p.s2 * cov_corr(K, pdist<D>(sr + r * dim, sc + c * dim, dim) * p.inv_rho);
+                if (gi == gj) {
+                    v += p.t2;
+                    rs[a] = fma(v, xc[c], rs[a]);  // the diagonal entry: its row only
+                } else {
+                    rs[a] = fma(v, xc[c], rs[a]);
+                    cs[b] = fma(v, xr[r], cs[b]);
                 }
             }
-            double v = p.s2 * cov_corr(K, sqrt(s) * p.inv_rho);
-            if (js + c == i) v += p.t2;
-            acc = fma(v, sx[c], acc);
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) red_r[tc][4 * tr + a] = rs[a];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) red_c[tr][4 * tc + b] = cs[b];
+        __syncthreads();
+        if (tid < RT) {  // row sums of block I
+            double s = 0.0;
+            for (int q = 0; q < 16; ++q) s += red_r[q][tid];
+            if (dg)
+                for (int q = 0; q < 16; ++q) s += red_c[q][tid];
+            if (i0 + tid < n) partials[bj * n + i0 + tid] = s;
+        } else if (tid < 2 * RT && !dg) {  // column sums: rows of block J, slot I
+            const int c = tid - RT;
+            double s = 0.0;
+            for (int q = 0; q < 16; ++q) s += red_c[q][c];
+            if (j0 + c < n) partials[bi * n + j0 + c] = s;
         }
     }
-    if (i < n) partials[(int64_t)blockIdx.y * n + i] = acc;
 }
 
 // Pass 2: res_i = r0_i - sum_chunks partials (fixed chunk order).
@@ -263,27 +294,19 @@ hipError_t launch_cross_cov(hipStream_t s, CovParams p, int64_t n, int64_t m, co
     return hipGetLastError();
 }
 
-int resid_chunks(int64_t n) { return (int)((n + RES_COLS - 1) / RES_COLS); }
+int resid_chunks(int64_t n) { return (int)((n + RT - 1) / RT); }  // partial slots: one per 64-row block
 
 hipError_t launch_resid_matfree(hipStream_t s, CovParams p, int64_t n, const double *X,
                                 const double *r0, const double *x, double *res, double *partials,
                                 const int32_t *skip) {
     if (n <= 0) return hipSuccess;
     const int nch = resid_chunks(n);
-    dim3 g1((unsigned)((n + RES_ROWS - 1) / RES_ROWS), (unsigned)nch);
-    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, g1, dim3(256), 0, s, p, n, X, x, partials, skip); };
-    auto by_kind = [&](auto d) {
-        constexpr int D = decltype(d)::value;
-        if (p.kind == GP_EXP) go(k_resid_partial<D, GP_EXP>);
-        else if (p.kind == GP_MATERN32) go(k_resid_partial<D, GP_MATERN32>);
-        else go(k_resid_partial<D, GP_MATERN52>);
-    };
-    switch (p.dim) {
-    case 1: by_kind(std::integral_constant<int, 1>{}); break;
-    case 2: by_kind(std::integral_constant<int, 2>{}); break;
-    case 3: by_kind(std::integral_constant<int, 3>{}); break;
-    default: by_kind(std::integral_constant<int, 0>{}); break;
-    }
+    const int64_t ntiles = (int64_t)nch * (nch + 1) / 2;
+    const unsigned grid = (unsigned)(ntiles < 8192 ? ntiles : 8192);
+    by_dim_kind(p, [&](auto d, auto k) {
+        hipLaunchKernelGGL((k_resid_sym<decltype(d)::value, decltype(k)::value>), dim3(grid), dim3(256), 0, s, p, n,
+                           X, x, partials, skip);
+    });
     hipLaunchKernelGGL(k_resid_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, nch, r0,
                        partials, res, skip);
     return hipGetLastError();
