@@ -158,3 +158,24 @@ def test_tune_batched_picks_a_candidate(orc):
             assert abs(out[b, 0] - ll) <= 1e-11 * abs(ll)
     finally:
         h.set_options(batch_grid=saved.batch_grid)
+
+
+def test_batched_many_theta_over_shared_points(orc, grid):
+    """Many theta over one point set: every problem names the same points
+    (equal point offsets) with its own parameters and kernel."""
+    n = 333
+    X = synth.uniform_points(n, 97)
+    y = synth.smooth_field(X, 98, ell=0.1, t2=0.1)
+    ths = []
+    for b in range(6):
+        th = np.array([math.log(0.5 + 0.3 * b), math.log(0.05 + 0.03 * b), math.log(0.02 + 0.05 * b)])
+        ths.append((b % 3, th))
+    sizes = [n] * len(ths)
+    r = gp.loglik_batched(dev(X), dev(y), [gp.theta(k, log=t) for k, t in ths], sizes,
+                          x_off=[0] * len(ths))
+    out = r["out3"].cpu().numpy()
+    assert np.all(r["info"].cpu().numpy() == 0)
+    for b, (k, t) in enumerate(ths):
+        ll, ld, q = orc.loglik(k, t, X, y)
+        assert abs(out[b, 0] - ll) <= 1e-11 * abs(ll), (b, out[b], ll)
+        assert abs(out[b, 2] - q) <= 1e-11 * abs(q)
