@@ -387,17 +387,22 @@ GP_DEV void xr_step(double *p, int lane) {
 // signal and no flag or cache-wide fence sits on the dependency chain.
 constexpr uint64_t MBOX_EMPTY = 0x7FF4DEADBEEF0000ull;
 
+// The abort flag is read on every 32nd empty poll only: each read is a
+// round trip to memory, and reading it on every iteration would double the
+// time between two looks at the slot.
 GP_DEV double mbox_poll(const double *slot, int *abortf) {
     const uint64_t *p = reinterpret_cast<const uint64_t *>(slot);
     uint64_t v;
     int spins = 0;
     while ((v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == MBOX_EMPTY) {
-        if (__hip_atomic_load(abortf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > SPIN_LIMIT) {
-            __hip_atomic_store(abortf, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
+        if ((++spins & 31) == 0) {
+            if (__hip_atomic_load(abortf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            if (spins > SPIN_LIMIT) {
+                __hip_atomic_store(abortf, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
         }
+        __builtin_amdgcn_s_sleep(1);
     }
     return __longlong_as_double((long long)v);
 }
@@ -588,37 +593,91 @@ __global__ __launch_bounds__(256) void k_trsv_trans(const double *L, int64_t ldl
 // Solves in 128-row steps.  The chain of the 64-row solves above pays one
 // publish / poll round trip per 64 rows; here one workgroup of 8 waves takes
 // a 128-row block B (64-blocks s0 = 2B, s1 = 2B + 1) with diagonal block
-// D = [[L00, 0], [L10, L11]], so the chain pays one round trip per 128 rows.
-// Waves 4-7 take the far tiles as their values appear (wave 4 + h: row (or
-// column) half h & 1, every other tile by h >> 1).  Waves 0-3 hold the
-// quarters of the 128 x 128 near block in registers and, once the previous
-// block's halves land, form its product with them (one quarter each); then
-// the first half of the block is solved with its 64 x 64 inverse and
-// published, and the second half, which needs the first, follows.  Vectors
-// that every lane of a product needs are broadcast through LDS (one read per
-// term, four accumulators), not by cross-lane reads.
+// D = [[L00, 0], [L10, L11]], W0 = L00^{-1}, W1 = L11^{-1}, and
+// H = W1 L10 W0 (formed when the workgroup starts), so that
+//   D^{-1} = [[W0, 0], [-H, W1]]:  both halves of the block come out of
+// independent products once its right-hand side is known, and the chain
+// pays one round trip per 128 rows.  Waves 4-7 take the far tiles as their
+// values appear (wave 4 + h: row (or column) half h & 1, every other tile by
+// h >> 1).  Waves 0-3 hold the quarters of the 128 x 128 near block in
+// registers and form its product with the neighbouring block's values as
+// they land; then wave 0 solves the first half and wave 1 the second.
+// Vectors that every lane of a product needs are broadcast through LDS (one
+// read per term, four accumulators), not by cross-lane reads.
 constexpr int SB = 2 * DB;
 
-// Forward: x_B = D^{-1} (b_B - sum_{j < B} L[B, j] x_j);
-//   x_0 = W0 (b_0 - far_0 - N_0 x_prev),
-//   x_1 = W1 (b_1 - far_1 - N_1 x_prev - L10 x_0).
+struct Trsv2Smem {
+    double W0s[DB][DB + 1], W1s[DB][DB + 1];
+    double Ms[DB][DB + 1];  // L10, then H
+    double Ts[DB][DB + 1];  // L10 W0
+    double pf[4][DB], pn[4][DB], bv[2][DB], vb[4][DB];
+    int blk;
+};
+
+// Waves 0-3: W0, W1 and L10 = L[s1 rows, s0 columns] into LDS, then
+// H = W1 (L10 W0) (wave q: columns 16 q .. 16 q + 15).  Every wave of the
+// workgroup passes the two barriers.
+GP_DEV void trsv2_setup(Trsv2Smem &sm, const double *L, int64_t ldl, int64_t n, const double *dinv, int B,
+                        bool has1) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t R0 = (int64_t)B * SB;
+    if (w < 4) {
+        const double *W0 = dinv + (int64_t)(2 * B) * DB * DB;
+        for (int e = threadIdx.x; e < DB * DB; e += 256) {
+            const int a = e & (DB - 1), c = e >> 6;
+            sm.W0s[a][c] = W0[a + c * DB];
+            if (has1) {
+                sm.W1s[a][c] = dinv[(int64_t)(2 * B + 1) * DB * DB + a + c * DB];
+                const int64_t r = R0 + DB + a;
+                sm.Ms[a][c] = r < n ? L[r + (R0 + c) * ldl] : 0.0;
+            }
+        }
+    }
+    __syncthreads();
+    if (w < 4 && has1) {  // T = L10 W0
+        double t[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) t[c] = 0.0;
+        for (int k = 0; k < DB; ++k) {
+            const double l = sm.Ms[lane][k];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) t[c] = fma(l, sm.W0s[k][16 * w + c], t[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < 16; ++c) sm.Ts[lane][16 * w + c] = t[c];
+    }
+    __syncthreads();
+    if (w < 4 && has1) {  // H = W1 T (overwrites L10)
+        double t[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) t[c] = 0.0;
+        for (int k = 0; k < DB; ++k) {
+            const double a = sm.W1s[lane][k];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) t[c] = fma(a, sm.Ts[k][16 * w + c], t[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < 16; ++c) sm.Ms[lane][16 * w + c] = t[c];
+    }
+}
+
+// Forward: x_B = D^{-1} (b_B - sum_{j < B} L[B, j] x_j): with r = the
+// bracket, x_0 = W0 r_0 and x_1 = W1 r_1 - H r_0.
 __global__ __launch_bounds__(512) void k_trsv2_fwd(const double *L, int64_t ldl, double *x, int64_t n,
                                                    const double *dinv, int *sync, double *mbox,
                                                    const int32_t *info) {
-    __shared__ int s_blk;
-    __shared__ double W0s[DB][DB + 1], W1s[DB][DB + 1], L10s[DB][DB + 1];
-    __shared__ double pf[4][DB], pn[4][DB], xt[DB];
-    __shared__ double vb[4][DB];  // per-wave broadcast vectors (operands read by every lane)
+    __shared__ Trsv2Smem sm;
     if (info && *info) return;
     const int nsb = (int)((n + SB - 1) / SB), nblk = (int)((n + DB - 1) / DB);
-    if (threadIdx.x == 0) s_blk = atomicAdd(&sync[0], 1);
+    if (threadIdx.x == 0) sm.blk = atomicAdd(&sync[0], 1);
     __syncthreads();
-    const int B = s_blk;
+    const int B = sm.blk;
     if (B >= nsb) return;
     int *abortf = &sync[1];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t R0 = (int64_t)B * SB;
     const bool has1 = 2 * B + 1 < nblk;
+    trsv2_setup(sm, L, ldl, n, dinv, B, has1);
     if (w >= 4) {
         // far tiles t < 2B - 2 (all full, all rows of them published before x_prev)
         const int h = w - 4, rh = h & 1;
@@ -626,12 +685,13 @@ __global__ __launch_bounds__(512) void k_trsv2_fwd(const double *L, int64_t ldl,
         const bool rv = i < n;
         double acc = 0.0;
         for (int t = h >> 1; t < 2 * B - 2; t += 2) {
-            const double *Lc = L + i + (int64_t)t * DB * ldl;
-            const double xv = mbox_poll(&mbox[(int64_t)t * DB + lane], abortf);
-            if (rv) {  // all 64 loads of the tile in flight before the first product
-                double v[DB];
+            // the tile's 64 loads go out before the poll: they do not depend on x
+            const double *Lc = L + (rv ? i : R0) + (int64_t)t * DB * ldl;
+            double v[DB];
 #pragma unroll
-                for (int c = 0; c < DB; ++c) v[c] = Lc[(int64_t)c * ldl];
+            for (int c = 0; c < DB; ++c) v[c] = Lc[(int64_t)c * ldl];
+            const double xv = mbox_poll(&mbox[(int64_t)t * DB + lane], abortf);
+            if (rv) {
                 double a1 = 0.0;
 #pragma unroll
                 for (int c = 0; c < DB; c += 2) {
@@ -641,26 +701,14 @@ __global__ __launch_bounds__(512) void k_trsv2_fwd(const double *L, int64_t ldl,
                 acc += a1;
             }
         }
-        pf[h][lane] = acc;
+        sm.pf[h][lane] = acc;
         __syncthreads();  // #1
-        __syncthreads();  // #2
         return;
-    }
-    // waves 0-3: the diagonal block's inverses and L10 to LDS
-    const double *W0 = dinv + (int64_t)(2 * B) * DB * DB;
-    for (int e = threadIdx.x; e < DB * DB; e += 256) {
-        const int a = e & (DB - 1), c = e >> 6;
-        W0s[a][c] = W0[a + c * DB];
-        if (has1) {
-            W1s[a][c] = dinv[(int64_t)(2 * B + 1) * DB * DB + a + c * DB];
-            const int64_t r = R0 + DB + a;
-            L10s[a][c] = r < n ? L[r + (R0 + c) * ldl] : 0.0;
-        }
     }
     const int rq = w >> 1, cq = w & 1;
     const int64_t row = R0 + DB * rq + lane;  // this lane's row of the block
     const bool rv = row < n;
-    const double b = (w < 2 && (w == 0 || has1) && (R0 + DB * w + lane) < n) ? x[R0 + DB * w + lane] : 0.0;
+    if (w < 2) sm.bv[w][lane] = R0 + DB * w + lane < n ? x[R0 + DB * w + lane] : 0.0;  // b of half w
     double part = 0.0;
     if (B >= 1) {
         // quarter (rq, cq) of the near block: rows of half rq, columns of 64-block 2 (B - 1) + cq
@@ -668,92 +716,74 @@ __global__ __launch_bounds__(512) void k_trsv2_fwd(const double *L, int64_t ldl,
         double nv[DB];
 #pragma unroll
         for (int c = 0; c < DB; ++c) nv[c] = rv ? L[row + (c0 + c) * ldl] : 0.0;
-        vb[w][lane] = mbox_poll(&mbox[c0 + lane], abortf);
+        sm.vb[w][lane] = mbox_poll(&mbox[c0 + lane], abortf);
         wave_lds_sync();
         double a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
         for (int c = 0; c < DB; c += 4) {
-            part = fma(nv[c], vb[w][c], part);
-            a1 = fma(nv[c + 1], vb[w][c + 1], a1);
-            a2 = fma(nv[c + 2], vb[w][c + 2], a2);
-            a3 = fma(nv[c + 3], vb[w][c + 3], a3);
+            part = fma(nv[c], sm.vb[w][c], part);
+            a1 = fma(nv[c + 1], sm.vb[w][c + 1], a1);
+            a2 = fma(nv[c + 2], sm.vb[w][c + 2], a2);
+            a3 = fma(nv[c + 3], sm.vb[w][c + 3], a3);
         }
         part += (a1 + a2) + a3;
     }
-    pn[w][lane] = part;
+    sm.pn[w][lane] = part;
     __syncthreads();  // #1: far and near partials in
+    if (w >= 2 || (w == 1 && !has1)) return;
+    // r_0 into vb[0] (wave 0) or vb[2] (wave 1), r_1 into vb[1]
+    const double r0 = sm.bv[0][lane] - ((sm.pf[0][lane] + sm.pf[2][lane]) + (sm.pn[0][lane] + sm.pn[1][lane]));
+    double z0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
     if (w == 0) {
-        vb[0][lane] = b - ((pf[0][lane] + pf[2][lane]) + (pn[0][lane] + pn[1][lane]));
+        sm.vb[0][lane] = r0;
         wave_lds_sync();
-        double z0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
 #pragma unroll
         for (int c = 0; c < DB; c += 4) {
-            z0 = fma(W0s[lane][c], vb[0][c], z0);
-            z1 = fma(W0s[lane][c + 1], vb[0][c + 1], z1);
-            z2 = fma(W0s[lane][c + 2], vb[0][c + 2], z2);
-            z3 = fma(W0s[lane][c + 3], vb[0][c + 3], z3);
+            z0 = fma(sm.W0s[lane][c], sm.vb[0][c], z0);
+            z1 = fma(sm.W0s[lane][c + 1], sm.vb[0][c + 1], z1);
+            z2 = fma(sm.W0s[lane][c + 2], sm.vb[0][c + 2], z2);
+            z3 = fma(sm.W0s[lane][c + 3], sm.vb[0][c + 3], z3);
         }
-        const double z = (z0 + z1) + (z2 + z3);
-        const int64_t i = R0 + lane;
-        xt[lane] = i < n ? z : 0.0;
-        if (i < n) {
-            x[i] = z;
-            mbox_put(&mbox[i], z);
+    } else {
+        sm.vb[2][lane] = r0;
+        sm.vb[1][lane] = sm.bv[1][lane] - ((sm.pf[1][lane] + sm.pf[3][lane]) + (sm.pn[2][lane] + sm.pn[3][lane]));
+        wave_lds_sync();
+#pragma unroll
+        for (int c = 0; c < DB; c += 2) {
+            z0 = fma(sm.W1s[lane][c], sm.vb[1][c], z0);
+            z1 = fma(sm.W1s[lane][c + 1], sm.vb[1][c + 1], z1);
+            z2 = fma(-sm.Ms[lane][c], sm.vb[2][c], z2);
+            z3 = fma(-sm.Ms[lane][c + 1], sm.vb[2][c + 1], z3);
         }
     }
-    __syncthreads();  // #2: the first half is in xt
-    if (w == 1 && has1) {
-        double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
-#pragma unroll
-        for (int c = 0; c < DB; c += 4) {
-            r0 = fma(L10s[lane][c], xt[c], r0);
-            r1 = fma(L10s[lane][c + 1], xt[c + 1], r1);
-            r2 = fma(L10s[lane][c + 2], xt[c + 2], r2);
-            r3 = fma(L10s[lane][c + 3], xt[c + 3], r3);
-        }
-        vb[1][lane] = b - ((pf[1][lane] + pf[3][lane]) + (pn[2][lane] + pn[3][lane])) - ((r0 + r1) + (r2 + r3));
-        wave_lds_sync();
-        double z0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
-#pragma unroll
-        for (int c = 0; c < DB; c += 4) {
-            z0 = fma(W1s[lane][c], vb[1][c], z0);
-            z1 = fma(W1s[lane][c + 1], vb[1][c + 1], z1);
-            z2 = fma(W1s[lane][c + 2], vb[1][c + 2], z2);
-            z3 = fma(W1s[lane][c + 3], vb[1][c + 3], z3);
-        }
-        const double z = (z0 + z1) + (z2 + z3);
-        const int64_t i = R0 + DB + lane;
-        if (i < n) {
-            x[i] = z;
-            mbox_put(&mbox[i], z);
-        }
+    const double z = (z0 + z1) + (z2 + z3);
+    const int64_t i = R0 + DB * w + lane;
+    if (i < n) {
+        x[i] = z;
+        mbox_put(&mbox[i], z);
     }
 }
 
 // Backward: x_B = D^{-T} (b_B - sum_{j > B} L[j, B]^T x_j), taken from the
-// last block; D^T is upper triangular, so the second half goes first:
-//   x_1 = W1^T (b_1 - far_1 - N_1^T x_next),
-//   x_0 = W0^T (b_0 - far_0 - N_0^T x_next - L10^T x_1).
-// Far waves: lane (hh, r2) reads rows 2 r2, 2 r2 + 1 of a tile in columns
-// 2 q + hh as 16-byte loads (as in the 64-row backward solve).
+// last block: with r = the bracket, x_1 = W1^T r_1 and x_0 = W0^T r_0 -
+// H^T r_1.  Far waves: lane (hh, r2) reads rows 2 r2, 2 r2 + 1 of a tile in
+// columns 2 q + hh as 16-byte loads (as in the 64-row backward solve).
 __global__ __launch_bounds__(512) void k_trsv2_trans(const double *L, int64_t ldl, double *x, int64_t n,
                                                      const double *dinv, int *sync, double *mbox,
                                                      const int32_t *info) {
-    __shared__ int s_t;
-    __shared__ double W0s[DB][DB + 1], W1s[DB][DB + 1], L10s[DB][DB + 1];
-    __shared__ double pf[4][DB], pn[4][DB], xb[DB];
-    __shared__ double vb[4][DB];  // per-wave broadcast vectors
+    __shared__ Trsv2Smem sm;
     if (info && *info) return;
     const int nsb = (int)((n + SB - 1) / SB), nblk = (int)((n + DB - 1) / DB);
-    if (threadIdx.x == 0) s_t = atomicAdd(&sync[0], 1);
+    if (threadIdx.x == 0) sm.blk = atomicAdd(&sync[0], 1);
     __syncthreads();
-    const int tk = s_t;
+    const int tk = sm.blk;
     if (tk >= nsb) return;
     const int B = nsb - 1 - tk;
     int *abortf = &sync[1];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t C0 = (int64_t)B * SB;
     const bool has1 = 2 * B + 1 < nblk;
+    trsv2_setup(sm, L, ldl, n, dinv, B, has1);
     if (w >= 4) {
         // far row tiles t >= 2 (B + 2), last first; they exist only when this
         // block is not one of the last two, so its 128 columns are all < n
@@ -767,11 +797,12 @@ __global__ __launch_bounds__(512) void k_trsv2_trans(const double *L, int64_t ld
             const int64_t r = (int64_t)t * DB + 2 * r2;
             const double *Lr = L + r + (c0 + hh) * ldl;
             if (r + 1 < n) {
-                const double x0 = mbox_poll(&mbox[r], abortf);
-                const double x1 = mbox_poll(&mbox[r + 1], abortf);
+                // the tile's loads go out before the polls: they do not depend on x
                 gp_d2u v[DB / 2];
 #pragma unroll
                 for (int q = 0; q < DB / 2; ++q) v[q] = *reinterpret_cast<const gp_d2u *>(Lr + (int64_t)(2 * q) * ldl);
+                const double x0 = mbox_poll(&mbox[r], abortf);
+                const double x1 = mbox_poll(&mbox[r + 1], abortf);
 #pragma unroll
                 for (int q = 0; q < DB / 2; ++q) p[q] = fma(v[q].y, x1, fma(v[q].x, x0, p[q]));
             } else if (r < n) {
@@ -785,25 +816,14 @@ __global__ __launch_bounds__(512) void k_trsv2_trans(const double *L, int64_t ld
         xr_step<4>(p, lane);
         xr_step<2>(p, lane);
         xr_step<1>(p, lane);
-        pf[h][2 * r2 + hh] = p[0];
+        sm.pf[h][2 * r2 + hh] = p[0];
         __syncthreads();  // #1
-        __syncthreads();  // #2
         return;
-    }
-    const double *W0 = dinv + (int64_t)(2 * B) * DB * DB;
-    for (int e = threadIdx.x; e < DB * DB; e += 256) {
-        const int a = e & (DB - 1), c = e >> 6;
-        W0s[a][c] = W0[a + c * DB];
-        if (has1) {
-            W1s[a][c] = dinv[(int64_t)(2 * B + 1) * DB * DB + a + c * DB];
-            const int64_t r = C0 + DB + a;
-            L10s[a][c] = r < n ? L[r + (C0 + c) * ldl] : 0.0;
-        }
     }
     const int rq = w >> 1, cq = w & 1;
     const int64_t col = C0 + DB * cq + lane;  // this lane's column of the block
     const bool cvq = col < n;
-    const double b = (w < 2 && (w == 0 || has1) && (C0 + DB * w + lane) < n) ? x[C0 + DB * w + lane] : 0.0;
+    if (w < 2) sm.bv[w][lane] = cvq ? x[col] : 0.0;
     double part = 0.0;
     if (B + 1 < nsb) {
         // quarter (rq, cq) of the block below: rows of 64-block 2 (B + 1) + rq, columns of half cq
@@ -811,68 +831,53 @@ __global__ __launch_bounds__(512) void k_trsv2_trans(const double *L, int64_t ld
         double nv[DB];
 #pragma unroll
         for (int r = 0; r < DB; ++r) nv[r] = (cvq && r0 + r < n) ? L[r0 + r + col * ldl] : 0.0;
-        vb[w][lane] = r0 + lane < n ? mbox_poll(&mbox[r0 + lane], abortf) : 0.0;
+        sm.vb[w][lane] = r0 + lane < n ? mbox_poll(&mbox[r0 + lane], abortf) : 0.0;
         wave_lds_sync();
         double a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
         for (int r = 0; r < DB; r += 4) {
-            part = fma(nv[r], vb[w][r], part);
-            a1 = fma(nv[r + 1], vb[w][r + 1], a1);
-            a2 = fma(nv[r + 2], vb[w][r + 2], a2);
-            a3 = fma(nv[r + 3], vb[w][r + 3], a3);
+            part = fma(nv[r], sm.vb[w][r], part);
+            a1 = fma(nv[r + 1], sm.vb[w][r + 1], a1);
+            a2 = fma(nv[r + 2], sm.vb[w][r + 2], a2);
+            a3 = fma(nv[r + 3], sm.vb[w][r + 3], a3);
         }
         part += (a1 + a2) + a3;
     }
-    pn[w][lane] = part;
+    sm.pn[w][lane] = part;
     __syncthreads();  // #1
-    if (w == 1 && has1) {
-        vb[1][lane] = b - ((pf[1][lane] + pf[3][lane]) + (pn[1][lane] + pn[3][lane]));
+    if (w >= 2 || (w == 1 && !has1)) return;
+    const double r1 = has1 ? sm.bv[1][lane] - ((sm.pf[1][lane] + sm.pf[3][lane]) + (sm.pn[1][lane] + sm.pn[3][lane]))
+                           : 0.0;
+    double z0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
+    if (w == 1) {
+        sm.vb[1][lane] = r1;
         wave_lds_sync();
-        double z0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
 #pragma unroll
-        for (int r = 0; r < DB; r += 4) {  // (W1^T rhs)[lane] = sum_r W1(r, lane) rhs_r
-            z0 = fma(W1s[r][lane], vb[1][r], z0);
-            z1 = fma(W1s[r + 1][lane], vb[1][r + 1], z1);
-            z2 = fma(W1s[r + 2][lane], vb[1][r + 2], z2);
-            z3 = fma(W1s[r + 3][lane], vb[1][r + 3], z3);
+        for (int r = 0; r < DB; r += 4) {  // (W1^T r_1)[lane] = sum_r W1(r, lane) r_1[r]
+            z0 = fma(sm.W1s[r][lane], sm.vb[1][r], z0);
+            z1 = fma(sm.W1s[r + 1][lane], sm.vb[1][r + 1], z1);
+            z2 = fma(sm.W1s[r + 2][lane], sm.vb[1][r + 2], z2);
+            z3 = fma(sm.W1s[r + 3][lane], sm.vb[1][r + 3], z3);
         }
-        const double z = (z0 + z1) + (z2 + z3);
-        const int64_t i = C0 + DB + lane;
-        xb[lane] = i < n ? z : 0.0;
-        if (i < n) {
-            x[i] = z;
-            mbox_put(&mbox[i], z);
-        }
-    }
-    if (w == 1 && !has1) xb[lane] = 0.0;
-    __syncthreads();  // #2: the second half is in xb
-    if (w == 0) {
-        double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
-        if (has1) {
+    } else {
+        sm.vb[0][lane] = sm.bv[0][lane] - ((sm.pf[0][lane] + sm.pf[2][lane]) + (sm.pn[0][lane] + sm.pn[2][lane]));
+        sm.vb[2][lane] = r1;
+        wave_lds_sync();
 #pragma unroll
-            for (int r = 0; r < DB; r += 4) {  // (L10^T x_1)[lane] = sum_r L10(r, lane) x_1[r]
-                r0 = fma(L10s[r][lane], xb[r], r0);
-                r1 = fma(L10s[r + 1][lane], xb[r + 1], r1);
-                r2 = fma(L10s[r + 2][lane], xb[r + 2], r2);
-                r3 = fma(L10s[r + 3][lane], xb[r + 3], r3);
+        for (int r = 0; r < DB; r += 2) {  // W0^T r_0 - H^T r_1
+            z0 = fma(sm.W0s[r][lane], sm.vb[0][r], z0);
+            z1 = fma(sm.W0s[r + 1][lane], sm.vb[0][r + 1], z1);
+            if (has1) {
+                z2 = fma(-sm.Ms[r][lane], sm.vb[2][r], z2);
+                z3 = fma(-sm.Ms[r + 1][lane], sm.vb[2][r + 1], z3);
             }
         }
-        vb[0][lane] = b - ((pf[0][lane] + pf[2][lane]) + (pn[0][lane] + pn[2][lane])) - ((r0 + r1) + (r2 + r3));
-        wave_lds_sync();
-        double z0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
-#pragma unroll
-        for (int r = 0; r < DB; r += 4) {
-            z0 = fma(W0s[r][lane], vb[0][r], z0);
-            z1 = fma(W0s[r + 1][lane], vb[0][r + 1], z1);
-            z2 = fma(W0s[r + 2][lane], vb[0][r + 2], z2);
-            z3 = fma(W0s[r + 3][lane], vb[0][r + 3], z3);
-        }
-        const double z = (z0 + z1) + (z2 + z3);
-        const int64_t i = C0 + lane;
-        if (i < n) {
-            x[i] = z;
-            mbox_put(&mbox[i], z);
-        }
+    }
+    const double z = (z0 + z1) + (z2 + z3);
+    const int64_t i = C0 + DB * w + lane;
+    if (i < n) {
+        x[i] = z;
+        mbox_put(&mbox[i], z);
     }
 }
 
