@@ -7,14 +7,15 @@
 //    of Section 2.1 / Fig. 1; a non-positive pivot stops the factorisation
 //    and records the 1-based column (no pivoting -- Section 5).
 //  * k_diag_inv: the same inverse for every diagonal block of a given L.
-//  * k_trsv_fwd / k_trsv_trans: single-kernel blocked triangular solves
-//    (forward L^{-1} b and backward L^{-T} b -- Section 1's backsolve and the
-//    remoteForwardsolve / remoteBacksolve of Section 2.3.2).  Each workgroup
-//    owns one 64-row block; it takes a ticket from an atomic counter (so the
-//    blocks it depends on belong to workgroups already running), accumulates
-//    the off-diagonal products as soon as each dependency's flag is released,
-//    applies the block's inverse and releases its own flag.  L is read once,
-//    64 contiguous doubles per load.
+//  * k_trsv2_fwd / k_trsv2_trans (k_trsv_fwd / k_trsv_trans for n <= 128):
+//    single-kernel blocked triangular solves (forward L^{-1} b and backward
+//    L^{-T} b -- Section 1's backsolve and the remoteForwardsolve /
+//    remoteBacksolve of Section 2.3.2).  Each workgroup owns one 128-row
+//    (64-row) block; it takes a ticket from an atomic counter (so the blocks
+//    it depends on belong to workgroups already running), accumulates the
+//    off-diagonal products as soon as each dependency's values are published
+//    in the mailbox, applies the block's inverse and publishes its own
+//    values.  L is read once, 64 contiguous doubles per load.
 //  * k_loglik_reduce: compensated log|C| = 2 sum log L_ii, q = z^T z and the
 //    log-likelihood (Section 1; only these scalars leave the device, as in
 //    Section 2.2.2).
