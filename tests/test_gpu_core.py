@@ -121,7 +121,7 @@ def test_potrf_not_pd_reports_column(orc, bad):
     assert int(info.item()) == info_o == bad + 1
 
 
-@pytest.mark.parametrize("n", [1, 64, 65, 333, 1000, 2500])
+@pytest.mark.parametrize("n", [1, 64, 65, 128, 129, 192, 256, 333, 1000, 2500])
 @pytest.mark.parametrize("trans", [False, True])
 def test_trsv_parity(orc, n, trans):
     X = synth.uniform_points(n, 200 + n)
