@@ -84,7 +84,7 @@ typedef struct {
 
 typedef struct {
     int32_t nb;          /* outer panel width of the Cholesky, multiple of 64 (0 = automatic: 768 for FP64,
-                            512 for the mixed modes) */
+                            512 for FP32 trailing updates, 640 for BF16) */
     int32_t lookahead;   /* 1: factor panel k+1 on a side stream while the trailing update of k runs */
     int32_t band;        /* mixed modes: tiles within `band` 128-tile diagonals of the diagonal use FP64 */
     int32_t ir_max_iter; /* mixed modes: cap on iterative-refinement sweeps (0 = no refinement) */

@@ -69,7 +69,7 @@ struct PanelBufs {
 // 2 % faster than 512 in FP64; no difference in the mixed modes, where the
 // shorter accumulation keeps the log-determinant error lower).
 int64_t panel_width(gp_handle_t h, gp_prec_t prec) {
-    return h->opt.nb > 0 ? h->opt.nb : (prec == GP_FP64 ? 768 : 512);
+    return h->opt.nb > 0 ? h->opt.nb : (prec == GP_FP64 ? 768 : (prec == GP_FP32_TRAIL ? 512 : 640));
 }
 
 // Reserved compute unit r of `reserve`: spaced ncu / reserve apart and offset
