@@ -29,8 +29,11 @@
  *    Numerical failure is reported on the device: *info_dev = 0, or the
  *    1-based index of the first column at which the matrix was found not to be
  *    positive definite (the LAPACK potrf convention; there is no pivoting, so a
- *    matrix that is not numerically positive definite fails -- Section 5).  A
- *    failed evaluation writes NaN to its scalar outputs.
+ *    matrix that is not numerically positive definite fails -- Section 5), or
+ *    -1 when one of the bounded waits between concurrently running workgroups
+ *    gave up (a stall; never expected, but reported rather than hidden).  A
+ *    failed evaluation writes NaN to its scalar outputs (and to alpha and the
+ *    gradient where requested).
  *  - Workspace: the caller allocates `ws` (device memory, 256-byte aligned) of
  *    at least gp_workspace_size() bytes.  Its contents on entry are ignored.
  *  - theta is (log sigma^2, log rho, log tau^2); a log of -inf is an exact 0.
@@ -98,6 +101,11 @@ typedef struct {
     int32_t batch_grid;  /* gp_loglik_batched: 0 = one persistent launch with one workgroup per compute
                             unit; > 0 = a persistent launch of that many workgroups; -1 = level-synchronous
                             launches (three per tile column) */
+    int32_t fail_inject; /* test hook, 0 in normal use.  Bit 0: the abort flag of the fused panel kernel
+                            is raised before it starts; bit 1: that of every triangular solve inside
+                            gp_loglik / gp_loglik_grad.  Every bounded wait then gives up at once and
+                            the evaluation reports a stall (info = -1, NaN outputs) without any kernel
+                            running into its time limit. */
 } gp_options_t;
 
 /* ---- handle ------------------------------------------------------------ */

@@ -43,7 +43,8 @@ class Options(ctypes.Structure):
     _fields_ = [("nb", ctypes.c_int32), ("lookahead", ctypes.c_int32), ("band", ctypes.c_int32),
                 ("ir_max_iter", ctypes.c_int32), ("ir_tol", ctypes.c_double),
                 ("reorder", ctypes.c_int32), ("panel_cus", ctypes.c_int32),
-                ("fused_panel", ctypes.c_int32), ("batch_grid", ctypes.c_int32)]
+                ("fused_panel", ctypes.c_int32), ("batch_grid", ctypes.c_int32),
+                ("fail_inject", ctypes.c_int32)]
 
 
 class GPError(RuntimeError):

@@ -439,7 +439,8 @@ int potrf_impl(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda,
     auto diag_block = [&](hipStream_t st, int64_t c0, int64_t c1) -> int {
         if (h->opt.fused_panel && pb.pflags && c1 - c0 <= DB * PF_MAXB && (c1 == n || pb.vinv)) {
             HIPCHK(launch_panel_chol(st, A + c0 + c0 * lda, lda, (int)(c1 - c0), dinv + (c0 / DB) * DB * DB,
-                                     c1 < n ? pb.vinv : nullptr, c1 - c0, pb.pflags, info, c0));
+                                     c1 < n ? pb.vinv : nullptr, c1 - c0, pb.pflags, info, c0,
+                                     h->opt.fail_inject & 1));
             return GP_OK;
         }
         for (int64_t d = c0; d < c1; d += DB) {
@@ -672,14 +673,21 @@ int loglik_core(gp_handle_t h, gp_op_t op, gp_theta_t th, gp_prec_t prec, int64_
     HIPCHK(launch_cov_lower(s, cp, n, Xe, C, ldc, nullptr));
     int rc = potrf_impl(h, prec, n, C, ldc, info, dinv, panel_bufs(ws, lay));
     if (rc) return rc;
+    const int inj = (h->opt.fail_inject >> 1) & 1;
+    // every solve is followed by its status check: a wait that gave up turns info into -1
+    auto solve = [&](int trans, double *v, const int32_t *skip) -> hipError_t {
+        hipError_t e = launch_trsv(s, trans, C, ldc, v, n, dinv, sync, skip, inj);
+        if (e == hipSuccess && n > 0) e = launch_solve_status(s, sync, info);
+        return e;
+    };
     HIPCHK(launch_sub_mu(s, n, ye, mue, b));
     HIPCHK(launch_copy_vec(s, n, b, z));
-    HIPCHK(launch_trsv(s, 0, C, ldc, z, n, dinv, sync, info));
-    HIPCHK(launch_loglik_reduce(s, n, C, ldc, z, out3, info, sync));
+    HIPCHK(solve(0, z, info));
+    HIPCHK(launch_loglik_reduce(s, n, C, ldc, z, out3, info, nullptr));  // solve failures are in info
     const bool need_x = alpha_dev || grad3 || mixed;
     if (need_x) {
         HIPCHK(launch_copy_vec(s, n, z, x));
-        HIPCHK(launch_trsv(s, 1, C, ldc, x, n, dinv, sync, info));
+        HIPCHK(solve(1, x, info));
     }
     if (mixed) {
         double *res = at<double>(ws, lay.vec4), *dv = at<double>(ws, lay.vec5);
@@ -692,8 +700,8 @@ int loglik_core(gp_handle_t h, gp_op_t op, gp_theta_t th, gp_prec_t prec, int64_
             HIPCHK(launch_ir_check(s, n, res, state, done, it == maxit, h->opt.ir_tol));
             if (it == maxit) break;
             HIPCHK(launch_copy_skip(s, n, res, dv, done));
-            HIPCHK(launch_trsv(s, 0, C, ldc, dv, n, dinv, sync, done));
-            HIPCHK(launch_trsv(s, 1, C, ldc, dv, n, dinv, sync, done));
+            HIPCHK(solve(0, dv, done));
+            HIPCHK(solve(1, dv, done));
             HIPCHK(launch_axpy_skip(s, n, dv, x, done));
         }
         HIPCHK(launch_ir_finish(s, n, b, x, state, out3, ir, info));
@@ -712,6 +720,8 @@ int loglik_core(gp_handle_t h, gp_op_t op, gp_theta_t th, gp_prec_t prec, int64_
         HIPCHK(launch_grad_contract(s, cp, n, Xe, C, ldc, x, part, GRAD_PARTS, info));
         HIPCHK(launch_grad_finish(s, GRAD_PARTS, part, grad3, info));
     }
+    // a failure anywhere above (info != 0): NaN scalars, alpha and gradient
+    HIPCHK(launch_fail_outputs(s, n, info, out3, alpha_dev, grad3));
     return GP_OK;
 }
 
@@ -842,6 +852,7 @@ int gp_set_options(gp_handle_t h, const gp_options_t *opt) {
     if (opt->ir_max_iter < 0 || opt->band < -1 || opt->panel_cus < 0) return -2;
     if (opt->fused_panel != 0 && opt->fused_panel != 1) return -2;
     if (opt->batch_grid < -1) return -2;
+    if (opt->fail_inject < 0 || opt->fail_inject > 3) return -2;
     if (!(opt->ir_tol >= 0.0) || isinf(opt->ir_tol)) return GP_ERR_NONFINITE;
     h->opt = *opt;
     return GP_OK;

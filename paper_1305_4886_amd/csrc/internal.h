@@ -401,8 +401,10 @@ hipError_t launch_diag_inv(hipStream_t s, const double *L, int64_t ldl, int64_t 
 // A non-positive pivot sets *info = col0 + its 1-based column in the block.
 constexpr int PF_MAXB = 16;
 constexpr size_t panel_flags_bytes() { return sizeof(int) * (PF_MAXB * PF_MAXB + 64); }
+// raise_abort (test hook): the abort flag is raised before the launch, so
+// every wait gives up at once and the launch reports info = -1.
 hipError_t launch_panel_chol(hipStream_t s, double *A, int64_t lda, int K, double *dinv, double *W, int64_t ldw,
-                             int *flags, int32_t *info, int64_t col0);
+                             int *flags, int32_t *info, int64_t col0, int raise_abort = 0);
 // W_b = L_bb^{-1} (K x K, ld K, zeros above the diagonal, at W + b K^2) for the
 // nblocks consecutive K x K diagonal blocks b of a factored L (K % 64 == 0,
 // K <= 64 PF_MAXB), from their 64 x 64 block inverses (dinv, consecutive).  One
@@ -412,8 +414,15 @@ hipError_t launch_block_trtri(hipStream_t s, const double *L, int64_t ldl, int K
 // Work area of a triangular solve: trsv_work_bytes(n) bytes (counters and a
 // mailbox of n doubles); the abort flag is its int [1].
 size_t trsv_work_bytes(int64_t n);
+// A wait of the solve that gives up leaves NaN sentinels in x and raises the
+// abort flag in work; launch_solve_status then turns info 0 into -1.
+// raise_abort (test hook) raises that flag before the launch.
 hipError_t launch_trsv(hipStream_t s, int trans, const double *L, int64_t ldl, double *x, int64_t n,
-                       const double *dinv, void *work, const int32_t *info);
+                       const double *dinv, void *work, const int32_t *info, int raise_abort = 0);
+hipError_t launch_solve_status(hipStream_t s, const void *work, int32_t *info);
+// With *info != 0: out3 and grad3 (3 each) and alpha (n) set to NaN (null pointers skipped).
+hipError_t launch_fail_outputs(hipStream_t s, int64_t n, const int32_t *info, double *out3, double *alpha,
+                               double *grad3);
 hipError_t launch_sub_mu(hipStream_t s, int64_t n, const double *y, const double *mu, double *z);
 hipError_t launch_copy_vec(hipStream_t s, int64_t n, const double *a, double *b);
 hipError_t launch_loglik_reduce(hipStream_t s, int64_t n, const double *L, int64_t ldl,

@@ -100,15 +100,27 @@ GP_DEV void st_coh(double *p, double v) {
                        __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Thread 0 waits for flags[idx] (bounded); every thread gets the outcome.
-GP_DEV bool pf_wait(int *flags, int idx, int *s_ok) {
+// A bounded wait that gave up (timeout, or another workgroup's abort) turns
+// info 0 into -1; a pivot failure already recorded (a positive column) stays.
+GP_DEV void note_giveup(int32_t *info) {
+    if (info) atomicCAS(info, 0, -1);
+}
+
+// Thread 0 waits for flags[idx] (bounded); every thread gets the outcome.  The
+// abort flag is read beside the flag on every poll and takes precedence, so
+// once it is raised every later wait gives up at once.  A give-up is recorded
+// in info (note_giveup).
+GP_DEV bool pf_wait(int *flags, int idx, int *s_ok, int32_t *info) {
     if (threadIdx.x == 0) {
         int ok = 1, spins = 0;
-        while (__hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-            if (__hip_atomic_load(&flags[PF_ABORT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        for (;;) {
+            const int f = __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int ab = __hip_atomic_load(&flags[PF_ABORT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (ab) {
                 ok = 0;
                 break;
             }
+            if (f) break;
             __builtin_amdgcn_s_sleep(2);
             if (++spins > SPIN_LIMIT) {
                 __hip_atomic_store(&flags[PF_ABORT], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -116,6 +128,7 @@ GP_DEV bool pf_wait(int *flags, int idx, int *s_ok) {
                 break;
             }
         }
+        if (!ok) note_giveup(info);
         *s_ok = ok;
     }
     __syncthreads();
@@ -234,7 +247,7 @@ __global__ __launch_bounds__(256, 1) void k_panel_chol(double *A, int64_t lda, i
 
     // ---- phase 1 ----
     for (int k = 0; factor && k < b; ++k) {
-        if (!pf_wait(flags, k * PF_MAXB + k, &s_ok)) return;
+        if (!pf_wait(flags, k * PF_MAXB + k, &s_ok, info)) return;
         pf_load<false>(sm.g.op, dinv + (int64_t)k * DB * DB, DB, DB, DB);  // W_k
         __syncthreads();
         pf_gemm(nullptr, Ab + (int64_t)DB * k * lda, lda, rb, sm.g.op, acc, w, lane);  // L_bk = S_bk W_k^T
@@ -250,7 +263,7 @@ __global__ __launch_bounds__(256, 1) void k_panel_chol(double *A, int64_t lda, i
         for (int j = k + 1; j <= b; ++j) {
             const double (*Y)[DB + 1] = sm.g.lb;
             if (j < b) {
-                if (!pf_wait(flags, j * PF_MAXB + k, &s_ok)) return;
+                if (!pf_wait(flags, j * PF_MAXB + k, &s_ok, info)) return;
                 pf_load<false>(sm.g.op, A + DB * j + (int64_t)DB * k * lda, lda, DB, DB);  // L_jk
                 __syncthreads();
                 Y = sm.g.op;
@@ -280,7 +293,7 @@ __global__ __launch_bounds__(256, 1) void k_panel_chol(double *A, int64_t lda, i
         const int fail = wave_chol64(a, lane, sm.d.ls, sm.d.u.pn);
         if (fail) {
             if (lane == 0) {
-                *info = (int32_t)(col0 + DB * b + fail);
+                __hip_atomic_store(info, (int32_t)(col0 + DB * b + fail), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(&flags[PF_ABORT], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 s_ok = 0;
             }
@@ -319,13 +332,15 @@ __global__ __launch_bounds__(256, 1) void k_panel_chol(double *A, int64_t lda, i
         pf_load<true>(sm.g.lb, Wc + DB * k, ldw, DB, DB);  // lb[c][m] = W_kb(m, c)
         __syncthreads();
         for (int s2 = k + 1; s2 < nb; ++s2) {
-            if (factor && !pf_wait(flags, s2 * PF_MAXB + k, &s_ok)) return;
+            if (factor && !pf_wait(flags, s2 * PF_MAXB + k, &s_ok, info)) return;
             pf_gemm(nullptr, A + DB * s2 + (int64_t)DB * k * lda, lda, DB, sm.g.lb, acc, w, lane);  // L_sk W_kb
             pf_accum(Wc + DB * s2, ldw, acc, 1.0, DB, DB, false, w, lane);                       // T_sb +=
         }
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();  // T stores complete
-        if (!pf_wait(flags, (k + 1) * PF_MAXB + (k + 1), &s_ok)) return;
+        // W_{k+1} is published by workgroup k + 1; in inverse-only mode it is
+        // an input (dinv) and this workgroup reads only its own blocks of W
+        if (factor && !pf_wait(flags, (k + 1) * PF_MAXB + (k + 1), &s_ok, info)) return;
         pf_load<true>(sm.g.op, Wc + DB * (k + 1), ldw, DB, DB);  // op[c][m] = T(m, c)
         __syncthreads();
         pf_gemm(nullptr, dinv + (int64_t)(k + 1) * DB * DB, DB, DB, sm.g.op, acc, w, lane);  // W_{k+1} T
@@ -904,6 +919,28 @@ __global__ void k_fill_zero(uint32_t *p, int64_t cnt) {
 
 __global__ void k_set_info(int32_t *info) { *info = 0; }
 
+__global__ void k_raise_flag(int *p) { *p = 1; }
+
+// After a solve: a wait of the solve that gave up (its abort flag, sync[1])
+// turns info 0 into -1, so the evaluation reports the failure (the solved
+// values then hold NaN sentinels).
+__global__ void k_solve_status(const int *sync, int32_t *info) {
+    if (sync[1] != 0 && *info == 0) *info = -1;
+}
+
+// A failed evaluation (info != 0): NaN scalars, NaN alpha and gradient.
+__global__ __launch_bounds__(256) void k_fail_outputs(int64_t n, const int32_t *info, double *out3, double *alpha,
+                                                      double *grad3) {
+    if (*info == 0) return;
+    const double nan = __builtin_nan("");
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < 3) {
+        if (out3) out3[i] = nan;
+        if (grad3) grad3[i] = nan;
+    }
+    if (alpha && i < n) alpha[i] = nan;
+}
+
 __global__ void k_sub_mu(int64_t n, const double *y, const double *mu, double *z) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) z[i] = y[i] - (mu ? mu[i] : 0.0);
@@ -963,11 +1000,12 @@ hipError_t launch_diag_potrf(hipStream_t s, double *A, int64_t lda, int jb, doub
 }
 
 hipError_t launch_panel_chol(hipStream_t s, double *A, int64_t lda, int K, double *dinv, double *W, int64_t ldw,
-                             int *flags, int32_t *info, int64_t col0) {
+                             int *flags, int32_t *info, int64_t col0, int raise_abort) {
     if (K <= 0) return hipSuccess;
     if (K > DB * PF_MAXB || (W && (K % DB != 0 || ldw < K))) return hipErrorInvalidValue;
     hipError_t e = launch_fill(s, flags, panel_flags_bytes());
     if (e != hipSuccess) return e;
+    if (raise_abort) hipLaunchKernelGGL(k_raise_flag, dim3(1), dim3(1), 0, s, flags + PF_ABORT);
     hipLaunchKernelGGL(k_panel_chol, dim3((unsigned)((K + DB - 1) / DB)), dim3(256), 0, s, A, lda, K, dinv, W, ldw,
                        flags, info, col0, 1, (int64_t)0, (int64_t)0, (int64_t)0, (int64_t)0);
     return hipGetLastError();
@@ -1002,13 +1040,14 @@ hipError_t launch_fill(hipStream_t s, void *p, size_t bytes) {
 size_t trsv_work_bytes(int64_t n) { return 256 + sizeof(double) * (size_t)((n + DB - 1) / DB) * DB; }
 
 hipError_t launch_trsv(hipStream_t s, int trans, const double *L, int64_t ldl, double *x, int64_t n,
-                       const double *dinv, void *work, const int32_t *info) {
+                       const double *dinv, void *work, const int32_t *info, int raise_abort) {
     if (n <= 0) return hipSuccess;
     const int nblk = (int)((n + DB - 1) / DB);
     int *sync = static_cast<int *>(work);
     double *mbox = reinterpret_cast<double *>(static_cast<char *>(work) + 256);
     hipError_t e = launch_fill(s, sync, 256);
     if (e != hipSuccess) return e;
+    if (raise_abort) hipLaunchKernelGGL(k_raise_flag, dim3(1), dim3(1), 0, s, sync + 1);
     const int64_t cnt = (int64_t)nblk * DB;
     hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
                        reinterpret_cast<uint64_t *>(mbox), cnt, MBOX_EMPTY);
@@ -1023,6 +1062,19 @@ hipError_t launch_trsv(hipStream_t s, int trans, const double *L, int64_t ldl, d
     } else {
         hipLaunchKernelGGL(k_trsv2_fwd, dim3((unsigned)nsb), dim3(512), 0, s, L, ldl, x, n, dinv, sync, mbox, info);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_status(hipStream_t s, const void *work, int32_t *info) {
+    hipLaunchKernelGGL(k_solve_status, dim3(1), dim3(1), 0, s, static_cast<const int *>(work), info);
+    return hipGetLastError();
+}
+
+hipError_t launch_fail_outputs(hipStream_t s, int64_t n, const int32_t *info, double *out3, double *alpha,
+                               double *grad3) {
+    const int64_t cnt = alpha && n > 3 ? n : 3;
+    hipLaunchKernelGGL(k_fail_outputs, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, n, info, out3, alpha,
+                       grad3);
     return hipGetLastError();
 }
 

@@ -68,26 +68,33 @@ def test_cross_cov(orc, n, m):
     np.testing.assert_allclose(M, orc.cross_cov(1, t, X, Xs), rtol=1e-14, atol=1e-300)
 
 
-# (n, panel width, lookahead, compute units reserved for the lookahead chain,
-#  fused panel kernel or the per-64-column launch chain)
+# (n, panel width (0: the default), lookahead, compute units reserved for the
+#  lookahead chain, fused panel kernel or the per-64-column launch chain,
+#  leading dimension - n).  An odd leading dimension keeps the trailing update
+#  on its 4-byte copies; ld = n with even n (the benchmark's layout) takes the
+#  16-byte copies of the main trailing-update kernel.
 POTRF_CASES = [
-    (1, 256, 1, 8, 1), (2, 256, 1, 8, 1), (63, 256, 1, 8, 1), (64, 256, 1, 8, 1), (65, 256, 1, 8, 1),
-    (127, 64, 0, 0, 1), (200, 128, 1, 8, 1), (257, 256, 1, 0, 1), (500, 64, 1, 8, 1), (1000, 256, 1, 8, 1),
-    (1000, 256, 0, 8, 1), (1100, 128, 1, 0, 1), (2048, 512, 1, 8, 1), (3001, 256, 1, 16, 1),
-    (3001, 192, 1, 8, 1), (4500, 512, 1, 8, 1), (3001, 768, 1, 0, 1), (2500, 1024, 1, 0, 1),
-    (2500, 1024, 0, 0, 1),
-    (127, 64, 0, 0, 0), (1000, 256, 1, 8, 0), (3001, 192, 1, 8, 0), (4500, 512, 1, 0, 0),
+    (1, 256, 1, 8, 1, 3), (2, 256, 1, 8, 1, 3), (63, 256, 1, 8, 1, 3), (64, 256, 1, 8, 1, 3),
+    (65, 256, 1, 8, 1, 3), (127, 64, 0, 0, 1, 3), (200, 128, 1, 8, 1, 3), (257, 256, 1, 0, 1, 3),
+    (500, 64, 1, 8, 1, 3), (1000, 256, 1, 8, 1, 3), (1000, 256, 0, 8, 1, 3), (1100, 128, 1, 0, 1, 3),
+    (2048, 512, 1, 8, 1, 3), (3001, 256, 1, 16, 1, 3), (3001, 192, 1, 8, 1, 3), (4500, 512, 1, 8, 1, 3),
+    (3001, 768, 1, 0, 1, 3), (2500, 1024, 1, 0, 1, 3), (2500, 1024, 0, 0, 1, 3),
+    (127, 64, 0, 0, 0, 3), (1000, 256, 1, 8, 0, 3), (3001, 192, 1, 8, 0, 3), (4500, 512, 1, 0, 0, 3),
+    # the benchmark's configuration: default panel width (768), lookahead, ld = n
+    (8192, 0, 1, 0, 1, 0), (4096, 0, 1, 0, 1, 0), (3000, 0, 1, 0, 1, 0), (4000, 512, 0, 0, 1, 0),
+    (2050, 0, 1, 0, 1, 2),
 ]
 
 
-@pytest.mark.parametrize("n,nb,la,pc,fused", POTRF_CASES)
-def test_potrf_parity(orc, n, nb, la, pc, fused):
+@pytest.mark.parametrize("n,nb,la,pc,fused,pad", POTRF_CASES)
+def test_potrf_parity(orc, n, nb, la, pc, fused, pad):
     X = synth.uniform_points(n, 100 + n)
     t = logth(1.0, 0.1, 0.1)
     C = orc.cov(0, t, X)
-    S = gp.colmajor_storage(n, ld=n + 3)
+    S = gp.colmajor_storage(n, ld=n + pad)
     S.fill_(-3.25)
     gp.colmajor(S, n).copy_(torch.as_tensor(np.tril(C) + np.triu(np.full((n, n), -3.25), 1)))
+    del C
     h = gp.handle()
     saved = h.options()
     h.set_options(nb=nb, lookahead=la, panel_cus=pc, fused_panel=fused)
@@ -101,6 +108,8 @@ def test_potrf_parity(orc, n, nb, la, pc, fused):
     M = gp.colmajor(S, n).cpu().numpy()
     assert np.all(M[np.triu_indices(n, 1)] == -3.25), "upper triangle must stay untouched"
     L = np.tril(M)
+    del M
+    C = orc.cov(0, t, X)
     Lo, info_o = orc.potrf(C)
     assert info_o == 0
     err = np.linalg.norm(L - Lo) / np.linalg.norm(Lo)
