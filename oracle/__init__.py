@@ -60,6 +60,12 @@ def lib():
         L.orc_loglik_grad.restype = _i64
         L.orc_krige.argtypes = [ctypes.c_int, _dp, _i64, _i64, ctypes.c_int, _dp, _dp, _dp, _i64,
                                 _dp, ctypes.c_double, ctypes.c_int, _dp, _dp]
+        L.orc_krige_cov.argtypes = [ctypes.c_int, _dp, _i64, _i64, ctypes.c_int, _dp, _dp, _dp, _i64,
+                                    ctypes.c_int, _dp, _i64]
+        L.orc_trmm.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64]
+        L.orc_simulate.argtypes = [ctypes.c_int, _dp, _i64, _i64, ctypes.c_int, _dp, _dp, _dp, _i64, _dp,
+                                   ctypes.c_double, ctypes.c_int, _i64, _dp, _i64, _dp, _i64, _dp]
+        L.orc_simulate.restype = _i64
         _lib = L
     return _lib
 
@@ -180,3 +186,58 @@ def krige(kernel, theta, X, Xs, L, alpha, mu=0.0, include_nugget=False):
     lib().orc_krige(kernel, _p(th), n, m, d, _p(X), _p(Xs), _p(L), max(n, 1), _p(_vec(alpha)),
                     float(mu), 1 if include_nugget else 0, _p(mean), _p(var))
     return mean, var
+
+
+def krige_cov(kernel, theta, X, Xs, L=None, include_nugget=False):
+    """Full m x m prediction covariance (lower triangle filled, upper zero).
+    X = None (or n = 0) gives the prior covariance of the new points."""
+    Xs = np.ascontiguousarray(Xs, dtype=np.float64)
+    m, d = Xs.shape
+    if X is None:
+        X = np.zeros((0, d))
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    n = X.shape[0]
+    Lf = np.asfortranarray(L if L is not None else np.zeros((1, 1)), dtype=np.float64)
+    S = np.zeros((m, m), order="F")
+    th = _th(theta)
+    lib().orc_krige_cov(kernel, _p(th), n, m, d, _p(X), _p(Xs), _p(Lf), max(n, 1),
+                        1 if include_nugget else 0, _p(S), max(m, 1))
+    return np.tril(S)
+
+
+def trmm(L, B):
+    """L B for lower-triangular L (only its lower triangle is read)."""
+    L = np.asfortranarray(L, dtype=np.float64)
+    B = np.array(B, dtype=np.float64, order="F", copy=True)
+    if B.ndim == 1:
+        B = B.reshape(-1, 1, order="F")
+    n, r = B.shape
+    lib().orc_trmm(n, r, _p(L), max(n, 1), _p(B), max(n, 1))
+    return B
+
+
+def simulate(kernel, theta, Xs, eps, X=None, L=None, alpha=None, mu=0.0, include_nugget=False,
+             want_factor=False):
+    """Realizations mean + L_S eps (m x nreal): unconditional when X is None,
+    else conditional on the data whose factor L and alpha = C^{-1}(y - mu)
+    are given.  Returns (out, info) or, with want_factor, (out, info, L_S)."""
+    Xs = np.ascontiguousarray(Xs, dtype=np.float64)
+    m, d = Xs.shape
+    eps = np.asfortranarray(eps, dtype=np.float64)
+    if eps.ndim == 1:
+        eps = eps.reshape(-1, 1, order="F")
+    r = eps.shape[1]
+    if X is None:
+        X = np.zeros((0, d))
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    n = X.shape[0]
+    Lf = np.asfortranarray(L if L is not None else np.zeros((1, 1)), dtype=np.float64)
+    a = _vec(alpha) if alpha is not None else np.zeros(1)
+    out = np.zeros((m, r), order="F")
+    LS = np.zeros((m, m), order="F")
+    th = _th(theta)
+    info = lib().orc_simulate(kernel, _p(th), n, m, d, _p(X), _p(Xs), _p(Lf), max(n, 1), _p(a), float(mu),
+                              1 if include_nugget else 0, r, _p(eps), max(m, 1), _p(out), max(m, 1), _p(LS))
+    if want_factor:
+        return out, int(info), LS
+    return out, int(info)

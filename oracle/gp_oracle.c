@@ -284,3 +284,94 @@ void orc_krige(int kind, const double th[3], i64 n, i64 m, int dim, const double
         free(c);
     }
 }
+
+/* Full prediction covariance at m new points (Section 1: the variance of the
+ * prediction; the full prediction variance matrix among the kriging methods of
+ * Section 2.3.3, built from the cross-product of W = L^{-1} C* with itself,
+ * Section 2.3.2):
+ *   S_ij = sigma^2 k(|s_i - s_j|/rho) (+ tau^2 [i == j] if include_nugget)
+ *          - sum_k W_ki W_kj,        W_:j = L^{-1} c_j (forward substitution).
+ * With n = 0 (no data) S is the prior covariance of the new points.
+ * Lower triangle of S (m x m, ld lds) written; L from orc_loglik.            */
+void orc_krige_cov(int kind, const double th[3], i64 n, i64 m, int dim, const double *X,
+                   const double *Xs, const double *L, i64 ldl, int include_nugget,
+                   double *S, i64 lds)
+{
+    const double s2 = exp(th[0]), rho = exp(th[1]), t2 = exp(th[2]);
+    double *W = (double *)malloc((size_t)(n > 0 ? n : 1) * (size_t)(m > 0 ? m : 1) * sizeof(double));
+#pragma omp parallel for schedule(dynamic, 4)
+    for (i64 j = 0; j < m; ++j) {
+        double *w = W + j * n;
+        for (i64 i = 0; i < n; ++i)
+            w[i] = s2 * corr_k(kind, dist(dim, X + i * dim, Xs + j * dim) / rho);
+        orc_trsv(0, n, L, ldl, w);
+    }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (i64 j = 0; j < m; ++j)
+        for (i64 i = j; i < m; ++i) {
+            double t = s2 * corr_k(kind, dist(dim, Xs + i * dim, Xs + j * dim) / rho);
+            if (include_nugget && i == j) t += t2;
+            for (i64 k = 0; k < n; ++k) t -= W[k + i * n] * W[k + j * n];
+            S[i + j * lds] = t;
+        }
+    free(W);
+}
+
+/* Product with a lower-triangular factor, B (n x r, ld ldb) <- L B: the
+ * multiplication by the Cholesky factor that turns independent standard
+ * normal draws into correlated ones (Section 2.3.2).  Rows are formed from
+ * the bottom up so that each still reads the original entries above it.      */
+void orc_trmm(i64 n, i64 r, const double *L, i64 ldl, double *B, i64 ldb)
+{
+#pragma omp parallel for schedule(static)
+    for (i64 c = 0; c < r; ++c) {
+        double *b = B + c * ldb;
+        for (i64 i = n - 1; i >= 0; --i) {
+            double t = 0.0;
+            for (i64 k = 0; k <= i; ++k) t += L[i + k * ldl] * b[k];
+            b[i] = t;
+        }
+    }
+}
+
+/* Realizations of the latent process at m new points (Section 1: simulate
+ * realizations; unconditional simulation and simulation conditional on the
+ * data among the methods listed there):
+ *   unconditional (n = 0): mean_i = mu, S = sigma^2 k(|s_i - s_j|/rho);
+ *   conditional (n > 0):   mean_i = mu + c_i^T alpha, S = orc_krige_cov;
+ *   (+ tau^2 on the diagonal of S if include_nugget)
+ *   S = L_S L_S^T (orc_potrf: no pivoting, so a singular S fails),
+ *   out_:r = mean + L_S eps_:r   for r = 0 .. nreal - 1.
+ * eps (m x nreal, ld ldeps) are the standard normal draws, supplied by the
+ * caller.  Returns the factorisation's info; on failure out is NaN.
+ * Ls (m x m, ld m, nullable) receives L_S.                                   */
+i64 orc_simulate(int kind, const double th[3], i64 n, i64 m, int dim, const double *X,
+                 const double *Xs, const double *L, i64 ldl, const double *alpha, double mu,
+                 int include_nugget, i64 nreal, const double *eps, i64 ldeps, double *out,
+                 i64 ldo, double *Ls)
+{
+    const double s2 = exp(th[0]), rho = exp(th[1]);
+    double *S = (double *)calloc((size_t)(m > 0 ? m : 1) * (size_t)(m > 0 ? m : 1), sizeof(double));
+    double *mean = (double *)malloc((size_t)(m > 0 ? m : 1) * sizeof(double));
+    orc_krige_cov(kind, th, n, m, dim, X, Xs, L, ldl, include_nugget, S, m);
+    for (i64 i = 0; i < m; ++i) {
+        double t = 0.0;
+        for (i64 k = 0; k < n; ++k)
+            t += s2 * corr_k(kind, dist(dim, X + k * dim, Xs + i * dim) / rho) * alpha[k];
+        mean[i] = mu + t;
+    }
+    i64 info = orc_potrf(m, S, m);
+    for (i64 r = 0; r < nreal; ++r)
+        for (i64 i = 0; i < m; ++i) out[i + r * ldo] = info ? NAN : eps[i + r * ldeps];
+    if (!info) {
+        for (i64 j = 0; j < m; ++j)
+            for (i64 i = 0; i < j; ++i) S[i + j * m] = 0.0;
+        orc_trmm(m, nreal, S, m, out, ldo);
+        for (i64 r = 0; r < nreal; ++r)
+            for (i64 i = 0; i < m; ++i) out[i + r * ldo] += mean[i];
+        if (Ls) memcpy(Ls, S, (size_t)m * (size_t)m * sizeof(double));
+    }
+    free(S);
+    free(mean);
+    return info;
+}

@@ -412,3 +412,131 @@ def test_trsv_both_directions(orc):
     np.testing.assert_allclose(L.T @ a, b, rtol=0, atol=1e-10 * np.abs(b).max())
     W = orc.inv_lower(L)
     np.testing.assert_allclose(W @ L, np.eye(n), atol=1e-9)
+
+
+# --------------------------------------------------------------------------
+# Full prediction covariance, product with the factor, simulation
+# (Section 1: variance of the prediction, unconditional and conditional
+# simulation of realizations)
+# --------------------------------------------------------------------------
+def dense_pred_cov(orc, kernel, t, X, Xs, include_nugget):
+    """C** - C*^T C^{-1} C* with a LAPACK solve (scipy), independent of the
+    oracle's substitution route."""
+    Css = orc.cov(kernel, np.array([t[0], t[1], -np.inf]), Xs)
+    if include_nugget:
+        Css = Css + math.exp(t[2]) * np.eye(Xs.shape[0])
+    if X is None or X.shape[0] == 0:
+        return Css
+    C = orc.cov(kernel, t, X)
+    Cs = orc.cross_cov(kernel, t, X, Xs)
+    return Css - Cs.T @ sla.solve(C, Cs, assume_a="pos")
+
+
+@pytest.mark.parametrize("n,m,kernel,nug", [(1, 1, 0, False), (40, 17, 1, False), (300, 60, 2, True),
+                                            (200, 33, 0, True)])
+def test_krige_cov_against_dense_formula(orc, n, m, kernel, nug):
+    X = synth.uniform_points(n, 40 + n)
+    Xs = synth.uniform_points(m, 50 + m)
+    t = th(1.3, 0.2, 0.05)
+    (_, _, _), L, _ = orc.loglik(kernel, t, X, synth.normals(n, 5), want=True)
+    S = orc.krige_cov(kernel, t, X, Xs, L, include_nugget=nug)
+    ref = dense_pred_cov(orc, kernel, t, X, Xs, nug)
+    np.testing.assert_allclose(S, np.tril(ref), rtol=0, atol=1e-12)
+    assert np.all(np.triu(S, 1) == 0.0)
+
+
+@pytest.mark.parametrize("nug", [False, True])
+def test_krige_cov_compound_symmetry_closed_form(orc, nug):
+    # rho = 1e300: every correlation is exp(-d / rho) = 1 exactly, so C = tau^2 I
+    # + sigma^2 1 1^T and every entry of C** - C*^T C^{-1} C* equals
+    # sigma^2 tau^2 / (tau^2 + n sigma^2)
+    n, m, s2, t2 = 500, 20, 2.0, 0.3
+    X = synth.uniform_points(n, 3)
+    Xs = synth.uniform_points(m, 4)
+    t = th(s2, 1e300, t2)
+    (_, _, _), L, _ = orc.loglik(0, t, X, synth.normals(n, 6), want=True)
+    S = orc.krige_cov(0, t, X, Xs, L, include_nugget=nug)
+    val = s2 * t2 / (t2 + n * s2)
+    ref = np.tril(np.full((m, m), val) + (t2 * np.eye(m) if nug else 0.0))
+    np.testing.assert_allclose(S, ref, rtol=1e-12, atol=1e-15)
+
+
+def test_krige_cov_single_point_closed_form(orc):
+    # n = 1: S_ij = c**_ij - c_i c_j / C_11
+    X = np.array([[0.4, 0.6]])
+    Xs = np.array([[0.1, 0.2], [0.5, 0.5], [0.9, 0.3]])
+    s2, rho, t2 = 1.5, 0.3, 0.2
+    t = th(s2, rho, t2)
+    L = np.array([[math.sqrt(s2 + t2)]])
+    S = orc.krige_cov(2, t, X, Xs, L)
+    k = lambda a, b: s2 * matern_kv(2.5, np.array([np.linalg.norm(a - b) / rho]))[0]  # noqa: E731
+    c = np.array([k(X[0], s) for s in Xs])
+    ref = np.array([[k(a, b) for b in Xs] for a in Xs]) - np.outer(c, c) / (s2 + t2)
+    np.testing.assert_allclose(S, np.tril(ref), rtol=1e-13, atol=1e-15)
+
+
+def test_krige_cov_diagonal_is_krige_variance_and_prior_without_data(orc):
+    X = synth.uniform_points(150, 8)
+    Xs = synth.uniform_points(25, 9)
+    t = th(1.0, 0.1, 0.02)
+    (_, _, _), L, a = orc.loglik(1, t, X, synth.normals(150, 2), want=True)
+    S = orc.krige_cov(1, t, X, Xs, L)
+    _, var = orc.krige(1, t, X, Xs, L, a)
+    np.testing.assert_allclose(np.diag(S), var, rtol=0, atol=1e-13)
+    P = orc.krige_cov(1, t, None, Xs)
+    np.testing.assert_array_equal(P, np.tril(orc.cov(1, th(1.0, 0.1, 0.0), Xs)))
+
+
+def test_krige_cov_interpolation_is_zero_at_data(orc):
+    # no nugget, prediction at data points: nothing is left unknown there
+    g = np.linspace(0.05, 0.95, 6)
+    X = np.array([[a, b] for a in g for b in g])  # 36 separated points
+    t = th(1.0, 0.15, 0.0)
+    (_, _, _), L, _ = orc.loglik(0, t, X, synth.normals(36, 1), want=True)
+    Xs = np.vstack([X[[0, 7, 35]], [[0.5, 0.5]]])
+    S = orc.krige_cov(0, t, X, Xs, L)
+    S = S + np.tril(S, -1).T
+    assert np.abs(S[:3, :]).max() <= 1e-12 and np.abs(S[:, :3]).max() <= 1e-12
+    assert S[3, 3] > 1e-3
+
+
+@pytest.mark.parametrize("n,r", [(1, 1), (9, 4), (70, 13)])
+def test_trmm_integer_exact(orc, n, r):
+    rng = np.random.default_rng(n)
+    L = np.tril(rng.integers(-9, 10, size=(n, n))).astype(np.float64)
+    B = rng.integers(-9, 10, size=(n, r)).astype(np.float64)
+    Lg = L + np.triu(rng.standard_normal((n, n)), 1)  # the strict upper triangle is never read
+    np.testing.assert_array_equal(orc.trmm(Lg, B), L @ B)
+
+
+@pytest.mark.parametrize("conditional", [False, True])
+def test_simulate_unit_draws_reproduce_the_covariance(orc, conditional):
+    # eps = I: the realizations minus the mean are the columns of L_S, and
+    # (out - mean)(out - mean)^T = L_S L_S^T must be the dense covariance
+    n, m = 120, 30
+    X = synth.uniform_points(n, 21) if conditional else None
+    Xs = synth.uniform_points(m, 22)
+    t = th(1.0, 0.2, 0.05)
+    L = a = None
+    mean = np.full(m, 0.7)
+    if conditional:
+        y = synth.normals(n, 3)
+        (_, _, _), L, a = orc.loglik(1, t, X, y, mu=0.7, want=True)
+        mean, _ = orc.krige(1, t, X, Xs, L, a, mu=0.7)
+    out, info = orc.simulate(1, t, Xs, np.eye(m), X=X, L=L, alpha=a, mu=0.7, include_nugget=True)
+    assert info == 0
+    D = out - mean[:, None]
+    assert np.all(np.triu(D, 1) == 0.0)  # lower-triangular factor
+    ref = dense_pred_cov(orc, 1, t, X, Xs, True)
+    np.testing.assert_allclose(D @ D.T, ref, rtol=0, atol=1e-12)
+    z, _ = orc.simulate(1, t, Xs, np.zeros((m, 2)), X=X, L=L, alpha=a, mu=0.7, include_nugget=True)
+    np.testing.assert_allclose(z, np.column_stack([mean, mean]), rtol=1e-14, atol=1e-14)
+
+
+def test_simulate_singular_covariance_fails(orc):
+    # two coincident prediction points and no nugget: the second pivot is
+    # sigma^2 - sigma^2 = 0 exactly, and without pivoting the factor fails there
+    Xs = np.array([[0.2, 0.3], [0.2, 0.3], [0.8, 0.1]])
+    out, info = orc.simulate(0, th(1.0, 0.3, 0.1), Xs, np.ones((3, 2)))
+    assert info == 2
+    assert np.all(np.isnan(out))
