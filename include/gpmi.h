@@ -60,6 +60,10 @@ extern "C" {
 #define GP_ERR_HIP (-1003)          /* a HIP runtime call failed (no device, launch failure, ...) */
 #define GP_ERR_NOT_SUPPORTED (-1004)/* combination of options not implemented */
 #define GP_ERR_BAD_HANDLE (-1005)
+#define GP_ERR_SCRATCH_LIMIT (-1006)/* gp_loglik_noalloc: the problem's workspace exceeds GP_SCRATCH_BYTES */
+
+/* Size of the static per-device workspace of gp_loglik_noalloc (128 MiB). */
+#define GP_SCRATCH_BYTES (128u << 20)
 
 typedef struct gp_handle_s *gp_handle_t;
 
@@ -197,6 +201,24 @@ int gp_loglik(gp_handle_t h, gp_theta_t th, gp_prec_t prec, int64_t n, int32_t d
               const double *X, const double *y, const double *mu, double *C, int64_t ldc,
               double *out3_dev, double *alpha_dev, int32_t *info_dev, double *ir_dev, void *ws,
               size_t ws_bytes);
+
+/* gp_loglik for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): same
+ * arguments, results and kernels as gp_loglik, without the workspace.  The
+ * workspace is a static array of GP_SCRATCH_BYTES bytes that the library's
+ * code object holds on every device it is loaded on until the process ends;
+ * the call itself allocates nothing.  Returns GP_ERR_SCRATCH_LIMIT when
+ * gp_workspace_size(GP_OP_LOGLIK, n, prec) exceeds GP_SCRATCH_BYTES (FP64
+ * with the default panel width: n up to about 19,000) and
+ * GP_ERR_NOT_SUPPORTED when options.panel_cus > 0 (that option creates
+ * streams on first use).  The device current at the call must be the
+ * handle's.  Every call on one device shares the array: calls that overlap
+ * on one device (on different streams or handles) race and must be
+ * serialised by the caller.  Nothing in the array needs to be cleared
+ * between calls: every buffer in it is initialised by the call's own kernels. */
+int gp_loglik_noalloc(gp_handle_t h, gp_theta_t th, gp_prec_t prec, int64_t n, int32_t dim,
+                      const double *X, const double *y, const double *mu, double *C, int64_t ldc,
+                      double *out3_dev, double *alpha_dev, int32_t *info_dev, double *ir_dev);
 
 /* As gp_loglik, plus grad3_dev [dev, 3] = d loglik / d (log sigma^2, log rho,
  * log tau^2) by the adjoint 1/2 sum_ij (alpha_i alpha_j - (C^{-1})_ij) dC_ij /

@@ -31,7 +31,7 @@ PRECS = {"fp64": GP_FP64, "fp32": GP_FP32_TRAIL, "bf16": GP_BF16_TRAIL}
 EXPORTED = ["gp_create", "gp_destroy", "gp_set_stream", "gp_set_options", "gp_get_options",
             "gp_strerror", "gp_profile", "gp_profile_read", "gp_workspace_size", "gp_cov_build", "gp_cross_cov_build", "gp_potrf",
             "gp_trsv", "gp_trsm", "gp_loglik", "gp_loglik_grad", "gp_krige", "gp_loglik_batched",
-            "gp_morton_order", "gp_tune_potrf", "gp_tune_batched"]
+            "gp_morton_order", "gp_tune_potrf", "gp_tune_batched", "gp_loglik_noalloc"]
 
 
 class Theta(ctypes.Structure):
@@ -93,6 +93,7 @@ def lib():
         L.gp_trsv.argtypes = [vp, ctypes.c_int, i64, vp, i64, vp, vp, sz]
         L.gp_trsm.argtypes = [vp, ctypes.c_int, i64, i64, vp, i64, vp, i64, vp, sz]
         L.gp_loglik.argtypes = [vp, Theta, ctypes.c_int, i64, i32, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, sz]
+        L.gp_loglik_noalloc.argtypes = [vp, Theta, ctypes.c_int, i64, i32, vp, vp, vp, vp, i64, vp, vp, vp, vp]
         L.gp_loglik_grad.argtypes = [vp, Theta, ctypes.c_int, i64, i32, vp, vp, vp, vp, i64, vp, vp, vp, vp,
                                      vp, vp, sz]
         L.gp_krige.argtypes = [vp, Theta, i64, i64, i32, vp, vp, vp, i64, vp, dbl, vp, vp, i32, vp, sz]
@@ -342,6 +343,25 @@ def loglik(X, y, th, prec=GP_FP64, mu=None, S=None, want_alpha=False, ws=None):
     ws = ws if ws is not None else h.workspace(GP_OP_LOGLIK, n, 0, prec)
     check(lib().gp_loglik(h.ptr, th, prec, n, d, _ptr(X), _ptr(y), _ptr(mu_t), _ptr(S), S.shape[1],
                           _ptr(out3), _ptr(alpha), _ptr(info), _ptr(ir), _ptr(ws), ws.numel()))
+    return dict(out3=out3, info=info, S=S, alpha=alpha, ir=ir)
+
+
+def loglik_noalloc(X, y, th, prec=GP_FP64, mu=None, S=None, want_alpha=False):
+    """gp_loglik_noalloc: as loglik(), with the library's static workspace
+    instead of a caller-allocated one (the outputs are still allocated here
+    unless S is given)."""
+    torch = _torch()
+    X, y = _f64(X), _f64(y)
+    n, d = X.shape
+    h = handle()
+    S = S if S is not None else colmajor_storage(n)
+    out3 = torch.empty(3, dtype=torch.float64, device="cuda")
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ir = torch.zeros(3, dtype=torch.float64, device="cuda")
+    alpha = torch.empty(n, dtype=torch.float64, device="cuda") if want_alpha else None
+    mu_t = None if mu is None else _f64(torch.as_tensor(mu, dtype=torch.float64, device="cuda").expand(n).contiguous())
+    check(lib().gp_loglik_noalloc(h.ptr, th, prec, n, d, _ptr(X), _ptr(y), _ptr(mu_t), _ptr(S), S.shape[1],
+                                  _ptr(out3), _ptr(alpha), _ptr(info), _ptr(ir)))
     return dict(out3=out3, info=info, S=S, alpha=alpha, ir=ir)
 
 

@@ -14,6 +14,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "internal.h"
@@ -737,6 +738,7 @@ const char *gp_strerror(int code) {
     if (code == GP_ERR_HIP) return "HIP runtime error";
     if (code == GP_ERR_NOT_SUPPORTED) return "option combination not supported";
     if (code == GP_ERR_BAD_HANDLE) return "invalid handle";
+    if (code == GP_ERR_SCRATCH_LIMIT) return "problem needs more than the GP_SCRATCH_BYTES static workspace";
     if (code < 0 && code > -100) return "invalid argument (index = -code)";
     return "unknown status";
 }
@@ -753,6 +755,37 @@ static void default_options(gp_options_t *o) {
     o->fused_panel = 1;
     o->batch_grid = 0;
 }
+
+}  // extern "C"
+
+// ---- static workspace of gp_loglik_noalloc ------------------------------------
+// One array per device, part of this code object: it is allocated when the
+// code object is loaded on a device and held until the process ends.  In host
+// code `scratch` names a host-side shadow, never the device memory: kernels
+// get the address hipGetSymbolAddress returns for the current device, looked
+// up once per device at gp_create and kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[GP_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Address of `scratch` on `dev` (the current device), looked up on the first
+// call for that device; null if the lookup failed.
+void *device_scratch(int dev) {
+    if (dev < 0 || dev >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch_ptr[dev] = p;
+        else (void)hipGetLastError();
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" {
 
 int gp_create(gp_handle_t *h, void *stream) {
     if (!h) return -1;
@@ -782,6 +815,9 @@ int gp_create(gp_handle_t *h, void *stream) {
         delete p;
         return GP_ERR_HIP;
     }
+    // the static workspace's address on this device (null if the lookup
+    // failed: gp_loglik_noalloc then returns GP_ERR_HIP)
+    p->scratch = device_scratch(p->device);
     *h = p;
     return GP_OK;
 }
@@ -1054,6 +1090,31 @@ int gp_loglik(gp_handle_t h, gp_theta_t th, gp_prec_t prec, int64_t n, int32_t d
     if (ws_bytes < lay.total) return GP_ERR_WS_TOO_SMALL;
     return loglik_core(h, GP_OP_LOGLIK, th, prec, n, dim, X, y, mu, C, ldc, out3_dev, nullptr, alpha_dev,
                        info_dev, ir_dev, ws);
+}
+
+int gp_loglik_noalloc(gp_handle_t h, gp_theta_t th, gp_prec_t prec, int64_t n, int32_t dim, const double *X,
+                      const double *y, const double *mu, double *C, int64_t ldc, double *out3_dev,
+                      double *alpha_dev, int32_t *info_dev, double *ir_dev) {
+    if (!ok_handle(h)) return -1;
+    if (int e = check_theta(th)) return e == 1 ? -2 : GP_ERR_NONFINITE;
+    if ((int)prec < GP_FP64 || (int)prec > GP_BF16_TRAIL) return -3;
+    if (n < 0) return -4;
+    if (dim < 1 || dim > 16) return -5;
+    if (n > 0 && !X) return -6;
+    if (n > 0 && !y) return -7;
+    if (n > 0 && !C) return -9;
+    if (ldc < (n > 1 ? n : 1)) return -10;
+    if (!out3_dev) return -11;
+    if (!info_dev) return -13;
+    // panel_cus > 0 would create CU-masked streams on first use
+    if (h->opt.panel_cus > 0) return GP_ERR_NOT_SUPPORTED;
+    const Layout lay = layout(h, GP_OP_LOGLIK, n, 0, prec);
+    if (lay.total > (size_t)GP_SCRATCH_BYTES) return GP_ERR_SCRATCH_LIMIT;
+    if (!h->scratch) return GP_ERR_HIP;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != h->device) return GP_ERR_HIP;
+    return loglik_core(h, GP_OP_LOGLIK, th, prec, n, dim, X, y, mu, C, ldc, out3_dev, nullptr, alpha_dev,
+                       info_dev, ir_dev, h->scratch);
 }
 
 int gp_loglik_grad(gp_handle_t h, gp_theta_t th, gp_prec_t prec, int64_t n, int32_t dim, const double *X,

@@ -48,6 +48,7 @@ struct gp_handle_s {
     int64_t prof_launches = 0;
     int num_cu = 256;                 // compute units of the device
     void *batch_staging = nullptr;    // host staging of the batched task table
+    void *scratch = nullptr;          // this device's static workspace (gp_loglik_noalloc), or null
     int magic = 0x67706d69;
 };
 
