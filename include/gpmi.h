@@ -79,7 +79,8 @@ typedef enum { GP_NOTRANS = 0, GP_TRANS = 1 } gp_trans_t;
 
 typedef enum {
     GP_OP_POTRF = 0, GP_OP_TRSV = 1, GP_OP_TRSM = 2, GP_OP_LOGLIK = 3,
-    GP_OP_LOGLIK_GRAD = 4, GP_OP_KRIGE = 5, GP_OP_BATCHED = 6, GP_OP_MORTON = 7
+    GP_OP_LOGLIK_GRAD = 4, GP_OP_KRIGE = 5, GP_OP_BATCHED = 6, GP_OP_MORTON = 7,
+    GP_OP_KRIGE_COV = 8, GP_OP_TRMM = 9, GP_OP_SIMULATE = 10
 } gp_op_t;
 
 typedef struct {
@@ -133,7 +134,8 @@ int gp_profile(gp_handle_t h, int enable);
 int gp_profile_read(gp_handle_t h, double *out3);
 
 /* Bytes of workspace the call `op` needs for problem size n (and m new points
- * for GP_OP_KRIGE / right-hand sides for GP_OP_TRSM; for GP_OP_BATCHED, n is
+ * for GP_OP_KRIGE, GP_OP_KRIGE_COV and GP_OP_SIMULATE (n = 0: no data) /
+ * right-hand sides for GP_OP_TRSM and GP_OP_TRMM; for GP_OP_BATCHED, n is
  * the largest problem and m the number of problems).  The factorising calls
  * size a panel buffer by the handle's panel width: query after gp_set_options. */
 int gp_workspace_size(gp_handle_t h, gp_op_t op, int64_t n, int64_t m, gp_prec_t prec,
@@ -244,6 +246,51 @@ int gp_krige(gp_handle_t h, gp_theta_t th, int64_t n, int64_t m, int32_t dim, co
              const double *Xs, const double *L, int64_t ldl, const double *alpha, double mu,
              double *mean_dev, double *var_dev, int32_t include_nugget, void *ws,
              size_t ws_bytes);
+
+/* Full prediction covariance at the m new points Xs [dev, m x dim] (Section 1:
+ * the variance of the prediction; the full prediction variance matrix of the
+ * kriging methods in Section 2.3.3, formed as the cross-product of
+ * W = L^{-1} C* with itself, Section 2.3.2):
+ *   S_ij = sigma^2 k(|s_i - s_j| / rho) (+ tau^2 [i == j] if include_nugget)
+ *          - (W^T W)_ij,
+ * written to the lower triangle of S [dev, m x m, lds >= m] (the strict upper
+ * triangle is untouched).  L [dev] is the factor of the n data points X as
+ * left by gp_loglik (reorder off).  With n = 0, S is the prior covariance of
+ * the new points (X and L are not read).  W^T is built and solved from the
+ * right in the workspace as in gp_krige; S -= W^T W is one SYRK on the matrix
+ * cores.  Its diagonal equals gp_krige's variance. */
+int gp_krige_cov(gp_handle_t h, gp_theta_t th, int64_t n, int64_t m, int32_t dim, const double *X,
+                 const double *Xs, const double *L, int64_t ldl, int32_t include_nugget, double *S,
+                 int64_t lds, void *ws, size_t ws_bytes);
+
+/* Product with a lower-triangular matrix (the multiplication by the Cholesky
+ * factor of Section 2.3.2 that turns independent normal draws into correlated
+ * ones): out [dev, n x nrhs, ldo >= n] = L B, L [dev, n x n, ldl >= n] lower
+ * (its strict upper triangle is not read), B [dev, n x nrhs, ldb >= n]; out
+ * must not overlap B.  Workspace: gp_workspace_size(GP_OP_TRMM, n, nrhs). */
+int gp_trmm(gp_handle_t h, int64_t n, int64_t nrhs, const double *L, int64_t ldl, const double *B,
+            int64_t ldb, double *out, int64_t ldo, void *ws, size_t ws_bytes);
+
+/* Realizations of the latent process at the m new points Xs (Section 1:
+ * simulation of realizations, unconditional and conditional on the data;
+ * the simulation method of Section 2.3.3):
+ *   n = 0  (unconditional): mean_i = mu, S = prior covariance of the points;
+ *   n > 0  (conditional on the data whose factor L and alpha = C^{-1}(y - mu)
+ *           come from gp_loglik, reorder off): mean_i = mu + c_i^T alpha and
+ *           S = the prediction covariance of gp_krige_cov;
+ *   (+ tau^2 on the diagonal of S if include_nugget), then S = L_S L_S^T and
+ *   out[:, r] = mean + L_S eps[:, r],   r = 0 .. nreal - 1.
+ * eps [dev, m x nreal, ldeps >= m] holds the caller's standard normal draws;
+ * out [dev, m x nreal, ldo >= m].  S [dev, m x m, lds >= m] is caller-owned
+ * storage: on return it holds L_S with zeros above the diagonal.  The factor
+ * has no pivoting (Section 5): when S is not numerically positive definite
+ * (e.g. coincident new points without a nugget) *info_dev gets the failing
+ * 1-based column and out is NaN.  Workspace: gp_workspace_size(GP_OP_SIMULATE,
+ * n, m); the draws are multiplied 512 realizations at a time. */
+int gp_simulate(gp_handle_t h, gp_theta_t th, int64_t n, int64_t m, int32_t dim, const double *X,
+                const double *Xs, const double *L, int64_t ldl, const double *alpha, double mu,
+                int32_t include_nugget, int64_t nreal, const double *eps, int64_t ldeps, double *out,
+                int64_t ldo, double *S, int64_t lds, int32_t *info_dev, void *ws, size_t ws_bytes);
 
 /* ---- many independent likelihoods in one call ------------------------------
  * Problem b has n_host[b] points starting at point x_off_host[b] of X [dev,

@@ -23,7 +23,7 @@ GP_EXP, GP_MATERN32, GP_MATERN52 = 0, 1, 2
 GP_FP64, GP_FP32_TRAIL, GP_BF16_TRAIL = 0, 1, 2
 GP_NOTRANS, GP_TRANS = 0, 1
 (GP_OP_POTRF, GP_OP_TRSV, GP_OP_TRSM, GP_OP_LOGLIK, GP_OP_LOGLIK_GRAD, GP_OP_KRIGE,
- GP_OP_BATCHED, GP_OP_MORTON) = range(8)
+ GP_OP_BATCHED, GP_OP_MORTON, GP_OP_KRIGE_COV, GP_OP_TRMM, GP_OP_SIMULATE) = range(11)
 
 KERNELS = {"exp": GP_EXP, "exponential": GP_EXP, "matern32": GP_MATERN32, "matern52": GP_MATERN52}
 PRECS = {"fp64": GP_FP64, "fp32": GP_FP32_TRAIL, "bf16": GP_BF16_TRAIL}
@@ -31,7 +31,8 @@ PRECS = {"fp64": GP_FP64, "fp32": GP_FP32_TRAIL, "bf16": GP_BF16_TRAIL}
 EXPORTED = ["gp_create", "gp_destroy", "gp_set_stream", "gp_set_options", "gp_get_options",
             "gp_strerror", "gp_profile", "gp_profile_read", "gp_workspace_size", "gp_cov_build", "gp_cross_cov_build", "gp_potrf",
             "gp_trsv", "gp_trsm", "gp_loglik", "gp_loglik_grad", "gp_krige", "gp_loglik_batched",
-            "gp_morton_order", "gp_tune_potrf", "gp_tune_batched", "gp_loglik_noalloc"]
+            "gp_morton_order", "gp_tune_potrf", "gp_tune_batched", "gp_loglik_noalloc", "gp_krige_cov",
+            "gp_trmm", "gp_simulate"]
 
 
 class Theta(ctypes.Structure):
@@ -97,6 +98,10 @@ def lib():
         L.gp_loglik_grad.argtypes = [vp, Theta, ctypes.c_int, i64, i32, vp, vp, vp, vp, i64, vp, vp, vp, vp,
                                      vp, vp, sz]
         L.gp_krige.argtypes = [vp, Theta, i64, i64, i32, vp, vp, vp, i64, vp, dbl, vp, vp, i32, vp, sz]
+        L.gp_krige_cov.argtypes = [vp, Theta, i64, i64, i32, vp, vp, vp, i64, i32, vp, i64, vp, sz]
+        L.gp_trmm.argtypes = [vp, i64, i64, vp, i64, vp, i64, vp, i64, vp, sz]
+        L.gp_simulate.argtypes = [vp, Theta, i64, i64, i32, vp, vp, vp, i64, vp, dbl, i32, i64, vp, i64, vp, i64,
+                                  vp, i64, vp, vp, sz]
         L.gp_loglik_batched.argtypes = [vp, i32, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, sz]
         L.gp_morton_order.argtypes = [vp, i64, i32, vp, vp, vp, sz]
         L.gp_tune_batched.argtypes = [vp, i32, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, ctypes.POINTER(i32), i32,
@@ -396,6 +401,65 @@ def krige(X, Xs, S, alpha, th, mu=0.0, include_nugget=False, ws=None):
     check(lib().gp_krige(h.ptr, th, n, m, d, _ptr(X), _ptr(Xs), _ptr(S), S.shape[1], _ptr(alpha),
                          float(mu), _ptr(mean), _ptr(var), 1 if include_nugget else 0, _ptr(ws), ws.numel()))
     return mean, var
+
+
+def krige_cov(X, Xs, S_data, th, include_nugget=False, out=None, ws=None):
+    """gp_krige_cov: the m x m prediction covariance of the new points Xs given
+    the data X with factor storage S_data (X = None: the prior covariance).
+    Returns column-major storage P (shape (m, m), element (i, j) at P[j, i]),
+    lower triangle filled."""
+    torch = _torch()
+    Xs = _f64(Xs)
+    m, d = Xs.shape
+    n = 0 if X is None else X.shape[0]
+    X = None if X is None else _f64(X)
+    h = handle()
+    P = out if out is not None else colmajor_storage(m)
+    ws = ws if ws is not None else h.workspace(GP_OP_KRIGE_COV, n, m)
+    ldl = S_data.shape[1] if S_data is not None else 1
+    check(lib().gp_krige_cov(h.ptr, th, n, m, d, _ptr(X), _ptr(Xs), _ptr(S_data), ldl,
+                             1 if include_nugget else 0, _ptr(P), P.shape[1], _ptr(ws), ws.numel()))
+    return P
+
+
+def trmm(S, E, ws=None):
+    """gp_trmm: L E for the lower factor in storage S (shape (n, ld)) and E in
+    column-major storage of shape (nrhs, n); returns storage of shape (nrhs, n)."""
+    torch = _torch()
+    E = _f64(E)
+    nrhs, n = E.shape
+    h = handle()
+    out = torch.empty((nrhs, n), dtype=torch.float64, device="cuda")
+    ws = ws if ws is not None else h.workspace(GP_OP_TRMM, n, nrhs)
+    check(lib().gp_trmm(h.ptr, n, nrhs, _ptr(S), S.shape[1], _ptr(E), max(n, 1), _ptr(out), max(n, 1),
+                        _ptr(ws), ws.numel()))
+    return out
+
+
+def simulate(Xs, th, eps, X=None, S_data=None, alpha=None, mu=0.0, include_nugget=False, S=None, ws=None):
+    """gp_simulate: realizations mean + L_S eps at the new points Xs,
+    unconditional (X None) or conditional on the data (X, its factor storage
+    S_data and alpha from loglik).  eps: column-major storage of shape
+    (nreal, m) (realization r is eps[r]).  Returns dict(out (nreal, m), info,
+    S (the factor L_S, storage (m, m)))."""
+    torch = _torch()
+    Xs = _f64(Xs)
+    eps = _f64(eps)
+    m, d = Xs.shape
+    nreal = eps.shape[0]
+    assert eps.shape[1] == m
+    n = 0 if X is None else X.shape[0]
+    X = None if X is None else _f64(X)
+    h = handle()
+    S = S if S is not None else colmajor_storage(m)
+    out = torch.empty((nreal, m), dtype=torch.float64, device="cuda")
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ws = ws if ws is not None else h.workspace(GP_OP_SIMULATE, n, m)
+    ldl = S_data.shape[1] if S_data is not None else 1
+    check(lib().gp_simulate(h.ptr, th, n, m, d, _ptr(X), _ptr(Xs), _ptr(S_data), ldl, _ptr(alpha), float(mu),
+                            1 if include_nugget else 0, nreal, _ptr(eps), max(m, 1), _ptr(out), max(m, 1),
+                            _ptr(S), S.shape[1], _ptr(info), _ptr(ws), ws.numel()))
+    return dict(out=out, info=info, S=S)
 
 
 def loglik_batched(X, y, thetas, sizes, x_off=None, C_pool=None, ws=None):

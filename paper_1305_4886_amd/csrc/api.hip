@@ -54,6 +54,8 @@ struct Layout {
     size_t dinv = 0, sync = 0, z = 0, vec2 = 0, vec3 = 0, vec4 = 0, vec5 = 0, part = 0, big1 = 0, big2 = 0,
            big3 = 0, irst = 0, perm = 0, keys = 0, box = 0, xp = 0, yp = 0, mup = 0, pbuf = 0, vinv = 0,
            vtmp = 0, qbuf = 0, big4 = 0, pflags = 0, kw = 0, total = 0;
+    // second factorisation (gp_simulate: the covariance of the new points)
+    size_t dinv2 = 0, pflags2 = 0, pbuf2 = 0, vinv2 = 0, vtmp2 = 0, et = 0, meanv = 0;
 };
 
 // Buffers of the panel steps of the factorisation (null when n <= NB).
@@ -106,6 +108,10 @@ size_t trtri_tmp_elems(int64_t n) {
 }
 
 constexpr int GRAD_PARTS = 2048;
+
+// Realizations per product of the simulation (the transposed normals of one
+// chunk, SIM_CHUNK x m doubles, live in the workspace).
+constexpr int64_t SIM_CHUNK = 512;
 
 // Column band of the kriging solve C*^T L^{-T}: each band is solved by one
 // product with the inverse of its diagonal block, then the columns right of
@@ -180,6 +186,33 @@ Layout layout(gp_handle_t h, gp_op_t op, int64_t n, int64_t m, gp_prec_t prec) {
         L.keys = take(sizeof(uint64_t) * (size_t)next_pow2(n > 0 ? n : 1));
         L.box = take(sizeof(double) * 4);
         break;
+    case GP_OP_TRMM:  // m = right-hand sides: their transpose
+        L.et = take(sizeof(double) * (size_t)(n > 0 ? n : 1) * (size_t)(m > 0 ? m : 1));
+        break;
+    case GP_OP_SIMULATE: {
+        // n data points (0: unconditional), m new points
+        const size_t mm = (size_t)(m > 0 ? m : 1);
+        if (n > 0) {
+            L.dinv = take(sizeof(double) * DB * DB * (size_t)nb);
+            L.big1 = take(sizeof(double) * (size_t)n * mm);
+            L.part = take(sizeof(double) * KRIGE_BAND * mm);
+            L.pflags = take(panel_flags_bytes());
+            if (n >= KRIGE_BAND) L.kw = take(sizeof(double) * (size_t)(n / KRIGE_BAND) * KRIGE_BAND * KRIGE_BAND);
+            L.big2 = take(sizeof(double) * 2 * mm * (size_t)rowreduce_chunks(n));
+        }
+        L.dinv2 = take(sizeof(double) * DB * DB * (size_t)nblocks(m));
+        L.pflags2 = take(panel_flags_bytes());
+        const int64_t NB2 = panel_width(h, GP_FP64);
+        if (m > NB2) {
+            L.pbuf2 = take(sizeof(double) * (size_t)(m - NB2) * (size_t)NB2);
+            L.vinv2 = take(sizeof(double) * (size_t)NB2 * (size_t)NB2);
+            L.vtmp2 = take(sizeof(double) * trtri_tmp_elems(NB2));
+        }
+        L.et = take(sizeof(double) * SIM_CHUNK * mm);
+        L.meanv = take(sizeof(double) * mm);
+        break;
+    }
+    case GP_OP_KRIGE_COV:
     case GP_OP_KRIGE:
         L.dinv = take(sizeof(double) * DB * DB * (size_t)nb);
         L.big1 = take(sizeof(double) * (size_t)(n > 0 ? n : 1) * (size_t)(m > 0 ? m : 1));  // C*^T, m x n
@@ -726,6 +759,49 @@ int loglik_core(gp_handle_t h, gp_op_t op, gp_theta_t th, gp_prec_t prec, int64_
     return GP_OK;
 }
 
+// ---- products with the lower factor and the prediction covariance -----------
+// out = beta out + L E (L m x m lower, only its lower triangle read; E m x r,
+// ld lde): the blocks strictly below the 128-row diagonal blocks on the
+// matrix cores (E transposed into Et, r x m, so both operands stream rows),
+// then the diagonal blocks by a small kernel that reads only their lower part.
+int trmm_lower(hipStream_t s, int64_t m, int64_t r, const double *L, int64_t ldl, const double *E, int64_t lde,
+               double *Et, double *out, int64_t ldo, double beta, const int32_t *info) {
+    if (m <= 0 || r <= 0) return GP_OK;
+    HIPCHK(launch_transpose_copy(s, m, r, E, lde, 0, Et, r, 0, 1));
+    GemmDesc d{};
+    d.A = L; d.lda = ldl; d.B = Et; d.ldb = r; d.C = out; d.ldc = ldo;
+    d.M = m; d.N = r; d.K = m; d.alpha = 1.0; d.beta = beta;
+    d.ta = 0; d.tb = 1; d.khi_i = 2; d.batch = 1; d.info = info;
+    HIPCHK(launch_gemm_nt_dma(s, d));
+    HIPCHK(launch_trmm_diag(s, m, r, L, ldl, E, lde, out, ldo, info));
+    return GP_OK;
+}
+
+// The m new points against the n data points: Y = (L^{-1} C*)^T (m x n, ld m)
+// and, if mean is non-null, mean_j = mu + c_j^T alpha (before the solve).
+int cross_solve(hipStream_t s, const CovParams &cp, int64_t n, int64_t m, const double *X, const double *Xs,
+                const double *L, int64_t ldl, const double *alpha, double mu, double *mean, void *ws,
+                const Layout &lay) {
+    double *Y = at<double>(ws, lay.big1);
+    double *dinv = at<double>(ws, lay.dinv);
+    HIPCHK(launch_diag_inv(s, L, ldl, n, dinv));
+    HIPCHK(launch_cross_cov(s, cp, m, n, Xs, X, Y, m));  // Y(j, i) = sigma^2 k(|s_j - x_i| / rho)
+    if (mean) HIPCHK(launch_rowreduce(s, 0, m, n, Y, m, alpha, mu, at<double>(ws, lay.big2), mean));
+    return trsm_right_lt(s, n, m, L, ldl, Y, dinv, at<double>(ws, lay.part), lay.kw ? at<double>(ws, lay.kw) : nullptr,
+                         at<int>(ws, lay.pflags), nullptr);
+}
+
+// S (lower, m x m) = C** (+ tau^2 I) - Y Y^T: the prior covariance of the new
+// points less the part the data explain (nothing subtracted when n = 0).
+int pred_cov(hipStream_t s, const CovParams &cp, int include_nugget, int64_t n, int64_t m, const double *Xs,
+             const double *Y, double *S, int64_t lds) {
+    CovParams pp = cp;
+    if (!include_nugget) pp.t2 = 0.0;
+    HIPCHK(launch_cov_lower(s, pp, m, Xs, S, lds, nullptr));
+    if (n > 0) HIPCHK(launch_syrk_dma(s, Y, m, S, lds, m, n, -1.0, 1.0, 0, nullptr));
+    return GP_OK;
+}
+
 }  // namespace
 
 // ============================================================================
@@ -903,7 +979,7 @@ int gp_get_options(gp_handle_t h, gp_options_t *opt) {
 
 int gp_workspace_size(gp_handle_t h, gp_op_t op, int64_t n, int64_t m, gp_prec_t prec, size_t *bytes) {
     if (!ok_handle(h)) return -1;
-    if ((int)op < GP_OP_POTRF || (int)op > GP_OP_MORTON) return -2;
+    if ((int)op < GP_OP_POTRF || (int)op > GP_OP_SIMULATE) return -2;
     if (n < 0) return -3;
     if (m < 0) return -4;
     if ((int)prec < GP_FP64 || (int)prec > GP_BF16_TRAIL) return -5;
@@ -1178,6 +1254,109 @@ int gp_krige(gp_handle_t h, gp_theta_t th, int64_t n, int64_t m, int32_t dim, co
                            at<int>(ws, lay.pflags), nullptr);  // rows of L^{-1} C*, transposed
     if (rc) return rc;
     HIPCHK(launch_rowreduce(s, 1, m, n, Y, m, nullptr, base_var, partials, var_dev));
+    return GP_OK;
+}
+
+int gp_krige_cov(gp_handle_t h, gp_theta_t th, int64_t n, int64_t m, int32_t dim, const double *X,
+                 const double *Xs, const double *L, int64_t ldl, int32_t include_nugget, double *S, int64_t lds,
+                 void *ws, size_t ws_bytes) {
+    if (!ok_handle(h)) return -1;
+    if (int e = check_theta(th)) return e == 1 ? -2 : GP_ERR_NONFINITE;
+    if (n < 0) return -3;
+    if (m < 0) return -4;
+    if (dim < 1 || dim > 16) return -5;
+    if (n > 0 && !X) return -6;
+    if (m > 0 && !Xs) return -7;
+    if (n > 0 && !L) return -8;
+    if (ldl < (n > 1 ? n : 1)) return -9;
+    if (include_nugget != 0 && include_nugget != 1) return -10;
+    if (m > 0 && !S) return -11;
+    if (lds < (m > 1 ? m : 1)) return -12;
+    Layout lay = layout(h, GP_OP_KRIGE_COV, n, m, GP_FP64);
+    if (!ws) return -13;
+    if (ws_bytes < lay.total) return GP_ERR_WS_TOO_SMALL;
+    if (m == 0) return GP_OK;
+    hipStream_t s = h->stream;
+    const CovParams cp = cov_params(th, dim);
+    if (n > 0) {
+        int rc = cross_solve(s, cp, n, m, X, Xs, L, ldl, nullptr, 0.0, nullptr, ws, lay);
+        if (rc) return rc;
+    }
+    return pred_cov(s, cp, include_nugget, n, m, Xs, n > 0 ? at<double>(ws, lay.big1) : nullptr, S, lds);
+}
+
+int gp_trmm(gp_handle_t h, int64_t n, int64_t nrhs, const double *L, int64_t ldl, const double *B, int64_t ldb,
+            double *out, int64_t ldo, void *ws, size_t ws_bytes) {
+    if (!ok_handle(h)) return -1;
+    if (n < 0) return -2;
+    if (nrhs < 0) return -3;
+    if (n > 0 && !L) return -4;
+    if (ldl < (n > 1 ? n : 1)) return -5;
+    if (n > 0 && nrhs > 0 && !B) return -6;
+    if (ldb < (n > 1 ? n : 1)) return -7;
+    if (n > 0 && nrhs > 0 && !out) return -8;
+    if (ldo < (n > 1 ? n : 1)) return -9;
+    Layout lay = layout(h, GP_OP_TRMM, n, nrhs, GP_FP64);
+    if (!ws) return -10;
+    if (ws_bytes < lay.total) return GP_ERR_WS_TOO_SMALL;
+    return trmm_lower(h->stream, n, nrhs, L, ldl, B, ldb, at<double>(ws, lay.et), out, ldo, 0.0, nullptr);
+}
+
+int gp_simulate(gp_handle_t h, gp_theta_t th, int64_t n, int64_t m, int32_t dim, const double *X, const double *Xs,
+                const double *L, int64_t ldl, const double *alpha, double mu, int32_t include_nugget, int64_t nreal,
+                const double *eps, int64_t ldeps, double *out, int64_t ldo, double *S, int64_t lds, int32_t *info_dev,
+                void *ws, size_t ws_bytes) {
+    if (!ok_handle(h)) return -1;
+    if (int e = check_theta(th)) return e == 1 ? -2 : GP_ERR_NONFINITE;
+    if (n < 0) return -3;
+    if (m < 0) return -4;
+    if (dim < 1 || dim > 16) return -5;
+    if (n > 0 && !X) return -6;
+    if (m > 0 && !Xs) return -7;
+    if (n > 0 && !L) return -8;
+    if (ldl < (n > 1 ? n : 1)) return -9;
+    if (n > 0 && !alpha) return -10;
+    if (!isfinite(mu)) return GP_ERR_NONFINITE;
+    if (include_nugget != 0 && include_nugget != 1) return -12;
+    if (nreal < 0) return -13;
+    if (m > 0 && nreal > 0 && !eps) return -14;
+    if (ldeps < (m > 1 ? m : 1)) return -15;
+    if (m > 0 && nreal > 0 && !out) return -16;
+    if (ldo < (m > 1 ? m : 1)) return -17;
+    if (m > 0 && !S) return -18;
+    if (lds < (m > 1 ? m : 1)) return -19;
+    if (!info_dev) return -20;
+    Layout lay = layout(h, GP_OP_SIMULATE, n, m, GP_FP64);
+    if (!ws) return -21;
+    if (ws_bytes < lay.total) return GP_ERR_WS_TOO_SMALL;
+    hipStream_t s = h->stream;
+    if (m == 0) return launch_set_info(s, info_dev) == hipSuccess ? GP_OK : GP_ERR_HIP;
+    const CovParams cp = cov_params(th, dim);
+    double *mean = n > 0 ? at<double>(ws, lay.meanv) : nullptr;
+    if (n > 0) {
+        int rc = cross_solve(s, cp, n, m, X, Xs, L, ldl, alpha, mu, mean, ws, lay);
+        if (rc) return rc;
+    }
+    int rc = pred_cov(s, cp, include_nugget, n, m, Xs, n > 0 ? at<double>(ws, lay.big1) : nullptr, S, lds);
+    if (rc) return rc;
+    PanelBufs pb;
+    if (lay.vinv2) {
+        pb.pbuf = at<double>(ws, lay.pbuf2);
+        pb.vinv = at<double>(ws, lay.vinv2);
+        pb.vtmp = at<double>(ws, lay.vtmp2);
+    }
+    pb.pflags = at<int>(ws, lay.pflags2);
+    rc = potrf_impl(h, GP_FP64, m, S, lds, info_dev, at<double>(ws, lay.dinv2), pb);
+    if (rc) return rc;
+    HIPCHK(launch_zero_upper(s, m, S, lds));
+    double *Et = at<double>(ws, lay.et);
+    for (int64_t r0 = 0; r0 < nreal; r0 += SIM_CHUNK) {
+        const int64_t rc2 = nreal - r0 < SIM_CHUNK ? nreal - r0 : SIM_CHUNK;
+        HIPCHK(launch_bcast_rows(s, m, rc2, mean, mu, out + r0 * ldo, ldo));
+        rc = trmm_lower(s, m, rc2, S, lds, eps + r0 * ldeps, ldeps, Et, out + r0 * ldo, ldo, 1.0, info_dev);
+        if (rc) return rc;
+    }
+    HIPCHK(launch_fail_fill(s, m, nreal, out, ldo, info_dev));
     return GP_OK;
 }
 

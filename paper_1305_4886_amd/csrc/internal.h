@@ -343,7 +343,8 @@ struct GemmDesc {
     int lower;     // tiles and elements with i < j are skipped (C's (0,0) lies on the diagonal)
     int klo_i;     // skip k < tile row start (op(A) upper-zero structure)
     int klo_j;     // skip k < tile col start (op(B) lower-zero structure)
-    int khi_i;     // skip k >= tile row end (op(A) lower-triangular)
+    int khi_i;     // 1: skip k >= tile row end (op(A) lower-triangular); 2: skip k >= tile row
+                   // start (only the blocks of op(A) strictly left of the tile's diagonal block)
     int khi_j;     // skip k >= tile col end (op(B) upper-triangular)
     int64_t koff;   // absolute index of local k = 0 for the K-range flags (K split into chunks)
     int64_t batch;  // number of independent products
@@ -468,6 +469,19 @@ hipError_t launch_tune_fill(hipStream_t s, double *A, int64_t lda, int64_t n);
 int64_t rowreduce_chunks(int64_t n);
 hipError_t launch_rowreduce(hipStream_t s, int mode, int64_t m, int64_t n, const double *Y, int64_t ldy,
                             const double *v, double base, double *partials, double *out);
+// out[i + c ldo] += sum_{b <= a} L(i0 + a, i0 + b) E(i0 + b, c) over the
+// 128-row diagonal blocks (i = i0 + a): the part of L E that the products on
+// strictly lower blocks leave out.  Only the lower triangle of L is read.
+constexpr int TRMM_DB = 128;
+hipError_t launch_trmm_diag(hipStream_t s, int64_t m, int64_t r, const double *L, int64_t ldl, const double *E,
+                            int64_t lde, double *out, int64_t ldo, const int32_t *info);
+// out[i + c ldo] = mean ? mean[i] : mu  (m x r)
+hipError_t launch_bcast_rows(hipStream_t s, int64_t m, int64_t r, const double *mean, double mu, double *out,
+                             int64_t ldo);
+// With *info != 0: out (m x r) set to NaN.
+hipError_t launch_fail_fill(hipStream_t s, int64_t m, int64_t r, double *out, int64_t ldo, const int32_t *info);
+// Strict upper triangle of the m x m matrix A set to zero.
+hipError_t launch_zero_upper(hipStream_t s, int64_t m, double *A, int64_t lda);
 
 // k_batch.hip
 size_t batch_ws_bytes(int64_t nmax, int64_t nbatch, bool persistent);

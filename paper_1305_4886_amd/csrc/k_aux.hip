@@ -424,3 +424,125 @@ hipError_t launch_scatter_vec(hipStream_t s, int64_t n, const int64_t *perm, con
     hipLaunchKernelGGL(k_scatter_vec, dim3(nb256(n)), dim3(256), 0, s, n, perm, src, dst);
     return hipGetLastError();
 }
+
+// ---- product with the lower factor (simulation of realizations) -------------
+namespace {
+
+constexpr int TRMM_NC = 32;  // columns of E per workgroup
+
+// Workgroup (block b, column chunk): the 128 x 32 slab of E staged in LDS;
+// thread t owns row a = t % 128 and 16 of the 32 columns.  L is read down the
+// block's columns (consecutive rows across threads), entries above the
+// diagonal are never loaded.
+__global__ __launch_bounds__(256) void k_trmm_diag(int64_t m, int64_t r, const double *L, int64_t ldl,
+                                                   const double *E, int64_t lde, double *out, int64_t ldo,
+                                                   const int32_t *info) {
+    __shared__ double Es[TRMM_DB][TRMM_NC + 1];
+    if (info && *info) return;
+    const int64_t i0 = (int64_t)blockIdx.x * TRMM_DB, c0 = (int64_t)blockIdx.y * TRMM_NC;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < TRMM_DB * TRMM_NC; e += 256) {
+        const int bb = e % TRMM_DB, cc = e / TRMM_DB;
+        const int64_t k = i0 + bb, c = c0 + cc;
+        Es[bb][cc] = (k < m && c < r) ? E[k + c * lde] : 0.0;
+    }
+    __syncthreads();
+    const int a = tid % TRMM_DB, h = tid / TRMM_DB;
+    const int64_t i = i0 + a;
+    const int bmax = (int)((m - i0) < TRMM_DB ? (m - i0) : TRMM_DB);
+    double acc[TRMM_NC / 2];
+#pragma unroll
+    for (int q = 0; q < TRMM_NC / 2; ++q) acc[q] = 0.0;
+    for (int b = 0; b < bmax; ++b) {
+        const double l = (b <= a && i < m) ? L[i + (i0 + b) * ldl] : 0.0;
+#pragma unroll
+        for (int q = 0; q < TRMM_NC / 2; ++q) acc[q] = fma(l, Es[b][h * (TRMM_NC / 2) + q], acc[q]);
+    }
+    if (i >= m) return;
+#pragma unroll
+    for (int q = 0; q < TRMM_NC / 2; ++q) {
+        const int64_t c = c0 + h * (TRMM_NC / 2) + q;
+        if (c < r) out[i + c * ldo] += acc[q];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bcast_rows(int64_t m, int64_t r, const double *mean, double mu, double *out,
+                                                    int64_t ldo) {
+    const int64_t c = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256)
+        out[i + c * ldo] = mean ? mean[i] : mu;
+}
+
+__global__ __launch_bounds__(256) void k_fail_fill(int64_t m, int64_t r, double *out, int64_t ldo, const int32_t *info) {
+    if (*info == 0) return;
+    const int64_t c = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256)
+        out[i + c * ldo] = __builtin_nan("");
+}
+
+// column j = j0 + blockIdx.y: rows 0 .. j - 1 set to zero
+__global__ __launch_bounds__(256) void k_zero_upper(int64_t j0, double *A, int64_t lda) {
+    const int64_t j = j0 + blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < j; i += (int64_t)gridDim.x * 256)
+        A[i + j * lda] = 0.0;
+}
+
+// grid.y carries the columns: at most 65535 per launch
+constexpr int64_t MAX_GRID_Y = 65535;
+
+unsigned row_blocks(int64_t m) {
+    const int64_t b = (m + 255) / 256;
+    return (unsigned)(b < 1024 ? (b > 0 ? b : 1) : 1024);
+}
+
+}  // namespace
+
+hipError_t launch_trmm_diag(hipStream_t s, int64_t m, int64_t r, const double *L, int64_t ldl, const double *E,
+                            int64_t lde, double *out, int64_t ldo, const int32_t *info) {
+    if (m <= 0 || r <= 0) return hipSuccess;
+    const int64_t nblk = (m + TRMM_DB - 1) / TRMM_DB, nch = (r + TRMM_NC - 1) / TRMM_NC;
+    for (int64_t c0 = 0; c0 < nch; c0 += MAX_GRID_Y) {
+        const int64_t cn = nch - c0 < MAX_GRID_Y ? nch - c0 : MAX_GRID_Y;
+        hipLaunchKernelGGL(k_trmm_diag, dim3((unsigned)nblk, (unsigned)cn), dim3(256), 0, s, m, r - c0 * TRMM_NC, L,
+                           ldl, E + c0 * TRMM_NC * lde, lde, out + c0 * TRMM_NC * ldo, ldo, info);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_bcast_rows(hipStream_t s, int64_t m, int64_t r, const double *mean, double mu, double *out,
+                             int64_t ldo) {
+    for (int64_t c0 = 0; c0 < r; c0 += MAX_GRID_Y) {
+        const int64_t cn = r - c0 < MAX_GRID_Y ? r - c0 : MAX_GRID_Y;
+        if (m <= 0) break;
+        hipLaunchKernelGGL(k_bcast_rows, dim3(row_blocks(m), (unsigned)cn), dim3(256), 0, s, m, cn, mean, mu,
+                           out + c0 * ldo, ldo);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_fail_fill(hipStream_t s, int64_t m, int64_t r, double *out, int64_t ldo, const int32_t *info) {
+    for (int64_t c0 = 0; c0 < r; c0 += MAX_GRID_Y) {
+        const int64_t cn = r - c0 < MAX_GRID_Y ? r - c0 : MAX_GRID_Y;
+        if (m <= 0) break;
+        hipLaunchKernelGGL(k_fail_fill, dim3(row_blocks(m), (unsigned)cn), dim3(256), 0, s, m, cn, out + c0 * ldo, ldo,
+                           info);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_zero_upper(hipStream_t s, int64_t m, double *A, int64_t lda) {
+    for (int64_t c0 = 1; c0 < m; c0 += MAX_GRID_Y) {
+        const int64_t cn = m - c0 < MAX_GRID_Y ? m - c0 : MAX_GRID_Y;
+        // columns c0 .. c0 + cn - 1, rows 0 .. j - 1 (j the absolute column)
+        hipLaunchKernelGGL(k_zero_upper, dim3(row_blocks(c0 + cn), (unsigned)cn), dim3(256), 0, s, c0, A, lda);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}

@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmDesc d, TileMap tm) {
     int64_t klo = 0, khi = d.K;
     if (d.klo_i && i0 > klo) klo = i0;
     if (d.klo_j && j0 > klo) klo = j0;
-    if (d.khi_i && i0 + BM < khi) khi = i0 + BM;
+    if (d.khi_i && i0 + (d.khi_i == 2 ? 0 : BM) < khi) khi = i0 + (d.khi_i == 2 ? 0 : BM);
     if (d.khi_j && j0 + BN < khi) khi = j0 + BN;
     klo = (klo / BK) * BK;
 
@@ -398,7 +398,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
     int64_t klo = 0, khi = d.K;
     if (d.klo_i && i0 - d.koff > klo) klo = i0 - d.koff;
     if (d.klo_j && j0 - d.koff > klo) klo = j0 - d.koff;
-    if (d.khi_i && i0 + BM - d.koff < khi) khi = i0 + BM - d.koff;
+    if (d.khi_i && i0 + (d.khi_i == 2 ? 0 : BM) - d.koff < khi) khi = i0 + (d.khi_i == 2 ? 0 : BM) - d.koff;
     if (d.khi_j && j0 + BM - d.koff < khi) khi = j0 + BM - d.koff;
     if (khi <= klo && d.beta == 1.0) return;  // nothing to add to this tile
     const int kf = (int)(klo / BKD);
