@@ -7,7 +7,10 @@ in ``gp_oracle.c`` (plain C, no BLAS), this file only marshals numpy arrays.
 
 Parameters are ``theta = (log sigma^2, log rho, log tau^2)``; kernels are
 0 = exponential, 1 = Matern-3/2, 2 = Matern-5/2 (Rasmussen-Williams scaling
-sqrt(2 nu) d / rho).  Matrices are numpy arrays in Fortran (column-major) order.
+sqrt(2 nu) d / rho), and 3 = the example's separable family (points
+(t, w, v): product of Matern-2 correlations in t and w, random effect tau^2
+shared by equal t, noise variance v on the diagonal; theta has a fourth
+entry log rho_w and the gradient four components).  Matrices are numpy arrays in Fortran (column-major) order.
 
 Parity unpinned: none -- every function here is pinned by ``tests/test_oracle_pins.py``
 (closed forms, hand-derived factors, exact rational arithmetic, LAPACK, finite
@@ -79,7 +82,12 @@ def _vec(a):
 
 
 def _th(theta):
-    return np.ascontiguousarray(theta, dtype=np.float64).reshape(3)
+    """(log sigma^2, log rho, log tau^2[, log rho_w]) -> 4 doubles (the fourth
+    is read only by the separable family, kernel 3)."""
+    t = np.ascontiguousarray(theta, dtype=np.float64).reshape(-1)
+    if t.size not in (3, 4):
+        raise ValueError("theta needs 3 (or 4 for kernel 3) values")
+    return np.concatenate([t, np.zeros(4 - t.size)])
 
 
 class NotPositiveDefinite(RuntimeError):
@@ -158,12 +166,12 @@ def loglik_grad(kernel, theta, X, y, mu=None):
     y = _vec(y)
     mu_a = None if mu is None else _vec(np.broadcast_to(mu, (n,)))
     out = np.zeros(3)
-    g = np.zeros(3)
+    g = np.zeros(4)
     th = _th(theta)
     info = lib().orc_loglik_grad(kernel, _p(th), n, d, _p(X), _p(y), _p(mu_a), _p(out), _p(g))
     if info:
         raise NotPositiveDefinite(info)
-    return (float(out[0]), float(out[1]), float(out[2])), g
+    return (float(out[0]), float(out[1]), float(out[2])), (g if kernel == 3 else g[:3])
 
 
 def inv_lower(L):

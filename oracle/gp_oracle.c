@@ -52,6 +52,77 @@ static double dist(int dim, const double *xi, const double *xj)
     return sqrt(s);
 }
 
+/* ------------------------------------------------------------------ */
+/* The example's covariance family (Section 4.2): a Gaussian process    */
+/* in phase t and log-wavelength w with a product of two Matern         */
+/* correlations of smoothness 2, a random effect shared by all          */
+/* observations of one phase, and known per-observation noise           */
+/* variances.  A point is (t, w, v) with v its noise variance.  With    */
+/* th[0] = log sigma^2, th[1] = log rho_t, th[2] = log tau^2 (the       */
+/* random-effect variance), th[3] = log rho_w:                          */
+/*   C_ij = sigma^2 M(|t_i - t_j|/rho_t) M(|w_i - w_j|/rho_w)           */
+/*          + tau^2 [t_i == t_j] + v_i [i == j],                        */
+/*   M(r) = 2^{1-nu} / Gamma(nu) r^nu K_nu(r) = r^2 K_2(r) / 2  (nu = 2), */
+/* the Matern correlation as parameterised by the package the example   */
+/* loads for it (range scaling d / rho, no sqrt(2 nu)).                 */
+/* ------------------------------------------------------------------ */
+
+/* exp(x) K_nu(x), x > 0, nu = 1 or 2, from the integral
+ *   K_nu(x) = int_0^inf exp(-x cosh t) cosh(nu t) dt
+ * (Abramowitz & Stegun 9.6.24) by the trapezoidal rule, summed until the
+ * terms fall below 1e-19 of the sum.  The integrand is analytic and decays
+ * double-exponentially, so the rule converges geometrically in 1/step; for
+ * large x the integrand is a peak of width about x^{-1/2} at t = 0 and the
+ * error behaves like exp(-(2 pi / step)^2 / (2 x)), so the step is
+ * min(1/16, 0.6 / sqrt(x)) (exponent below -54 for every x).  cosh t - 1 is
+ * formed as 2 sinh^2(t/2).                                                 */
+static double bessel_k_scaled(int nu, double x)
+{
+    const double h = fmin(1.0 / 16.0, 0.6 / sqrt(x));
+    double s = 0.5;
+    for (int k = 1; k < 20000; ++k) {
+        double t = k * h, sh = sinh(0.5 * t);
+        double e = exp(-x * 2.0 * sh * sh);
+        double term = e * cosh(nu * t);
+        s += term;
+        if (term < 1e-19 * s && x * 2.0 * sh * sh > 1.0) break;
+    }
+    return h * s;
+}
+
+/* M(r) = r^2 K_2(r) / 2 and g(r) = -r M'(r) = r^3 K_1(r) / 2
+ * (d/dr [r^2 K_2(r)] = -r^2 K_1(r), A&S 9.6.28).                        */
+static double sep_m(double r)
+{
+    if (r == 0.0) return 1.0;
+    return 0.5 * r * r * exp(-r) * bessel_k_scaled(2, r);
+}
+static double sep_g(double r)
+{
+    if (r == 0.0) return 0.0;
+    return 0.5 * r * r * r * exp(-r) * bessel_k_scaled(1, r);
+}
+
+/* Covariance entry between points i and j (same_index: i == j) of any
+ * family; cross-covariances (to new points) take neither nugget, random
+ * effect nor noise. */
+static double cov_entry(int kind, const double *th, int dim, const double *xi, const double *xj,
+                        int same_index, int cross)
+{
+    const double s2 = exp(th[0]), rho = exp(th[1]), t2 = exp(th[2]);
+    if (kind == 3) {
+        const double rw = exp(th[3]);
+        double v = s2 * sep_m(fabs(xi[0] - xj[0]) / rho) * sep_m(fabs(xi[1] - xj[1]) / rw);
+        if (!cross) {
+            if (xi[0] == xj[0]) v += t2;
+            if (same_index) v += xi[2];
+        }
+        return v;
+    }
+    double r = dist(dim, xi, xj) / rho;
+    return s2 * corr_k(kind, r) + ((same_index && !cross) ? t2 : 0.0);
+}
+
 /* Neumaier-compensated running sum. */
 typedef struct { double s, c; } csum;
 static void cs_add(csum *a, double v)
@@ -64,29 +135,25 @@ static double cs_val(const csum *a) { return a->s + a->c; }
 
 /* C_ij = sigma^2 k(|x_i - x_j|/rho) + tau^2 [i == j]; full square written.
  * The nugget goes with the index (i == j), not with coincident locations. */
-int orc_cov(int kind, const double th[3], i64 n, int dim, const double *X, double *C, i64 ldc)
+int orc_cov(int kind, const double th[4], i64 n, int dim, const double *X, double *C, i64 ldc)
 {
     if (n < 0 || ldc < (n > 0 ? n : 1)) return -1;
-    const double s2 = exp(th[0]), rho = exp(th[1]), t2 = exp(th[2]);
 #pragma omp parallel for schedule(static)
     for (i64 j = 0; j < n; ++j)
-        for (i64 i = 0; i < n; ++i) {
-            double r = dist(dim, X + i * dim, X + j * dim) / rho;
-            C[i + j * ldc] = s2 * corr_k(kind, r) + (i == j ? t2 : 0.0);
-        }
+        for (i64 i = 0; i < n; ++i)
+            C[i + j * ldc] = cov_entry(kind, th, dim, X + i * dim, X + j * dim, i == j, 0);
     return 0;
 }
 
 /* Cross-covariance between data points and new points, no nugget. n x m. */
-int orc_cross_cov(int kind, const double th[3], i64 n, i64 m, int dim, const double *X,
+int orc_cross_cov(int kind, const double th[4], i64 n, i64 m, int dim, const double *X,
                   const double *Xs, double *Cs, i64 ld)
 {
     if (n < 0 || m < 0 || ld < (n > 0 ? n : 1)) return -1;
-    const double s2 = exp(th[0]), rho = exp(th[1]);
 #pragma omp parallel for schedule(static)
     for (i64 j = 0; j < m; ++j)
         for (i64 i = 0; i < n; ++i)
-            Cs[i + j * ld] = s2 * corr_k(kind, dist(dim, X + i * dim, Xs + j * dim) / rho);
+            Cs[i + j * ld] = cov_entry(kind, th, dim, X + i * dim, Xs + j * dim, 0, 1);
     return 0;
 }
 
@@ -167,7 +234,7 @@ void orc_logdet_q(i64 n, const double *L, i64 ldl, const double *z, double out[2
  *   l = -1/2 (n log(2 pi) + log|C| + (y-mu)^T C^{-1} (y-mu)).
  * out = {l, logdet, q}.  L (n x n, ld n) receives the factor, alpha (nullable)
  * receives C^{-1}(y - mu).  mu may be NULL (zero mean).  Returns info.        */
-i64 orc_loglik(int kind, const double th[3], i64 n, int dim, const double *X, const double *y,
+i64 orc_loglik(int kind, const double th[4], i64 n, int dim, const double *X, const double *y,
                const double *mu, double *L, double out[3], double *alpha)
 {
     orc_cov(kind, th, n, dim, X, L, n);
@@ -210,14 +277,14 @@ void orc_inv_lower(i64 n, const double *L, i64 ldl, double *W, i64 ldw)
  *   dC/dlog sigma^2 = sigma^2 k(r),  dC/dlog rho = sigma^2 g(r),
  *   dC/dlog tau^2   = tau^2 [i == j].
  * out = {l, logdet, q}; grad = 3 values.  Returns info.                       */
-i64 orc_loglik_grad(int kind, const double th[3], i64 n, int dim, const double *X,
-                    const double *y, const double *mu, double out[3], double grad[3])
+i64 orc_loglik_grad(int kind, const double th[4], i64 n, int dim, const double *X,
+                    const double *y, const double *mu, double out[3], double grad[4])
 {
     size_t nn = (size_t)(n > 0 ? n : 1) * (size_t)(n > 0 ? n : 1);
     double *L = (double *)malloc(nn * sizeof(double));
     double *alpha = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
     i64 info = orc_loglik(kind, th, n, dim, X, y, mu, L, out, alpha);
-    if (info) { grad[0] = grad[1] = grad[2] = NAN; free(L); free(alpha); return info; }
+    if (info) { grad[0] = grad[1] = grad[2] = grad[3] = NAN; free(L); free(alpha); return info; }
     double *W = (double *)malloc(nn * sizeof(double));
     orc_inv_lower(n, L, n, W, n);
     const double s2 = exp(th[0]), rho = exp(th[1]), t2 = exp(th[2]);
@@ -225,34 +292,49 @@ i64 orc_loglik_grad(int kind, const double th[3], i64 n, int dim, const double *
      * symmetric pair (i, j), (j, i) is counted once with weight 1, the
      * diagonal with weight 1/2), then the columns are added in order j = 0..n-1,
      * so the result does not depend on the thread count. */
-    double *part = (double *)malloc((size_t)(n > 0 ? n : 1) * 3 * sizeof(double));
+    double *part = (double *)malloc((size_t)(n > 0 ? n : 1) * 4 * sizeof(double));
 #pragma omp parallel for schedule(dynamic, 4)
     for (i64 j = 0; j < n; ++j) {
-        csum p0 = {0, 0}, p1 = {0, 0}, p2 = {0, 0};
+        csum p0 = {0, 0}, p1 = {0, 0}, p2 = {0, 0}, p3 = {0, 0};
         for (i64 i = j; i < n; ++i) {
             double cinv = 0.0; /* (C^{-1})_ij = sum_{k >= i} W_ki W_kj */
             for (i64 k = i; k < n; ++k) cinv += W[k + i * n] * W[k + j * n];
-            double r = dist(dim, X + i * dim, X + j * dim) / rho;
             double a = alpha[i] * alpha[j] - cinv;
             double w = (i == j) ? 0.5 : 1.0;
-            cs_add(&p0, w * a * s2 * corr_k(kind, r));
-            cs_add(&p1, w * a * s2 * corr_g(kind, r));
-            if (i == j) cs_add(&p2, w * a * t2);
+            if (kind == 3) {
+                /* dC/dlog sigma^2 = sigma^2 M_t M_w, dC/dlog rho_t = sigma^2 g_t M_w,
+                 * dC/dlog tau^2 = tau^2 [t_i == t_j], dC/dlog rho_w = sigma^2 M_t g_w */
+                const double *xi = X + i * dim, *xj = X + j * dim;
+                double rt = fabs(xi[0] - xj[0]) / rho, rw = fabs(xi[1] - xj[1]) / exp(th[3]);
+                double mt = sep_m(rt), mw = sep_m(rw);
+                cs_add(&p0, w * a * s2 * mt * mw);
+                cs_add(&p1, w * a * s2 * sep_g(rt) * mw);
+                if (xi[0] == xj[0]) cs_add(&p2, w * a * t2);
+                cs_add(&p3, w * a * s2 * mt * sep_g(rw));
+            } else {
+                double r = dist(dim, X + i * dim, X + j * dim) / rho;
+                cs_add(&p0, w * a * s2 * corr_k(kind, r));
+                cs_add(&p1, w * a * s2 * corr_g(kind, r));
+                if (i == j) cs_add(&p2, w * a * t2);
+            }
         }
-        part[3 * j + 0] = cs_val(&p0);
-        part[3 * j + 1] = cs_val(&p1);
-        part[3 * j + 2] = cs_val(&p2);
+        part[4 * j + 0] = cs_val(&p0);
+        part[4 * j + 1] = cs_val(&p1);
+        part[4 * j + 2] = cs_val(&p2);
+        part[4 * j + 3] = cs_val(&p3);
     }
-    csum g0 = {0, 0}, g1 = {0, 0}, g2 = {0, 0};
+    csum g0 = {0, 0}, g1 = {0, 0}, g2 = {0, 0}, g3 = {0, 0};
     for (i64 j = 0; j < n; ++j) {
-        cs_add(&g0, part[3 * j + 0]);
-        cs_add(&g1, part[3 * j + 1]);
-        cs_add(&g2, part[3 * j + 2]);
+        cs_add(&g0, part[4 * j + 0]);
+        cs_add(&g1, part[4 * j + 1]);
+        cs_add(&g2, part[4 * j + 2]);
+        cs_add(&g3, part[4 * j + 3]);
     }
     free(part);
     grad[0] = cs_val(&g0);
     grad[1] = cs_val(&g1);
     grad[2] = cs_val(&g2);
+    grad[3] = cs_val(&g3);
     free(W); free(L); free(alpha);
     return 0;
 }
@@ -261,25 +343,28 @@ i64 orc_loglik_grad(int kind, const double th[3], i64 n, int dim, const double *
  *   c_j = sigma^2 k(|x_i - s_j|/rho),  mean_j = mu + c_j^T alpha,
  *   w_j = L^{-1} c_j,  var_j = sigma^2 - w_j^T w_j (+ tau^2 if include_nugget).
  * L and alpha come from orc_loglik.  No clamping of var.                      */
-void orc_krige(int kind, const double th[3], i64 n, i64 m, int dim, const double *X,
+void orc_krige(int kind, const double th[4], i64 n, i64 m, int dim, const double *X,
                const double *Xs, const double *L, i64 ldl, const double *alpha, double mu,
                int include_nugget, double *mean, double *var)
 {
-    const double s2 = exp(th[0]), rho = exp(th[1]), t2 = exp(th[2]);
+    const double s2 = exp(th[0]), t2 = exp(th[2]);
 #pragma omp parallel
     {
         double *c = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
 #pragma omp for schedule(dynamic, 4)
         for (i64 j = 0; j < m; ++j) {
             for (i64 i = 0; i < n; ++i)
-                c[i] = s2 * corr_k(kind, dist(dim, X + i * dim, Xs + j * dim) / rho);
+                c[i] = cov_entry(kind, th, dim, X + i * dim, Xs + j * dim, 0, 1);
             double mj = 0.0;
             for (i64 i = 0; i < n; ++i) mj += c[i] * alpha[i];
             mean[j] = mu + mj;
             orc_trsv(0, n, L, ldl, c);
             double ww = 0.0;
             for (i64 i = 0; i < n; ++i) ww += c[i] * c[i];
-            var[j] = s2 - ww + (include_nugget ? t2 : 0.0);
+            if (kind == 3) /* prior variance of the point: sigma^2 (+ tau^2 + v_j) */
+                var[j] = cov_entry(kind, th, dim, Xs + j * dim, Xs + j * dim, 1, !include_nugget) - ww;
+            else
+                var[j] = s2 - ww + (include_nugget ? t2 : 0.0);
         }
         free(c);
     }
@@ -293,24 +378,22 @@ void orc_krige(int kind, const double th[3], i64 n, i64 m, int dim, const double
  *          - sum_k W_ki W_kj,        W_:j = L^{-1} c_j (forward substitution).
  * With n = 0 (no data) S is the prior covariance of the new points.
  * Lower triangle of S (m x m, ld lds) written; L from orc_loglik.            */
-void orc_krige_cov(int kind, const double th[3], i64 n, i64 m, int dim, const double *X,
+void orc_krige_cov(int kind, const double th[4], i64 n, i64 m, int dim, const double *X,
                    const double *Xs, const double *L, i64 ldl, int include_nugget,
                    double *S, i64 lds)
 {
-    const double s2 = exp(th[0]), rho = exp(th[1]), t2 = exp(th[2]);
     double *W = (double *)malloc((size_t)(n > 0 ? n : 1) * (size_t)(m > 0 ? m : 1) * sizeof(double));
 #pragma omp parallel for schedule(dynamic, 4)
     for (i64 j = 0; j < m; ++j) {
         double *w = W + j * n;
         for (i64 i = 0; i < n; ++i)
-            w[i] = s2 * corr_k(kind, dist(dim, X + i * dim, Xs + j * dim) / rho);
+            w[i] = cov_entry(kind, th, dim, X + i * dim, Xs + j * dim, 0, 1);
         orc_trsv(0, n, L, ldl, w);
     }
 #pragma omp parallel for schedule(dynamic, 4)
     for (i64 j = 0; j < m; ++j)
         for (i64 i = j; i < m; ++i) {
-            double t = s2 * corr_k(kind, dist(dim, Xs + i * dim, Xs + j * dim) / rho);
-            if (include_nugget && i == j) t += t2;
+            double t = cov_entry(kind, th, dim, Xs + i * dim, Xs + j * dim, i == j, !include_nugget);
             for (i64 k = 0; k < n; ++k) t -= W[k + i * n] * W[k + j * n];
             S[i + j * lds] = t;
         }
@@ -345,19 +428,18 @@ void orc_trmm(i64 n, i64 r, const double *L, i64 ldl, double *B, i64 ldb)
  * eps (m x nreal, ld ldeps) are the standard normal draws, supplied by the
  * caller.  Returns the factorisation's info; on failure out is NaN.
  * Ls (m x m, ld m, nullable) receives L_S.                                   */
-i64 orc_simulate(int kind, const double th[3], i64 n, i64 m, int dim, const double *X,
+i64 orc_simulate(int kind, const double th[4], i64 n, i64 m, int dim, const double *X,
                  const double *Xs, const double *L, i64 ldl, const double *alpha, double mu,
                  int include_nugget, i64 nreal, const double *eps, i64 ldeps, double *out,
                  i64 ldo, double *Ls)
 {
-    const double s2 = exp(th[0]), rho = exp(th[1]);
     double *S = (double *)calloc((size_t)(m > 0 ? m : 1) * (size_t)(m > 0 ? m : 1), sizeof(double));
     double *mean = (double *)malloc((size_t)(m > 0 ? m : 1) * sizeof(double));
     orc_krige_cov(kind, th, n, m, dim, X, Xs, L, ldl, include_nugget, S, m);
     for (i64 i = 0; i < m; ++i) {
         double t = 0.0;
         for (i64 k = 0; k < n; ++k)
-            t += s2 * corr_k(kind, dist(dim, X + k * dim, Xs + i * dim) / rho) * alpha[k];
+            t += cov_entry(kind, th, dim, X + k * dim, Xs + i * dim, 0, 1) * alpha[k];
         mean[i] = mu + t;
     }
     i64 info = orc_potrf(m, S, m);

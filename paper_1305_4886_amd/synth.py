@@ -19,6 +19,8 @@ Recipes (all numpy PCG64 through ``numpy.random.default_rng(seed)``):
   amplitude of the workloads' fields; it is a stand-in response for sizes at
   which a dense factor of the model covariance is too slow to draw y from.
 * ``batch_sizes(nb, seed, lo, hi)``: problem sizes uniform on {lo..hi}.
+* ``spectral_points(n_phase, n_wave, seed)``: (phase, log-wavelength, noise
+  variance) rows on the grid layout of the paper's spectral example.
 """
 from __future__ import annotations
 
@@ -62,6 +64,25 @@ def smooth_field(X: np.ndarray, seed: int, s2: float = 1.0, ell: float = 0.05,
     b = rng.uniform(0.0, 2.0 * np.pi, size=n_waves)
     f = np.sqrt(2.0 * s2 / n_waves) * np.cos(X @ w.T + b).sum(axis=1)
     return f + np.sqrt(t2) * rng.standard_normal(X.shape[0])
+
+
+def spectral_points(n_phase: int, n_wave: int, seed: int, t_range=(-15.0, 24.0), lam_range=(5600.0, 6650.0),
+                    noise_sd=(0.005, 0.02)) -> np.ndarray:
+    """Rows (t, w, v) on a phase x log-wavelength grid, the layout of the
+    paper's example data (25 phases x 2691 wavelengths = 67,275
+    observations): n_phase phases uniform on t_range (sorted), n_wave
+    log-wavelengths w = log(lambda) equally spaced over lam_range (Angstrom),
+    and per-observation noise variances v = sd^2 with sd uniform on noise_sd.
+    Phase-major order: all wavelengths of the first phase, then the next."""
+    rng = np.random.default_rng(seed)
+    t = np.sort(rng.uniform(t_range[0], t_range[1], size=n_phase))
+    w = np.log(np.linspace(lam_range[0], lam_range[1], n_wave))
+    sd = rng.uniform(noise_sd[0], noise_sd[1], size=n_phase * n_wave)
+    out = np.empty((n_phase * n_wave, 3))
+    out[:, 0] = np.repeat(t, n_wave)
+    out[:, 1] = np.tile(w, n_phase)
+    out[:, 2] = sd * sd
+    return out
 
 
 def batch_sizes(nb: int, seed: int, lo: int = 256, hi: int = 4096) -> np.ndarray:

@@ -540,3 +540,101 @@ def test_simulate_singular_covariance_fails(orc):
     out, info = orc.simulate(0, th(1.0, 0.3, 0.1), Xs, np.ones((3, 2)))
     assert info == 2
     assert np.all(np.isnan(out))
+
+
+# --------------------------------------------------------------------------
+# The example's covariance family (Section 4.2): product of Matern
+# correlations of smoothness 2 in phase and log-wavelength, a random effect
+# shared by one phase, known per-observation noise variances
+# --------------------------------------------------------------------------
+SEP_TH = (0.0071, 2.33, 2.6e-5, 0.0089)  # sigma^2, rho_t, tau^2, rho_w: the paper's estimates
+
+
+def sep_theta(s2, rt, t2, rw):
+    return np.array([math.log(s2), math.log(rt), math.log(t2), math.log(rw)])
+
+
+def matern2(r):
+    r = np.asarray(r, dtype=np.float64)
+    out = np.ones_like(r)
+    nz = r > 0
+    out[nz] = 0.5 * r[nz] ** 2 * sps.kv(2, r[nz])
+    return out
+
+
+def sep_dense(X, s2, rt, t2, rw):
+    dt = np.abs(X[:, None, 0] - X[None, :, 0])
+    dw = np.abs(X[:, None, 1] - X[None, :, 1])
+    return s2 * matern2(dt / rt) * matern2(dw / rw) + t2 * (dt == 0) + np.diag(X[:, 2])
+
+
+@pytest.mark.parametrize("r", [1e-9, 1e-4, 0.03, 0.5, 1.0, 2.0, 3.7, 8.0, 19.0, 21.0, 45.0, 120.0, 400.0, 600.0])
+def test_sep_matern2_against_bessel(orc, r):
+    # two observations at phase distance r rho_t (same wavelength) and two at
+    # log-wavelength distance r rho_w (same phase: the random effect enters)
+    s2, rt, t2, rw = 1.5, 2.0, 0.25, 0.01
+    X = np.array([[0.0, 0.0, 0.0], [r * rt, 0.0, 0.0], [5.0, 0.0, 0.0], [5.0, r * rw, 0.0]])
+    C = orc.cov(3, sep_theta(s2, rt, t2, rw), X)
+    ref = 0.5 * r * r * sps.kv(2, r)
+    np.testing.assert_allclose(C[1, 0], s2 * ref, rtol=2e-14, atol=0)
+    np.testing.assert_allclose(C[3, 2] - t2, s2 * ref, rtol=2e-14, atol=2 * U * t2)  # t2 + ... rounded
+
+
+def test_sep_covariance_structure(orc):
+    X = synth.spectral_points(4, 30, 5)
+    s2, rt, t2, rw = SEP_TH
+    C = orc.cov(3, sep_theta(s2, rt, t2, rw), X)
+    np.testing.assert_allclose(C, sep_dense(X, s2, rt, t2, rw), rtol=1e-13, atol=1e-19)
+    # the random effect ties every pair of one phase, the noise only the diagonal
+    assert C[0, 29] > t2 and abs(C[0, 30] - s2 * matern2(abs(X[0, 0] - X[30, 0]) / rt)) < 1e-16
+    Cs = orc.cross_cov(3, sep_theta(s2, rt, t2, rw), X, X[:7])
+    np.testing.assert_allclose(Cs, sep_dense(X, s2, rt, 0.0, rw)[:, :7] - np.diag(X[:, 2])[:, :7],
+                               rtol=1e-13, atol=1e-19)
+
+
+def test_sep_loglik_against_lapack(orc):
+    X = synth.spectral_points(5, 60, 6)
+    s2, rt, t2, rw = SEP_TH
+    C = sep_dense(X, s2, rt, t2, rw)
+    y = sla.cholesky(C, lower=True) @ synth.normals(X.shape[0], 7)
+    ll, ld, q = orc.loglik(3, sep_theta(s2, rt, t2, rw), X, y)
+    cf = sla.cho_factor(C, lower=True)
+    ld_ref = 2.0 * np.log(np.diag(cf[0])).sum()
+    q_ref = y @ sla.cho_solve(cf, y)
+    n = X.shape[0]
+    assert abs(ld - ld_ref) <= 1e-10 * abs(ld_ref)
+    assert abs(q - q_ref) <= 1e-9 * q_ref
+    assert abs(ll + 0.5 * (n * LOG2PI + ld_ref + q_ref)) <= 1e-10 * abs(ll)
+
+
+def test_sep_gradient_central_differences(orc):
+    X = synth.spectral_points(4, 40, 8)
+    t = sep_theta(*SEP_TH)
+    C = sep_dense(X, *SEP_TH)
+    y = sla.cholesky(C, lower=True) @ synth.normals(X.shape[0], 9) + 0.01 * synth.normals(X.shape[0], 10)
+    (_, _, _), g = orc.loglik_grad(3, t, X, y)
+    assert g.shape == (4,)
+    h = 1e-5
+    for k in range(4):
+        tp, tm = t.copy(), t.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd = (orc.loglik(3, tp, X, y)[0] - orc.loglik(3, tm, X, y)[0]) / (2 * h)
+        assert abs(g[k] - fd) <= 1e-6 * max(1.0, abs(g[k])), (k, g[k], fd)
+
+
+def test_sep_krige_against_dense_formula(orc):
+    X = synth.spectral_points(3, 50, 11)
+    Xs = np.column_stack([np.full(20, X[60, 0]), np.linspace(X[0, 1], X[49, 1], 20), np.zeros(20)])
+    s2, rt, t2, rw = SEP_TH
+    t = sep_theta(s2, rt, t2, rw)
+    C = sep_dense(X, s2, rt, t2, rw)
+    y = sla.cholesky(C, lower=True) @ synth.normals(X.shape[0], 12)
+    (_, _, _), L, a = orc.loglik(3, t, X, y, want=True)
+    mean, var = orc.krige(3, t, X, Xs, L, a)
+    dt = np.abs(X[:, None, 0] - Xs[None, :, 0])
+    dw = np.abs(X[:, None, 1] - Xs[None, :, 1])
+    Cs = s2 * matern2(dt / rt) * matern2(dw / rw)
+    np.testing.assert_allclose(mean, Cs.T @ sla.solve(C, y, assume_a="pos"), rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(var, s2 - np.einsum("ij,ij->j", Cs, sla.solve(C, Cs, assume_a="pos")),
+                               rtol=0, atol=1e-12 * s2)
