@@ -7,7 +7,8 @@ random field + nugget noise).  One step = one pass over the hot path:
   * log-likelihood evaluation (FP64)                   -> evals/s
   * log-likelihood + adjoint gradient (FP64)           -> evals/s
   * mixed-precision log-likelihood (FP32 / BF16 trailing products + FP64
-    refinement), with its error against the FP64 result -> evals/s
+    refinement), with its error against the FP64 result -> evals/s; BF16
+    with hi/lo split operands (default) and, for context, without
   * kriging mean + variance at m = 4096 new points     -> predictions/s
   * full m x m prediction covariance, and 1000 realizations conditional
     on the data at the m points                        -> TFLOP/s, draws/s
@@ -177,7 +178,8 @@ def main():
         e1.record(stream)
         return r, (e0, e1)
 
-    results = {k: [] for k in ["chol", "loglik", "krige", "kcov", "sim", "grad", "mixed32", "mixed16", "batch"]}
+    results = {k: [] for k in ["chol", "loglik", "krige", "kcov", "sim", "grad", "mixed32", "mixed16", "mixed16s",
+                               "batch"]}
     syrk = [0, 0.0, 0.0]
     last = {}
     Xs = torch.as_tensor(synth.uniform_points(m, 41), device=dev)
@@ -257,6 +259,13 @@ def main():
             if record:
                 results["mixed16"].append(ev)
                 last["mixed16"] = m16
+            # the same with one BF16 product per block (no hi / lo split), for context
+            h.set_options(bf16_split=0)
+            m16s, ev = timed(lambda: gp.loglik(X, y, th, prec=gp.GP_BF16_TRAIL, S=S, ws=ws_m16))
+            h.set_options(bf16_split=1)
+            if record:
+                results["mixed16s"].append(ev)
+                last["mixed16s"] = m16s
         # 6. batch of 64 independent GPs in one call
         if "batch" in parts:
             bb, ev = timed(lambda: gp.loglik_batched(bX, by, bth, bsizes, C_pool=bpool, ws=ws_b))
@@ -317,7 +326,8 @@ def main():
         out_parts["loglik_grad_fp64"] = {"ms_median": gm, "evals_per_s": 1e3 / gm,
                                          "grad": g["grad"].cpu().numpy().tolist(),
                                          "loglik": float(g["out3"][0].item())}
-    for key, name in [("mixed32", "loglik_mixed_fp32"), ("mixed16", "loglik_mixed_bf16")]:
+    for key, name in [("mixed32", "loglik_mixed_fp32"), ("mixed16", "loglik_mixed_bf16"),
+                      ("mixed16s", "loglik_mixed_bf16_unsplit")]:
         if results[key]:
             mm = float(np.median(ms_of(results[key])))
             r = last[key]

@@ -67,7 +67,20 @@ extern "C" {
 
 typedef struct gp_handle_s *gp_handle_t;
 
-typedef enum { GP_EXP = 0, GP_MATERN32 = 1, GP_MATERN52 = 2 } gp_kernel_t;
+/* Covariance families.  GP_SEP_MATERN2 is the family of the paper's spectral
+ * example (Section 4.2): a point is (t, w, v) -- phase, log-wavelength and
+ * the known noise variance of that observation (dim must be 3) -- and
+ *     C_ij = sigma^2 M(|t_i - t_j| / rho) M(|w_i - w_j| / rho_w)
+ *            + tau^2 [t_i == t_j] + v_i [i == j],
+ *     M(r) = r^2 K_2(r) / 2   (Matern correlation of smoothness 2, range
+ *                              scaling d / rho, K_2 the modified Bessel
+ *                              function of the second kind),
+ * i.e. a product of Matern correlations in phase and log-wavelength, a
+ * random effect of variance tau^2 shared by the observations of one phase,
+ * and heteroscedastic noise.  Cross-covariances carry the first term only.
+ * Its gradient has four components (log sigma^2, log rho, log tau^2,
+ * log rho_w).  gp_loglik_batched does not take it. */
+typedef enum { GP_EXP = 0, GP_MATERN32 = 1, GP_MATERN52 = 2, GP_SEP_MATERN2 = 3 } gp_kernel_t;
 
 /* Precision of the Cholesky trailing updates.  Diagonal-block factorisations,
  * panel solves, the log-determinant and all residuals stay in FP64 in every
@@ -87,7 +100,9 @@ typedef struct {
     int32_t kind;      /* gp_kernel_t */
     double log_sigma2; /* log of the spatial variance sigma^2  */
     double log_rho;    /* log of the range rho (> 0)           */
-    double log_tau2;   /* log of the nugget variance tau^2     */
+    double log_tau2;   /* log of the nugget variance tau^2 (GP_SEP_MATERN2: the per-phase
+                          random-effect variance) */
+    double log_rho2;   /* GP_SEP_MATERN2 only: log of the log-wavelength range rho_w */
 } gp_theta_t;
 
 typedef struct {
@@ -111,6 +126,10 @@ typedef struct {
                             gp_loglik / gp_loglik_grad.  Every bounded wait then gives up at once and
                             the evaluation reports a stall (info = -1, NaN outputs) without any kernel
                             running into its time limit. */
+    int32_t bf16_split;  /* GP_BF16_TRAIL: 1 (default) = each trailing product formed from hi and lo
+                            BF16 parts of the panel (x = hi + lo, hi = bf16(x), lo = bf16(x - hi);
+                            hi hi^T + hi lo^T + lo hi^T on the BF16 matrix cores: about 16 significant
+                            bits per operand instead of 8); 0 = one BF16 product */
 } gp_options_t;
 
 /* ---- handle ------------------------------------------------------------ */
@@ -222,7 +241,8 @@ int gp_loglik_noalloc(gp_handle_t h, gp_theta_t th, gp_prec_t prec, int64_t n, i
                       const double *X, const double *y, const double *mu, double *C, int64_t ldc,
                       double *out3_dev, double *alpha_dev, int32_t *info_dev, double *ir_dev);
 
-/* As gp_loglik, plus grad3_dev [dev, 3] = d loglik / d (log sigma^2, log rho,
+/* As gp_loglik, plus grad3_dev [dev, 3; 4 for GP_SEP_MATERN2, whose fourth
+ * entry is d loglik / d log rho_w] = d loglik / d (log sigma^2, log rho,
  * log tau^2) by the adjoint 1/2 sum_ij (alpha_i alpha_j - (C^{-1})_ij) dC_ij /
  * dtheta (Rasmussen & Williams 2006, eq. 5.9), with C^{-1} formed from L on
  * the matrix cores and dC/dtheta regenerated from X.  On return C holds

@@ -19,13 +19,14 @@ import threading
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgpmi.so")
 
-GP_EXP, GP_MATERN32, GP_MATERN52 = 0, 1, 2
+GP_EXP, GP_MATERN32, GP_MATERN52, GP_SEP_MATERN2 = 0, 1, 2, 3
 GP_FP64, GP_FP32_TRAIL, GP_BF16_TRAIL = 0, 1, 2
 GP_NOTRANS, GP_TRANS = 0, 1
 (GP_OP_POTRF, GP_OP_TRSV, GP_OP_TRSM, GP_OP_LOGLIK, GP_OP_LOGLIK_GRAD, GP_OP_KRIGE,
  GP_OP_BATCHED, GP_OP_MORTON, GP_OP_KRIGE_COV, GP_OP_TRMM, GP_OP_SIMULATE) = range(11)
 
-KERNELS = {"exp": GP_EXP, "exponential": GP_EXP, "matern32": GP_MATERN32, "matern52": GP_MATERN52}
+KERNELS = {"exp": GP_EXP, "exponential": GP_EXP, "matern32": GP_MATERN32, "matern52": GP_MATERN52,
+           "sep_matern2": GP_SEP_MATERN2}
 PRECS = {"fp64": GP_FP64, "fp32": GP_FP32_TRAIL, "bf16": GP_BF16_TRAIL}
 
 EXPORTED = ["gp_create", "gp_destroy", "gp_set_stream", "gp_set_options", "gp_get_options",
@@ -37,7 +38,8 @@ EXPORTED = ["gp_create", "gp_destroy", "gp_set_stream", "gp_set_options", "gp_ge
 
 class Theta(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("log_sigma2", ctypes.c_double),
-                ("log_rho", ctypes.c_double), ("log_tau2", ctypes.c_double)]
+                ("log_rho", ctypes.c_double), ("log_tau2", ctypes.c_double),
+                ("log_rho2", ctypes.c_double)]
 
 
 class Options(ctypes.Structure):
@@ -45,7 +47,7 @@ class Options(ctypes.Structure):
                 ("ir_max_iter", ctypes.c_int32), ("ir_tol", ctypes.c_double),
                 ("reorder", ctypes.c_int32), ("panel_cus", ctypes.c_int32),
                 ("fused_panel", ctypes.c_int32), ("batch_grid", ctypes.c_int32),
-                ("fail_inject", ctypes.c_int32)]
+                ("fail_inject", ctypes.c_int32), ("bf16_split", ctypes.c_int32)]
 
 
 class GPError(RuntimeError):
@@ -115,16 +117,24 @@ def check(rc):
         raise GPError(rc, lib().gp_strerror(rc).decode())
 
 
-def theta(kernel, sigma2=None, rho=None, tau2=None, log=None):
-    """Theta from natural parameters or from log = (log s2, log rho, log t2)."""
+def theta(kernel, sigma2=None, rho=None, tau2=None, log=None, rho2=None):
+    """Theta from natural parameters or from log = (log s2, log rho, log t2
+    [, log rho_w]); rho2 / the fourth log entry is the log-wavelength range of
+    the separable family (GP_SEP_MATERN2)."""
     k = KERNELS.get(kernel, kernel) if isinstance(kernel, str) else int(kernel)
+    lr2 = 0.0
     if log is not None:
-        ls, lr, lt = (float(v) for v in log)
+        vals = [float(v) for v in log]
+        ls, lr, lt = vals[:3]
+        if len(vals) > 3:
+            lr2 = vals[3]
     else:
         ls = math.log(sigma2) if sigma2 > 0 else -math.inf
         lr = math.log(rho)
         lt = math.log(tau2) if tau2 > 0 else -math.inf
-    return Theta(k, ls, lr, lt)
+        if rho2 is not None:
+            lr2 = math.log(rho2)
+    return Theta(k, ls, lr, lt, lr2)
 
 
 def _torch():
@@ -377,7 +387,7 @@ def loglik_grad(X, y, th, prec=GP_FP64, mu=None, S=None, want_alpha=False, ws=No
     h = handle()
     S = S if S is not None else colmajor_storage(n)
     out3 = torch.empty(3, dtype=torch.float64, device="cuda")
-    grad3 = torch.empty(3, dtype=torch.float64, device="cuda")
+    grad3 = torch.empty(4 if th.kind == GP_SEP_MATERN2 else 3, dtype=torch.float64, device="cuda")
     info = torch.zeros(1, dtype=torch.int32, device="cuda")
     ir = torch.zeros(3, dtype=torch.float64, device="cuda")
     alpha = torch.empty(n, dtype=torch.float64, device="cuda") if want_alpha else None

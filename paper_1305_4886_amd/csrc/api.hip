@@ -32,11 +32,17 @@ bool ok_handle(gp_handle_t h) { return h && h->magic == 0x67706d69; }
 // theta check: log sigma^2 and log tau^2 may be -inf (an exact zero), never
 // +inf or NaN; log rho must be finite.
 int check_theta(const gp_theta_t &th) {
-    if (th.kind < GP_EXP || th.kind > GP_MATERN52) return 1;
+    if (th.kind < GP_EXP || th.kind > GP_SEP_MATERN2) return 1;
     if (isnan(th.log_sigma2) || th.log_sigma2 == INFINITY) return 2;
     if (!isfinite(th.log_rho)) return 2;
     if (isnan(th.log_tau2) || th.log_tau2 == INFINITY) return 2;
+    if (th.kind == GP_SEP_MATERN2 && !isfinite(th.log_rho2)) return 2;
     return 0;
+}
+
+// The separable family takes points (t, w, v): dimension 3.
+bool bad_dim(const gp_theta_t &th, int dim) {
+    return dim < 1 || dim > 16 || (th.kind == GP_SEP_MATERN2 && dim != 3);
 }
 
 CovParams cov_params(const gp_theta_t &th, int dim) {
@@ -46,6 +52,7 @@ CovParams cov_params(const gp_theta_t &th, int dim) {
     p.s2 = exp(th.log_sigma2);
     p.inv_rho = exp(-th.log_rho);
     p.t2 = exp(th.log_tau2);
+    p.inv_rho2 = th.kind == GP_SEP_MATERN2 ? exp(-th.log_rho2) : 0.0;
     return p;
 }
 
@@ -159,7 +166,8 @@ Layout layout(gp_handle_t h, gp_op_t op, int64_t n, int64_t m, gp_prec_t prec) {
         L.z = take(vec);     // L^{-1} b
         L.vec2 = take(vec);  // x = C^{-1} b (evaluation order)
         L.vec3 = take(vec);  // b = y - mu (evaluation order)
-        L.part = take(sizeof(double) * (size_t)(6 * GRAD_PARTS > 4 * (n + 8) ? 6 * GRAD_PARTS : 4 * (n + 8)));
+        L.part = take(sizeof(double) *
+                      (size_t)(2 * GRAD_NQ * GRAD_PARTS > 4 * (n + 8) ? 2 * GRAD_NQ * GRAD_PARTS : 4 * (n + 8)));
         if (prec != GP_FP64) {
             L.vec4 = take(vec);  // residual
             L.vec5 = take(vec);  // correction
@@ -301,7 +309,8 @@ hipError_t trailing_packed(gp_handle_t h, hipStream_t s, gp_prec_t prec, const d
         if (e == hipSuccess) e = launch_band_f64(h->band, h->opt.band, P, ldp, C, ldc, M, N, K, info);
         if (e == hipSuccess) e = hipEventRecord(h->ev_band_out, h->band);
     }
-    if (e == hipSuccess) e = launch_lowp_packed(s, prec, h->opt.band, P, ldp, Q, Mpack, qrow0, C, ldc, M, N, K, info);
+    if (e == hipSuccess)
+        e = launch_lowp_packed(s, prec, h->opt.band, P, ldp, Q, Mpack, qrow0, C, ldc, M, N, K, info, h->opt.bf16_split);
     if (e == hipSuccess && h->opt.band > 0) e = hipStreamWaitEvent(s, h->ev_band_out, 0);
     if (h->prof) {
         hipEventRecord(e1, s);
@@ -522,7 +531,7 @@ int potrf_impl(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda,
         const int64_t K = c1 - c0;
         const int64_t c2 = (c1 + NB < n) ? c1 + NB : n;
         const bool packed = prec != GP_FP64 && pb.qbuf && K % 32 == 0;
-        if (packed) HIPCHK(launch_pack_panel(s, prec, A + c1 + c0 * lda, lda, n - c1, K, pb.qbuf));
+        if (packed) HIPCHK(launch_pack_panel(s, prec, A + c1 + c0 * lda, lda, n - c1, K, pb.qbuf, h->opt.bf16_split));
         // trailing update of rows / columns [r0, r1) x [r0, ...) from panel rows r0 ..
         auto update = [&](int64_t r0, int64_t ncols) -> hipError_t {
             const int64_t M = n - r0;
@@ -687,6 +696,7 @@ int loglik_core(gp_handle_t h, gp_op_t op, gp_theta_t th, gp_prec_t prec, int64_
     const Layout lay = layout(h, op, n, 0, prec);
     hipStream_t s = h->stream;
     const CovParams cp = cov_params(th, dim);
+    const int ngrad = th.kind == GP_SEP_MATERN2 ? 4 : 3;
     double *dinv = at<double>(ws, lay.dinv);
     int *sync = at<int>(ws, lay.sync);
     double *z = at<double>(ws, lay.z);
@@ -752,10 +762,10 @@ int loglik_core(gp_handle_t h, gp_op_t op, gp_theta_t th, gp_prec_t prec, int64_
         }
         double *part = at<double>(ws, lay.part);
         HIPCHK(launch_grad_contract(s, cp, n, Xe, C, ldc, x, part, GRAD_PARTS, info));
-        HIPCHK(launch_grad_finish(s, GRAD_PARTS, part, grad3, info));
+        HIPCHK(launch_grad_finish(s, GRAD_PARTS, part, grad3, ngrad, info));
     }
     // a failure anywhere above (info != 0): NaN scalars, alpha and gradient
-    HIPCHK(launch_fail_outputs(s, n, info, out3, alpha_dev, grad3));
+    HIPCHK(launch_fail_outputs(s, n, info, out3, alpha_dev, grad3, ngrad));
     return GP_OK;
 }
 
@@ -830,6 +840,7 @@ static void default_options(gp_options_t *o) {
     o->reorder = 1;
     o->fused_panel = 1;
     o->batch_grid = 0;
+    o->bf16_split = 1;
 }
 
 }  // extern "C"
@@ -965,6 +976,7 @@ int gp_set_options(gp_handle_t h, const gp_options_t *opt) {
     if (opt->fused_panel != 0 && opt->fused_panel != 1) return -2;
     if (opt->batch_grid < -1) return -2;
     if (opt->fail_inject < 0 || opt->fail_inject > 3) return -2;
+    if (opt->bf16_split != 0 && opt->bf16_split != 1) return -2;
     if (!(opt->ir_tol >= 0.0) || isinf(opt->ir_tol)) return GP_ERR_NONFINITE;
     h->opt = *opt;
     return GP_OK;
@@ -993,7 +1005,7 @@ int gp_cov_build(gp_handle_t h, gp_theta_t th, int64_t n, int32_t dim, const dou
     if (!ok_handle(h)) return -1;
     if (int e = check_theta(th)) return e == 1 ? -2 : GP_ERR_NONFINITE;
     if (n < 0) return -3;
-    if (dim < 1 || dim > 16) return -4;
+    if (bad_dim(th, dim)) return -4;
     if (n > 0 && !X) return -5;
     if (n > 0 && !C) return -6;
     if (ldc < (n > 1 ? n : 1)) return -7;
@@ -1007,7 +1019,7 @@ int gp_cross_cov_build(gp_handle_t h, gp_theta_t th, int64_t n, int64_t m, int32
     if (int e = check_theta(th)) return e == 1 ? -2 : GP_ERR_NONFINITE;
     if (n < 0) return -3;
     if (m < 0) return -4;
-    if (dim < 1 || dim > 16) return -5;
+    if (bad_dim(th, dim)) return -5;
     if (n > 0 && !X) return -6;
     if (m > 0 && !Xs) return -7;
     if (n > 0 && m > 0 && !Cs) return -8;
@@ -1154,7 +1166,7 @@ int gp_loglik(gp_handle_t h, gp_theta_t th, gp_prec_t prec, int64_t n, int32_t d
     if (int e = check_theta(th)) return e == 1 ? -2 : GP_ERR_NONFINITE;
     if ((int)prec < GP_FP64 || (int)prec > GP_BF16_TRAIL) return -3;
     if (n < 0) return -4;
-    if (dim < 1 || dim > 16) return -5;
+    if (bad_dim(th, dim)) return -5;
     if (n > 0 && !X) return -6;
     if (n > 0 && !y) return -7;
     if (n > 0 && !C) return -9;
@@ -1175,7 +1187,7 @@ int gp_loglik_noalloc(gp_handle_t h, gp_theta_t th, gp_prec_t prec, int64_t n, i
     if (int e = check_theta(th)) return e == 1 ? -2 : GP_ERR_NONFINITE;
     if ((int)prec < GP_FP64 || (int)prec > GP_BF16_TRAIL) return -3;
     if (n < 0) return -4;
-    if (dim < 1 || dim > 16) return -5;
+    if (bad_dim(th, dim)) return -5;
     if (n > 0 && !X) return -6;
     if (n > 0 && !y) return -7;
     if (n > 0 && !C) return -9;
@@ -1201,7 +1213,7 @@ int gp_loglik_grad(gp_handle_t h, gp_theta_t th, gp_prec_t prec, int64_t n, int3
     if (int e = check_theta(th)) return e == 1 ? -2 : GP_ERR_NONFINITE;
     if ((int)prec < GP_FP64 || (int)prec > GP_BF16_TRAIL) return -3;
     if (n < 0) return -4;
-    if (dim < 1 || dim > 16) return -5;
+    if (bad_dim(th, dim)) return -5;
     if (n > 0 && !X) return -6;
     if (n > 0 && !y) return -7;
     if (n > 0 && !C) return -9;
@@ -1223,7 +1235,7 @@ int gp_krige(gp_handle_t h, gp_theta_t th, int64_t n, int64_t m, int32_t dim, co
     if (int e = check_theta(th)) return e == 1 ? -2 : GP_ERR_NONFINITE;
     if (n < 0) return -3;
     if (m < 0) return -4;
-    if (dim < 1 || dim > 16) return -5;
+    if (bad_dim(th, dim)) return -5;
     if (n > 0 && !X) return -6;
     if (m > 0 && !Xs) return -7;
     if (n > 0 && !L) return -8;
@@ -1264,7 +1276,7 @@ int gp_krige_cov(gp_handle_t h, gp_theta_t th, int64_t n, int64_t m, int32_t dim
     if (int e = check_theta(th)) return e == 1 ? -2 : GP_ERR_NONFINITE;
     if (n < 0) return -3;
     if (m < 0) return -4;
-    if (dim < 1 || dim > 16) return -5;
+    if (bad_dim(th, dim)) return -5;
     if (n > 0 && !X) return -6;
     if (m > 0 && !Xs) return -7;
     if (n > 0 && !L) return -8;
@@ -1310,7 +1322,7 @@ int gp_simulate(gp_handle_t h, gp_theta_t th, int64_t n, int64_t m, int32_t dim,
     if (int e = check_theta(th)) return e == 1 ? -2 : GP_ERR_NONFINITE;
     if (n < 0) return -3;
     if (m < 0) return -4;
-    if (dim < 1 || dim > 16) return -5;
+    if (bad_dim(th, dim)) return -5;
     if (n > 0 && !X) return -6;
     if (m > 0 && !Xs) return -7;
     if (n > 0 && !L) return -8;
@@ -1374,6 +1386,7 @@ int gp_loglik_batched(gp_handle_t h, int32_t nbatch, const gp_theta_t *th_host, 
     int64_t tot = 0;
     for (int b = 0; b < nbatch; ++b) {
         if (int e = check_theta(th_host[b])) return e == 1 ? -3 : GP_ERR_NONFINITE;
+        if (th_host[b].kind == GP_SEP_MATERN2) return GP_ERR_NOT_SUPPORTED;
         if (n_host[b] < 0) return -4;
         if (x_off_host[b] < 0) return -5;
         if (c_off_host[b] < 0) return -6;

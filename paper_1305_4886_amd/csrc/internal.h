@@ -62,7 +62,12 @@ struct CovParams {
     int kind;
     int dim;
     double s2, inv_rho, t2;
+    double inv_rho2;  // GP_SEP_MATERN2: 1 / rho_w
 };
+
+// Components of the gradient contraction's partial sums (the separable
+// family has four parameters, the others three).
+constexpr int GRAD_NQ = 4;
 
 GP_DEV double cov_corr(int kind, double r) {
     if (kind == GP_EXP) return exp(-r);
@@ -363,21 +368,23 @@ hipError_t launch_syrk_lower(hipStream_t s, gp_prec_t prec, int band, const doub
 // 0 .. Mpack - 1 of P (FP64, ld ldp, K columns) rounded once into Q
 // (packed_panel_bytes(Mpack, K) bytes); a call then updates the M x N lower
 // trapezoid whose panel rows start at packed row qrow0 (P points at that row).
-// K must be a multiple of 32.
+// K must be a multiple of 32.  split (BF16 only): the panel is packed as hi
+// and lo = bf16(x - hi) parts (packed_panel_bytes covers both) and every
+// product is formed as hi hi^T + hi lo^T + lo hi^T.
 int64_t packed_rows(int64_t M);
 size_t packed_panel_bytes(int64_t M, int64_t K);
 hipError_t launch_pack_panel(hipStream_t s, gp_prec_t prec, const double *P, int64_t ldp, int64_t M, int64_t K,
-                             void *Q);
+                             void *Q, int split = 0);
 hipError_t launch_syrk_packed(hipStream_t s, gp_prec_t prec, int band, const double *P, int64_t ldp, const void *Q,
                               int64_t Mpack, int64_t qrow0, double *C, int64_t ldc, int64_t M, int64_t N, int64_t K,
-                              const int32_t *info);
+                              const int32_t *info, int split = 0);
 // The two halves of launch_syrk_packed, for callers that overlap them: the FP64
 // tiles on the first `band` tile diagonals, and the low-precision rest.
 hipError_t launch_band_f64(hipStream_t s, int band, const double *P, int64_t ldp, double *C, int64_t ldc, int64_t M,
                            int64_t N, int64_t K, const int32_t *info);
 hipError_t launch_lowp_packed(hipStream_t s, gp_prec_t prec, int band, const double *P, int64_t ldp, const void *Q,
                               int64_t Mpack, int64_t qrow0, double *C, int64_t ldc, int64_t M, int64_t N, int64_t K,
-                              const int32_t *info);
+                              const int32_t *info, int split = 0);
 // C = beta C + alpha P P^T on the lower triangle of the M x M matrix C, P
 // M x K (ld ldp), on the direct-to-LDS MFMA kernel; klo_i: P is zero left of
 // its diagonal (P[i, k] = 0 for k < i), so tile rows i0.. start at k = i0.
@@ -422,9 +429,9 @@ size_t trsv_work_bytes(int64_t n);
 hipError_t launch_trsv(hipStream_t s, int trans, const double *L, int64_t ldl, double *x, int64_t n,
                        const double *dinv, void *work, const int32_t *info, int raise_abort = 0);
 hipError_t launch_solve_status(hipStream_t s, const void *work, int32_t *info);
-// With *info != 0: out3 and grad3 (3 each) and alpha (n) set to NaN (null pointers skipped).
+// With *info != 0: out3 (3), grad (ngrad) and alpha (n) set to NaN (null pointers skipped).
 hipError_t launch_fail_outputs(hipStream_t s, int64_t n, const int32_t *info, double *out3, double *alpha,
-                               double *grad3);
+                               double *grad, int ngrad = 3);
 hipError_t launch_sub_mu(hipStream_t s, int64_t n, const double *y, const double *mu, double *z);
 hipError_t launch_copy_vec(hipStream_t s, int64_t n, const double *a, double *b);
 hipError_t launch_loglik_reduce(hipStream_t s, int64_t n, const double *L, int64_t ldl,
@@ -444,7 +451,7 @@ hipError_t launch_transpose_copy(hipStream_t s, int64_t rows, int64_t cols, cons
 //   C = beta C + alpha A B^T  (A: M x K, B: N x K, both column-major),
 // with GemmDesc's lower / K-range / batch fields (ta = 0, tb = 1 form).
 hipError_t launch_gemm_nt_dma(hipStream_t s, const GemmDesc &d);
-hipError_t launch_grad_finish(hipStream_t s, int nparts, const double *partials, double *grad3,
+hipError_t launch_grad_finish(hipStream_t s, int nparts, const double *partials, double *grad, int ngrad,
                               const int32_t *info);
 // iterative refinement control (state: 8 doubles; done: int32 skip flag)
 hipError_t launch_ir_init(hipStream_t s, int64_t n, const double *b, double *state, int32_t *done,

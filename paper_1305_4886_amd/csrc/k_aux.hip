@@ -49,22 +49,22 @@ __global__ __launch_bounds__(256) void k_transpose_copy(int64_t rows, int64_t co
 
 // Final fixed-order combination of per-workgroup (s, c) partial sums of the
 // gradient contraction: grad[q] = sum over parts.
-__global__ __launch_bounds__(64) void k_grad_finish(int nparts, const double *partials, double *grad3,
+__global__ __launch_bounds__(64) void k_grad_finish(int nparts, const double *partials, double *grad, int ngrad,
                                                     const int32_t *info) {
     if (threadIdx.x != 0) return;
     if (info && *info) {
-        grad3[0] = grad3[1] = grad3[2] = __builtin_nan("");
+        for (int q = 0; q < ngrad; ++q) grad[q] = __builtin_nan("");
         return;
     }
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < ngrad; ++q) {
         CSum a;
         for (int p = 0; p < nparts; ++p) {
             CSum b;
-            b.s = partials[p * 6 + 2 * q];
-            b.c = partials[p * 6 + 2 * q + 1];
+            b.s = partials[p * 2 * GRAD_NQ + 2 * q];
+            b.c = partials[p * 2 * GRAD_NQ + 2 * q + 1];
             a.merge(b);
         }
-        grad3[q] = a.value();
+        grad[q] = a.value();
     }
 }
 
@@ -162,9 +162,9 @@ hipError_t launch_transpose_copy(hipStream_t s, int64_t rows, int64_t cols, cons
     return hipGetLastError();
 }
 
-hipError_t launch_grad_finish(hipStream_t s, int nparts, const double *partials, double *grad3,
+hipError_t launch_grad_finish(hipStream_t s, int nparts, const double *partials, double *grad, int ngrad,
                               const int32_t *info) {
-    hipLaunchKernelGGL(k_grad_finish, dim3(1), dim3(64), 0, s, nparts, partials, grad3, info);
+    hipLaunchKernelGGL(k_grad_finish, dim3(1), dim3(64), 0, s, nparts, partials, grad, ngrad, info);
     return hipGetLastError();
 }
 

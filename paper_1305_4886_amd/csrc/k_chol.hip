@@ -930,14 +930,12 @@ __global__ void k_solve_status(const int *sync, int32_t *info) {
 
 // A failed evaluation (info != 0): NaN scalars, NaN alpha and gradient.
 __global__ __launch_bounds__(256) void k_fail_outputs(int64_t n, const int32_t *info, double *out3, double *alpha,
-                                                      double *grad3) {
+                                                      double *grad, int ngrad) {
     if (*info == 0) return;
     const double nan = __builtin_nan("");
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < 3) {
-        if (out3) out3[i] = nan;
-        if (grad3) grad3[i] = nan;
-    }
+    if (i < 3 && out3) out3[i] = nan;
+    if (i < ngrad && grad) grad[i] = nan;
     if (alpha && i < n) alpha[i] = nan;
 }
 
@@ -1071,10 +1069,10 @@ hipError_t launch_solve_status(hipStream_t s, const void *work, int32_t *info) {
 }
 
 hipError_t launch_fail_outputs(hipStream_t s, int64_t n, const int32_t *info, double *out3, double *alpha,
-                               double *grad3) {
-    const int64_t cnt = alpha && n > 3 ? n : 3;
+                               double *grad, int ngrad) {
+    const int64_t cnt = alpha && n > 4 ? n : 4;
     hipLaunchKernelGGL(k_fail_outputs, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, n, info, out3, alpha,
-                       grad3);
+                       grad, ngrad);
     return hipGetLastError();
 }
 

@@ -590,10 +590,14 @@ __global__ __launch_bounds__(256, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
 // products from the FP64 tile.  D layout of both (checked with a probe):
 // lane l, register r holds row 4 (l / 16) + r, column l % 16.
 // ---------------------------------------------------------------------------
-template <int PREC>
+//   BF16 split (SPLIT 2): a second copy of the same layout follows the first
+//   (at element Mp Kp, Kp = K rounded up to 32) holding the remainders
+//   lo = bf16(x - hi), hi = bf16(x): x = hi + lo to about 16 significant bits.
+template <int PREC, int SPLIT = 1>
 __global__ void k_pack_panel(const double *__restrict__ P, int64_t lda, int64_t M, int64_t Mp, int64_t K,
                              void *__restrict__ Q) {
-    const int64_t total = Mp * K;
+    const int64_t Kp = PREC == 1 ? K : ((K + 31) / 32) * 32;
+    const int64_t total = Mp * Kp;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
         if (PREC == 1) {  // e = k Mp + r: coalesced in r on both sides
             const int64_t k = e / Mp, r = e - k * Mp;
@@ -601,24 +605,32 @@ __global__ void k_pack_panel(const double *__restrict__ P, int64_t lda, int64_t 
         } else {          // e = (s Mp + r) 32 + kk
             const int64_t kk = e & 31, sr = e >> 5;
             const int64_t sl = sr / Mp, r = sr - sl * Mp, k = 32 * sl + kk;
-            static_cast<__bf16 *>(Q)[e] = (r < M && k < K) ? (__bf16)P[r + k * lda] : (__bf16)0.f;
+            const double x = (r < M && k < K) ? P[r + k * lda] : 0.0;
+            const __bf16 hi = (__bf16)x;
+            static_cast<__bf16 *>(Q)[e] = hi;
+            if (SPLIT == 2) static_cast<__bf16 *>(Q)[total + e] = (__bf16)(x - (double)(float)hi);
         }
     }
 }
 
-template <int PREC, int TAG, int STAGES = 4, int BKD = (PREC == 1 ? 16 : 32)>
+// SPLIT 2 (BF16 only): the panel comes as hi and lo parts (k_pack_panel<2, 2>)
+// and each product is hi hi^T + hi lo^T + lo hi^T, three MFMAs per block
+// (the lo lo^T term, about 2^-16 of the product, is dropped).
+template <int PREC, int TAG, int STAGES = 4, int BKD = (PREC == 1 ? 16 : 32), int SPLIT = 1>
 __global__ __launch_bounds__(256, 2) void k_syrk_pk(GemmDesc d, TileMap tm, const void *__restrict__ Qv, int64_t Mp,
                                                     int64_t qrow0) {
     constexpr int BM = 128, WTM = 64, FM = 4, FN = 4;
     constexpr int EB = PREC == 1 ? 4 : 2;                       // bytes per element
-    constexpr int CHUNKS = 2 * BM * BKD * EB / 1024;            // 1 KB copies per slab (both operands)
+    constexpr int PART = BM * BKD * EB;                         // bytes of one operand part per slab
+    constexpr int CHUNKS = 2 * BM * BKD * EB / 1024;            // 1 KB copies per slab and part (both operands)
     constexpr int CPO = CHUNKS / 2;                             // per operand
-    constexpr int PER = CHUNKS / 4;                             // per wave
+    constexpr int PER = SPLIT * CHUNKS / 4;                     // per wave
     constexpr int NKK = PREC == 1 ? BKD / 4 : BKD / 32;         // MFMA K-steps per slab
+    static_assert(SPLIT == 1 || (PREC == 2 && SPLIT == 2 && BKD == 32), "split: BF16, one 32-column slab");
     static_assert((STAGES - 2) * PER < 64, "outstanding copies exceed vmcnt");
     static_assert(PER % NKK == 0 && (PREC == 1 ? BKD % 16 == 0 : BKD % 32 == 0), "slab shape");
-    static_assert(STAGES * 2 * BM * BKD * EB >= 4 * 2048 * 8, "the ring holds the epilogue's four wave regions");
-    __shared__ __attribute__((aligned(16))) char Ls[STAGES][2][BM * BKD * EB];
+    static_assert(STAGES * 2 * SPLIT * PART >= 4 * 2048 * 8, "the ring holds the epilogue's four wave regions");
+    __shared__ __attribute__((aligned(16))) char Ls[STAGES][2][SPLIT * PART];
 
     if (d.info && *d.info) return;
     const int64_t t = xcd_remap(tm);
@@ -642,16 +654,21 @@ __global__ __launch_bounds__(256, 2) void k_syrk_pk(GemmDesc d, TileMap tm, cons
 
     // copy q of this wave for slab `slab` into stage st: chunk c = wave + 4 q;
     // BF16 chunk cc is rows 16 (cc % 8) .. of the (cc / 8)-th 32-column slab
+    // (split: copies CHUNKS .. 2 CHUNKS - 1 take the lo part, one packed panel further on)
+    const int64_t part_bytes = SPLIT == 2 ? 2 * Mp * (((d.K + 31) / 32) * 32) : 0;
     auto copy1 = [&](int slab, int st, int q) {
-        const int c = wave + 4 * q;
+        const int c0 = wave + 4 * q;
+        const int part = c0 / CHUNKS, c = c0 % CHUNKS;
         const int op = c / CPO, cc = c % CPO;
         const int64_t row0 = qrow0 + (op ? j0 : i0);
         const char *src;
         if (PREC == 1)
             src = Q + 4 * ((int64_t)(slab * BKD + 2 * cc) * Mp + row0);
         else
-            src = Q + 2 * (((int64_t)(slab * (BKD / 32) + cc / 8) * Mp + row0) * 32 + 512 * (int64_t)(cc % 8));
-        lds_dma_dwordx4(reinterpret_cast<const double *>(src), voff, (uint32_t)(uintptr_t)&Ls[st][op][1024 * cc]);
+            src = Q + part * part_bytes +
+                  2 * (((int64_t)(slab * (BKD / 32) + cc / 8) * Mp + row0) * 32 + 512 * (int64_t)(cc % 8));
+        lds_dma_dwordx4(reinterpret_cast<const double *>(src), voff,
+                        (uint32_t)(uintptr_t)&Ls[st][op][part * PART + 1024 * cc]);
     };
 
 #pragma unroll
@@ -694,6 +711,35 @@ __global__ __launch_bounds__(256, 2) void k_syrk_pk(GemmDesc d, TileMap tm, cons
                         acc[q][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b[n], acc[q][n], 0, 0, 0);
                     __builtin_amdgcn_sched_barrier(0);
                     if (more && q == 3) copy1(ns, nst, kk);  // PER == NKK: one copy per K-step
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            } else if (SPLIT == 2) {
+                const __bf16 *A = reinterpret_cast<const __bf16 *>(&Ls[st][0][0]);
+                const __bf16 *B = reinterpret_cast<const __bf16 *>(&Ls[st][1][0]);
+                const __bf16 *Al = reinterpret_cast<const __bf16 *>(&Ls[st][0][PART]);
+                const __bf16 *Bl = reinterpret_cast<const __bf16 *>(&Ls[st][1][PART]);
+                v8bf a[FM], b[FN], al[FM], bl[FN];
+#pragma unroll
+                for (int m = 0; m < FM; ++m) {
+                    const int o = (wm * WTM + m * 16 + (lane & 15)) * 32 + 8 * (lane >> 4);
+                    a[m] = *reinterpret_cast<const v8bf *>(&A[o]);
+                    al[m] = *reinterpret_cast<const v8bf *>(&Al[o]);
+                }
+#pragma unroll
+                for (int n = 0; n < FN; ++n) {
+                    const int o = (wn * WTM + n * 16 + (lane & 15)) * 32 + 8 * (lane >> 4);
+                    b[n] = *reinterpret_cast<const v8bf *>(&B[o]);
+                    bl[n] = *reinterpret_cast<const v8bf *>(&Bl[o]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int q = 0; q < FM * FN; ++q) {
+                    const int m = q >> 2, n = q & 3;
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[m], b[n], acc[m][n], 0, 0, 0);
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bl[n], acc[m][n], 0, 0, 0);
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[n], acc[m][n], 0, 0, 0);
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (more && (q & 1) == 1) copy1(ns, nst, q >> 1);  // PER == 8 copies per slab
                     __builtin_amdgcn_sched_barrier(0);
                 }
             } else {
@@ -1035,17 +1081,20 @@ hipError_t launch_syrk_lower(hipStream_t s, gp_prec_t prec, int band, const doub
 int64_t packed_rows(int64_t M) { return ((M + 127) / 128 + 1) * 128; }
 
 size_t packed_panel_bytes(int64_t M, int64_t K) {
+    // FP32: one float per element; BF16 split: two bf16 parts -- the same size
     return (size_t)packed_rows(M) * (size_t)(((K + 31) / 32) * 32) * sizeof(float);
 }
 
 hipError_t launch_pack_panel(hipStream_t s, gp_prec_t prec, const double *P, int64_t ldp, int64_t M, int64_t K,
-                             void *Q) {
+                             void *Q, int split) {
     if (M <= 0 || K <= 0) return hipSuccess;
     const int64_t Mp = packed_rows(M);
     const int64_t total = prec == GP_FP32_TRAIL ? Mp * K : Mp * ((K + 31) / 32) * 32;
     const int64_t g = (total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096;
     if (prec == GP_FP32_TRAIL)
         hipLaunchKernelGGL((k_pack_panel<1>), dim3((unsigned)g), dim3(256), 0, s, P, ldp, M, Mp, K, Q);
+    else if (split)
+        hipLaunchKernelGGL((k_pack_panel<2, 2>), dim3((unsigned)g), dim3(256), 0, s, P, ldp, M, Mp, K, Q);
     else
         hipLaunchKernelGGL((k_pack_panel<2>), dim3((unsigned)g), dim3(256), 0, s, P, ldp, M, Mp, K, Q);
     return hipGetLastError();
@@ -1075,7 +1124,7 @@ hipError_t launch_band_f64(hipStream_t s, int band, const double *P, int64_t ldp
 
 hipError_t launch_lowp_packed(hipStream_t s, gp_prec_t prec, int band, const double *P, int64_t ldp, const void *Q,
                               int64_t Mpack, int64_t qrow0, double *C, int64_t ldc, int64_t M, int64_t N, int64_t K,
-                              const int32_t *info) {
+                              const int32_t *info, int split) {
     if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
     GemmDesc d{};
     d.A = P; d.lda = ldp; d.B = P; d.ldb = ldp; d.C = C; d.ldc = ldc;
@@ -1092,6 +1141,8 @@ hipError_t launch_lowp_packed(hipStream_t s, gp_prec_t prec, int band, const dou
     if (((uintptr_t)Q & 15) != 0 || qrow0 % 64 != 0) return hipErrorInvalidValue;  // 16-byte copies
     if (prec == GP_FP32_TRAIL)
         hipLaunchKernelGGL((k_syrk_pk<1, 1, 2, 32>), dim3((unsigned)g), dim3(256), 0, s, d, tm, Q, Mp, qrow0);
+    else if (split)  // hi / lo parts, one 32-column slab of each per LDS stage
+        hipLaunchKernelGGL((k_syrk_pk<2, 1, 2, 32, 2>), dim3((unsigned)g), dim3(256), 0, s, d, tm, Q, Mp, qrow0);
     else
         if (K % 64 == 0)  // two 32-column packed slabs per LDS stage
             hipLaunchKernelGGL((k_syrk_pk<2, 1, 2, 64>), dim3((unsigned)g), dim3(256), 0, s, d, tm, Q, Mp, qrow0);
@@ -1102,10 +1153,10 @@ hipError_t launch_lowp_packed(hipStream_t s, gp_prec_t prec, int band, const dou
 
 hipError_t launch_syrk_packed(hipStream_t s, gp_prec_t prec, int band, const double *P, int64_t ldp, const void *Q,
                               int64_t Mpack, int64_t qrow0, double *C, int64_t ldc, int64_t M, int64_t N, int64_t K,
-                              const int32_t *info) {
+                              const int32_t *info, int split) {
     hipError_t e = launch_band_f64(s, band, P, ldp, C, ldc, M, N, K, info);
     if (e != hipSuccess) return e;
-    return launch_lowp_packed(s, prec, band, P, ldp, Q, Mpack, qrow0, C, ldc, M, N, K, info);
+    return launch_lowp_packed(s, prec, band, P, ldp, Q, Mpack, qrow0, C, ldc, M, N, K, info, split);
 }
 
 hipError_t launch_gemm_nt_dma(hipStream_t s, const GemmDesc &d) {

@@ -11,7 +11,8 @@ to find the MLE; the paper's example uses L-BFGS-B, Section 4.3), prediction
 with standard errors, the full prediction covariance and simulation of
 realizations conditional on the data at the estimate.
 
-Parameters are log_theta = (log sigma^2, log rho, log tau^2).  Every
+Parameters are log_theta = (log sigma^2, log rho, log tau^2), with a fourth
+entry log rho_w for the separable spectral family (kernel 3).  Every
 numerical step runs in the GPU library; this module only keeps state and
 drives scipy's optimiser over the values and gradients the library returns.
 """
@@ -62,7 +63,7 @@ class KrigeProblem:
     # ---- bookkeeping ------------------------------------------------------
     @staticmethod
     def _key(log_theta, prec):
-        return (tuple(float(v) for v in np.asarray(log_theta, dtype=np.float64).reshape(3)), int(prec))
+        return (tuple(float(v) for v in np.asarray(log_theta, dtype=np.float64).reshape(-1)), int(prec))
 
     def _ws(self, grad, prec):
         cache = self._ws_g if grad else self._ws_l
@@ -71,7 +72,7 @@ class KrigeProblem:
         return cache[prec]
 
     def _th(self, log_theta):
-        return theta(self.kind, log=[float(v) for v in np.asarray(log_theta).reshape(3)])
+        return theta(self.kind, log=[float(v) for v in np.asarray(log_theta).reshape(-1)])
 
     @staticmethod
     def _check(r):
@@ -119,18 +120,18 @@ class KrigeProblem:
 
     def optimize(self, log_theta0=None, bounds=None, method="L-BFGS-B", options=None):
         """Maximise the log-likelihood over log_theta with scipy's L-BFGS-B on
-        the library's value and adjoint gradient.  bounds: 3 (lo, hi) pairs in
+        the library's value and adjoint gradient.  bounds: (lo, hi) pairs in
         log coordinates (None entries unbounded).  Sets and returns the
         estimate; the scipy result is kept in self.opt_result."""
         from scipy.optimize import minimize
 
-        x0 = np.asarray(self.theta if log_theta0 is None else log_theta0, dtype=np.float64).reshape(3)
+        x0 = np.asarray(self.theta if log_theta0 is None else log_theta0, dtype=np.float64).reshape(-1)
 
         def f(t):
             try:
                 ll, g = self.log_density_grad(t)
             except NotPositiveDefinite:
-                return math.inf, np.zeros(3)
+                return math.inf, np.zeros(x0.size)
             return -ll, -g
 
         res = minimize(f, x0, jac=True, method=method, bounds=bounds,

@@ -166,7 +166,7 @@ def th_(kind=0, ls=0.0, lr=math.log(0.1), lt=math.log(0.1)):
 def test_cov_build_arguments(ctx):
     L, c = gp.lib(), ctx
     h, n = c["h"].ptr, c["n"]
-    assert L.gp_cov_build(h, th_(kind=3), n, 2, P(c["X"]), P(c["S"]), n) == -2
+    assert L.gp_cov_build(h, th_(kind=4), n, 2, P(c["X"]), P(c["S"]), n) == -2
     assert L.gp_cov_build(h, th_(ls=math.nan), n, 2, P(c["X"]), P(c["S"]), n) == NONFINITE
     assert L.gp_cov_build(h, th_(lt=math.inf), n, 2, P(c["X"]), P(c["S"]), n) == NONFINITE
     assert L.gp_cov_build(h, th_(lr=-math.inf), n, 2, P(c["X"]), P(c["S"]), n) == NONFINITE
