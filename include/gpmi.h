@@ -61,6 +61,8 @@ extern "C" {
 #define GP_ERR_NOT_SUPPORTED (-1004)/* combination of options not implemented */
 #define GP_ERR_BAD_HANDLE (-1005)
 #define GP_ERR_SCRATCH_LIMIT (-1006)/* gp_loglik_noalloc: the problem's workspace exceeds GP_SCRATCH_BYTES */
+#define GP_ERR_NO_CANDIDATE (-1007) /* an autotuner could time no candidate (each needs more workspace) */
+#define GP_ERR_IO (-1008)           /* a tuning-table file could not be read, parsed or written */
 
 /* Size of the static per-device workspace of gp_loglik_noalloc (128 MiB). */
 #define GP_SCRATCH_BYTES (128u << 20)
@@ -130,6 +132,9 @@ typedef struct {
                             BF16 parts of the panel (x = hi + lo, hi = bf16(x), lo = bf16(x - hi);
                             hi hi^T + hi lo^T + lo hi^T on the BF16 matrix cores: about 16 significant
                             bits per operand instead of 8); 0 = one BF16 product */
+    int32_t syrk_slab;   /* FP64 trailing update, 128 x 128 tiles: K-slab shape staged through LDS per
+                            barrier -- 16 columns in 2 stages (16, and 0 = default) or 8 columns in 4
+                            stages (8).  Chosen per problem size by gp_tune_potrf. */
 } gp_options_t;
 
 /* ---- handle ------------------------------------------------------------ */
@@ -182,17 +187,22 @@ int gp_cross_cov_build(gp_handle_t h, gp_theta_t th, int64_t n, int64_t m, int32
 int gp_potrf(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda,
              int32_t *info_dev, void *ws, size_t ws_bytes);
 
-/* Autotuner for gp_potrf's panel width and reserved compute units: for each
- * pair (nb_cand[a], cu_cand[b]) [host arrays; nb a positive multiple of 64,
- * panel_cus >= 0] it fills A [dev, lda >= n; overwritten] with a synthetic
+/* Autotuner for gp_potrf's panel width, reserved compute units and (FP64)
+ * trailing-update tile shape: for each pair (nb_cand[a], cu_cand[b]) [host
+ * arrays; nb a positive multiple of 64, panel_cus >= 0] and, in FP64, each
+ * K-slab shape of the 128 x 128 trailing-update tile (16 columns x 2 stages,
+ * 8 x 4), it fills A [dev, lda >= n; overwritten] with a synthetic
  * positive-definite matrix of order n (exp(-8 |i - j| / n) + I), times
  * gp_potrf with lookahead on the handle's stream (HIP events, second of two
- * runs) and writes the milliseconds to ms_out[a * n_cu + b] [host, may be
- * NULL; -1 where the candidate's workspace exceeds ws_bytes].  The fastest
- * pair is stored in the handle's options (nb, lookahead = 1, panel_cus);
- * on error the options are left unchanged.  ws must hold
- * gp_workspace_size(GP_OP_POTRF, n) for the candidates to be timed.
- * Synchronises the handle's stream; info_dev [dev] is scratch. */
+ * runs) and writes the milliseconds of the faster tile shape to
+ * ms_out[a * n_cu + b] [host, may be NULL; -1 where the candidate's workspace
+ * exceeds ws_bytes].  The fastest choice is stored in the handle's options
+ * (nb, lookahead = 1, panel_cus, syrk_slab) and in its tuning table for
+ * (prec, floor(log2 n)), which gp_potrf and every factorising call consult
+ * when options.nb is 0 (automatic); on error the options are left
+ * unchanged.  Returns GP_ERR_NO_CANDIDATE when no candidate fits in ws (it
+ * must hold gp_workspace_size(GP_OP_POTRF, n)).  Synchronises the handle's
+ * stream; info_dev [dev] is scratch. */
 int gp_tune_potrf(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda,
                   const int32_t *nb_cand, int32_t n_nb, const int32_t *cu_cand, int32_t n_cu,
                   int32_t *info_dev, double *ms_out, void *ws, size_t ws_bytes);
@@ -340,14 +350,30 @@ int gp_loglik_batched(gp_handle_t h, int32_t nbatch, const gp_theta_t *th_host,
  * the batch given by the same arguments as gp_loglik_batched twice on the
  * handle's stream and writes the milliseconds of the second run to ms_out[c]
  * [host, may be NULL; -1 where the candidate's workspace exceeds ws_bytes].
- * The fastest candidate is stored in the handle's options (batch_grid); on
- * error the options are left unchanged.  C_pool, out3_dev and info_dev are
+ * The fastest candidate is stored in the handle's options (batch_grid) and
+ * in its tuning table for the largest problem's size bucket; on error the
+ * options are left unchanged (GP_ERR_NO_CANDIDATE: no candidate fits in ws).  C_pool, out3_dev and info_dev are
  * written as by gp_loglik_batched (they hold the last candidate's results).
  * Synchronises the handle's stream. */
 int gp_tune_batched(gp_handle_t h, int32_t nbatch, const gp_theta_t *th_host, const int64_t *n_host,
                     const int64_t *x_off_host, const int64_t *c_off_host, int32_t dim, const double *X,
                     const double *y, double *C_pool, double *out3_dev, int32_t *info_dev, const int32_t *grid_cand,
                     int32_t n_cand, double *ms_out, void *ws, size_t ws_bytes);
+
+/* ---- the tuning table -------------------------------------------------------
+ * The handle keeps the autotuners' choices per (operation, precision, size
+ * bucket floor(log2 n)): panel width, reserved compute units and trailing-
+ * update tile shape for the factorisation (used when options.nb = 0), the
+ * schedule for the batched call (used when options.batch_grid = 0; bucket of
+ * the largest problem).  gp_tune_save writes it to the text file `path` (one
+ * line per entry, tagged with the device's architecture name);
+ * gp_tune_load merges the entries of `path` that carry this device's
+ * architecture (*loaded [host, nullable] = their count); gp_tune_clear
+ * empties it.  File errors and malformed lines return GP_ERR_IO (nothing
+ * merged). */
+int gp_tune_save(gp_handle_t h, const char *path);
+int gp_tune_load(gp_handle_t h, const char *path, int32_t *loaded);
+int gp_tune_clear(gp_handle_t h);
 
 /* ---- spatial ordering ----------------------------------------------------
  * perm_dev [dev, n] <- the permutation that sorts the points X [dev, n x 2]

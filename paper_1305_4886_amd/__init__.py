@@ -18,6 +18,7 @@ import threading
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgpmi.so")
+TUNING_TABLE = os.path.join(_HERE, "tuning.txt")  # written by paper_1305_4886_amd/tune.py
 
 GP_EXP, GP_MATERN32, GP_MATERN52, GP_SEP_MATERN2 = 0, 1, 2, 3
 GP_FP64, GP_FP32_TRAIL, GP_BF16_TRAIL = 0, 1, 2
@@ -33,7 +34,7 @@ EXPORTED = ["gp_create", "gp_destroy", "gp_set_stream", "gp_set_options", "gp_ge
             "gp_strerror", "gp_profile", "gp_profile_read", "gp_workspace_size", "gp_cov_build", "gp_cross_cov_build", "gp_potrf",
             "gp_trsv", "gp_trsm", "gp_loglik", "gp_loglik_grad", "gp_krige", "gp_loglik_batched",
             "gp_morton_order", "gp_tune_potrf", "gp_tune_batched", "gp_loglik_noalloc", "gp_krige_cov",
-            "gp_trmm", "gp_simulate"]
+            "gp_trmm", "gp_simulate", "gp_tune_save", "gp_tune_load", "gp_tune_clear"]
 
 
 class Theta(ctypes.Structure):
@@ -47,7 +48,8 @@ class Options(ctypes.Structure):
                 ("ir_max_iter", ctypes.c_int32), ("ir_tol", ctypes.c_double),
                 ("reorder", ctypes.c_int32), ("panel_cus", ctypes.c_int32),
                 ("fused_panel", ctypes.c_int32), ("batch_grid", ctypes.c_int32),
-                ("fail_inject", ctypes.c_int32), ("bf16_split", ctypes.c_int32)]
+                ("fail_inject", ctypes.c_int32), ("bf16_split", ctypes.c_int32),
+                ("syrk_slab", ctypes.c_int32)]
 
 
 class GPError(RuntimeError):
@@ -100,6 +102,9 @@ def lib():
         L.gp_loglik_grad.argtypes = [vp, Theta, ctypes.c_int, i64, i32, vp, vp, vp, vp, i64, vp, vp, vp, vp,
                                      vp, vp, sz]
         L.gp_krige.argtypes = [vp, Theta, i64, i64, i32, vp, vp, vp, i64, vp, dbl, vp, vp, i32, vp, sz]
+        L.gp_tune_save.argtypes = [vp, ctypes.c_char_p]
+        L.gp_tune_load.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(i32)]
+        L.gp_tune_clear.argtypes = [vp]
         L.gp_krige_cov.argtypes = [vp, Theta, i64, i64, i32, vp, vp, vp, i64, i32, vp, i64, vp, sz]
         L.gp_trmm.argtypes = [vp, i64, i64, vp, i64, vp, i64, vp, i64, vp, sz]
         L.gp_simulate.argtypes = [vp, Theta, i64, i64, i32, vp, vp, vp, i64, vp, dbl, i32, i64, vp, i64, vp, i64,
@@ -159,6 +164,10 @@ class Handle:
         s = stream if stream is not None else torch.cuda.current_stream()
         check(lib().gp_create(ctypes.byref(self._h), ctypes.c_void_p(s.cuda_stream)))
         self.stream = s
+        # the tuned choices measured on this architecture and shipped with the
+        # package (entries of other architectures are skipped by the library)
+        if os.path.exists(TUNING_TABLE):
+            self.tune_load(TUNING_TABLE)
 
     def __del__(self):
         try:
@@ -186,6 +195,23 @@ class Handle:
             setattr(o, k, v)
         check(lib().gp_set_options(self._h, ctypes.byref(o)))
 
+    def tune_save(self, path):
+        check(lib().gp_tune_save(self._h, os.fsencode(path)))
+
+    def tune_load(self, path):
+        n = ctypes.c_int32(0)
+        check(lib().gp_tune_load(self._h, os.fsencode(path), ctypes.byref(n)))
+        return n.value
+
+    def tune_clear(self):
+        check(lib().gp_tune_clear(self._h))
+
+    def tune_reset(self):
+        """Back to the shipped table (or an empty one)."""
+        self.tune_clear()
+        if os.path.exists(TUNING_TABLE):
+            self.tune_load(TUNING_TABLE)
+
     def profile(self, enable=True):
         check(lib().gp_profile(self._h, 1 if enable else 0))
 
@@ -196,8 +222,9 @@ class Handle:
         return int(out[0]), float(out[1]), float(out[2])
 
     def tune_potrf(self, n, prec=GP_FP64, nb=(256, 384, 512, 768, 1024), panel_cus=(0, 8, 16)):
-        """Time gp_potrf over (nb, panel_cus) on a synthetic matrix of order n and keep the fastest
-        in this handle's options.  Returns {(nb, panel_cus): ms} (-1: did not fit)."""
+        """Time gp_potrf over (nb, panel_cus) -- and, in FP64, both trailing-update tile shapes --
+        on a synthetic matrix of order n; keep the fastest in this handle's options and in its
+        tuning table for n's size bucket.  Returns {(nb, panel_cus): ms} (-1: did not fit)."""
         torch = _torch()
         nb = [int(v) for v in nb]
         cus = [int(v) for v in panel_cus]
@@ -236,7 +263,7 @@ class Handle:
         c_off = np.concatenate([[0], np.cumsum(sizes * sizes)[:-1]]).astype(np.int64)
         th_arr = (Theta * nb)(*thetas)
         saved = self.options()
-        self.set_options(batch_grid=0)  # the persistent workspace is the larger one
+        self.set_options(batch_grid=1)  # a persistent schedule: its workspace is the larger one
         ws = self.workspace(GP_OP_BATCHED, int(sizes.max()), nb)
         self.set_options(batch_grid=saved.batch_grid)
         C_pool = torch.empty(max(int((sizes * sizes).sum()), 1), dtype=torch.float64, device="cuda")

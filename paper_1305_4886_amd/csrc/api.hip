@@ -12,6 +12,7 @@
 // runs, which keeps the diagonal-block chain (the critical path of Section 2.1)
 // off the critical path of the device.
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <mutex>
@@ -78,8 +79,50 @@ struct PanelBufs {
 // whose FP32 / BF16 products accumulate over the panel width (768 measured
 // 2 % faster than 512 in FP64; no difference in the mixed modes, where the
 // shorter accumulation keeps the log-determinant error lower).
-int64_t panel_width(gp_handle_t h, gp_prec_t prec) {
-    return h->opt.nb > 0 ? h->opt.nb : (prec == GP_FP64 ? 768 : (prec == GP_FP32_TRAIL ? 512 : 640));
+// Size bucket of the tuning table: floor(log2 n).
+int size_bucket(int64_t n) {
+    int b = 0;
+    while (b < 62 && (int64_t(2) << b) <= n) ++b;
+    return b;
+}
+
+const TuneEntry *tune_find(gp_handle_t h, int op, gp_prec_t prec, int64_t n) {
+    const int b = size_bucket(n);
+    for (const TuneEntry &e : h->tune)
+        if (e.op == op && e.prec == (int32_t)prec && e.bucket == b) return &e;
+    return nullptr;
+}
+
+void tune_store(gp_handle_t h, const TuneEntry &e) {
+    for (TuneEntry &x : h->tune)
+        if (x.op == e.op && x.prec == e.prec && x.bucket == e.bucket) {
+            x = e;
+            return;
+        }
+    h->tune.push_back(e);
+}
+
+// The factorisation's choices for (prec, n): explicit options (nb > 0) win;
+// with nb = 0 (automatic) a tuned entry for n's size bucket, else the
+// defaults.
+struct PotrfChoice {
+    int64_t nb;
+    int panel_cus, slab;
+};
+PotrfChoice potrf_choice(gp_handle_t h, gp_prec_t prec, int64_t n) {
+    if (h->opt.nb > 0 || h->tuning) return {h->opt.nb > 0 ? h->opt.nb : 768, h->opt.panel_cus, h->opt.syrk_slab};
+    if (const TuneEntry *e = tune_find(h, 0, prec, n)) return {e->nb, e->panel_cus, e->syrk_slab};
+    return {prec == GP_FP64 ? 768 : (prec == GP_FP32_TRAIL ? 512 : 640), h->opt.panel_cus, h->opt.syrk_slab};
+}
+
+int64_t panel_width(gp_handle_t h, gp_prec_t prec, int64_t n) { return potrf_choice(h, prec, n).nb; }
+
+// The batched call's schedule: the option unless it is the automatic 0 and a
+// tuned entry exists for the largest problem's size bucket.
+int batch_grid_choice(gp_handle_t h, int64_t nmax) {
+    if (h->opt.batch_grid != 0 || h->tuning) return h->opt.batch_grid;
+    if (const TuneEntry *e = tune_find(h, 1, GP_FP64, nmax)) return e->batch_grid;
+    return 0;
 }
 
 // Reserved compute unit r of `reserve`: spaced ncu / reserve apart and offset
@@ -135,7 +178,7 @@ Layout layout(gp_handle_t h, gp_op_t op, int64_t n, int64_t m, gp_prec_t prec) {
     };
     const int64_t nb = nblocks(n);
     const size_t vec = sizeof(double) * (size_t)(n > 0 ? n : 1);
-    const int64_t NB = panel_width(h, prec);
+    const int64_t NB = panel_width(h, prec, n);
     auto take_panel = [&]() {
         if (n <= NB) return;
         L.pbuf = take(sizeof(double) * (size_t)(n - NB) * (size_t)NB);
@@ -188,7 +231,7 @@ Layout layout(gp_handle_t h, gp_op_t op, int64_t n, int64_t m, gp_prec_t prec) {
         }
         break;
     case GP_OP_BATCHED:
-        L.total = batch_ws_bytes(n > 0 ? n : 1, m > 0 ? m : 1, h->opt.batch_grid >= 0);
+        L.total = batch_ws_bytes(n > 0 ? n : 1, m > 0 ? m : 1, batch_grid_choice(h, n) >= 0);
         return L;
     case GP_OP_MORTON:
         L.keys = take(sizeof(uint64_t) * (size_t)next_pow2(n > 0 ? n : 1));
@@ -210,7 +253,7 @@ Layout layout(gp_handle_t h, gp_op_t op, int64_t n, int64_t m, gp_prec_t prec) {
         }
         L.dinv2 = take(sizeof(double) * DB * DB * (size_t)nblocks(m));
         L.pflags2 = take(panel_flags_bytes());
-        const int64_t NB2 = panel_width(h, GP_FP64);
+        const int64_t NB2 = panel_width(h, GP_FP64, m);
         if (m > NB2) {
             L.pbuf2 = take(sizeof(double) * (size_t)(m - NB2) * (size_t)NB2);
             L.vinv2 = take(sizeof(double) * (size_t)NB2 * (size_t)NB2);
@@ -262,7 +305,7 @@ PanelBufs panel_bufs(void *ws, const Layout &L) {
 
 // Trailing update, bracketed by events when the handle profiles.
 hipError_t trailing(gp_handle_t h, hipStream_t s, gp_prec_t prec, const double *P, int64_t ldp, double *C,
-                    int64_t ldc, int64_t M, int64_t N, int64_t K, const int32_t *info) {
+                    int64_t ldc, int64_t M, int64_t N, int64_t K, const int32_t *info, int slab) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (h->prof) {
         while (h->prof_ev.size() < h->prof_used + 2) {
@@ -275,7 +318,7 @@ hipError_t trailing(gp_handle_t h, hipStream_t s, gp_prec_t prec, const double *
         h->prof_used += 2;
         hipEventRecord(e0, s);
     }
-    hipError_t e = launch_syrk_lower(s, prec, h->opt.band, P, ldp, C, ldc, M, N, K, info, 1);
+    hipError_t e = launch_syrk_lower(s, prec, h->opt.band, P, ldp, C, ldc, M, N, K, info, 1, slab);
     if (h->prof) {
         hipEventRecord(e1, s);
         h->prof_flops += syrk_flops(M, N, K);
@@ -461,14 +504,15 @@ static int make_masked_streams(gp_handle_t h, int reserve) {
 int potrf_impl(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda, int32_t *info,
                double *dinv, const PanelBufs &pb) {
     hipStream_t user = h->stream;
-    const int64_t NB = panel_width(h, prec);
+    const PotrfChoice ch = potrf_choice(h, prec, n);
+    const int64_t NB = ch.nb;
     HIPCHK(launch_set_info(user, info));
     if (n <= 0) return GP_OK;
 
     hipStream_t s = user, side = h->side;
     const bool la = h->opt.lookahead && n > NB;
-    if (la && h->opt.panel_cus > 0) {
-        int rc = make_masked_streams(h, h->opt.panel_cus);
+    if (la && ch.panel_cus > 0) {
+        int rc = make_masked_streams(h, ch.panel_cus);
         if (rc) return rc;
         if (h->main_cu) {
             s = h->main_cu;
@@ -538,7 +582,7 @@ int potrf_impl(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda,
             if (packed)
                 return trailing_packed(h, s, prec, A + r0 + c0 * lda, lda, pb.qbuf, n - c1, r0 - c1,
                                        A + r0 + r0 * lda, lda, M, ncols, K, info);
-            return trailing(h, s, prec, A + r0 + c0 * lda, lda, A + r0 + r0 * lda, lda, M, ncols, K, info);
+            return trailing(h, s, prec, A + r0 + c0 * lda, lda, A + r0 + r0 * lda, lda, M, ncols, K, info, ch.slab);
         };
         if (la) {
             // columns of the next panel first; then, on the side stream, its
@@ -825,6 +869,8 @@ const char *gp_strerror(int code) {
     if (code == GP_ERR_NOT_SUPPORTED) return "option combination not supported";
     if (code == GP_ERR_BAD_HANDLE) return "invalid handle";
     if (code == GP_ERR_SCRATCH_LIMIT) return "problem needs more than the GP_SCRATCH_BYTES static workspace";
+    if (code == GP_ERR_NO_CANDIDATE) return "no tuning candidate could be timed (each needs more workspace)";
+    if (code == GP_ERR_IO) return "tuning table file could not be read or written";
     if (code < 0 && code > -100) return "invalid argument (index = -code)";
     return "unknown status";
 }
@@ -905,6 +951,17 @@ int gp_create(gp_handle_t *h, void *stream) {
     // the static workspace's address on this device (null if the lookup
     // failed: gp_loglik_noalloc then returns GP_ERR_HIP)
     p->scratch = device_scratch(p->device);
+    {  // architecture name without its feature suffixes (gfx950:sramecc+:xnack- -> gfx950)
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) {
+            size_t k = 0;
+            while (k + 1 < sizeof p->arch && prop.gcnArchName[k] && prop.gcnArchName[k] != ':') {
+                p->arch[k] = prop.gcnArchName[k];
+                ++k;
+            }
+            p->arch[k] = 0;
+        }
+    }
     *h = p;
     return GP_OK;
 }
@@ -977,6 +1034,7 @@ int gp_set_options(gp_handle_t h, const gp_options_t *opt) {
     if (opt->batch_grid < -1) return -2;
     if (opt->fail_inject < 0 || opt->fail_inject > 3) return -2;
     if (opt->bf16_split != 0 && opt->bf16_split != 1) return -2;
+    if (opt->syrk_slab != 0 && opt->syrk_slab != 8 && opt->syrk_slab != 16) return -2;
     if (!(opt->ir_tol >= 0.0) || isinf(opt->ir_tol)) return GP_ERR_NONFINITE;
     h->opt = *opt;
     return GP_OK;
@@ -1070,13 +1128,18 @@ int gp_tune_potrf(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t l
         return GP_ERR_HIP;
     }
     int rc = GP_OK;
+    h->tuning = 1;
+    const int slabs[2] = {16, 8};
     for (int32_t a = 0; a < n_nb && rc == GP_OK; ++a) {
         for (int32_t b = 0; b < n_cu && rc == GP_OK; ++b) {
+          double pair_best = -1.0;
+          for (int sl = 0; sl < (prec == GP_FP64 ? 2 : 1) && rc == GP_OK; ++sl) {
             double ms = -1.0;
             h->opt = saved;
             h->opt.nb = nb_cand[a];
             h->opt.lookahead = 1;
             h->opt.panel_cus = cu_cand[b];
+            h->opt.syrk_slab = slabs[sl];
             const Layout L = layout(h, GP_OP_POTRF, n, 0, prec);
             if (L.total <= ws_bytes) {
                 for (int rep = 0; rep < 2 && rc == GP_OK; ++rep) {  // the first run also creates streams
@@ -1101,13 +1164,16 @@ int gp_tune_potrf(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t l
                     ms = t;
                 }
             }
-            if (ms_out) ms_out[a * n_cu + b] = ms;
+            if (ms >= 0.0 && (pair_best < 0.0 || ms < pair_best)) pair_best = ms;
             if (ms >= 0.0 && (best < 0.0 || ms < best)) {
                 best = ms;
                 best_opt = h->opt;
             }
+          }
+          if (ms_out) ms_out[a * n_cu + b] = pair_best;
         }
     }
+    h->tuning = 0;
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (rc) {
@@ -1116,9 +1182,11 @@ int gp_tune_potrf(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t l
     }
     if (best < 0.0) {
         h->opt = saved;
-        return GP_ERR_WS_TOO_SMALL;
+        return GP_ERR_NO_CANDIDATE;
     }
     h->opt = best_opt;
+    tune_store(h, TuneEntry{0, (int32_t)prec, size_bucket(n), (int32_t)best_opt.nb, best_opt.panel_cus,
+                            best_opt.syrk_slab, 0});
     return GP_OK;
 }
 
@@ -1195,7 +1263,7 @@ int gp_loglik_noalloc(gp_handle_t h, gp_theta_t th, gp_prec_t prec, int64_t n, i
     if (!out3_dev) return -11;
     if (!info_dev) return -13;
     // panel_cus > 0 would create CU-masked streams on first use
-    if (h->opt.panel_cus > 0) return GP_ERR_NOT_SUPPORTED;
+    if (potrf_choice(h, prec, n).panel_cus > 0) return GP_ERR_NOT_SUPPORTED;
     const Layout lay = layout(h, GP_OP_LOGLIK, n, 0, prec);
     if (lay.total > (size_t)GP_SCRATCH_BYTES) return GP_ERR_SCRATCH_LIMIT;
     if (!h->scratch) return GP_ERR_HIP;
@@ -1383,7 +1451,7 @@ int gp_loglik_batched(gp_handle_t h, int32_t nbatch, const gp_theta_t *th_host, 
     if (nbatch > 0 && !x_off_host) return -5;
     if (nbatch > 0 && !c_off_host) return -6;
     if (dim < 1 || dim > 16) return -7;
-    int64_t tot = 0;
+    int64_t tot = 0, nmax = 1;
     for (int b = 0; b < nbatch; ++b) {
         if (int e = check_theta(th_host[b])) return e == 1 ? -3 : GP_ERR_NONFINITE;
         if (th_host[b].kind == GP_SEP_MATERN2) return GP_ERR_NOT_SUPPORTED;
@@ -1391,13 +1459,15 @@ int gp_loglik_batched(gp_handle_t h, int32_t nbatch, const gp_theta_t *th_host, 
         if (x_off_host[b] < 0) return -5;
         if (c_off_host[b] < 0) return -6;
         tot += n_host[b];
+        nmax = n_host[b] > nmax ? n_host[b] : nmax;
     }
     if (tot > 0 && (!X || !y || !C_pool)) return !X ? -8 : (!y ? -9 : -10);
     if (nbatch > 0 && !out3_dev) return -11;
     if (nbatch > 0 && !info_dev) return -12;
     if (!ws) return -13;
     if (nbatch == 0) return GP_OK;
-    return batch_run(h->stream, h->num_cu, h->opt.batch_grid, h->batch_staging, nbatch, th_host, n_host, x_off_host, c_off_host, dim,
+    return batch_run(h->stream, h->num_cu, batch_grid_choice(h, nmax), h->batch_staging, nbatch, th_host, n_host,
+                     x_off_host, c_off_host, dim,
                      X, y, C_pool, out3_dev, info_dev, ws, ws_bytes);
 }
 
@@ -1425,6 +1495,7 @@ int gp_tune_batched(gp_handle_t h, int32_t nbatch, const gp_theta_t *th_host, co
         return GP_ERR_HIP;
     }
     int rc = GP_OK;
+    h->tuning = 1;
     for (int32_t c = 0; c < n_cand && rc == GP_OK; ++c) {
         double ms = -1.0;
         h->opt = saved;
@@ -1453,12 +1524,68 @@ int gp_tune_batched(gp_handle_t h, int32_t nbatch, const gp_theta_t *th_host, co
             best_grid = grid_cand[c];
         }
     }
+    h->tuning = 0;
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     h->opt = saved;
     if (rc) return rc;
-    if (best < 0.0) return GP_ERR_WS_TOO_SMALL;
+    if (best < 0.0) return GP_ERR_NO_CANDIDATE;
     h->opt.batch_grid = best_grid;
+    tune_store(h, TuneEntry{1, (int32_t)GP_FP64, size_bucket(nmax), 0, 0, 0, best_grid});
+    return GP_OK;
+}
+
+int gp_tune_save(gp_handle_t h, const char *path) {
+    if (!ok_handle(h)) return -1;
+    if (!path) return -2;
+    FILE *f = fopen(path, "w");
+    if (!f) return GP_ERR_IO;
+    fprintf(f, "# gpmi tuning table: arch op prec bucket nb panel_cus syrk_slab batch_grid\n");
+    fprintf(f, "# op 0 = factorisation, 1 = batched call; bucket = floor(log2 n)\n");
+    for (const TuneEntry &e : h->tune)
+        fprintf(f, "%s %d %d %d %d %d %d %d\n", h->arch, e.op, e.prec, e.bucket, e.nb, e.panel_cus, e.syrk_slab,
+                e.batch_grid);
+    const bool ok = fclose(f) == 0;
+    return ok ? GP_OK : GP_ERR_IO;
+}
+
+int gp_tune_load(gp_handle_t h, const char *path, int32_t *loaded) {
+    if (!ok_handle(h)) return -1;
+    if (!path) return -2;
+    FILE *f = fopen(path, "r");
+    if (!f) return GP_ERR_IO;
+    char line[256];
+    int32_t cnt = 0;
+    std::vector<TuneEntry> got;
+    while (fgets(line, sizeof line, f)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        char arch[64];
+        TuneEntry e{};
+        if (sscanf(line, "%63s %d %d %d %d %d %d %d", arch, &e.op, &e.prec, &e.bucket, &e.nb, &e.panel_cus,
+                   &e.syrk_slab, &e.batch_grid) != 8) {
+            fclose(f);
+            return GP_ERR_IO;
+        }
+        if (strcmp(arch, h->arch) != 0) continue;  // another device's measurements
+        const bool valid = (e.op == 0 || e.op == 1) && e.prec >= GP_FP64 && e.prec <= GP_BF16_TRAIL && e.bucket >= 0 &&
+                           e.bucket < 63 && (e.op == 1 || (e.nb > 0 && e.nb % DB == 0)) && e.panel_cus >= 0 &&
+                           (e.syrk_slab == 0 || e.syrk_slab == 8 || e.syrk_slab == 16) && e.batch_grid >= -1;
+        if (!valid) {
+            fclose(f);
+            return GP_ERR_IO;
+        }
+        got.push_back(e);
+        ++cnt;
+    }
+    fclose(f);
+    for (const TuneEntry &e : got) tune_store(h, e);
+    if (loaded) *loaded = cnt;
+    return GP_OK;
+}
+
+int gp_tune_clear(gp_handle_t h) {
+    if (!ok_handle(h)) return -1;
+    h->tune.clear();
     return GP_OK;
 }
 

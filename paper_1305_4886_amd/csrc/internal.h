@@ -19,6 +19,13 @@ constexpr int TB = 128;
 
 #include <vector>
 
+// One tuned choice: for operation `op` (0 the factorisation, 1 the batched
+// call) at precision `prec` and problem sizes n with floor(log2 n) == bucket.
+struct TuneEntry {
+    int32_t op, prec, bucket;
+    int32_t nb, panel_cus, syrk_slab, batch_grid;
+};
+
 struct gp_handle_s {
     hipStream_t stream = nullptr;  // caller's stream
     hipStream_t side = nullptr;    // lookahead stream (default priority)
@@ -49,6 +56,9 @@ struct gp_handle_s {
     int num_cu = 256;                 // compute units of the device
     void *batch_staging = nullptr;    // host staging of the batched task table
     void *scratch = nullptr;          // this device's static workspace (gp_loglik_noalloc), or null
+    std::vector<TuneEntry> tune;      // tuned choices by (op, precision, size bucket)
+    char arch[64] = {0};              // architecture name of the device (e.g. gfx950)
+    int tuning = 0;                   // inside a tuner: explicit options only, no table lookups
     int magic = 0x67706d69;
 };
 
@@ -355,6 +365,7 @@ struct GemmDesc {
     int64_t batch;  // number of independent products
     int64_t sA, sB, sC; // element strides between batch members
     const int32_t *info; // skip everything if *info != 0 (may be null)
+    int slab;            // FP64 direct-to-LDS kernel: K-slab of 16 columns in 2 stages (0, 16) or 8 in 4 (8)
 };
 hipError_t launch_gemm_f64(hipStream_t s, const GemmDesc &d);
 // Trailing updates C -= P P^T restricted to the lower triangle, compute type
@@ -363,7 +374,7 @@ hipError_t launch_gemm_f64(hipStream_t s, const GemmDesc &d);
 // role: 1 trailing update, 2 update inside a panel (separate kernel names in traces).
 hipError_t launch_syrk_lower(hipStream_t s, gp_prec_t prec, int band, const double *P,
                              int64_t ldp, double *C, int64_t ldc, int64_t M, int64_t N, int64_t K,
-                             const int32_t *info, int role);
+                             const int32_t *info, int role, int slab = 0);
 // Low-precision trailing updates from a packed copy of the panel: rows
 // 0 .. Mpack - 1 of P (FP64, ld ldp, K columns) rounded once into Q
 // (packed_panel_bytes(Mpack, K) bytes); a call then updates the M x N lower

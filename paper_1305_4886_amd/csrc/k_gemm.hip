@@ -1048,7 +1048,9 @@ hipError_t run_dma(hipStream_t s, const GemmDesc &d) {
     const bool x4 = d.M >= 2 && d.N >= 2 && d.M % 2 == 0 && d.N % 2 == 0 && d.lda % 2 == 0 && d.ldb % 2 == 0 &&
                     ((uintptr_t)d.A & 15) == 0 && ((uintptr_t)d.B & 15) == 0 &&
                     (d.batch == 1 || (d.sA % 2 == 0 && d.sB % 2 == 0));
-    if (x4)
+    if (x4 && d.slab == 8)  // 8-column slabs in four stages
+        hipLaunchKernelGGL((k_syrk_dma<4, 8, TAG, true>), dim3((unsigned)g, (unsigned)d.batch), dim3(256), 0, s, d, tm);
+    else if (x4)            // 16-column slabs in two stages
         hipLaunchKernelGGL((k_syrk_dma<2, 16, TAG, true>), dim3((unsigned)g, (unsigned)d.batch), dim3(256), 0, s, d, tm);
     else
         hipLaunchKernelGGL((k_syrk_dma<4, 8, TAG, false>), dim3((unsigned)g, (unsigned)d.batch), dim3(256), 0, s, d,
@@ -1060,11 +1062,11 @@ hipError_t run_dma(hipStream_t s, const GemmDesc &d) {
 
 hipError_t launch_syrk_lower(hipStream_t s, gp_prec_t prec, int band, const double *P, int64_t ldp,
                              double *C, int64_t ldc, int64_t M, int64_t N, int64_t K,
-                             const int32_t *info, int role) {
+                             const int32_t *info, int role, int slab) {
     GemmDesc d{};
     d.A = P; d.lda = ldp; d.B = P; d.ldb = ldp; d.C = C; d.ldc = ldc;
     d.M = M; d.N = N; d.K = K; d.alpha = -1.0; d.beta = 1.0;
-    d.ta = 0; d.tb = 1; d.lower = 1; d.batch = 1; d.info = info;
+    d.ta = 0; d.tb = 1; d.lower = 1; d.batch = 1; d.info = info; d.slab = slab;
     if (prec == GP_FP64) {
         if (K % 8 == 0) return role == 1 ? run_dma<1>(s, d) : run_dma<2>(s, d);
         if (role == 1) return run_f64<128, 128, 2, 2, 0, 1, 1>(s, d);

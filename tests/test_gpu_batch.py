@@ -161,6 +161,7 @@ def test_tune_batched_picks_a_candidate(orc):
             assert abs(out[b, 0] - ll) <= 1e-11 * abs(ll)
     finally:
         h.set_options(batch_grid=saved.batch_grid)
+        h.tune_reset()
 
 
 def test_batched_many_theta_over_shared_points(orc, grid):

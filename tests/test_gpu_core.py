@@ -241,4 +241,5 @@ def test_tune_potrf_picks_a_candidate_and_factors_correctly(orc):
         L = lower_of(S, n)
         assert np.linalg.norm(L - Lo) <= 1e-12 * np.linalg.norm(Lo)
     finally:
-        h.set_options(nb=saved.nb, lookahead=saved.lookahead, panel_cus=saved.panel_cus)
+        h.set_options(nb=saved.nb, lookahead=saved.lookahead, panel_cus=saved.panel_cus, syrk_slab=saved.syrk_slab)
+        h.tune_reset()
