@@ -135,6 +135,9 @@ typedef struct {
     int32_t syrk_slab;   /* FP64 trailing update, 128 x 128 tiles: K-slab shape staged through LDS per
                             barrier -- 16 columns in 2 stages (16, and 0 = default) or 8 columns in 4
                             stages (8).  Chosen per problem size by gp_tune_potrf. */
+    int32_t batch_tile;  /* gp_loglik_batched, persistent launch: tile edge 64 or 128 (0 = automatic: the
+                            tuning table's choice for the largest problem's size bucket, else 128).  The
+                            level-synchronous launches (batch_grid = -1) always use 64. */
 } gp_options_t;
 
 /* ---- handle ------------------------------------------------------------ */
@@ -328,7 +331,8 @@ int gp_simulate(gp_handle_t h, gp_theta_t th, int64_t n, int64_t m, int32_t dim,
  * C_pool[c_off_host[b] + i + j * n_host[b]] (ld = n_b).  th_host[b] is its
  * parameter set.  Writes out3_dev[3 b + {0,1,2}] = {loglik, logdet, q} and
  * info_dev[b].  Same model and definitions as gp_loglik (FP64).  The
- * problems are factored together in 64 x 64 tiles.  By default (options
+ * problems are factored together in square tiles (options batch_tile: 128
+ * by default, or 64).  By default (options
  * batch_grid >= 0) one persistent launch takes every tile of every problem
  * as a task (covariance tile, left-looking update, then factor + inverse or
  * the product with the diagonal inverse), ordered so that each task's inputs
@@ -337,28 +341,33 @@ int gp_simulate(gp_handle_t h, gp_theta_t th, int64_t n, int64_t m, int32_t dim,
  * batch_grid = -1 instead runs one tile column per step for all problems at
  * once (three launches per step plus one for the solves).  A stall of the
  * persistent launch (never expected) sets info_dev[b] = -1 and leaves NaN.
- * The workspace size depends on batch_grid (the persistent launch keeps a
- * tile-major copy of the factors). */
+ * The workspace size query (GP_OP_BATCHED) covers every schedule and tile
+ * edge unless batch_grid = -1 is set explicitly (the persistent launch keeps
+ * a tile-major copy of the factors). */
 int gp_loglik_batched(gp_handle_t h, int32_t nbatch, const gp_theta_t *th_host,
                       const int64_t *n_host, const int64_t *x_off_host, const int64_t *c_off_host,
                       int32_t dim, const double *X, const double *y, double *C_pool,
                       double *out3_dev, int32_t *info_dev, void *ws, size_t ws_bytes);
 
-/* Autotuner for gp_loglik_batched's schedule: for each candidate batch_grid
- * grid_cand[c] [host; -1 = level-synchronous launches, 0 = one persistent
- * workgroup per compute unit, > 0 = that many persistent workgroups] it runs
- * the batch given by the same arguments as gp_loglik_batched twice on the
- * handle's stream and writes the milliseconds of the second run to ms_out[c]
- * [host, may be NULL; -1 where the candidate's workspace exceeds ws_bytes].
- * The fastest candidate is stored in the handle's options (batch_grid) and
- * in its tuning table for the largest problem's size bucket; on error the
- * options are left unchanged (GP_ERR_NO_CANDIDATE: no candidate fits in ws).  C_pool, out3_dev and info_dev are
- * written as by gp_loglik_batched (they hold the last candidate's results).
- * Synchronises the handle's stream. */
+/* Autotuner for gp_loglik_batched's schedule: candidate c is the pair
+ * (grid_cand[c], tile_cand[c]) [host; grid: -1 = level-synchronous launches,
+ * 0 = one persistent workgroup per compute unit, > 0 = that many persistent
+ * workgroups; tile: 64 or 128 = tile edge of the persistent launch, 0 = the
+ * automatic choice; tile_cand may be NULL (every candidate keeps the
+ * options' tile)].  Each candidate runs the batch given by the same arguments
+ * as gp_loglik_batched twice on the handle's stream; ms_out[c] [host, may be
+ * NULL] receives the milliseconds of the second run (-1 where the
+ * candidate's workspace exceeds ws_bytes).  The fastest candidate is stored
+ * in the handle's options (batch_grid, batch_tile) and in its tuning table
+ * for the largest problem's size bucket; on error the options are left
+ * unchanged (GP_ERR_NO_CANDIDATE: no candidate fits in ws).  C_pool, out3_dev
+ * and info_dev are written as by gp_loglik_batched (they hold the last
+ * candidate's results).  Synchronises the handle's stream.  Argument errors:
+ * -13 grid_cand, -14 tile_cand, -15 n_cand, -17 ws. */
 int gp_tune_batched(gp_handle_t h, int32_t nbatch, const gp_theta_t *th_host, const int64_t *n_host,
                     const int64_t *x_off_host, const int64_t *c_off_host, int32_t dim, const double *X,
                     const double *y, double *C_pool, double *out3_dev, int32_t *info_dev, const int32_t *grid_cand,
-                    int32_t n_cand, double *ms_out, void *ws, size_t ws_bytes);
+                    const int32_t *tile_cand, int32_t n_cand, double *ms_out, void *ws, size_t ws_bytes);
 
 /* ---- the tuning table -------------------------------------------------------
  * The handle keeps the autotuners' choices per (operation, precision, size

@@ -49,7 +49,7 @@ class Options(ctypes.Structure):
                 ("reorder", ctypes.c_int32), ("panel_cus", ctypes.c_int32),
                 ("fused_panel", ctypes.c_int32), ("batch_grid", ctypes.c_int32),
                 ("fail_inject", ctypes.c_int32), ("bf16_split", ctypes.c_int32),
-                ("syrk_slab", ctypes.c_int32)]
+                ("syrk_slab", ctypes.c_int32), ("batch_tile", ctypes.c_int32)]
 
 
 class GPError(RuntimeError):
@@ -111,8 +111,8 @@ def lib():
                                   vp, i64, vp, vp, sz]
         L.gp_loglik_batched.argtypes = [vp, i32, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, sz]
         L.gp_morton_order.argtypes = [vp, i64, i32, vp, vp, vp, sz]
-        L.gp_tune_batched.argtypes = [vp, i32, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, ctypes.POINTER(i32), i32,
-                                      ctypes.POINTER(dbl), vp, sz]
+        L.gp_tune_batched.argtypes = [vp, i32, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, ctypes.POINTER(i32),
+                                      ctypes.POINTER(i32), i32, ctypes.POINTER(dbl), vp, sz]
         _lib = L
     return _lib
 
@@ -246,10 +246,14 @@ class Handle:
                                   _ptr(info), ms, _ptr(ws), ws.numel()))
         return {(nb[a], cus[b]): ms[a * len(cus) + b] for a in range(len(nb)) for b in range(len(cus))}
 
-    def tune_batched(self, X, y, thetas, sizes, grids=None):
-        """Time gp_loglik_batched over candidate schedules (batch_grid: -1 level-synchronous,
-        0 one persistent workgroup per compute unit, > 0 that many) and keep the fastest in this
-        handle's options.  Returns {batch_grid: ms} (-1: did not fit)."""
+    def tune_batched(self, X, y, thetas, sizes, grids=None, tiles=None):
+        """Time gp_loglik_batched over candidate schedules and keep the fastest in this
+        handle's options and tuning table.  Candidates are (batch_grid, batch_tile) pairs:
+        `grids` (-1 level-synchronous, 0 one persistent workgroup per compute unit, > 0 that
+        many) with `tiles` (64 / 128 / 0 automatic, one per grid; None: every grid keeps the
+        options' tile).  Default: the level-synchronous launches, and one workgroup per
+        compute unit and twice that with each tile edge.  Returns {(grid, tile): ms}
+        (-1: did not fit)."""
         torch = _torch()
         import numpy as np
         X, y = _f64(X), _f64(y)
@@ -257,26 +261,31 @@ class Handle:
         sizes = np.asarray(sizes, dtype=np.int64)
         if grids is None:
             ncu = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
-            grids = (-1, 0, ncu // 2, 2 * ncu)
+            grids = (-1, 0, 0, 2 * ncu, 2 * ncu)
+            tiles = (0, 64, 128, 64, 128)
         grids = [int(g) for g in grids]
+        tiles = [self.options().batch_tile] * len(grids) if tiles is None else [int(v) for v in tiles]
+        if len(tiles) != len(grids):
+            raise ValueError("one tile per grid candidate")
         x_off = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
         c_off = np.concatenate([[0], np.cumsum(sizes * sizes)[:-1]]).astype(np.int64)
         th_arr = (Theta * nb)(*thetas)
         saved = self.options()
-        self.set_options(batch_grid=1)  # a persistent schedule: its workspace is the larger one
+        self.set_options(batch_grid=1)  # persistent: the workspace query then covers every schedule and tile
         ws = self.workspace(GP_OP_BATCHED, int(sizes.max()), nb)
         self.set_options(batch_grid=saved.batch_grid)
         C_pool = torch.empty(max(int((sizes * sizes).sum()), 1), dtype=torch.float64, device="cuda")
         out3 = torch.empty(3 * nb, dtype=torch.float64, device="cuda")
         info = torch.zeros(nb, dtype=torch.int32, device="cuda")
         cand = (ctypes.c_int32 * len(grids))(*grids)
+        tcand = (ctypes.c_int32 * len(grids))(*tiles)
         ms = (ctypes.c_double * len(grids))()
         check(lib().gp_tune_batched(self._h, nb, ctypes.cast(th_arr, ctypes.c_void_p),
                                     sizes.ctypes.data_as(ctypes.c_void_p), x_off.ctypes.data_as(ctypes.c_void_p),
                                     c_off.ctypes.data_as(ctypes.c_void_p), X.shape[1], _ptr(X), _ptr(y),
-                                    _ptr(C_pool), _ptr(out3), _ptr(info), cand, len(grids), ms, _ptr(ws),
+                                    _ptr(C_pool), _ptr(out3), _ptr(info), cand, tcand, len(grids), ms, _ptr(ws),
                                     ws.numel()))
-        return {grids[c]: ms[c] for c in range(len(grids))}
+        return {(grids[c], tiles[c]): ms[c] for c in range(len(grids))}
 
     def workspace(self, op, n, m=0, prec=GP_FP64):
         torch = _torch()

@@ -125,6 +125,23 @@ int batch_grid_choice(gp_handle_t h, int64_t nmax) {
     return 0;
 }
 
+// Tile edge of the persistent batched launch, resolved the same way (128 by default).
+int batch_tile_choice(gp_handle_t h, int64_t nmax) {
+    if (h->opt.batch_tile != 0 || h->tuning) return h->opt.batch_tile != 0 ? h->opt.batch_tile : 128;
+    if (const TuneEntry *e = tune_find(h, 1, GP_FP64, nmax))
+        if (e->batch_tile != 0) return e->batch_tile;
+    return 128;
+}
+
+// Workspace of the batched call: the largest over the tile edges a later call
+// could pick (the table can change between the query and the call).
+size_t batch_ws_any(gp_handle_t h, int64_t nmax, int64_t nbatch) {
+    if (batch_grid_choice(h, nmax) < 0 && h->opt.batch_grid != 0) return batch_ws_bytes(nmax, nbatch, false, 64);
+    const size_t a = batch_ws_bytes(nmax, nbatch, true, 64), b = batch_ws_bytes(nmax, nbatch, true, 128);
+    const size_t c = batch_ws_bytes(nmax, nbatch, false, 64);
+    return std::max(std::max(a, b), c);
+}
+
 // Reserved compute unit r of `reserve`: spaced ncu / reserve apart and offset
 // by r mod 8, which gives every XCD the same share whether mask bits are
 // numbered XCD by XCD or round-robin over the eight XCDs.
@@ -231,7 +248,7 @@ Layout layout(gp_handle_t h, gp_op_t op, int64_t n, int64_t m, gp_prec_t prec) {
         }
         break;
     case GP_OP_BATCHED:
-        L.total = batch_ws_bytes(n > 0 ? n : 1, m > 0 ? m : 1, batch_grid_choice(h, n) >= 0);
+        L.total = batch_ws_any(h, n > 0 ? n : 1, m > 0 ? m : 1);
         return L;
     case GP_OP_MORTON:
         L.keys = take(sizeof(uint64_t) * (size_t)next_pow2(n > 0 ? n : 1));
@@ -887,6 +904,7 @@ static void default_options(gp_options_t *o) {
     o->fused_panel = 1;
     o->batch_grid = 0;
     o->bf16_split = 1;
+    o->batch_tile = 0;
 }
 
 }  // extern "C"
@@ -1035,6 +1053,7 @@ int gp_set_options(gp_handle_t h, const gp_options_t *opt) {
     if (opt->fail_inject < 0 || opt->fail_inject > 3) return -2;
     if (opt->bf16_split != 0 && opt->bf16_split != 1) return -2;
     if (opt->syrk_slab != 0 && opt->syrk_slab != 8 && opt->syrk_slab != 16) return -2;
+    if (opt->batch_tile != 0 && opt->batch_tile != 64 && opt->batch_tile != 128) return -2;
     if (!(opt->ir_tol >= 0.0) || isinf(opt->ir_tol)) return GP_ERR_NONFINITE;
     h->opt = *opt;
     return GP_OK;
@@ -1466,7 +1485,8 @@ int gp_loglik_batched(gp_handle_t h, int32_t nbatch, const gp_theta_t *th_host, 
     if (nbatch > 0 && !info_dev) return -12;
     if (!ws) return -13;
     if (nbatch == 0) return GP_OK;
-    return batch_run(h->stream, h->num_cu, batch_grid_choice(h, nmax), h->batch_staging, nbatch, th_host, n_host,
+    return batch_run(h->stream, h->num_cu, batch_grid_choice(h, nmax), batch_tile_choice(h, nmax), h->batch_staging,
+                     nbatch, th_host, n_host,
                      x_off_host, c_off_host, dim,
                      X, y, C_pool, out3_dev, info_dev, ws, ws_bytes);
 }
@@ -1474,21 +1494,23 @@ int gp_loglik_batched(gp_handle_t h, int32_t nbatch, const gp_theta_t *th_host, 
 int gp_tune_batched(gp_handle_t h, int32_t nbatch, const gp_theta_t *th_host, const int64_t *n_host,
                     const int64_t *x_off_host, const int64_t *c_off_host, int32_t dim, const double *X,
                     const double *y, double *C_pool, double *out3_dev, int32_t *info_dev, const int32_t *grid_cand,
-                    int32_t n_cand, double *ms_out, void *ws, size_t ws_bytes) {
+                    const int32_t *tile_cand, int32_t n_cand, double *ms_out, void *ws, size_t ws_bytes) {
     if (!ok_handle(h)) return -1;
     if (nbatch < 1) return -2;
     if (!grid_cand) return -13;
-    if (n_cand < 1) return -14;
-    for (int32_t c = 0; c < n_cand; ++c)
+    if (n_cand < 1) return -15;
+    for (int32_t c = 0; c < n_cand; ++c) {
         if (grid_cand[c] < -1) return -13;
-    if (!ws) return -16;
+        if (tile_cand && tile_cand[c] != 0 && tile_cand[c] != 64 && tile_cand[c] != 128) return -14;
+    }
+    if (!ws) return -17;
     int64_t nmax = 1;
     if (n_host)
         for (int32_t b = 0; b < nbatch; ++b) nmax = n_host[b] > nmax ? n_host[b] : nmax;
     hipStream_t s = h->stream;
     const gp_options_t saved = h->opt;
     double best = -1.0;
-    int32_t best_grid = saved.batch_grid;
+    int32_t best_grid = saved.batch_grid, best_tile = saved.batch_tile;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         if (e0) hipEventDestroy(e0);
@@ -1500,7 +1522,9 @@ int gp_tune_batched(gp_handle_t h, int32_t nbatch, const gp_theta_t *th_host, co
         double ms = -1.0;
         h->opt = saved;
         h->opt.batch_grid = grid_cand[c];
-        if (batch_ws_bytes(nmax, nbatch, grid_cand[c] >= 0) <= ws_bytes) {
+        h->opt.batch_tile = tile_cand ? tile_cand[c] : saved.batch_tile;
+        const bool pers = grid_cand[c] >= 0;
+        if (batch_ws_bytes(nmax, nbatch, pers, pers ? batch_tile_choice(h, nmax) : 64) <= ws_bytes) {
             for (int rep = 0; rep < 2 && rc == GP_OK; ++rep) {  // the first run warms the staging
                 if (hipEventRecord(e0, s) != hipSuccess) {
                     rc = GP_ERR_HIP;
@@ -1522,6 +1546,7 @@ int gp_tune_batched(gp_handle_t h, int32_t nbatch, const gp_theta_t *th_host, co
         if (ms >= 0.0 && (best < 0.0 || ms < best)) {
             best = ms;
             best_grid = grid_cand[c];
+            best_tile = pers ? batch_tile_choice(h, nmax) : 0;
         }
     }
     h->tuning = 0;
@@ -1531,7 +1556,8 @@ int gp_tune_batched(gp_handle_t h, int32_t nbatch, const gp_theta_t *th_host, co
     if (rc) return rc;
     if (best < 0.0) return GP_ERR_NO_CANDIDATE;
     h->opt.batch_grid = best_grid;
-    tune_store(h, TuneEntry{1, (int32_t)GP_FP64, size_bucket(nmax), 0, 0, 0, best_grid});
+    h->opt.batch_tile = best_tile;
+    tune_store(h, TuneEntry{1, (int32_t)GP_FP64, size_bucket(nmax), 0, 0, 0, best_grid, best_tile});
     return GP_OK;
 }
 
@@ -1540,11 +1566,11 @@ int gp_tune_save(gp_handle_t h, const char *path) {
     if (!path) return -2;
     FILE *f = fopen(path, "w");
     if (!f) return GP_ERR_IO;
-    fprintf(f, "# gpmi tuning table: arch op prec bucket nb panel_cus syrk_slab batch_grid\n");
+    fprintf(f, "# gpmi tuning table: arch op prec bucket nb panel_cus syrk_slab batch_grid batch_tile\n");
     fprintf(f, "# op 0 = factorisation, 1 = batched call; bucket = floor(log2 n)\n");
     for (const TuneEntry &e : h->tune)
-        fprintf(f, "%s %d %d %d %d %d %d %d\n", h->arch, e.op, e.prec, e.bucket, e.nb, e.panel_cus, e.syrk_slab,
-                e.batch_grid);
+        fprintf(f, "%s %d %d %d %d %d %d %d %d\n", h->arch, e.op, e.prec, e.bucket, e.nb, e.panel_cus, e.syrk_slab,
+                e.batch_grid, e.batch_tile);
     const bool ok = fclose(f) == 0;
     return ok ? GP_OK : GP_ERR_IO;
 }
@@ -1561,15 +1587,17 @@ int gp_tune_load(gp_handle_t h, const char *path, int32_t *loaded) {
         if (line[0] == '#' || line[0] == '\n') continue;
         char arch[64];
         TuneEntry e{};
-        if (sscanf(line, "%63s %d %d %d %d %d %d %d", arch, &e.op, &e.prec, &e.bucket, &e.nb, &e.panel_cus,
-                   &e.syrk_slab, &e.batch_grid) != 8) {
+        const int got_n = sscanf(line, "%63s %d %d %d %d %d %d %d %d", arch, &e.op, &e.prec, &e.bucket, &e.nb,
+                                 &e.panel_cus, &e.syrk_slab, &e.batch_grid, &e.batch_tile);
+        if (got_n != 8 && got_n != 9) {  // 8 fields: a table written before the tile column (tile automatic)
             fclose(f);
             return GP_ERR_IO;
         }
         if (strcmp(arch, h->arch) != 0) continue;  // another device's measurements
         const bool valid = (e.op == 0 || e.op == 1) && e.prec >= GP_FP64 && e.prec <= GP_BF16_TRAIL && e.bucket >= 0 &&
                            e.bucket < 63 && (e.op == 1 || (e.nb > 0 && e.nb % DB == 0)) && e.panel_cus >= 0 &&
-                           (e.syrk_slab == 0 || e.syrk_slab == 8 || e.syrk_slab == 16) && e.batch_grid >= -1;
+                           (e.syrk_slab == 0 || e.syrk_slab == 8 || e.syrk_slab == 16) && e.batch_grid >= -1 &&
+                           (e.batch_tile == 0 || e.batch_tile == 64 || e.batch_tile == 128);
         if (!valid) {
             fclose(f);
             return GP_ERR_IO;

@@ -23,7 +23,7 @@ constexpr int TB = 128;
 // call) at precision `prec` and problem sizes n with floor(log2 n) == bucket.
 struct TuneEntry {
     int32_t op, prec, bucket;
-    int32_t nb, panel_cus, syrk_slab, batch_grid;
+    int32_t nb, panel_cus, syrk_slab, batch_grid, batch_tile;
 };
 
 struct gp_handle_s {
@@ -329,6 +329,50 @@ GP_DEV void wave_inv64_blocked(const double (*Ls)[DB + 1], double (*Wl)[DB + 1],
     wave_lds_sync();
 }
 
+// Direct-to-LDS copies and the explicit waits that order them.
+template <int N>
+GP_DEV void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt is a 6-bit field");
+    // s_waitcnt vmcnt(N), expcnt and lgkmcnt left unconstrained (gfx9 encoding)
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// Wait until at most j (0 <= j <= J) slabs of PER copies each are outstanding.
+template <int PER, int J>
+GP_DEV void wait_slabs(int j) {
+    if constexpr (J == 0) {
+        wait_vmcnt<0>();
+    } else {
+        if (j >= J)
+            wait_vmcnt<J * PER>();
+        else
+            wait_slabs<PER, J - 1>(j);
+    }
+}
+
+// One 256-byte LDS-DMA copy: lane l moves the dword at base + voff to LDS
+// address lds + 4 l.  Written as inline assembly so that the compiler's
+// wait-count pass, which cannot tell LDS-DMA targets apart, does not drain
+// every copy in flight before each LDS read; the kernel orders the copies
+// itself with explicit vmcnt waits and barriers.  m0 is restored afterwards.
+GP_DEV void lds_dma_dword(const double *base, uint32_t voff, uint32_t lds_uniform) {
+    uint32_t saved;
+    asm volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %3\n\ts_nop 0\n\tglobal_load_lds_dword %1, %2\n\ts_mov_b32 m0, %0"
+                 : "=&s"(saved)
+                 : "v"(voff), "s"(base), "s"(lds_uniform)
+                 : "memory");
+}
+
+// The same with 16 bytes per lane (gfx950): lane l moves base + voff .. + 15
+// to LDS address lds + 16 l, so one instruction fills a 1 KB LDS span.
+GP_DEV void lds_dma_dwordx4(const double *base, uint32_t voff, uint32_t lds_uniform) {
+    uint32_t saved;
+    asm volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %3\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, %2\n\ts_mov_b32 m0, %0"
+                 : "=&s"(saved)
+                 : "v"(voff), "s"(base), "s"(lds_uniform)
+                 : "memory");
+}
+
 // ---------------------------------------------------------------------------
 // Launchers (all enqueue on `s`, return hipError_t of the launch).
 // ---------------------------------------------------------------------------
@@ -502,8 +546,8 @@ hipError_t launch_fail_fill(hipStream_t s, int64_t m, int64_t r, double *out, in
 hipError_t launch_zero_upper(hipStream_t s, int64_t m, double *A, int64_t lda);
 
 // k_batch.hip
-size_t batch_ws_bytes(int64_t nmax, int64_t nbatch, bool persistent);
-int batch_run(hipStream_t s, int num_cu, int grid, void *&staging, int32_t nb, const gp_theta_t *th, const int64_t *nh,
+size_t batch_ws_bytes(int64_t nmax, int64_t nbatch, bool persistent, int tile);
+int batch_run(hipStream_t s, int num_cu, int grid, int tile, void *&staging, int32_t nb, const gp_theta_t *th, const int64_t *nh,
               const int64_t *xoff, const int64_t *coff, int32_t dim, const double *X, const double *y,
               double *C_pool, double *out3, int32_t *info, void *ws, size_t ws_bytes);
 void batch_staging_free(void *p);

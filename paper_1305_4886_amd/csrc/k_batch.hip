@@ -395,7 +395,8 @@ struct alignas(16) PersistSmem {
 // published (the caller may take every column below it without waiting) and
 // the state (1 ready, 2 the problem failed, 0 abort).  Block-uniform: every
 // exit test of the poll loop is wave-uniform (ballots, readfirstlane).
-GP_DEV void bensure(PersistSmem &sm, int *flags, const int *fl, int64_t ri_base, int64_t rk_base, int j, int k,
+template <typename SM>
+GP_DEV void bensure(SM &sm, int *flags, const int *fl, int64_t ri_base, int64_t rk_base, int j, int k,
                     int &ready, int &state) {
     if (threadIdx.x < 64) {
         const int lane = threadIdx.x, c = j + lane;
@@ -436,7 +437,8 @@ GP_DEV void bensure(PersistSmem &sm, int *flags, const int *fl, int64_t ri_base,
 }
 
 // Thread 0 waits for one flag; returns its value (1 / 2) or 0 on abort.  Block-uniform.
-GP_DEV int bwait1(PersistSmem &sm, int *flags, const int *f) {
+template <typename SM>
+GP_DEV int bwait1(SM &sm, int *flags, const int *f) {
     if (threadIdx.x == 0) {
         int v, spins = 0;
         while ((v = bflag(f)) == 0) {
@@ -829,6 +831,545 @@ __global__ __launch_bounds__(256, 1) void k_bpersist(const BProb *__restrict__ p
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Persistent dataflow launch on 128 x 128 tiles.
+//
+// The task graph, queues, flags and publication rules of k_bpersist, with
+// tiles twice as wide: one left-looking step moves two 128 KB operand tiles
+// for 4.2 MFLOP (16 flop per byte against 8 with 64 x 64 tiles), and each
+// wave keeps sixteen independent accumulators.  Task (p, i, k) accumulates
+// G = A_ik^T = C_ki - sum_{j<k} L_kj L_ij^T, 128 rows m (tile k) by 128
+// columns r (tile i), wave w holding columns 32 w .. 32 w + 31 of every row.
+// The operands arrive as K-slabs of 16 columns of the tiles' tile-major
+// copies, copied straight into a two-stage LDS ring.  An off-diagonal task
+// then forms L_ik^T = W_k G on the matrix cores, taking G as the B operand
+// straight from its accumulators: the D layout of v_mfma_f64_16x16x4 (lane l,
+// register r: row l / 16 + 4 r, column l % 16) is the B layout of the K-step
+// over rows 4 r .. 4 r + 3.  A diagonal task factors its tile in LDS as a
+// 2 x 2 matrix of 64 x 64 blocks -- L11 and W11 = L11^{-1} by one wave,
+// L21 = A21 W11^T and A22 - L21 L21^T on the matrix cores, L22 and W22 by one
+// wave, W21 = -W22 (L21 W11) -- then forms z_k = W_k (y_k - sum_j L_kj z_j)
+// and the tile's log-determinant / quadratic-form partials.
+// ---------------------------------------------------------------------------
+constexpr int T2 = 128, BK2 = 16;
+constexpr int BP_NW = 8;  // waves per workgroup of the 128-tile launch (two per SIMD)
+
+struct alignas(16) P128Smem {
+    union {
+        double ring[4][2][BK2][T2];  // [stage][operand: 0 = L_kj, 1 = L_ij][column][row]
+        double Wt[T2][T2 + 2];       // off-diagonal task: W_k as [c][m] (row c at 1040 bytes: no bank conflicts)
+        struct {                     // diagonal task: 64 x 64 blocks
+            double B11[DB][DB + 1], B21[DB][DB + 1], B22[DB][DB + 1], Wb[DB][DB + 1];
+        } d;
+    } u;
+    union {
+        double pn[DB][17];
+        double t32[32][33];
+    } U;
+    double px[2][T2][2];  // planar points: rows m (tile k), columns r (tile i)
+    double rd[DB];
+    double zk[T2];        // off-diagonal task: z_k
+    double ys[T2];        // y_k - sum_j L_kj z_j
+    double lg[T2];        // log L_mm
+    double zq[T2];        // z_m^2
+    int64_t ticket;
+    int ready, state;
+};
+
+template <typename Tp>
+GP_DEV Tp *uni_ptr(Tp *p) {  // a pointer the compiler cannot prove wave-uniform, in scalar registers
+    const uint64_t v = (uint64_t)(uintptr_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (Tp *)(uintptr_t)(((uint64_t)hi << 32) | lo);
+}
+
+// x[mi][ni] += sum_{m < 64} A(32 wr + 16 mi + i, m) B(m, 32 wc + 16 ni + j) for
+// one wave's 32 x 32 block of a 64 x 64 product, operands through callables.
+template <typename FA, typename FB>
+GP_DEV void blk32_mm(v4d (&x)[2][2], FA fa, FB fb, int wr, int wc, int lane) {
+#pragma unroll 4
+    for (int kk = 0; kk < DB; kk += 4) {
+        double a[2], bb[2];
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi) a[mi] = fa(32 * wr + 16 * mi + (lane & 15), kk + (lane >> 4));
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni) bb[ni] = fb(kk + (lane >> 4), 32 * wc + 16 * ni + (lane & 15));
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 2; ++ni)
+                x[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mi], bb[ni], x[mi][ni], 0, 0, 0);
+    }
+}
+
+// Element (row, column) of register r in block (mi, ni) of blk32_mm's result.
+GP_DEV int blk_row(int wr, int mi, int lane, int r) { return 32 * wr + 16 * mi + (lane >> 4) + 4 * r; }
+GP_DEV int blk_col(int wc, int ni, int lane) { return 32 * wc + 16 * ni + (lane & 15); }
+
+template <int NW>
+__global__ __launch_bounds__(64 * NW, 1) void k_bp128(const BProb *__restrict__ probs, const uint2 *__restrict__ tasks,
+                                                  const int64_t *__restrict__ qstart, int dim,
+                                                  const double *__restrict__ X, const double *__restrict__ y,
+                                                  double *C_pool, double *lt, double *wbuf, double *zbuf, double *part,
+                                                  double *pbuf, int *flags, double *out3, int32_t *info) {
+    constexpr int NT = 64 * NW, RB = 8 / NW, CW = 16 * RB;  // threads, 16-column blocks and columns per wave
+    __shared__ P128Smem sm;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t total = qstart[BQ];
+    int qx = blockIdx.x % BQ, qleft = 0;
+    auto take = [&]() -> int64_t {
+        while (qleft < BQ) {
+            const int64_t a = atomicAdd(flags + BF_TICKET + 32 * qx, 1);
+            if (a < qstart[qx + 1] - qstart[qx]) return qstart[qx] + a;
+            qx = (qx + 1) % BQ;
+            ++qleft;
+        }
+        return total;
+    };
+    if (tid == 0) sm.ticket = take();
+    __syncthreads();
+    for (int64_t t = sm.ticket; t < total; t = sm.ticket) {
+        const uint2 task = tasks[t];
+        int64_t nxt = 0;  // thread 0: the next task, taken now and handed over at the end of this one
+        if (tid == 0) nxt = take();
+        const int b = __builtin_amdgcn_readfirstlane((int)task.x);
+        const int i = __builtin_amdgcn_readfirstlane((int)(task.y & 0xffffu));
+        const int k = __builtin_amdgcn_readfirstlane((int)(task.y >> 16));
+        const BProb P = probs[b];
+        const bool diag = (i == k);
+        const int64_t ld = P.n, i0 = (int64_t)i * T2, k0 = (int64_t)k * T2;
+        const int ri = (int)((P.n - i0) < T2 ? (P.n - i0) : T2), rk = (int)((P.n - k0) < T2 ? (P.n - k0) : T2);
+        double *L = C_pool + P.c_off;
+        int *fl = flags + BF_TILES + P.f_off;  // flag of tile (r, c): fl[r (r + 1) / 2 + c]
+        const int64_t fi = tri64(i), fk = tri64(k);
+        const double *Xb = X + P.x_off * dim;
+        const bool planar = dim <= 2;
+
+        // 1. points of the two tiles to LDS (planar), then the first slab's
+        //    copies, then the covariance tile while they fly
+        if (planar && tid < 2 * T2) {
+            const int q = tid >> 7, e = tid & 127, cnt = q ? ri : rk;
+            const double *p = Xb + ((q ? i0 : k0) + (e < cnt ? e : 0)) * dim;
+            sm.px[q][e][0] = p[0];
+            sm.px[q][e][1] = dim == 2 ? p[1] : 0.0;
+        }
+        if (tid == 0) sm.state = 1;
+        __syncthreads();
+        int ready = 0, state = 1;
+        const int nsl = 8 * k;  // K-slabs of the left-looking update (8 per tile column j < k)
+        const double *LK = uni_ptr(lt + (P.f_off + fk) * (T2 * T2));  // tile (k, 0); (k, j) at + j T2^2
+        const double *LI = uni_ptr(lt + (P.f_off + fi) * (T2 * T2));
+        // copy c of this wave for slab s into stage st: column w + NW q of the
+        // slab, operand op (c = 2 q + op; a diagonal task copies L_kj only, c = q)
+        const int per = diag ? 16 / NW : 32 / NW;  // copies per wave and slab
+        auto copy_slot = [&](int s, int st, int c) {
+            const int q = diag ? c : (c >> 1), op = diag ? 0 : (c & 1);
+            const int tt = w + NW * q;
+            const int64_t col = (int64_t)(s >> 3) * T2 * T2 + (int64_t)(16 * (s & 7) + tt) * T2;
+            lds_dma_dwordx4(uni_ptr((op ? LI : LK) + col), 16u * lane,
+                            __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)&sm.u.ring[st][op][tt][0]));
+        };
+        if (nsl > 0) {
+            bensure(sm, flags, fl, fi, fk, 0, k, ready, state);
+            if (state == 1) {
+#pragma nounroll
+                for (int s0 = 0; s0 < 3 && s0 < nsl; ++s0) {
+#pragma nounroll
+                    for (int c = 0; c < per; ++c) copy_slot(s0, s0, c);
+                }
+            }
+        }
+        v4d acc[8][RB];  // -sum_j L_kj L_ij^T, then + C_ki: G
+#pragma unroll
+        for (int mb = 0; mb < 8; ++mb)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) acc[mb][rb] = v4d{0.0, 0.0, 0.0, 0.0};
+
+        // 2. G -= L_kj L_ij^T over the slabs through a four-stage ring: the
+        //    copies of slab s + 3 go out between the matrix instructions of
+        //    slab s.  The ring's waits and barriers are explicit (vmcnt counts
+        //    the copies; a __syncthreads would drain every copy in flight).
+        for (int s = 0; s < nsl && state == 1; ++s) {
+            const int st = s & 3, sn = s + 3;
+            const bool more = sn < nsl;
+            if (more && (sn >> 3) >= ready) {
+                bensure(sm, flags, fl, fi, fk, sn >> 3, k, ready, state);
+                if (state != 1) {
+                    wait_vmcnt<0>();  // no copy may land in LDS after this task
+                    break;
+                }
+            }
+            const int later = nsl - 1 - s < 2 ? nsl - 1 - s : 2;  // slabs after s already in flight
+            if (diag)
+                wait_slabs<16 / NW, 2>(later);
+            else
+                wait_slabs<32 / NW, 2>(later);
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_s_barrier();  // slab s is in stage st; stage (s + 3) & 3 was last read in slab s - 1
+            asm volatile("" ::: "memory");
+            const double(*Rk)[T2] = sm.u.ring[st][0];
+            const double(*Ri)[T2] = sm.u.ring[st][diag ? 0 : 1];
+            double a[8], bb[RB];
+#pragma unroll
+            for (int mb = 0; mb < 8; ++mb) a[mb] = -Rk[lane >> 4][16 * mb + (lane & 15)];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) bb[rb] = Ri[lane >> 4][CW * w + 16 * rb + (lane & 15)];
+#pragma unroll
+            for (int kk = 0; kk < BK2 / 4; ++kk) {
+                double an[8], bn[RB];
+                if (kk + 1 < BK2 / 4) {
+                    const int kn = 4 * (kk + 1) + (lane >> 4);
+#pragma unroll
+                    for (int mb = 0; mb < 8; ++mb) an[mb] = -Rk[kn][16 * mb + (lane & 15)];
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb) bn[rb] = Ri[kn][CW * w + 16 * rb + (lane & 15)];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int g = 0; g < 2; ++g) {
+#pragma unroll
+                    for (int mb = 4 * g; mb < 4 * g + 4; ++mb)
+#pragma unroll
+                        for (int rb = 0; rb < RB; ++rb)
+                            acc[mb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mb], bb[rb], acc[mb][rb], 0, 0, 0);
+                    __builtin_amdgcn_sched_barrier(0);
+                    const int sl = 2 * kk + g;  // eight slots per slab, the copies spread over them
+                    if (more && (sl * per) / 8 != ((sl + 1) * per) / 8) copy_slot(sn, sn & 3, (sl * per) / 8);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                if (kk + 1 < BK2 / 4) {
+#pragma unroll
+                    for (int mb = 0; mb < 8; ++mb) a[mb] = an[mb];
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb) bb[rb] = bn[rb];
+                }
+            }
+        }
+        // 3. + the covariance tile, in two halves of 64 rows computed into the
+        //    (now idle) ring and added to the accumulators: G[m][c] = C(k0 + m,
+        //    i0 + c), identity on the padded diagonal of a diagonal tile
+        if (state == 1) {
+            double(*GT)[T2] = reinterpret_cast<double(*)[T2]>(&sm.u.ring[0][0][0][0]);
+            __syncthreads();  // every wave is past its ring reads
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+#pragma nounroll
+                for (int e = tid; e < 64 * T2; e += NT) {
+                    const int ml = e >> 7, c = e & (T2 - 1), m = 64 * hh + ml;
+                    double v = 0.0;
+                    if (m < rk && c < ri) {
+                        const int64_t gm = k0 + m, gc = i0 + c;
+                        double d;
+                        if (planar) {
+                            const double d0 = sm.px[1][c][0] - sm.px[0][m][0], d1 = sm.px[1][c][1] - sm.px[0][m][1];
+                            d = sqrt(fma(d1, d1, d0 * d0));  // the rounding of point_dist
+                        } else {
+                            d = point_dist(Xb + gc * dim, Xb + gm * dim, dim);
+                        }
+                        v = P.s2 * cov_corr(P.kind, d * P.inv_rho) + (gm == gc ? P.t2 : 0.0);
+                    } else if (diag && m == c) {
+                        v = 1.0;  // identity padding decouples the rows past the problem
+                    }
+                    GT[ml][c] = v;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int mb = 4 * hh; mb < 4 * hh + 4; ++mb)
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            acc[mb][rb][r] += GT[16 * (mb - 4 * hh) + (lane >> 4) + 4 * r][CW * w + 16 * rb + (lane & 15)];
+                __syncthreads();
+            }
+        }
+        if (state == 0) {  // stalled: leave (the abort flag stops every workgroup)
+            if (tid == 0) info[b] = -1;
+            return;
+        }
+
+        if (!diag) {
+            // 3a. L_ik^T = W_k G once the diagonal task of column k has published W_k
+            if (state == 1) state = bwait1(sm, flags, fl + fk + k);
+            if (state == 0) {
+                if (tid == 0) info[b] = -1;
+                return;
+            }
+            if (state == 1) {
+                __syncthreads();  // every wave is past its ring reads
+                const double *Wk = uni_ptr(wbuf + P.w_off + k0 * T2);  // row-major: (c, m) at c T2 + m
+#pragma nounroll
+                for (int q = 0; q < T2 / NW; ++q) {
+                    const int c = w + NW * q;
+                    lds_dma_dwordx4(uni_ptr(Wk + (int64_t)c * T2), 16u * lane,
+                                    __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)&sm.u.Wt[c][0]));
+                }
+                if (tid < T2) sm.zk[tid] = tid < rk ? bld(zbuf + P.z_off + k0 + tid) : 0.0;
+                wait_vmcnt<0>();
+                __syncthreads();
+                // Four quarters of 32 output rows c: W_k is lower triangular, so
+                // block (cb, mb) is zero for mb > cb.  A quarter's result goes to
+                // the LDS rows of W_k it has just finished reading, then out as
+                // whole 1 KB columns of L_ik (and its tile-major copy).
+                double *Lt = lt + (P.f_off + fi + k) * (T2 * T2);
+                double pz = 0.0;  // thread rr < 128: (L_ik z_k)(rr)
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    v4d o[2][RB];
+#pragma unroll
+                    for (int cq = 0; cq < 2; ++cq)
+#pragma unroll
+                        for (int rb = 0; rb < RB; ++rb) o[cq][rb] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int mb = 0; mb < 2 * h + 2; ++mb)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int m = 16 * mb + 4 * r + (lane >> 4);
+#pragma unroll
+                            for (int cq = 0; cq < 2; ++cq) {
+                                const int cb = 2 * h + cq;
+                                if (mb > cb) continue;
+                                const double wv = sm.u.Wt[16 * cb + (lane & 15)][m];
+#pragma unroll
+                                for (int rb = 0; rb < RB; ++rb)
+                                    o[cq][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(wv, acc[mb][rb][r], o[cq][rb], 0,
+                                                                                     0, 0);
+                            }
+                        }
+                    __syncthreads();  // rows 32 h .. 32 h + 31 of W_k are read by every wave
+#pragma unroll
+                    for (int cq = 0; cq < 2; ++cq)
+#pragma unroll
+                        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)  // L_ik(rr, c) at row c
+                                sm.u.Wt[16 * (2 * h + cq) + (lane >> 4) + 4 * r][CW * w + 16 * rb + (lane & 15)] =
+                                    o[cq][rb][r];
+                    __syncthreads();
+#pragma nounroll
+                    for (int e = tid; e < 32 * T2; e += NT) {
+                        const int c = 32 * h + (e >> 7), rr = e & (T2 - 1);
+                        const double v = sm.u.Wt[c][rr];
+                        bst(Lt + rr + (int64_t)c * T2, v);
+                        if (rr < ri && c < rk) L[(i0 + rr) + (k0 + c) * ld] = v;
+                    }
+                    if (tid < T2) {
+#pragma unroll 8
+                        for (int c = 32 * h; c < 32 * h + 32; ++c) pz = fma(sm.u.Wt[c][tid], sm.zk[c], pz);
+                    }
+                }
+                // L_ik z_k (the diagonal task of tile row i sums these over k, in order)
+                if (tid < T2) bst(pbuf + (P.f_off + fi + k) * T2 + tid, pz);
+            }
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            if (tid == 0) {
+                __hip_atomic_store(fl + fi + k, state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                sm.ticket = bflag(flags + BF_ABORT) ? total : nxt;
+            }
+            __syncthreads();
+            continue;
+        }
+
+        // 3b. diagonal tile: factor, invert, forward-solve block k, partials
+        if (state == 1) {
+            __syncthreads();  // every wave is past its ring reads
+            auto &D = sm.u.d;
+#pragma unroll
+            for (int mb = 0; mb < 8; ++mb)
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int m = 16 * mb + (lane >> 4) + 4 * r, c = CW * w + 16 * rb + (lane & 15);
+                        if (CW * w + 16 * rb < 64) {
+                            if (mb < 4) D.B11[m][c] = acc[mb][rb][r];
+                            else D.B21[m - 64][c] = acc[mb][rb][r];
+                        } else if (mb >= 4) {
+                            D.B22[m - 64][c - 64] = acc[mb][rb][r];
+                        }
+                    }
+            if (tid < T2) {  // y_k - sum_j L_kj z_j, the products published by the tasks (k, j)
+                double tsum = 0.0;
+                for (int j = 0; j < k; ++j) tsum += bld(pbuf + (P.f_off + fk + j) * T2 + tid);
+                sm.ys[tid] = tid < rk ? y[P.x_off + k0 + tid] - tsum : 0.0;
+            }
+            __syncthreads();
+            double *Lkk = L + k0 + k0 * ld;
+            const int wr = w & 1, wc = w >> 1;
+            v4d x[2][2];
+            // the two diagonal blocks in turn, through one copy of the
+            // one-wave factor / inverse code: half 0 factors A11 into B11 and
+            // inverts it into Wb; then L21 and A22 - L21 L21^T; half 1 factors
+            // that into B22 and inverts it into B11 (L11 is stored by then)
+#pragma nounroll
+            for (int hb = 0; hb < 2 && state == 1; ++hb) {
+                double(*Bd)[DB + 1] = hb ? D.B22 : D.B11;
+                double(*Wo)[DB + 1] = hb ? D.B11 : D.Wb;
+                const int o = 64 * hb;
+                if (w == 0) {
+                    double a[DB];
+#pragma unroll
+                    for (int c = 0; c < DB; ++c) a[c] = (c <= lane) ? Bd[lane][c] : 0.0;
+                    const int fail = wave_chol64(a, lane, Wo, sm.U.pn);
+                    if (fail) {
+                        if (lane == 0) {
+                            info[b] = (int32_t)(k0 + o + fail);
+                            sm.state = 2;
+                        }
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < DB; ++c) {
+                            Bd[lane][c] = a[c];
+                            if (o + lane < rk && o + c < rk && c <= lane)
+                                Lkk[(o + lane) + (int64_t)(o + c) * ld] = a[c];
+                        }
+                        wave_lds_sync();
+                        sm.lg[o + lane] = o + lane < rk ? log(Bd[lane][lane]) : 0.0;
+                        wave_inv64_blocked(Bd, Wo, sm.U.t32, sm.rd, lane);
+                    }
+                }
+                __syncthreads();
+                state = sm.state;
+                if (hb == 1 || state != 1) break;
+                // L21 = A21 W11^T
+#pragma unroll
+                for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < 2; ++ni) x[mi][ni] = v4d{0.0, 0.0, 0.0, 0.0};
+                if (w < 4)
+                    blk32_mm(x, [&](int r, int m) { return D.B21[r][m]; }, [&](int m, int c) { return D.Wb[c][m]; },
+                             wr, wc, lane);
+                __syncthreads();
+                if (w < 4) {
+#pragma unroll
+                    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                const int rr = blk_row(wr, mi, lane, r), c = blk_col(wc, ni, lane);
+                                D.B21[rr][c] = x[mi][ni][r];
+                                if (64 + rr < rk && c < rk) Lkk[(64 + rr) + (int64_t)c * ld] = x[mi][ni][r];
+                            }
+                }
+                __syncthreads();
+                if (w < 4 && wr >= wc) {  // A22 -= L21 L21^T, lower blocks
+#pragma unroll
+                    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+                                x[mi][ni][r] = D.B22[blk_row(wr, mi, lane, r)][blk_col(wc, ni, lane)];
+                    blk32_mm(x, [&](int r, int m) { return -D.B21[r][m]; }, [&](int m, int c) { return D.B21[c][m]; },
+                             wr, wc, lane);
+#pragma unroll
+                    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+                                D.B22[blk_row(wr, mi, lane, r)][blk_col(wc, ni, lane)] = x[mi][ni][r];
+                }
+                __syncthreads();
+            }
+            if (state == 1) {  // W21 = -W22 (L21 W11): X = L21 W11 into B21, then W21 into B21
+#pragma unroll
+                for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < 2; ++ni) x[mi][ni] = v4d{0.0, 0.0, 0.0, 0.0};
+                if (w < 4)
+                    blk32_mm(x, [&](int r, int m) { return D.B21[r][m]; }, [&](int m, int c) { return D.Wb[m][c]; },
+                             wr, wc, lane);
+                __syncthreads();
+                if (w < 4) {
+#pragma unroll
+                    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+                                D.B21[blk_row(wr, mi, lane, r)][blk_col(wc, ni, lane)] = x[mi][ni][r];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < 2; ++ni) x[mi][ni] = v4d{0.0, 0.0, 0.0, 0.0};
+                if (w < 4)
+                    blk32_mm(x, [&](int r, int m) { return -D.B11[r][m]; }, [&](int m, int c) { return D.B21[m][c]; },
+                             wr, wc, lane);
+                __syncthreads();
+                if (w < 4) {
+#pragma unroll
+                    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+                                D.B21[blk_row(wr, mi, lane, r)][blk_col(wc, ni, lane)] = x[mi][ni][r];
+                }
+                __syncthreads();
+                // W_k = [[W11, 0], [W21, W22]] out, row-major (c, m) at c 128 + m
+                double *Wk = wbuf + P.w_off + k0 * T2;
+                for (int e = tid; e < T2 * T2; e += NT) {
+                    const int m = e & (T2 - 1), c = e >> 7;
+                    const double v = c < 64 ? (m < 64 ? D.Wb[c][m] : 0.0) : (m < 64 ? D.B21[c - 64][m] : D.B11[c - 64][m - 64]);
+                    bst(Wk + e, v);
+                }
+                // z_k = W_k (y_k - sum_j L_kj z_j); thread c < 128
+                if (tid < T2) {
+                    const int c = tid;
+                    double zr = 0.0;
+                    if (c < 64) {
+#pragma unroll 8
+                        for (int m = 0; m < 64; ++m) zr = fma(D.Wb[c][m], sm.ys[m], zr);
+                    } else {
+#pragma unroll 8
+                        for (int m = 0; m < 64; ++m) zr = fma(D.B21[c - 64][m], sm.ys[m], zr);
+#pragma unroll 8
+                        for (int m = 0; m < 64; ++m) zr = fma(D.B11[c - 64][m], sm.ys[64 + m], zr);
+                    }
+                    if (c < rk) bst(zbuf + P.z_off + k0 + c, zr);
+                    sm.zq[c] = c < rk ? zr * zr : 0.0;
+                }
+                __syncthreads();
+                if (tid == 0 || tid == 64) {  // the two partials, one wave each
+                    const double *v = tid == 0 ? sm.lg : sm.zq;
+                    CSum acc_s;
+                    for (int c = 0; c < T2; ++c) acc_s.add(v[c]);
+                    bst(part + P.p_off + 2 * k + (tid == 0 ? 0 : 1), acc_s.value());
+                }
+            }
+        }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (tid == 0) {
+            __hip_atomic_store(fl + fk + k, state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (k == P.nt - 1) {  // the last diagonal tile: every partial of the problem is published
+                double *o = out3 + 3 * (int64_t)b;
+                if (state == 1) {
+                    CSum sl, sq;
+                    for (int j = 0; j < P.nt; ++j) {
+                        sl.add(bld(part + P.p_off + 2 * j));
+                        sq.add(bld(part + P.p_off + 2 * j + 1));
+                    }
+                    const double logdet = 2.0 * sl.value(), qf = sq.value();
+                    o[1] = logdet;
+                    o[2] = qf;
+                    o[0] = -0.5 * (((double)P.n * 1.8378770664093453 + logdet) + qf);
+                }  // failed: the NaNs written at the start stay
+            }
+            sm.ticket = bflag(flags + BF_ABORT) ? total : nxt;
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -842,19 +1383,22 @@ namespace {
 inline size_t al256b(size_t x) { return (x + 255) & ~(size_t)255; }
 }
 
-size_t batch_ws_bytes(int64_t nmax, int64_t nbatch, bool persistent) {
-    const int64_t nt = (nmax + T - 1) / T;
+size_t batch_ws_bytes(int64_t nmax, int64_t nbatch, bool persistent, int tile) {
+    const int TT = persistent ? tile : T;  // the level-synchronous launches use 64 x 64 tiles
+    const int64_t nt = (nmax + TT - 1) / TT;
     size_t b = 0;
     b += al256b(sizeof(BProb) * (size_t)nbatch);
     b += al256b(sizeof(int32_t) * (size_t)nbatch);                              // size order
     b += al256b(sizeof(int64_t) * (size_t)(2 * nt + 1) * (size_t)(nbatch + 1));  // per-level prefix counts
     b += al256b(sizeof(double) * (size_t)nmax * (size_t)nbatch);                 // z
-    b += al256b(sizeof(double) * (size_t)nt * T * T * (size_t)nbatch);           // diagonal inverses
+    b += al256b(sizeof(double) * (size_t)nt * TT * TT * (size_t)nbatch);         // diagonal inverses
     b += al256b(sizeof(int) * ((size_t)BF_TILES + (size_t)(nt * (nt + 1) / 2) * (size_t)nbatch));  // tile flags
     b += al256b(sizeof(double) * 2 * (size_t)nt * (size_t)nbatch);               // per-tile partials
     b += al256b(8 * (size_t)(nt * (nt + 1) / 2) * (size_t)nbatch + 8 * (BQ + 1));  // task list, queue starts
-    if (persistent)  // tile-major copy of the factor's tiles, read back inside the launch
-        b += al256b(sizeof(double) * T * T * (size_t)(nt * (nt + 1) / 2) * (size_t)nbatch);
+    if (persistent) {  // tile-major copy of the factor's tiles, read back inside the launch, and L_ik z_k
+        b += al256b(sizeof(double) * TT * TT * (size_t)(nt * (nt + 1) / 2) * (size_t)nbatch);
+        b += al256b(sizeof(double) * TT * (size_t)(nt * (nt + 1) / 2) * (size_t)nbatch);
+    }
     return b + 256;
 }
 
@@ -867,7 +1411,7 @@ struct BatchStaging {
     hipEvent_t done = nullptr;
 };
 
-int batch_run(hipStream_t s, int num_cu, int grid, void *&staging_ptr, int32_t nb, const gp_theta_t *th,
+int batch_run(hipStream_t s, int num_cu, int grid, int tile, void *&staging_ptr, int32_t nb, const gp_theta_t *th,
               const int64_t *nh, const int64_t *xoff, const int64_t *coff, int32_t dim, const double *X,
               const double *y, double *C_pool, double *out3, int32_t *info, void *ws, size_t ws_bytes) {
     BatchStaging *st = static_cast<BatchStaging *>(staging_ptr);
@@ -882,8 +1426,10 @@ int batch_run(hipStream_t s, int num_cu, int grid, void *&staging_ptr, int32_t n
     }
     int64_t nmax = 1;
     for (int b = 0; b < nb; ++b) nmax = std::max(nmax, nh[b]);
-    if (ws_bytes < batch_ws_bytes(nmax, nb, grid >= 0)) return GP_ERR_WS_TOO_SMALL;
-    const int64_t ntmax = (nmax + T - 1) / T;
+    if (grid >= 0 && tile != T && tile != T2) return GP_ERR_NOT_SUPPORTED;
+    const int TT = grid >= 0 ? tile : T;  // tile edge of this call
+    if (ws_bytes < batch_ws_bytes(nmax, nb, grid >= 0, TT)) return GP_ERR_WS_TOO_SMALL;
+    const int64_t ntmax = (nmax + TT - 1) / TT;
     st->probs.assign(nb, BProb{});
     int64_t zoff = 0, woff = 0, foff = 0, poff_ = 0;
     for (int b = 0; b < nb; ++b) {
@@ -891,11 +1437,11 @@ int batch_run(hipStream_t s, int num_cu, int grid, void *&staging_ptr, int32_t n
         p.n = nh[b];
         p.x_off = xoff[b];
         p.c_off = coff[b];
-        p.nt = (int32_t)((p.n + T - 1) / T);
+        p.nt = (int32_t)((p.n + TT - 1) / TT);
         p.z_off = zoff;
         zoff += p.n;
         p.w_off = woff;
-        woff += (int64_t)p.nt * T * T;
+        woff += (int64_t)p.nt * TT * TT;
         p.f_off = foff;
         foff += (int64_t)p.nt * (p.nt + 1) / 2;
         p.p_off = poff_;
@@ -938,7 +1484,7 @@ int batch_run(hipStream_t s, int num_cu, int grid, void *&staging_ptr, int32_t n
     int32_t *d_order = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)nb));
     int64_t *d_offs = reinterpret_cast<int64_t *>(take(sizeof(int64_t) * st->offs.size()));
     double *d_z = reinterpret_cast<double *>(take(sizeof(double) * (size_t)nmax * (size_t)nb));
-    double *d_w = reinterpret_cast<double *>(take(sizeof(double) * (size_t)ntmax * T * T * (size_t)nb));
+    double *d_w = reinterpret_cast<double *>(take(sizeof(double) * (size_t)ntmax * TT * TT * (size_t)nb));
 
     if (grid >= 0) {
         // Persistent launch.  Problems go to the BQ queues largest first, each
@@ -1002,7 +1548,8 @@ int batch_run(hipStream_t s, int num_cu, int grid, void *&staging_ptr, int32_t n
         double *d_part = reinterpret_cast<double *>(take(sizeof(double) * (size_t)(poff_ > 0 ? poff_ : 1)));
         uint2 *d_tasks = reinterpret_cast<uint2 *>(take(tbytes));
         int64_t *d_qs = reinterpret_cast<int64_t *>(take(qbytes));
-        double *d_lt = reinterpret_cast<double *>(take(sizeof(double) * T * T * (size_t)(foff > 0 ? foff : 1)));
+        double *d_lt = reinterpret_cast<double *>(take(sizeof(double) * TT * TT * (size_t)(foff > 0 ? foff : 1)));
+        double *d_pz = reinterpret_cast<double *>(take(sizeof(double) * TT * (size_t)(foff > 0 ? foff : 1)));
         if (off > ws_bytes) return GP_ERR_WS_TOO_SMALL;
         if (hipMemcpyAsync(d_probs, st->probs.data(), sizeof(BProb) * (size_t)nb, hipMemcpyHostToDevice, s) !=
                 hipSuccess ||
@@ -1016,8 +1563,12 @@ int batch_run(hipStream_t s, int num_cu, int grid, void *&staging_ptr, int32_t n
         if (total > 0) {
             int64_t g = grid > 0 ? grid : (int64_t)(num_cu > 0 ? num_cu : 1);
             if (g > total) g = total;
-            hipLaunchKernelGGL(k_bpersist, dim3((unsigned)g), dim3(256), 0, s, d_probs, d_tasks, d_qs, (int)dim, X, y,
-                               C_pool, d_lt, d_w, d_z, d_part, d_flags, out3, info);
+            if (TT == T2)
+                hipLaunchKernelGGL(k_bp128<BP_NW>, dim3((unsigned)g), dim3(64 * BP_NW), 0, s, d_probs, d_tasks, d_qs, (int)dim, X, y,
+                                   C_pool, d_lt, d_w, d_z, d_part, d_pz, d_flags, out3, info);
+            else
+                hipLaunchKernelGGL(k_bpersist, dim3((unsigned)g), dim3(256), 0, s, d_probs, d_tasks, d_qs, (int)dim, X,
+                                   y, C_pool, d_lt, d_w, d_z, d_part, d_flags, out3, info);
         }
         return hipGetLastError() == hipSuccess ? GP_OK : GP_ERR_HIP;
     }

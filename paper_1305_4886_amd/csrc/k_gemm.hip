@@ -320,49 +320,6 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmDesc d, TileMap tm) {
 // K loop of a tile starts at its first row (an operand that is zero left of
 // its diagonal, such as the transpose of a lower-triangular matrix).
 // ---------------------------------------------------------------------------
-template <int N>
-GP_DEV void wait_vmcnt() {
-    static_assert(N >= 0 && N < 64, "vmcnt is a 6-bit field");
-    // s_waitcnt vmcnt(N), expcnt and lgkmcnt left unconstrained (gfx9 encoding)
-    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
-}
-
-// Wait until at most j (0 <= j <= J) slabs of PER copies each are outstanding.
-template <int PER, int J>
-GP_DEV void wait_slabs(int j) {
-    if constexpr (J == 0) {
-        wait_vmcnt<0>();
-    } else {
-        if (j >= J)
-            wait_vmcnt<J * PER>();
-        else
-            wait_slabs<PER, J - 1>(j);
-    }
-}
-
-// One 256-byte LDS-DMA copy: lane l moves the dword at base + voff to LDS
-// address lds + 4 l.  Written as inline assembly so that the compiler's
-// wait-count pass, which cannot tell LDS-DMA targets apart, does not drain
-// every copy in flight before each LDS read; the kernel orders the copies
-// itself with explicit vmcnt waits and barriers.  m0 is restored afterwards.
-GP_DEV void lds_dma_dword(const double *base, uint32_t voff, uint32_t lds_uniform) {
-    uint32_t saved;
-    asm volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %3\n\ts_nop 0\n\tglobal_load_lds_dword %1, %2\n\ts_mov_b32 m0, %0"
-                 : "=&s"(saved)
-                 : "v"(voff), "s"(base), "s"(lds_uniform)
-                 : "memory");
-}
-
-// The same with 16 bytes per lane (gfx950): lane l moves base + voff .. + 15
-// to LDS address lds + 16 l, so one instruction fills a 1 KB LDS span.
-GP_DEV void lds_dma_dwordx4(const double *base, uint32_t voff, uint32_t lds_uniform) {
-    uint32_t saved;
-    asm volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %3\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, %2\n\ts_mov_b32 m0, %0"
-                 : "=&s"(saved)
-                 : "v"(voff), "s"(base), "s"(lds_uniform)
-                 : "memory");
-}
-
 // X4: one 16-byte-per-lane copy moves a whole 128-row column of a slab (four
 // copies per wave and slab instead of sixteen 4-byte ones); needs 16-byte
 // aligned column starts (even leading dimensions, aligned bases) and an even

@@ -1,9 +1,9 @@
 """Batched likelihoods: each problem of a ragged batch must match the
 single-problem CPU oracle (same model and definitions, Section 1), including
 per-problem failure reporting.  Every schedule is covered: the persistent
-launch with its automatic grid, with one workgroup (every task in ticket
-order on one workgroup) and with a small odd grid, and the level-synchronous
-launches."""
+launch on 128- and on 64-wide tiles, each with its automatic grid, with one
+workgroup (every task in ticket order on one workgroup) and with a small odd
+grid, and the level-synchronous launches."""
 import math
 
 import numpy as np
@@ -41,16 +41,19 @@ def make_batch(sizes, seed, kernels=None):
     return Xs, ys, ths
 
 
-GRIDS = [0, 1, 7, -1]  # persistent (automatic, one workgroup, seven workgroups), level-synchronous
+# (batch_grid, batch_tile): persistent launches (one workgroup per compute
+# unit, one workgroup, seven workgroups) with 128- and 64-wide tiles, and the
+# level-synchronous launches
+GRIDS = [(0, 128), (1, 128), (7, 128), (0, 64), (1, 64), (7, 64), (-1, 0)]
 
 
-@pytest.fixture(params=GRIDS, ids=lambda g: "grid%d" % g)
+@pytest.fixture(params=GRIDS, ids=lambda g: "grid%d_tile%d" % g)
 def grid(request):
     h = gp.handle()
     saved = h.options()
-    h.set_options(batch_grid=request.param)
+    h.set_options(batch_grid=request.param[0], batch_tile=request.param[1])
     yield request.param
-    h.set_options(batch_grid=saved.batch_grid)
+    h.set_options(batch_grid=saved.batch_grid, batch_tile=saved.batch_tile)
 
 
 @pytest.mark.parametrize("sizes", [[1], [64], [65, 3, 200], [300, 0, 129, 1000, 64, 777, 511, 2]])
@@ -104,6 +107,29 @@ def test_batched_more_than_64_tile_columns(orc, grid):
         assert abs(out[b, 2] - q) <= 1e-11 * abs(q)
 
 
+_BIG = {}
+
+
+def test_batched_more_than_64_wide_tile_columns(orc, grid):
+    """n = 8300 has 65 tile columns of 128: the dependency polls of the
+    128-wide tiles also span more than one wave's width."""
+    if grid[0] < 0 or grid[1] != 128:
+        pytest.skip("128-wide tiles only")
+    sizes = [8300, 130]
+    Xs, ys, ths = make_batch(sizes, 87, kernels=[0, 2])
+    if not _BIG:
+        _BIG.update({b: orc.loglik(ths[b][0], ths[b][1], Xs[b], ys[b]) for b in range(2)})
+    r = gp.loglik_batched(dev(np.concatenate(Xs)), dev(np.concatenate(ys)),
+                          [gp.theta(k, log=t) for k, t in ths], sizes)
+    out = r["out3"].cpu().numpy()
+    assert np.all(r["info"].cpu().numpy() == 0)
+    for b in range(2):
+        ll, ld, q = _BIG[b]
+        assert abs(out[b, 0] - ll) <= 1e-11 * abs(ll), (b, out[b], ll)
+        assert abs(out[b, 1] - ld) <= 1e-11 * abs(ld)
+        assert abs(out[b, 2] - q) <= 1e-11 * abs(q)
+
+
 def test_batched_workload_64_problems(orc):
     sizes = synth.batch_sizes(64, 40)
     Xs, ys, ths = make_batch(sizes, 4000, kernels=[0] * 64)
@@ -150,17 +176,18 @@ def test_tune_batched_picks_a_candidate(orc):
     h = gp.handle()
     saved = h.options()
     try:
-        ms = h.tune_batched(X, y, thetas, sizes, grids=(-1, 0, 5))
-        assert set(ms) == {-1, 0, 5} and all(v > 0 for v in ms.values()), ms
+        ms = h.tune_batched(X, y, thetas, sizes, grids=(-1, 0, 5, 0), tiles=(0, 64, 128, 128))
+        assert set(ms) == {(-1, 0), (0, 64), (5, 128), (0, 128)} and all(v > 0 for v in ms.values()), ms
         best = min(ms, key=ms.get)
-        assert h.options().batch_grid == best
+        assert h.options().batch_grid == best[0]
+        assert best[0] < 0 or h.options().batch_tile == best[1]
         out = gp.loglik_batched(X, y, thetas, sizes)["out3"].cpu().numpy()
         for b in range(len(sizes)):
             k, t = ths[b]
             ll, _, _ = orc.loglik(k, t, Xs[b], ys[b])
             assert abs(out[b, 0] - ll) <= 1e-11 * abs(ll)
     finally:
-        h.set_options(batch_grid=saved.batch_grid)
+        h.set_options(batch_grid=saved.batch_grid, batch_tile=saved.batch_tile)
         h.tune_reset()
 
 
