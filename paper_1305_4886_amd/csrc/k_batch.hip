@@ -982,13 +982,13 @@ __global__ __launch_bounds__(64 * NW, 1) void k_bp128(const BProb *__restrict__ 
                 }
             }
         }
-        v4d acc[8][RB];  // -sum_j L_kj L_ij^T, then + C_ki: G
+        v4d acc[8][RB];  // sum_j L_kj L_ij^T, then C_ki minus that: G
 #pragma unroll
         for (int mb = 0; mb < 8; ++mb)
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) acc[mb][rb] = v4d{0.0, 0.0, 0.0, 0.0};
 
-        // 2. G -= L_kj L_ij^T over the slabs through a four-stage ring: the
+        // 2. sum_j L_kj L_ij^T over the slabs through a four-stage ring: the
         //    copies of slab s + 3 go out between the matrix instructions of
         //    slab s.  The ring's waits and barriers are explicit (vmcnt counts
         //    the copies; a __syncthreads would drain every copy in flight).
@@ -999,7 +999,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_bp128(const BProb *__restrict__ 
                 bensure(sm, flags, fl, fi, fk, sn >> 3, k, ready, state);
                 if (state != 1) {
                     wait_vmcnt<0>();  // no copy may land in LDS after this task
-                    break;
+                    continue;         // (the loop condition ends the loop)
                 }
             }
             const int later = nsl - 1 - s < 2 ? nsl - 1 - s : 2;  // slabs after s already in flight
@@ -1014,7 +1014,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_bp128(const BProb *__restrict__ 
             const double(*Ri)[T2] = sm.u.ring[st][diag ? 0 : 1];
             double a[8], bb[RB];
 #pragma unroll
-            for (int mb = 0; mb < 8; ++mb) a[mb] = -Rk[lane >> 4][16 * mb + (lane & 15)];
+            for (int mb = 0; mb < 8; ++mb) a[mb] = Rk[lane >> 4][16 * mb + (lane & 15)];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) bb[rb] = Ri[lane >> 4][CW * w + 16 * rb + (lane & 15)];
 #pragma unroll
@@ -1023,7 +1023,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_bp128(const BProb *__restrict__ 
                 if (kk + 1 < BK2 / 4) {
                     const int kn = 4 * (kk + 1) + (lane >> 4);
 #pragma unroll
-                    for (int mb = 0; mb < 8; ++mb) an[mb] = -Rk[kn][16 * mb + (lane & 15)];
+                    for (int mb = 0; mb < 8; ++mb) an[mb] = Rk[kn][16 * mb + (lane & 15)];
 #pragma unroll
                     for (int rb = 0; rb < RB; ++rb) bn[rb] = Ri[kn][CW * w + 16 * rb + (lane & 15)];
                 }
@@ -1048,8 +1048,8 @@ __global__ __launch_bounds__(64 * NW, 1) void k_bp128(const BProb *__restrict__ 
                 }
             }
         }
-        // 3. + the covariance tile, in two halves of 64 rows computed into the
-        //    (now idle) ring and added to the accumulators: G[m][c] = C(k0 + m,
+        // 3. the covariance tile, in two halves of 64 rows computed into the
+        //    (now idle) ring, minus the accumulated products: G[m][c] = C(k0 + m,
         //    i0 + c), identity on the padded diagonal of a diagonal tile
         if (state == 1) {
             double(*GT)[T2] = reinterpret_cast<double(*)[T2]>(&sm.u.ring[0][0][0][0]);
@@ -1082,7 +1082,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_bp128(const BProb *__restrict__ 
                     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                         for (int r = 0; r < 4; ++r)
-                            acc[mb][rb][r] += GT[16 * (mb - 4 * hh) + (lane >> 4) + 4 * r][CW * w + 16 * rb + (lane & 15)];
+                            acc[mb][rb][r] = GT[16 * (mb - 4 * hh) + (lane >> 4) + 4 * r][CW * w + 16 * rb + (lane & 15)] - acc[mb][rb][r];
                 __syncthreads();
             }
         }
@@ -1193,8 +1193,17 @@ __global__ __launch_bounds__(64 * NW, 1) void k_bp128(const BProb *__restrict__ 
                         }
                     }
             if (tid < T2) {  // y_k - sum_j L_kj z_j, the products published by the tasks (k, j)
+                const double *pk = pbuf + (P.f_off + fk) * T2 + tid;
                 double tsum = 0.0;
-                for (int j = 0; j < k; ++j) tsum += bld(pbuf + (P.f_off + fk + j) * T2 + tid);
+                int j = 0;
+                for (; j + 8 <= k; j += 8) {  // eight loads in flight, summed in order
+                    double v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) v[u] = bld(pk + (int64_t)(j + u) * T2);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) tsum += v[u];
+                }
+                for (; j < k; ++j) tsum += bld(pk + (int64_t)j * T2);
                 sm.ys[tid] = tid < rk ? y[P.x_off + k0 + tid] - tsum : 0.0;
             }
             __syncthreads();

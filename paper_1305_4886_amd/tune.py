@@ -1,13 +1,15 @@
 """Measure the library's tunable choices on this GPU and write the tuning table.
 
-    python -m paper_1305_4886_amd.tune [--out PATH] [--sizes 4096,8192,...] [--quick]
+    python -m paper_1305_4886_amd.tune [--out PATH] [--sizes 4096,8192,...] [--quick] [--batched-only]
 
 For each precision (FP64 and the FP32 / BF16 trailing-update modes) and each
 size, gp_tune_potrf times the factorisation for every candidate panel width
 and, in FP64, both K-slab shapes of the 128 x 128 trailing-update tile, and
 records the fastest in the handle's table under the size bucket
-floor(log2 n); gp_tune_batched times the schedules of the batched call for a
-batch of 64 problems with sizes uniform on [256, 4096].  The table is then
+floor(log2 n); gp_tune_batched times the schedules of the batched call (the
+launch grid and the tile edge) for a batch of 64 problems with sizes uniform
+on [256, 4096].  --batched-only keeps the factorisation entries of the
+existing table and measures the batched call alone.  The table is then
 written (default: the package's tuning.txt, which every handle loads when it
 is created; entries of another architecture are ignored there).
 """
@@ -29,6 +31,7 @@ def main(argv=None):
     ap.add_argument("--out", default=os.path.join(HERE, "tuning.txt"))
     ap.add_argument("--sizes", default="2048,4096,8192,16384,32768,65536")
     ap.add_argument("--quick", action="store_true", help="fewer panel widths")
+    ap.add_argument("--batched-only", action="store_true", help="re-measure the batched call only")
     a = ap.parse_args(argv)
     import torch
 
@@ -36,8 +39,9 @@ def main(argv=None):
     from paper_1305_4886_amd import synth
 
     h = gp.handle()
-    h.tune_clear()  # measure from scratch, not on top of a loaded table
-    sizes = [int(v) for v in a.sizes.split(",") if v]
+    if not a.batched_only:
+        h.tune_clear()  # measure from scratch, not on top of a loaded table
+    sizes = [] if a.batched_only else [int(v) for v in a.sizes.split(",") if v]
     widths = {gp.GP_FP64: [512, 640, 768, 896, 1024], gp.GP_FP32_TRAIL: [384, 512, 640, 768],
               gp.GP_BF16_TRAIL: [384, 512, 640, 768]}
     if a.quick:
@@ -59,8 +63,8 @@ def main(argv=None):
                         device="cuda")
     th = gp.theta(gp.GP_EXP, 1.0, 0.1, 0.1)
     r = h.tune_batched(X, y, [th] * len(sizes_b), sizes_b)
-    print("batched: %s -> grid %d" % (r, h.options().batch_grid), flush=True)
-    h.set_options(batch_grid=0)
+    print("batched: %s -> grid %d tile %d" % (r, h.options().batch_grid, h.options().batch_tile), flush=True)
+    h.set_options(batch_grid=0, batch_tile=0)
     h.tune_save(a.out)
     print("wrote", a.out)
 
