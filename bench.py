@@ -354,7 +354,7 @@ def main():
     traffic, traffic_src = measured_traffic()
     # algorithmic HBM bytes of the same launches: the lower-triangle C tile
     # read and written once (8 B each way per flop pair / K) plus the panel
-    nb = h.options().nb or 768  # 0: the automatic FP64 panel width
+    nb = h.potrf_plan(n)[0]  # the panel width (K of each trailing update) the factorisation used
     alg_bytes = (2 * 8 * syrk_per_launch_flops / (2 * nb)) if syrk_per_launch_flops else None
     roofline = {"kernel": "trailing SYRK (k_syrk_dma<2,16,1,x4>, role 1)", "bound": "mfma",
                 "achieved": syrk_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",

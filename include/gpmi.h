@@ -210,6 +210,14 @@ int gp_tune_potrf(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t l
                   const int32_t *nb_cand, int32_t n_nb, const int32_t *cu_cand, int32_t n_cu,
                   int32_t *info_dev, double *ms_out, void *ws, size_t ws_bytes);
 
+/* The factorisation's resolved choices for an n x n matrix at precision prec
+ * under the handle's current options and tuning table (what gp_potrf and the
+ * factorising calls would use): *nb = outer panel width, *panel_cus =
+ * compute units reserved for the lookahead chain, *syrk_slab = K-slab shape
+ * of the FP64 trailing-update tile (16 or 8) [host, each nullable].  No
+ * device work. */
+int gp_potrf_plan(gp_handle_t h, gp_prec_t prec, int64_t n, int32_t *nb, int32_t *panel_cus, int32_t *syrk_slab);
+
 /* ---- triangular solves with the lower factor (Section 1 "backsolve";
  *      the remoteForwardsolve / remoteBacksolve of Section 2.3.2) --------- */
 /* x [dev, n] <- L^{-1} x (GP_NOTRANS) or L^{-T} x (GP_TRANS), in place. */

@@ -34,7 +34,7 @@ EXPORTED = ["gp_create", "gp_destroy", "gp_set_stream", "gp_set_options", "gp_ge
             "gp_strerror", "gp_profile", "gp_profile_read", "gp_workspace_size", "gp_cov_build", "gp_cross_cov_build", "gp_potrf",
             "gp_trsv", "gp_trsm", "gp_loglik", "gp_loglik_grad", "gp_krige", "gp_loglik_batched",
             "gp_morton_order", "gp_tune_potrf", "gp_tune_batched", "gp_loglik_noalloc", "gp_krige_cov",
-            "gp_trmm", "gp_simulate", "gp_tune_save", "gp_tune_load", "gp_tune_clear"]
+            "gp_trmm", "gp_simulate", "gp_tune_save", "gp_tune_load", "gp_tune_clear", "gp_potrf_plan"]
 
 
 class Theta(ctypes.Structure):
@@ -105,6 +105,7 @@ def lib():
         L.gp_tune_save.argtypes = [vp, ctypes.c_char_p]
         L.gp_tune_load.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(i32)]
         L.gp_tune_clear.argtypes = [vp]
+        L.gp_potrf_plan.argtypes = [vp, i32, i64, vp, vp, vp]
         L.gp_krige_cov.argtypes = [vp, Theta, i64, i64, i32, vp, vp, vp, i64, i32, vp, i64, vp, sz]
         L.gp_trmm.argtypes = [vp, i64, i64, vp, i64, vp, i64, vp, i64, vp, sz]
         L.gp_simulate.argtypes = [vp, Theta, i64, i64, i32, vp, vp, vp, i64, vp, dbl, i32, i64, vp, i64, vp, i64,
@@ -205,6 +206,12 @@ class Handle:
 
     def tune_clear(self):
         check(lib().gp_tune_clear(self._h))
+
+    def potrf_plan(self, n, prec=GP_FP64):
+        """(panel width, reserved CUs, K-slab) the factorisation of an n x n matrix would use."""
+        v = [ctypes.c_int32(0) for _ in range(3)]
+        check(lib().gp_potrf_plan(self._h, int(prec), int(n), *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
 
     def tune_reset(self):
         """Back to the shipped table (or an empty one)."""

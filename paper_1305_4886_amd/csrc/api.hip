@@ -1119,6 +1119,17 @@ int gp_potrf(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda, i
     return potrf_impl(h, prec, n, A, lda, info_dev, at<double>(ws, L.dinv), panel_bufs(ws, L));
 }
 
+int gp_potrf_plan(gp_handle_t h, gp_prec_t prec, int64_t n, int32_t *nb, int32_t *panel_cus, int32_t *syrk_slab) {
+    if (!ok_handle(h)) return -1;
+    if (prec < GP_FP64 || prec > GP_BF16_TRAIL) return -2;
+    if (n < 0) return -3;
+    const PotrfChoice c = potrf_choice(h, prec, n);
+    if (nb) *nb = (int32_t)c.nb;
+    if (panel_cus) *panel_cus = c.panel_cus;
+    if (syrk_slab) *syrk_slab = c.slab == 0 ? 16 : c.slab;
+    return GP_OK;
+}
+
 int gp_tune_potrf(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda, const int32_t *nb_cand,
                   int32_t n_nb, const int32_t *cu_cand, int32_t n_cu, int32_t *info_dev, double *ms_out, void *ws,
                   size_t ws_bytes) {

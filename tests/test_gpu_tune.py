@@ -67,6 +67,9 @@ def test_table_round_trip_and_lookup(tmp_path):
         # the bucket 1024 .. 2047 takes the tuned width, bucket 2048 .. 4095 the default
         assert ws_bytes(h, n) == tuned and ws_bytes(h, 1100) == tuned_1100
         assert ws_bytes(h, 3000) == default_3000
+        # the plan query reports the same resolution: tuned width in the bucket, default outside
+        assert h.potrf_plan(n)[0] == best_nb and h.potrf_plan(1100)[0] == best_nb
+        assert h.potrf_plan(3000) == (768, 0, 16)
         # the factor with the tuned choice still matches the oracle
         X = synth.uniform_points(n, 5)
         t = np.array([0.0, math.log(0.1), math.log(0.1)])
