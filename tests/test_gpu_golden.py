@@ -12,9 +12,11 @@ Workloads:
   log|C|, q, sampled entries of L and of alpha, kriging mean and variance at
   m = 4096 points, and the gradient (also against central differences);
 * n = 32768 exponential (sigma^2 = 1, rho = 0.1, tau^2 = 0.1), the benchmark
-  workload in its own launch configuration (default panel width 768,
-  lookahead, ld = n, so the 16-byte-copy trailing update): loglik, log|C|, q,
-  sampled L and alpha; the mixed FP32 / BF16 paths against the same values.
+  workload in its own launch configuration (automatic panel width, which the
+  shipped tuning table sets to 640 at this size, lookahead, ld = n, so the
+  16-byte-copy trailing update) and at the untuned default width 768:
+  loglik, log|C|, q, sampled L and alpha; the mixed FP32 / BF16 paths
+  against the same values.
 
 The sampled entries of L sit uniformly over the lower triangle and on the
 edges of the 64-, 128- and 768-wide blocks, so a tile placed or decoded
@@ -161,14 +163,20 @@ def test_c3_gradient_oracle_and_central_differences(c2):
     assert np.all(np.abs(grad - fd) <= 1e-6 * np.maximum(1.0, np.abs(grad))), (grad, fd)
 
 
-def test_c4_fp64_benchmark_configuration(c4):
+@pytest.mark.parametrize("nb", [0, 768])
+def test_c4_fp64_benchmark_configuration(c4, nb):
     g = c4
     h = gp.handle()
     o = h.options()
     assert o.nb == 0 and o.lookahead == 1 and o.fused_panel == 1  # the defaults the benchmark runs
-    r = gp.loglik(dev(g["X"]), dev(g["y"]), th_of(g), want_alpha=True)
+    try:
+        h.set_options(nb=nb)
+        print("panel width used:", h.potrf_plan(int(g["n"]))[0])
+        r = gp.loglik(dev(g["X"]), dev(g["y"]), th_of(g), want_alpha=True)
+    finally:
+        h.set_options(nb=0)
     assert r["S"].shape[1] == int(g["n"])  # ld = n
-    check_fp64(g, r, "n=32768 exp")
+    check_fp64(g, r, "n=32768 exp nb=%d" % nb)
 
 
 @pytest.mark.parametrize("prec", [gp.GP_FP32_TRAIL, gp.GP_BF16_TRAIL])
