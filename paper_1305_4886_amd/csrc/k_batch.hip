@@ -877,6 +877,8 @@ struct alignas(16) P128Smem {
     int ready, state;
 };
 
+__shared__ P128Smem bp_sm;  // the 128-tile launch's LDS (shared with its diagonal-task finish)
+
 template <typename Tp>
 GP_DEV Tp *uni_ptr(Tp *p) {  // a pointer the compiler cannot prove wave-uniform, in scalar registers
     const uint64_t v = (uint64_t)(uintptr_t)p;
@@ -908,6 +910,192 @@ GP_DEV void blk32_mm(v4d (&x)[2][2], FA fa, FB fb, int wr, int wc, int lane) {
 GP_DEV int blk_row(int wr, int mi, int lane, int r) { return 32 * wr + 16 * mi + (lane >> 4) + 4 * r; }
 GP_DEV int blk_col(int wc, int ni, int lane) { return 32 * wc + 16 * ni + (lane & 15); }
 
+// The diagonal task's finish, called once per diagonal tile with the tile G
+// in the LDS blocks B11 / B21 / B22: y_k - sum_j L_kj z_j, the 2 x 2 block
+// factorisation and inverse, W_k, z_k and the partials.  A call of its own
+// (not inlined) so that its one-wave register factorisation is allocated
+// apart from the accumulators and ring addresses of the persistent loop.
+// Returns the tile's state (1 done, 2 not positive definite).
+template <int NW>
+__device__ __attribute__((noinline)) int diag128_finish(const BProb *__restrict__ probs, int b, int k, double *C_pool,
+                                                        const double *__restrict__ y, double *wbuf, double *zbuf,
+                                                        double *part, double *pbuf, int32_t *info) {
+    constexpr int NT = 64 * NW;
+    P128Smem &sm = bp_sm;
+    auto &D = sm.u.d;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const BProb P = probs[b];
+    const int64_t ld = P.n, k0 = (int64_t)k * T2, fk = tri64(k);
+    const int rk = (int)((P.n - k0) < T2 ? (P.n - k0) : T2);
+    double *L = C_pool + P.c_off;
+    int state = 1;
+    if (tid == 0) sm.state = 1;
+    if (tid < T2) {  // y_k - sum_j L_kj z_j, the products published by the tasks (k, j)
+        const double *pk = pbuf + (P.f_off + fk) * T2 + tid;
+        double tsum = 0.0;
+        int j = 0;
+        for (; j + 8 <= k; j += 8) {  // eight loads in flight, summed in order
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = bld(pk + (int64_t)(j + u) * T2);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) tsum += v[u];
+        }
+        for (; j < k; ++j) tsum += bld(pk + (int64_t)j * T2);
+        sm.ys[tid] = tid < rk ? y[P.x_off + k0 + tid] - tsum : 0.0;
+    }
+    __syncthreads();
+    double *Lkk = L + k0 + k0 * ld;
+    const int wr = w & 1, wc = w >> 1;
+    v4d x[2][2];
+    // the two diagonal blocks in turn, through one copy of the
+    // one-wave factor / inverse code: half 0 factors A11 into B11 and
+    // inverts it into Wb; then L21 and A22 - L21 L21^T; half 1 factors
+    // that into B22 and inverts it into B11 (L11 is stored by then)
+#pragma nounroll
+    for (int hb = 0; hb < 2 && state == 1; ++hb) {
+        double(*Bd)[DB + 1] = hb ? D.B22 : D.B11;
+        double(*Wo)[DB + 1] = hb ? D.B11 : D.Wb;
+        const int o = 64 * hb;
+        if (w == 0) {
+            double a[DB];
+#pragma unroll
+            for (int c = 0; c < DB; ++c) a[c] = (c <= lane) ? Bd[lane][c] : 0.0;
+            const int fail = wave_chol64(a, lane, Wo, sm.U.pn);
+            if (fail) {
+                if (lane == 0) {
+                    info[b] = (int32_t)(k0 + o + fail);
+                    sm.state = 2;
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < DB; ++c) {
+                    Bd[lane][c] = a[c];
+                    if (o + lane < rk && o + c < rk && c <= lane)
+                        Lkk[(o + lane) + (int64_t)(o + c) * ld] = a[c];
+                }
+                wave_lds_sync();
+                sm.lg[o + lane] = o + lane < rk ? log(Bd[lane][lane]) : 0.0;
+                wave_inv64_blocked(Bd, Wo, sm.U.t32, sm.rd, lane);
+            }
+        }
+        __syncthreads();
+        state = sm.state;
+        if (hb == 1 || state != 1) break;
+        // L21 = A21 W11^T
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 2; ++ni) x[mi][ni] = v4d{0.0, 0.0, 0.0, 0.0};
+        if (w < 4)
+            blk32_mm(x, [&](int r, int m) { return D.B21[r][m]; }, [&](int m, int c) { return D.Wb[c][m]; },
+                     wr, wc, lane);
+        __syncthreads();
+        if (w < 4) {
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int rr = blk_row(wr, mi, lane, r), c = blk_col(wc, ni, lane);
+                        D.B21[rr][c] = x[mi][ni][r];
+                        if (64 + rr < rk && c < rk) Lkk[(64 + rr) + (int64_t)c * ld] = x[mi][ni][r];
+                    }
+        }
+        __syncthreads();
+        if (w < 4 && wr >= wc) {  // A22 -= L21 L21^T, lower blocks
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        x[mi][ni][r] = D.B22[blk_row(wr, mi, lane, r)][blk_col(wc, ni, lane)];
+            blk32_mm(x, [&](int r, int m) { return -D.B21[r][m]; }, [&](int m, int c) { return D.B21[c][m]; },
+                     wr, wc, lane);
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        D.B22[blk_row(wr, mi, lane, r)][blk_col(wc, ni, lane)] = x[mi][ni][r];
+        }
+        __syncthreads();
+    }
+    if (state == 1) {  // W21 = -W22 (L21 W11): X = L21 W11 into B21, then W21 into B21
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 2; ++ni) x[mi][ni] = v4d{0.0, 0.0, 0.0, 0.0};
+        if (w < 4)
+            blk32_mm(x, [&](int r, int m) { return D.B21[r][m]; }, [&](int m, int c) { return D.Wb[m][c]; },
+                     wr, wc, lane);
+        __syncthreads();
+        if (w < 4) {
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        D.B21[blk_row(wr, mi, lane, r)][blk_col(wc, ni, lane)] = x[mi][ni][r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 2; ++ni) x[mi][ni] = v4d{0.0, 0.0, 0.0, 0.0};
+        if (w < 4)
+            blk32_mm(x, [&](int r, int m) { return -D.B11[r][m]; }, [&](int m, int c) { return D.B21[m][c]; },
+                     wr, wc, lane);
+        __syncthreads();
+        if (w < 4) {
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        D.B21[blk_row(wr, mi, lane, r)][blk_col(wc, ni, lane)] = x[mi][ni][r];
+        }
+        __syncthreads();
+        // W_k = [[W11, 0], [W21, W22]] out, row-major (c, m) at c 128 + m
+        double *Wk = wbuf + P.w_off + k0 * T2;
+        for (int e = tid; e < T2 * T2; e += NT) {
+            const int m = e & (T2 - 1), c = e >> 7;
+            const double v = c < 64 ? (m < 64 ? D.Wb[c][m] : 0.0) : (m < 64 ? D.B21[c - 64][m] : D.B11[c - 64][m - 64]);
+            bst(Wk + e, v);
+        }
+        // z_k = W_k (y_k - sum_j L_kj z_j); thread c < 128
+        if (tid < T2) {
+            const int c = tid;
+            double zr = 0.0;
+            if (c < 64) {
+#pragma unroll 8
+                for (int m = 0; m < 64; ++m) zr = fma(D.Wb[c][m], sm.ys[m], zr);
+            } else {
+#pragma unroll 8
+                for (int m = 0; m < 64; ++m) zr = fma(D.B21[c - 64][m], sm.ys[m], zr);
+#pragma unroll 8
+                for (int m = 0; m < 64; ++m) zr = fma(D.B11[c - 64][m], sm.ys[64 + m], zr);
+            }
+            if (c < rk) bst(zbuf + P.z_off + k0 + c, zr);
+            sm.zq[c] = c < rk ? zr * zr : 0.0;
+        }
+        __syncthreads();
+        if (tid == 0 || tid == 64) {  // the two partials, one wave each
+            const double *v = tid == 0 ? sm.lg : sm.zq;
+            CSum acc_s;
+            for (int c = 0; c < T2; ++c) acc_s.add(v[c]);
+            bst(part + P.p_off + 2 * k + (tid == 0 ? 0 : 1), acc_s.value());
+        }
+    }
+    return state;
+}
+
 template <int NW>
 __global__ __launch_bounds__(64 * NW, 1) void k_bp128(const BProb *__restrict__ probs, const uint2 *__restrict__ tasks,
                                                   const int64_t *__restrict__ qstart, int dim,
@@ -915,7 +1103,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_bp128(const BProb *__restrict__ 
                                                   double *C_pool, double *lt, double *wbuf, double *zbuf, double *part,
                                                   double *pbuf, int *flags, double *out3, int32_t *info) {
     constexpr int NT = 64 * NW, RB = 8 / NW, CW = 16 * RB;  // threads, 16-column blocks and columns per wave
-    __shared__ P128Smem sm;
+    P128Smem &sm = bp_sm;
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t total = qstart[BQ];
@@ -1192,168 +1380,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_bp128(const BProb *__restrict__ 
                             D.B22[m - 64][c - 64] = acc[mb][rb][r];
                         }
                     }
-            if (tid < T2) {  // y_k - sum_j L_kj z_j, the products published by the tasks (k, j)
-                const double *pk = pbuf + (P.f_off + fk) * T2 + tid;
-                double tsum = 0.0;
-                int j = 0;
-                for (; j + 8 <= k; j += 8) {  // eight loads in flight, summed in order
-                    double v[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) v[u] = bld(pk + (int64_t)(j + u) * T2);
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) tsum += v[u];
-                }
-                for (; j < k; ++j) tsum += bld(pk + (int64_t)j * T2);
-                sm.ys[tid] = tid < rk ? y[P.x_off + k0 + tid] - tsum : 0.0;
-            }
-            __syncthreads();
-            double *Lkk = L + k0 + k0 * ld;
-            const int wr = w & 1, wc = w >> 1;
-            v4d x[2][2];
-            // the two diagonal blocks in turn, through one copy of the
-            // one-wave factor / inverse code: half 0 factors A11 into B11 and
-            // inverts it into Wb; then L21 and A22 - L21 L21^T; half 1 factors
-            // that into B22 and inverts it into B11 (L11 is stored by then)
-#pragma nounroll
-            for (int hb = 0; hb < 2 && state == 1; ++hb) {
-                double(*Bd)[DB + 1] = hb ? D.B22 : D.B11;
-                double(*Wo)[DB + 1] = hb ? D.B11 : D.Wb;
-                const int o = 64 * hb;
-                if (w == 0) {
-                    double a[DB];
-#pragma unroll
-                    for (int c = 0; c < DB; ++c) a[c] = (c <= lane) ? Bd[lane][c] : 0.0;
-                    const int fail = wave_chol64(a, lane, Wo, sm.U.pn);
-                    if (fail) {
-                        if (lane == 0) {
-                            info[b] = (int32_t)(k0 + o + fail);
-                            sm.state = 2;
-                        }
-                    } else {
-#pragma unroll
-                        for (int c = 0; c < DB; ++c) {
-                            Bd[lane][c] = a[c];
-                            if (o + lane < rk && o + c < rk && c <= lane)
-                                Lkk[(o + lane) + (int64_t)(o + c) * ld] = a[c];
-                        }
-                        wave_lds_sync();
-                        sm.lg[o + lane] = o + lane < rk ? log(Bd[lane][lane]) : 0.0;
-                        wave_inv64_blocked(Bd, Wo, sm.U.t32, sm.rd, lane);
-                    }
-                }
-                __syncthreads();
-                state = sm.state;
-                if (hb == 1 || state != 1) break;
-                // L21 = A21 W11^T
-#pragma unroll
-                for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-                    for (int ni = 0; ni < 2; ++ni) x[mi][ni] = v4d{0.0, 0.0, 0.0, 0.0};
-                if (w < 4)
-                    blk32_mm(x, [&](int r, int m) { return D.B21[r][m]; }, [&](int m, int c) { return D.Wb[c][m]; },
-                             wr, wc, lane);
-                __syncthreads();
-                if (w < 4) {
-#pragma unroll
-                    for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-                        for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-                            for (int r = 0; r < 4; ++r) {
-                                const int rr = blk_row(wr, mi, lane, r), c = blk_col(wc, ni, lane);
-                                D.B21[rr][c] = x[mi][ni][r];
-                                if (64 + rr < rk && c < rk) Lkk[(64 + rr) + (int64_t)c * ld] = x[mi][ni][r];
-                            }
-                }
-                __syncthreads();
-                if (w < 4 && wr >= wc) {  // A22 -= L21 L21^T, lower blocks
-#pragma unroll
-                    for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-                        for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-                            for (int r = 0; r < 4; ++r)
-                                x[mi][ni][r] = D.B22[blk_row(wr, mi, lane, r)][blk_col(wc, ni, lane)];
-                    blk32_mm(x, [&](int r, int m) { return -D.B21[r][m]; }, [&](int m, int c) { return D.B21[c][m]; },
-                             wr, wc, lane);
-#pragma unroll
-                    for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-                        for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-                            for (int r = 0; r < 4; ++r)
-                                D.B22[blk_row(wr, mi, lane, r)][blk_col(wc, ni, lane)] = x[mi][ni][r];
-                }
-                __syncthreads();
-            }
-            if (state == 1) {  // W21 = -W22 (L21 W11): X = L21 W11 into B21, then W21 into B21
-#pragma unroll
-                for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-                    for (int ni = 0; ni < 2; ++ni) x[mi][ni] = v4d{0.0, 0.0, 0.0, 0.0};
-                if (w < 4)
-                    blk32_mm(x, [&](int r, int m) { return D.B21[r][m]; }, [&](int m, int c) { return D.Wb[m][c]; },
-                             wr, wc, lane);
-                __syncthreads();
-                if (w < 4) {
-#pragma unroll
-                    for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-                        for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-                            for (int r = 0; r < 4; ++r)
-                                D.B21[blk_row(wr, mi, lane, r)][blk_col(wc, ni, lane)] = x[mi][ni][r];
-                }
-                __syncthreads();
-#pragma unroll
-                for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-                    for (int ni = 0; ni < 2; ++ni) x[mi][ni] = v4d{0.0, 0.0, 0.0, 0.0};
-                if (w < 4)
-                    blk32_mm(x, [&](int r, int m) { return -D.B11[r][m]; }, [&](int m, int c) { return D.B21[m][c]; },
-                             wr, wc, lane);
-                __syncthreads();
-                if (w < 4) {
-#pragma unroll
-                    for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-                        for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-                            for (int r = 0; r < 4; ++r)
-                                D.B21[blk_row(wr, mi, lane, r)][blk_col(wc, ni, lane)] = x[mi][ni][r];
-                }
-                __syncthreads();
-                // W_k = [[W11, 0], [W21, W22]] out, row-major (c, m) at c 128 + m
-                double *Wk = wbuf + P.w_off + k0 * T2;
-                for (int e = tid; e < T2 * T2; e += NT) {
-                    const int m = e & (T2 - 1), c = e >> 7;
-                    const double v = c < 64 ? (m < 64 ? D.Wb[c][m] : 0.0) : (m < 64 ? D.B21[c - 64][m] : D.B11[c - 64][m - 64]);
-                    bst(Wk + e, v);
-                }
-                // z_k = W_k (y_k - sum_j L_kj z_j); thread c < 128
-                if (tid < T2) {
-                    const int c = tid;
-                    double zr = 0.0;
-                    if (c < 64) {
-#pragma unroll 8
-                        for (int m = 0; m < 64; ++m) zr = fma(D.Wb[c][m], sm.ys[m], zr);
-                    } else {
-#pragma unroll 8
-                        for (int m = 0; m < 64; ++m) zr = fma(D.B21[c - 64][m], sm.ys[m], zr);
-#pragma unroll 8
-                        for (int m = 0; m < 64; ++m) zr = fma(D.B11[c - 64][m], sm.ys[64 + m], zr);
-                    }
-                    if (c < rk) bst(zbuf + P.z_off + k0 + c, zr);
-                    sm.zq[c] = c < rk ? zr * zr : 0.0;
-                }
-                __syncthreads();
-                if (tid == 0 || tid == 64) {  // the two partials, one wave each
-                    const double *v = tid == 0 ? sm.lg : sm.zq;
-                    CSum acc_s;
-                    for (int c = 0; c < T2; ++c) acc_s.add(v[c]);
-                    bst(part + P.p_off + 2 * k + (tid == 0 ? 0 : 1), acc_s.value());
-                }
-            }
+            state = diag128_finish<NW>(probs, b, k, C_pool, y, wbuf, zbuf, part, pbuf, info);
         }
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
