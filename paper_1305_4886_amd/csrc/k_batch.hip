@@ -837,20 +837,23 @@ __global__ __launch_bounds__(256, 1) void k_bpersist(const BProb *__restrict__ p
 //
 // The task graph, queues, flags and publication rules of k_bpersist, with
 // tiles twice as wide: one left-looking step moves two 128 KB operand tiles
-// for 4.2 MFLOP (16 flop per byte against 8 with 64 x 64 tiles), and each
-// wave keeps sixteen independent accumulators.  Task (p, i, k) accumulates
-// G = A_ik^T = C_ki - sum_{j<k} L_kj L_ij^T, 128 rows m (tile k) by 128
-// columns r (tile i), wave w holding columns 32 w .. 32 w + 31 of every row.
-// The operands arrive as K-slabs of 16 columns of the tiles' tile-major
-// copies, copied straight into a two-stage LDS ring.  An off-diagonal task
-// then forms L_ik^T = W_k G on the matrix cores, taking G as the B operand
-// straight from its accumulators: the D layout of v_mfma_f64_16x16x4 (lane l,
-// register r: row l / 16 + 4 r, column l % 16) is the B layout of the K-step
-// over rows 4 r .. 4 r + 3.  A diagonal task factors its tile in LDS as a
-// 2 x 2 matrix of 64 x 64 blocks -- L11 and W11 = L11^{-1} by one wave,
-// L21 = A21 W11^T and A22 - L21 L21^T on the matrix cores, L22 and W22 by one
-// wave, W21 = -W22 (L21 W11) -- then forms z_k = W_k (y_k - sum_j L_kj z_j)
-// and the tile's log-determinant / quadratic-form partials.
+// for 4.2 MFLOP (16 flop per byte against 8 with 64 x 64 tiles).  A
+// workgroup has NW waves (eight by default: two per SIMD).  Task (p, i, k)
+// first accumulates S = sum_{j<k} L_kj L_ij^T, 128 rows m (tile k) by 128
+// columns r (tile i), each wave holding 128 / NW columns of every row; the
+// operands arrive as K-slabs of 16 columns of the tiles' tile-major copies,
+// copied straight into a four-stage LDS ring (three slabs in flight).  It
+// then builds the covariance tile in the idle ring and forms
+// G = A_ik^T = C_ki - S.  An off-diagonal task forms L_ik^T = W_k G on the
+// matrix cores, taking G as the B operand straight from its accumulators:
+// the D layout of v_mfma_f64_16x16x4 (lane l, register r: row l / 16 + 4 r,
+// column l % 16) is the B layout of the K-step over rows 4 r .. 4 r + 3; it
+// also publishes L_ik z_k for the diagonal task of row i.  A diagonal task
+// (diag128_finish) factors its tile in LDS as a 2 x 2 matrix of 64 x 64
+// blocks -- L11 and W11 = L11^{-1} by one wave, L21 = A21 W11^T and
+// A22 - L21 L21^T on the matrix cores, L22 and W22 by one wave,
+// W21 = -W22 (L21 W11) -- then forms z_k = W_k (y_k - sum_j L_kj z_j) and
+// the tile's log-determinant / quadratic-form partials.
 // ---------------------------------------------------------------------------
 constexpr int T2 = 128, BK2 = 16;
 constexpr int BP_NW = 8;  // waves per workgroup of the 128-tile launch (two per SIMD)
