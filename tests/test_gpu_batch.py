@@ -210,3 +210,25 @@ def test_batched_many_theta_over_shared_points(orc, grid):
         ll, ld, q = orc.loglik(k, t, X, y)
         assert abs(out[b, 0] - ll) <= 1e-11 * abs(ll), (b, out[b], ll)
         assert abs(out[b, 2] - q) <= 1e-11 * abs(q)
+
+
+@pytest.mark.parametrize("dim", [1, 3])
+def test_batched_other_point_dimensions(orc, grid, dim):
+    """Points on a line (dim 1) and in space (dim 3): the persistent launches
+    take their coordinates through the general distance path, not the planar
+    one staged in LDS."""
+    sizes = [130, 257, 64, 1]
+    rng = np.random.default_rng(70 + dim)
+    Xs = [rng.uniform(0.0, 1.0, size=(n, dim)) for n in sizes]
+    ys = [rng.standard_normal(n) for n in sizes]
+    ths = [(b % 3, np.array([math.log(1.0 + 0.2 * b), math.log(0.2), math.log(0.05)])) for b in range(len(sizes))]
+    r = gp.loglik_batched(dev(np.concatenate(Xs)), dev(np.concatenate(ys)), [gp.theta(k, log=t) for k, t in ths],
+                          sizes)
+    out = r["out3"].cpu().numpy()
+    assert np.all(r["info"].cpu().numpy() == 0)
+    for b in range(len(sizes)):
+        k, t = ths[b]
+        ll, ld, q = orc.loglik(k, t, Xs[b], ys[b])
+        assert abs(out[b, 0] - ll) <= 1e-11 * abs(ll), (dim, b, out[b], ll)
+        assert abs(out[b, 1] - ld) <= 1e-11 * max(1.0, abs(ld)), (dim, b)
+        assert abs(out[b, 2] - q) <= 1e-11 * abs(q), (dim, b)
