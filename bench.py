@@ -356,7 +356,7 @@ def main():
     # read and written once (8 B each way per flop pair / K) plus the panel
     nb = h.potrf_plan(n)[0]  # the panel width (K of each trailing update) the factorisation used
     alg_bytes = (2 * 8 * syrk_per_launch_flops / (2 * nb)) if syrk_per_launch_flops else None
-    roofline = {"kernel": "trailing SYRK (k_syrk_dma<2,16,1,x4>, role 1)", "bound": "mfma",
+    roofline = {"kernel": "trailing SYRK (k_syrk_dma<2,16,1,x4,8 waves>, role 1)", "bound": "mfma",
                 "achieved": syrk_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": (syrk_tflops / FP64_PEAK_TFLOPS) if syrk_tflops else None,
                 "traffic": traffic, "traffic_unit": "B/launch", "traffic_source": traffic_src,

@@ -324,15 +324,23 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmDesc d, TileMap tm) {
 // copies per wave and slab instead of sixteen 4-byte ones); needs 16-byte
 // aligned column starts (even leading dimensions, aligned bases) and an even
 // row count so that a lane's two rows never straddle the last row.
-template <int STAGES, int BKD, int TAG, bool X4 = false>
-__global__ __launch_bounds__(256, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
-    constexpr int BM = 128, WTM = 64, FM = 4, FN = 4;
-    constexpr int NKK = BKD / 4;           // MFMA K-steps per slab = panel columns each wave copies
-    constexpr int PER = X4 ? NKK * 2 : NKK * 2 * 4;  // copies per wave per slab
-    constexpr int CPK = PER / NKK;         // copies per K-step, one after every 8 / CPK MFMA pairs
-    static_assert(BKD % 4 == 0 && STAGES >= 2, "slab shape");
+// NW waves per workgroup, 2 x (NW / 2) of 64 x (256 / NW): with NW = 8 (16-byte
+// copies only) each wave holds 64 x 32 (eight accumulators, 108 VGPRs), so two
+// workgroups give four waves per SIMD instead of two, which hides the
+// per-slab barrier and LDS latencies better (measured 61.4 against 60.5
+// TFLOP/s on the trailing update at n = 32768).
+template <int STAGES, int BKD, int TAG, bool X4 = false, int NW = 4>
+__global__ __launch_bounds__(64 * NW, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
+    static_assert(NW == 4 || (NW == 8 && X4), "eight waves only with 16-byte copies");
+    constexpr int BM = 128, WTM = 64, WTN = 256 / NW, FM = 4, FN = WTN / 16, NT = 64 * NW;
+    constexpr int NKK = BKD / 4;           // MFMA K-steps per slab
+    constexpr int PER = X4 ? NKK * 8 / NW : NKK * 2 * 4;  // copies per wave per slab
+    constexpr int CPK = PER / NKK;         // copies per K-step
+    constexpr int NPAIR = FM * FN / 2;     // MFMA pairs per K-step; a copy follows every NPAIR / CPK of them
+    constexpr int CPOS = NW == 8 ? 0 : NPAIR / CPK - 1;  // which pair of such a group the copy follows (measured)
+    static_assert(BKD % 4 == 0 && STAGES >= 2 && NPAIR % CPK == 0, "slab shape");
     static_assert((STAGES - 2) * PER < 64, "outstanding copies exceed vmcnt");
-    static_assert(STAGES * 2 * BKD * BM >= 4 * 2048, "the ring holds the epilogue's four wave regions");
+    static_assert(STAGES * 2 * BKD * BM >= NW * 32 * WTN, "the ring holds the epilogue's wave regions");
     __shared__ double Ls[STAGES][2][BKD][BM];  // [stage][operand][k][row]
 
     if (d.info && *d.info) return;
@@ -380,10 +388,10 @@ __global__ __launch_bounds__(256, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
         }
     }
     // copy c (0 .. PER - 1) of this wave for slab `slab` into stage st:
-    //   X4: column wave + 4 (c / 2) of operand c % 2, all 128 rows;
+    //   X4: column wave + NW (c / 2) of operand c % 2, all 128 rows;
     //   else: column wave + 4 (c / 8), q = c % 8: operand A rows 32 q.. (q < 4), else B
     auto copy1 = [&](int slab, int st, int c) {
-        const int kk = wave + 4 * (X4 ? c >> 1 : c >> 3);
+        const int kk = wave + (X4 ? NW * (c >> 1) : 4 * (c >> 3));
         int64_t kc = (int64_t)(kf + slab) * BKD + kk;
         if (kc >= d.K) kc = d.K - 1;  // tail columns: any valid address, zeroed in LDS below
         if (X4) {
@@ -424,7 +432,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
         const int ns = k + STAGES - 1, nst = st == 0 ? STAGES - 1 : st - 1;
         if (k == nk - 1 && ktail < BKD) {  // columns past K contribute zero (uniform branch)
             const int nz = (BKD - ktail) * BM;
-            for (int e = tid; e < 2 * nz; e += 256) {
+            for (int e = tid; e < 2 * nz; e += NT) {
                 const int op = e >= nz, r = e - op * nz;
                 Ls[st][op][ktail + r / BM][r % BM] = 0.0;
             }
@@ -434,7 +442,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
 #pragma unroll
         for (int m = 0; m < FM; ++m) a[m] = Ls[st][0][(lane >> 4)][wm * WTM + m * 16 + (lane & 15)];
 #pragma unroll
-        for (int n = 0; n < FN; ++n) b[n] = Ls[st][1][(lane >> 4)][wn * WTM + n * 16 + (lane & 15)];
+        for (int n = 0; n < FN; ++n) b[n] = Ls[st][1][(lane >> 4)][wn * WTN + n * 16 + (lane & 15)];
 #pragma unroll
         for (int kk = 0; kk < NKK; ++kk) {
             double an[FM], bn[FN];
@@ -444,16 +452,16 @@ __global__ __launch_bounds__(256, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
                     an[m] = Ls[st][0][4 * (kk + 1) + (lane >> 4)][wm * WTM + m * 16 + (lane & 15)];
 #pragma unroll
                 for (int n = 0; n < FN; ++n)
-                    bn[n] = Ls[st][1][4 * (kk + 1) + (lane >> 4)][wn * WTM + n * 16 + (lane & 15)];
+                    bn[n] = Ls[st][1][4 * (kk + 1) + (lane >> 4)][wn * WTN + n * 16 + (lane & 15)];
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int m = q >> 1, n0 = (q & 1) * 2;
+            for (int q = 0; q < NPAIR; ++q) {
+                const int m = q / (FN / 2), n0 = (q % (FN / 2)) * 2;
                 acc[m][n0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[n0], acc[m][n0], 0, 0, 0);
                 acc[m][n0 + 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[n0 + 1], acc[m][n0 + 1], 0, 0, 0);
                 __builtin_amdgcn_sched_barrier(0);
-                if (more && q % (8 / CPK) == 8 / CPK - 1) copy1(ns, nst, kk * CPK + q / (8 / CPK));
+                if (more && q % (NPAIR / CPK) == CPOS) copy1(ns, nst, kk * CPK + q / (NPAIR / CPK));
                 __builtin_amdgcn_sched_barrier(0);
             }
             if (kk + 1 < NKK) {
@@ -466,12 +474,12 @@ __global__ __launch_bounds__(256, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
         st = st + 1 == STAGES ? 0 : st + 1;
     }
 
-    // Epilogue through the (now idle) LDS ring: each wave writes its 64 x 64
-    // accumulator block in two halves of 32 rows into a private 16 KB region
-    // and reads it back with lane = row, so the C tile is read and written
-    // as 256-byte column segments (the MFMA D layout -- lane l, register r:
-    // row l / 16 + 4 r, column l % 16 -- would give 32-byte pieces of 16
-    // columns per instruction).  The C loads of a half are issued before the
+    // Epilogue through the (now idle) LDS ring: each wave writes its 64 x WTN
+    // accumulator block in two halves of 32 rows into a private region
+    // (32 WTN doubles) and reads it back with lane = row, so the C tile is
+    // read and written as 256-byte column segments (the MFMA D layout -- lane
+    // l, register r: row l / 16 + 4 r, column l % 16 -- would give 32-byte
+    // pieces of 16 columns per instruction).  The C loads of a half are issued before the
     // LDS exchange.  Region: element (row p, column g) at g 32 + (p ^ 2 (g % 16)),
     // a swizzle that keeps both the writes and the reads free of bank conflicts.
     // Tiles on the diagonal or the matrix edge keep the direct, guarded
@@ -479,17 +487,17 @@ __global__ __launch_bounds__(256, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
     const bool interior = (i0 + BM <= d.M) && (j0 + BM <= d.N) && (!d.lower || i0 >= j0 + BM);
     const bool use_c = d.beta != 0.0;
     if (interior) {
-        double *R = &Ls[0][0][0][0] + wave * 2048;
+        double *R = &Ls[0][0][0][0] + wave * (32 * WTN);
         const int p = lane & 31, hc = lane >> 5;
         __syncthreads();  // every wave is past its last ring read
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int64_t gi = i0 + wm * WTM + 32 * h + p;
-            double *Cc = C + gi + (j0 + wn * WTM + hc) * d.ldc;
-            double cv[32];
+            double *Cc = C + gi + (j0 + wn * WTN + hc) * d.ldc;
+            double cv[WTN / 2];
             if (use_c) {
 #pragma unroll
-                for (int q = 0; q < 32; ++q) cv[q] = Cc[(int64_t)(2 * q) * d.ldc];
+                for (int q = 0; q < WTN / 2; ++q) cv[q] = Cc[(int64_t)(2 * q) * d.ldc];
             }
 #pragma unroll
             for (int mm = 0; mm < 2; ++mm)
@@ -502,7 +510,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
                     }
             // the wave reads back only its own region: its LDS operations complete in order
 #pragma unroll
-            for (int q = 0; q < 32; ++q) {
+            for (int q = 0; q < WTN / 2; ++q) {
                 const int g = 2 * q + hc;
                 const double v = R[g * 32 + (p ^ (2 * (g & 15)))];
                 Cc[(int64_t)(2 * q) * d.ldc] = use_c ? fma(d.beta, cv[q], d.alpha * v) : d.alpha * v;
@@ -511,7 +519,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk_dma(GemmDesc d, TileMap tm) {
         return;
     }
     const int64_t rb0 = i0 + wm * WTM + (lane >> 4);
-    const int64_t cb0 = j0 + wn * WTM + (lane & 15);
+    const int64_t cb0 = j0 + wn * WTN + (lane & 15);
 #pragma unroll
     for (int m = 0; m < FM; ++m) {
         double cv[FN][4];
@@ -992,7 +1000,7 @@ namespace {
 // Operands whose columns start on 16-byte boundaries, with even row counts,
 // take 16-byte copies and two LDS stages of 16 panel columns; others four
 // stages of 8 columns with 4-byte copies.  Both rings are 64 KB (two
-// workgroups per CU).  Measured at K = 512, M = 32256 / 16310 / 8210:
+// workgroups per CU; the 16-byte form runs eight waves per workgroup).  Measured at K = 512, M = 32256 / 16310 / 8210:
 // 65.0 / 60.7 / 53.0 TFLOP/s against 62.8 / 58.5 / 50.1.
 template <int TAG>
 hipError_t run_dma(hipStream_t s, const GemmDesc &d) {
@@ -1007,8 +1015,9 @@ hipError_t run_dma(hipStream_t s, const GemmDesc &d) {
                     (d.batch == 1 || (d.sA % 2 == 0 && d.sB % 2 == 0));
     if (x4 && d.slab == 8)  // 8-column slabs in four stages
         hipLaunchKernelGGL((k_syrk_dma<4, 8, TAG, true>), dim3((unsigned)g, (unsigned)d.batch), dim3(256), 0, s, d, tm);
-    else if (x4)            // 16-column slabs in two stages
-        hipLaunchKernelGGL((k_syrk_dma<2, 16, TAG, true>), dim3((unsigned)g, (unsigned)d.batch), dim3(256), 0, s, d, tm);
+    else if (x4)            // 16-column slabs in two stages, eight waves
+        hipLaunchKernelGGL((k_syrk_dma<2, 16, TAG, true, 8>), dim3((unsigned)g, (unsigned)d.batch), dim3(512), 0, s, d,
+                           tm);
     else
         hipLaunchKernelGGL((k_syrk_dma<4, 8, TAG, false>), dim3((unsigned)g, (unsigned)d.batch), dim3(256), 0, s, d,
                            tm);
@@ -1075,7 +1084,7 @@ hipError_t launch_band_f64(hipStream_t s, int band, const double *P, int64_t ldp
     if (K % 8 != 0)
         hipLaunchKernelGGL((k_gemm_f64<128, 128, 2, 2, 0, 1, 4>), dim3((unsigned)g), dim3(256), 0, s, d, tb);
     else if (x4)
-        hipLaunchKernelGGL((k_syrk_dma<2, 16, 4, true>), dim3((unsigned)g), dim3(256), 0, s, d, tb);
+        hipLaunchKernelGGL((k_syrk_dma<2, 16, 4, true, 8>), dim3((unsigned)g), dim3(512), 0, s, d, tb);
     else
         hipLaunchKernelGGL((k_syrk_dma<4, 8, 4, false>), dim3((unsigned)g), dim3(256), 0, s, d, tb);
     return hipGetLastError();
