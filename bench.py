@@ -180,7 +180,7 @@ def main():
 
     results = {k: [] for k in ["chol", "loglik", "krige", "kcov", "sim", "grad", "mixed32", "mixed16", "mixed16s",
                                "batch"]}
-    syrk = [0, 0.0, 0.0]
+    syrk = [0, 0.0, 0.0, 0.0]
     last = {}
     Xs = torch.as_tensor(synth.uniform_points(m, 41), device=dev)
     ws_k = h.workspace(gp.GP_OP_KRIGE, n, m) if "krige" in parts else None
@@ -217,11 +217,12 @@ def main():
         if record:
             results["chol"].append(ev)
             torch.cuda.synchronize()
-            launches, ms, fl = h.profile_read()
+            launches, ms, fl, by = h.profile_read()
             h.profile(False)
             syrk[0] += launches
             syrk[1] += ms
             syrk[2] += fl
+            syrk[3] += by
             assert int(info.item()) == 0
         # 2. FP64 log-likelihood evaluation (cov build + Cholesky + solves + logdet), alpha kept
         r, ev = timed(lambda: gp.loglik(X, y, th, S=S, ws=ws_l, want_alpha=True))
@@ -352,10 +353,9 @@ def main():
     syrk_tflops = syrk[2] / (syrk[1] / 1e3) / 1e12 if syrk[1] > 0 else None
     syrk_per_launch_flops = syrk[2] / syrk[0] if syrk[0] else None
     traffic, traffic_src = measured_traffic()
-    # algorithmic HBM bytes of the same launches: the lower-triangle C tile
-    # read and written once (8 B each way per flop pair / K) plus the panel
-    nb = h.potrf_plan(n)[0]  # the panel width (K of each trailing update) the factorisation used
-    alg_bytes = (2 * 8 * syrk_per_launch_flops / (2 * nb)) if syrk_per_launch_flops else None
+    # algorithmic HBM bytes of the same launches (from the library's count): the
+    # lower-triangle C entries read and written once, 8 B each way
+    alg_bytes = syrk[3] / syrk[0] if syrk[0] else None
     roofline = {"kernel": "trailing SYRK (k_syrk_dma<2,16,1,x4,8 waves>, role 1)", "bound": "mfma",
                 "achieved": syrk_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": (syrk_tflops / FP64_PEAK_TFLOPS) if syrk_tflops else None,

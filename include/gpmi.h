@@ -138,6 +138,10 @@ typedef struct {
     int32_t batch_tile;  /* gp_loglik_batched, persistent launch: tile edge 64 or 128 (0 = automatic: the
                             tuning table's choice for the largest problem's size bucket, else 128).  The
                             level-synchronous launches (batch_grid = -1) always use 64. */
+    int32_t tail_nb;     /* Cholesky: panel width once at most 24 x tail_nb columns remain to be factored,
+                            where the chain of diagonal-block steps of a wide panel outlasts the trailing
+                            update it overlaps (0 = automatic: 512; -1 = the outer width throughout).
+                            Used only when narrower than the outer width; a multiple of 64 otherwise. */
 } gp_options_t;
 
 /* ---- handle ------------------------------------------------------------ */
@@ -154,11 +158,13 @@ const char *gp_strerror(int code);
 /* Kernel timing for measurement tools.  While enabled, every trailing-update
  * launch of the Cholesky (the matrix-core SYRK/GEMM that carries almost all of
  * its work, Section 2.1) is bracketed by events on the handle's stream.
- * gp_profile_read waits for those events and returns out3 [host, 3] =
- * {launches, total milliseconds, algorithmic flops} accumulated since the
- * previous read, then resets the counters. */
+ * gp_profile_read waits for those events and returns out4 [host, 4] =
+ * {launches, total milliseconds, algorithmic flops, algorithmic bytes}
+ * accumulated since the previous read, then resets the counters.  A launch
+ * that updates E lower-triangle entries with a rank-K product counts 2 K E
+ * flops and 16 E bytes (each entry read and written once in FP64). */
 int gp_profile(gp_handle_t h, int enable);
-int gp_profile_read(gp_handle_t h, double *out3);
+int gp_profile_read(gp_handle_t h, double *out4);
 
 /* Bytes of workspace the call `op` needs for problem size n (and m new points
  * for GP_OP_KRIGE, GP_OP_KRIGE_COV and GP_OP_SIMULATE (n = 0: no data) /
@@ -214,9 +220,11 @@ int gp_tune_potrf(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t l
  * under the handle's current options and tuning table (what gp_potrf and the
  * factorising calls would use): *nb = outer panel width, *panel_cus =
  * compute units reserved for the lookahead chain, *syrk_slab = K-slab shape
- * of the FP64 trailing-update tile (16 or 8) [host, each nullable].  No
- * device work. */
-int gp_potrf_plan(gp_handle_t h, gp_prec_t prec, int64_t n, int32_t *nb, int32_t *panel_cus, int32_t *syrk_slab);
+ * of the FP64 trailing-update tile (16 or 8), *tail_nb = width of the panels
+ * that start where at most 24 x tail_nb columns remain (equal to *nb when the
+ * width does not change) [host, each nullable].  No device work. */
+int gp_potrf_plan(gp_handle_t h, gp_prec_t prec, int64_t n, int32_t *nb, int32_t *panel_cus, int32_t *syrk_slab,
+                  int32_t *tail_nb);
 
 /* ---- triangular solves with the lower factor (Section 1 "backsolve";
  *      the remoteForwardsolve / remoteBacksolve of Section 2.3.2) --------- */

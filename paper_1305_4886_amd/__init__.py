@@ -49,7 +49,7 @@ class Options(ctypes.Structure):
                 ("reorder", ctypes.c_int32), ("panel_cus", ctypes.c_int32),
                 ("fused_panel", ctypes.c_int32), ("batch_grid", ctypes.c_int32),
                 ("fail_inject", ctypes.c_int32), ("bf16_split", ctypes.c_int32),
-                ("syrk_slab", ctypes.c_int32), ("batch_tile", ctypes.c_int32)]
+                ("syrk_slab", ctypes.c_int32), ("batch_tile", ctypes.c_int32), ("tail_nb", ctypes.c_int32)]
 
 
 class GPError(RuntimeError):
@@ -105,7 +105,7 @@ def lib():
         L.gp_tune_save.argtypes = [vp, ctypes.c_char_p]
         L.gp_tune_load.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(i32)]
         L.gp_tune_clear.argtypes = [vp]
-        L.gp_potrf_plan.argtypes = [vp, i32, i64, vp, vp, vp]
+        L.gp_potrf_plan.argtypes = [vp, i32, i64, vp, vp, vp, vp]
         L.gp_krige_cov.argtypes = [vp, Theta, i64, i64, i32, vp, vp, vp, i64, i32, vp, i64, vp, sz]
         L.gp_trmm.argtypes = [vp, i64, i64, vp, i64, vp, i64, vp, i64, vp, sz]
         L.gp_simulate.argtypes = [vp, Theta, i64, i64, i32, vp, vp, vp, i64, vp, dbl, i32, i64, vp, i64, vp, i64,
@@ -208,8 +208,9 @@ class Handle:
         check(lib().gp_tune_clear(self._h))
 
     def potrf_plan(self, n, prec=GP_FP64):
-        """(panel width, reserved CUs, K-slab) the factorisation of an n x n matrix would use."""
-        v = [ctypes.c_int32(0) for _ in range(3)]
+        """(panel width, reserved CUs, K-slab, tail panel width) the factorisation of an
+        n x n matrix would use."""
+        v = [ctypes.c_int32(0) for _ in range(4)]
         check(lib().gp_potrf_plan(self._h, int(prec), int(n), *[ctypes.byref(x) for x in v]))
         return tuple(x.value for x in v)
 
@@ -223,10 +224,11 @@ class Handle:
         check(lib().gp_profile(self._h, 1 if enable else 0))
 
     def profile_read(self):
-        """(launches, milliseconds, algorithmic flops) of trailing updates since the last read."""
-        out = (ctypes.c_double * 3)()
+        """(launches, milliseconds, algorithmic flops, algorithmic bytes) of trailing updates
+        since the last read."""
+        out = (ctypes.c_double * 4)()
         check(lib().gp_profile_read(self._h, out))
-        return int(out[0]), float(out[1]), float(out[2])
+        return int(out[0]), float(out[1]), float(out[2]), float(out[3])
 
     def tune_potrf(self, n, prec=GP_FP64, nb=(256, 384, 512, 768, 1024), panel_cus=(0, 8, 16)):
         """Time gp_potrf over (nb, panel_cus) -- and, in FP64, both trailing-update tile shapes --

@@ -105,17 +105,42 @@ void tune_store(gp_handle_t h, const TuneEntry &e) {
 // The factorisation's choices for (prec, n): explicit options (nb > 0) win;
 // with nb = 0 (automatic) a tuned entry for n's size bucket, else the
 // defaults.
+// The tail width: panels that start where at most TAIL_SPAN x tail columns
+// remain are that narrow (when it is below nb), because there a wide panel's
+// chain of diagonal-block steps on the side stream outlasts the trailing
+// update it overlaps.
+constexpr int64_t TAIL_SPAN = 24;
 struct PotrfChoice {
     int64_t nb;
     int panel_cus, slab;
+    int64_t tail;
 };
 PotrfChoice potrf_choice(gp_handle_t h, gp_prec_t prec, int64_t n) {
-    if (h->opt.nb > 0 || h->tuning) return {h->opt.nb > 0 ? h->opt.nb : 768, h->opt.panel_cus, h->opt.syrk_slab};
-    if (const TuneEntry *e = tune_find(h, 0, prec, n)) return {e->nb, e->panel_cus, e->syrk_slab};
-    return {prec == GP_FP64 ? 768 : (prec == GP_FP32_TRAIL ? 512 : 640), h->opt.panel_cus, h->opt.syrk_slab};
+    PotrfChoice c;
+    if (h->opt.nb > 0 || h->tuning)
+        c = {h->opt.nb > 0 ? h->opt.nb : 768, h->opt.panel_cus, h->opt.syrk_slab, 0};
+    else if (const TuneEntry *e = tune_find(h, 0, prec, n))
+        c = {e->nb, e->panel_cus, e->syrk_slab, 0};
+    else
+        c = {prec == GP_FP64 ? 768 : (prec == GP_FP32_TRAIL ? 512 : 640), h->opt.panel_cus, h->opt.syrk_slab, 0};
+    const int64_t tw = h->opt.tail_nb == 0 ? 512 : h->opt.tail_nb;
+    c.tail = (tw > 0 && tw < c.nb) ? tw : c.nb;
+    return c;
 }
 
-int64_t panel_width(gp_handle_t h, gp_prec_t prec, int64_t n) { return potrf_choice(h, prec, n).nb; }
+// Width of the panel that starts at column c of an n-column factorisation (the
+// last one clipped to n).  Widths never grow along the factorisation.
+int64_t panel_at(const PotrfChoice &ch, int64_t n, int64_t c) {
+    const int64_t w = (ch.tail < ch.nb && n - c <= TAIL_SPAN * ch.tail) ? ch.tail : ch.nb;
+    return c + w < n ? w : n - c;
+}
+
+// The widest panel (the first): what the panel buffers of the workspace hold.
+int64_t panel_width(gp_handle_t h, gp_prec_t prec, int64_t n) {
+    const PotrfChoice ch = potrf_choice(h, prec, n);
+    const int64_t w = (ch.tail < ch.nb && n <= TAIL_SPAN * ch.tail) ? ch.tail : ch.nb;
+    return w;
+}
 
 // The batched call's schedule: the option unless it is the automatic 0 and a
 // tuned entry exists for the largest problem's size bucket.
@@ -339,6 +364,7 @@ hipError_t trailing(gp_handle_t h, hipStream_t s, gp_prec_t prec, const double *
     if (h->prof) {
         hipEventRecord(e1, s);
         h->prof_flops += syrk_flops(M, N, K);
+        h->prof_bytes += 16.0 * syrk_entries(M, N);
         h->prof_launches += 1;
     }
     return e;
@@ -375,6 +401,7 @@ hipError_t trailing_packed(gp_handle_t h, hipStream_t s, gp_prec_t prec, const d
     if (h->prof) {
         hipEventRecord(e1, s);
         h->prof_flops += syrk_flops(M, N, K);
+        h->prof_bytes += 16.0 * syrk_entries(M, N);
         h->prof_launches += 1;
     }
     return e;
@@ -522,12 +549,12 @@ int potrf_impl(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda,
                double *dinv, const PanelBufs &pb) {
     hipStream_t user = h->stream;
     const PotrfChoice ch = potrf_choice(h, prec, n);
-    const int64_t NB = ch.nb;
     HIPCHK(launch_set_info(user, info));
     if (n <= 0) return GP_OK;
+    auto width = [&](int64_t c) { return panel_at(ch, n, c); };
 
     hipStream_t s = user, side = h->side;
-    const bool la = h->opt.lookahead && n > NB;
+    const bool la = h->opt.lookahead && n > width(0);
     if (la && ch.panel_cus > 0) {
         int rc = make_masked_streams(h, ch.panel_cus);
         if (rc) return rc;
@@ -582,15 +609,15 @@ int potrf_impl(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda,
 
     int rc = 0;
     {
-        const int64_t c1 = NB < n ? NB : n;
+        const int64_t c1 = width(0);
         if ((rc = diag_block(s, 0, c1))) return rc;
         if (c1 < n && (rc = below(s, 0, c1))) return rc;
     }
-    for (int64_t c0 = 0; c0 < n; c0 += NB) {
-        const int64_t c1 = (c0 + NB < n) ? c0 + NB : n;
-        if (c1 >= n) break;
+    // panel [c0, c1) is factored; its trailing update runs while the next
+    // panel [c1, c2) is factored on the side stream
+    for (int64_t c0 = 0, c1 = width(0); c1 < n; c0 = c1, c1 += width(c1)) {
         const int64_t K = c1 - c0;
-        const int64_t c2 = (c1 + NB < n) ? c1 + NB : n;
+        const int64_t c2 = c1 + width(c1);
         const bool packed = prec != GP_FP64 && pb.qbuf && K % 32 == 0;
         if (packed) HIPCHK(launch_pack_panel(s, prec, A + c1 + c0 * lda, lda, n - c1, K, pb.qbuf, h->opt.bf16_split));
         // trailing update of rows / columns [r0, r1) x [r0, ...) from panel rows r0 ..
@@ -905,6 +932,7 @@ static void default_options(gp_options_t *o) {
     o->batch_grid = 0;
     o->bf16_split = 1;
     o->batch_tile = 0;
+    o->tail_nb = 0;
 }
 
 }  // extern "C"
@@ -990,9 +1018,9 @@ int gp_profile(gp_handle_t h, int enable) {
     return GP_OK;
 }
 
-int gp_profile_read(gp_handle_t h, double *out3) {
+int gp_profile_read(gp_handle_t h, double *out4) {
     if (!ok_handle(h)) return -1;
-    if (!out3) return -2;
+    if (!out4) return -2;
     double ms = 0.0;
     for (size_t i = 0; i + 1 < h->prof_used; i += 2) {
         if (hipEventSynchronize(h->prof_ev[i + 1]) != hipSuccess) return GP_ERR_HIP;
@@ -1000,12 +1028,14 @@ int gp_profile_read(gp_handle_t h, double *out3) {
         if (hipEventElapsedTime(&t, h->prof_ev[i], h->prof_ev[i + 1]) != hipSuccess) return GP_ERR_HIP;
         ms += t;
     }
-    out3[0] = (double)h->prof_launches;
-    out3[1] = ms;
-    out3[2] = h->prof_flops;
+    out4[0] = (double)h->prof_launches;
+    out4[1] = ms;
+    out4[2] = h->prof_flops;
+    out4[3] = h->prof_bytes;
     h->prof_used = 0;
     h->prof_launches = 0;
     h->prof_flops = 0.0;
+    h->prof_bytes = 0.0;
     return GP_OK;
 }
 
@@ -1054,6 +1084,7 @@ int gp_set_options(gp_handle_t h, const gp_options_t *opt) {
     if (opt->bf16_split != 0 && opt->bf16_split != 1) return -2;
     if (opt->syrk_slab != 0 && opt->syrk_slab != 8 && opt->syrk_slab != 16) return -2;
     if (opt->batch_tile != 0 && opt->batch_tile != 64 && opt->batch_tile != 128) return -2;
+    if (opt->tail_nb < -1 || (opt->tail_nb > 0 && opt->tail_nb % DB != 0)) return -2;
     if (!(opt->ir_tol >= 0.0) || isinf(opt->ir_tol)) return GP_ERR_NONFINITE;
     h->opt = *opt;
     return GP_OK;
@@ -1119,7 +1150,8 @@ int gp_potrf(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda, i
     return potrf_impl(h, prec, n, A, lda, info_dev, at<double>(ws, L.dinv), panel_bufs(ws, L));
 }
 
-int gp_potrf_plan(gp_handle_t h, gp_prec_t prec, int64_t n, int32_t *nb, int32_t *panel_cus, int32_t *syrk_slab) {
+int gp_potrf_plan(gp_handle_t h, gp_prec_t prec, int64_t n, int32_t *nb, int32_t *panel_cus, int32_t *syrk_slab,
+                  int32_t *tail_nb) {
     if (!ok_handle(h)) return -1;
     if (prec < GP_FP64 || prec > GP_BF16_TRAIL) return -2;
     if (n < 0) return -3;
@@ -1127,6 +1159,7 @@ int gp_potrf_plan(gp_handle_t h, gp_prec_t prec, int64_t n, int32_t *nb, int32_t
     if (nb) *nb = (int32_t)c.nb;
     if (panel_cus) *panel_cus = c.panel_cus;
     if (syrk_slab) *syrk_slab = c.slab == 0 ? 16 : c.slab;
+    if (tail_nb) *tail_nb = (int32_t)c.tail;
     return GP_OK;
 }
 

@@ -52,6 +52,7 @@ struct gp_handle_s {
     std::vector<hipEvent_t> prof_ev;  // start/stop pairs
     size_t prof_used = 0;             // events in use
     double prof_flops = 0.0;
+    double prof_bytes = 0.0;
     int64_t prof_launches = 0;
     int num_cu = 256;                 // compute units of the device
     void *batch_staging = nullptr;    // host staging of the batched task table
@@ -445,11 +446,12 @@ hipError_t launch_lowp_packed(hipStream_t s, gp_prec_t prec, int band, const dou
 // its diagonal (P[i, k] = 0 for k < i), so tile rows i0.. start at k = i0.
 hipError_t launch_syrk_dma(hipStream_t s, const double *P, int64_t ldp, double *C, int64_t ldc, int64_t M, int64_t K,
                            double alpha, double beta, int klo_i, const int32_t *info);
-// Algorithmic flops of a lower-trapezoid update of M rows x N columns (N <= M)
-// with inner dimension K: 2 K (N M - N (N - 1) / 2).
-inline double syrk_flops(int64_t M, int64_t N, int64_t K) {
-    return 2.0 * (double)K * ((double)N * (double)M - 0.5 * (double)N * (double)(N - 1));
+// Entries of a lower trapezoid of M rows x N columns (N <= M): N M - N (N - 1) / 2;
+// an update of them with inner dimension K takes 2 K of flops per entry.
+inline double syrk_entries(int64_t M, int64_t N) {
+    return (double)N * (double)M - 0.5 * (double)N * (double)(N - 1);
 }
+inline double syrk_flops(int64_t M, int64_t N, int64_t K) { return 2.0 * (double)K * syrk_entries(M, N); }
 // Panel solve in place: A[0:M, 0:jb] <- A[0:M, 0:jb] * Winv^T (Winv jb x jb lower, ld DB).
 hipError_t launch_panel_solve(hipStream_t s, double *A, int64_t lda, const double *Winv,
                               int64_t M, int jb, const int32_t *info);

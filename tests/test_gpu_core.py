@@ -70,24 +70,32 @@ def test_cross_cov(orc, n, m):
 
 # (n, panel width (0: the default), lookahead, compute units reserved for the
 #  lookahead chain, fused panel kernel or the per-64-column launch chain,
-#  leading dimension - n).  An odd leading dimension keeps the trailing update
-#  on its 4-byte copies; ld = n with even n (the benchmark's layout) takes the
-#  16-byte copies of the main trailing-update kernel.
+#  leading dimension - n, tail panel width (-1: none, 0: the default)).  An odd
+#  leading dimension keeps the trailing update on its 4-byte copies; ld = n
+#  with even n (the benchmark's layout) takes the 16-byte copies of the main
+#  trailing-update kernel.  A tail width w takes over once at most 24 w
+#  columns remain.
 POTRF_CASES = [
-    (1, 256, 1, 8, 1, 3), (2, 256, 1, 8, 1, 3), (63, 256, 1, 8, 1, 3), (64, 256, 1, 8, 1, 3),
-    (65, 256, 1, 8, 1, 3), (127, 64, 0, 0, 1, 3), (200, 128, 1, 8, 1, 3), (257, 256, 1, 0, 1, 3),
-    (500, 64, 1, 8, 1, 3), (1000, 256, 1, 8, 1, 3), (1000, 256, 0, 8, 1, 3), (1100, 128, 1, 0, 1, 3),
-    (2048, 512, 1, 8, 1, 3), (3001, 256, 1, 16, 1, 3), (3001, 192, 1, 8, 1, 3), (4500, 512, 1, 8, 1, 3),
-    (3001, 768, 1, 0, 1, 3), (2500, 1024, 1, 0, 1, 3), (2500, 1024, 0, 0, 1, 3),
-    (127, 64, 0, 0, 0, 3), (1000, 256, 1, 8, 0, 3), (3001, 192, 1, 8, 0, 3), (4500, 512, 1, 0, 0, 3),
-    # the benchmark's configuration: default panel width (768), lookahead, ld = n
-    (8192, 0, 1, 0, 1, 0), (4096, 0, 1, 0, 1, 0), (3000, 0, 1, 0, 1, 0), (4000, 512, 0, 0, 1, 0),
-    (2050, 0, 1, 0, 1, 2),
+    (1, 256, 1, 8, 1, 3, -1), (2, 256, 1, 8, 1, 3, -1), (63, 256, 1, 8, 1, 3, -1), (64, 256, 1, 8, 1, 3, -1),
+    (65, 256, 1, 8, 1, 3, -1), (127, 64, 0, 0, 1, 3, -1), (200, 128, 1, 8, 1, 3, -1), (257, 256, 1, 0, 1, 3, -1),
+    (500, 64, 1, 8, 1, 3, -1), (1000, 256, 1, 8, 1, 3, -1), (1000, 256, 0, 8, 1, 3, -1),
+    (1100, 128, 1, 0, 1, 3, -1), (2048, 512, 1, 8, 1, 3, -1), (3001, 256, 1, 16, 1, 3, -1),
+    (3001, 192, 1, 8, 1, 3, -1), (4500, 512, 1, 8, 1, 3, -1), (3001, 768, 1, 0, 1, 3, -1),
+    (2500, 1024, 1, 0, 1, 3, -1), (2500, 1024, 0, 0, 1, 3, -1),
+    (127, 64, 0, 0, 0, 3, -1), (1000, 256, 1, 8, 0, 3, -1), (3001, 192, 1, 8, 0, 3, -1), (4500, 512, 1, 0, 0, 3, -1),
+    # the benchmark's configuration: default panel width, lookahead, ld = n
+    (8192, 0, 1, 0, 1, 0, 0), (4096, 0, 1, 0, 1, 0, 0), (3000, 0, 1, 0, 1, 0, 0), (4000, 512, 0, 0, 1, 0, 0),
+    (2050, 0, 1, 0, 1, 2, 0),
+    # wide panels, then narrow ones for the last columns (both trailing-update copy widths,
+    # with and without lookahead, reserved compute units, the launch-chain panels)
+    (4500, 512, 1, 0, 1, 0, 128), (4500, 512, 1, 8, 1, 3, 128), (4500, 512, 0, 0, 1, 0, 128),
+    (8192, 768, 1, 0, 1, 0, 256), (3001, 384, 1, 0, 0, 3, 64), (700, 768, 1, 0, 1, 0, 0),
+    (2500, 1024, 1, 0, 1, 0, 0),
 ]
 
 
-@pytest.mark.parametrize("n,nb,la,pc,fused,pad", POTRF_CASES)
-def test_potrf_parity(orc, n, nb, la, pc, fused, pad):
+@pytest.mark.parametrize("n,nb,la,pc,fused,pad,tail", POTRF_CASES)
+def test_potrf_parity(orc, n, nb, la, pc, fused, pad, tail):
     X = synth.uniform_points(n, 100 + n)
     t = logth(1.0, 0.1, 0.1)
     C = orc.cov(0, t, X)
@@ -97,13 +105,17 @@ def test_potrf_parity(orc, n, nb, la, pc, fused, pad):
     del C
     h = gp.handle()
     saved = h.options()
-    h.set_options(nb=nb, lookahead=la, panel_cus=pc, fused_panel=fused)
+    h.set_options(nb=nb, lookahead=la, panel_cus=pc, fused_panel=fused, tail_nb=tail)
     try:
+        plan = h.potrf_plan(n)
+        print("plan (nb, panel_cus, slab, tail):", plan, flush=True)
+        if tail > 0:
+            assert plan[3] == min(tail, plan[0])
         info = gp.potrf(S, n)
         torch.cuda.synchronize()
     finally:
         h.set_options(nb=saved.nb, lookahead=saved.lookahead, panel_cus=saved.panel_cus,
-                      fused_panel=saved.fused_panel)
+                      fused_panel=saved.fused_panel, tail_nb=saved.tail_nb)
     assert int(info.item()) == 0
     M = gp.colmajor(S, n).cpu().numpy()
     assert np.all(M[np.triu_indices(n, 1)] == -3.25), "upper triangle must stay untouched"

@@ -69,7 +69,7 @@ def test_table_round_trip_and_lookup(tmp_path):
         assert ws_bytes(h, 3000) == default_3000
         # the plan query reports the same resolution: tuned width in the bucket, default outside
         assert h.potrf_plan(n)[0] == best_nb and h.potrf_plan(1100)[0] == best_nb
-        assert h.potrf_plan(3000) == (768, 0, 16)
+        assert h.potrf_plan(3000) == (768, 0, 16, 512)
         # the factor with the tuned choice still matches the oracle
         X = synth.uniform_points(n, 5)
         t = np.array([0.0, math.log(0.1), math.log(0.1)])
@@ -98,6 +98,10 @@ def test_malformed_or_missing_table(tmp_path):
     with pytest.raises(gp.GPError) as e:
         h.set_options(syrk_slab=12)
     assert e.value.code == -2
+    for bad_tail in (-2, 100):
+        with pytest.raises(gp.GPError) as e:
+            h.set_options(tail_nb=bad_tail)
+        assert e.value.code == -2
 
 
 def test_shipped_table_is_for_this_device():
@@ -122,12 +126,13 @@ def test_both_tile_shapes_factor_correctly(slab):
     h = gp.handle()
     saved = h.options()
     try:
-        h.set_options(nb=768, syrk_slab=slab)
+        h.set_options(nb=768, syrk_slab=slab, tail_nb=-1)
+        assert h.potrf_plan(n) == (768, 0, slab, 768)
         S = gp.colmajor_storage(n)
         gp.colmajor(S, n).copy_(torch.as_tensor(np.tril(C)))
         assert int(gp.potrf(S, n).item()) == 0
     finally:
-        h.set_options(nb=saved.nb, syrk_slab=saved.syrk_slab)
+        h.set_options(nb=saved.nb, syrk_slab=saved.syrk_slab, tail_nb=saved.tail_nb)
     Lo, _ = oracle.potrf(C)
     L = np.tril(S[:n, :n].T.cpu().numpy())
     err = np.linalg.norm(L - Lo) / np.linalg.norm(Lo)
