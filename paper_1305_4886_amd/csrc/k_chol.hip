@@ -73,7 +73,8 @@ __global__ __launch_bounds__(64) void k_diag_potrf(double *A, int64_t lda, int j
 // Phase 1 (workgroup b owns block row b; right-looking by block columns k):
 //   when L_kk and W_k = L_kk^{-1} are published:
 //     L_bk = S_bk W_k^T, published;  S_bj -= L_bk L_jk^T for k < j <= b
-//     (L_jk from workgroup j as soon as it is published);
+//     (L_jk from workgroup j as soon as it is published; S_bb is kept in
+//     registers, S_bk is read before W_k is waited for);
 //   after the last column: L_bb = chol(S_bb) and W_b (one wave, as in
 //   k_diag_potrf), published.  Critical path per 64 columns: two 64^3
 //   products, the 64 x 64 factor and inverse, and one flag round trip.
@@ -161,29 +162,46 @@ GP_DEV void pf_load(double (*dst)[DB + 1], const double *M, int64_t ld, int rows
     }
 }
 
-// acc[n][i] = sum_m X(row, m) Y[col][m] over m < 64, wave w: row = 16 w +
-// lane / 16 + 4 i, col = 16 n + lane % 16 (the D layout of
-// v_mfma_f64_16x16x4).  X from LDS (Xs[row][m]) or, with Xs null, from memory
-// (Xg[row + m ldx], rows >= xrows read as zero).
-GP_DEV void pf_gemm(const double (*Xs)[DB + 1], const double *Xg, int64_t ldx, int xrows, const double (*Y)[DB + 1],
-                    gp_v4d (&acc)[4], int w, int lane) {
+// The wave's A operand of a 64 x 64 x 64 product, X(row, m) for row = 16 w +
+// lane % 16, m = 4 q + lane / 16 (q < 16): from LDS (Xs[row][m]) or from
+// memory (Xg[row + m ldx]; rows >= xrows read row xrows - 1 and give zero).
+GP_DEV void pf_xload(const double (*Xs)[DB + 1], const double *Xg, int64_t ldx, int xrows, double (&a)[16], int w,
+                     int lane) {
     const int row = 16 * w + (lane & 15);
-    double a[16];
     if (Xs) {
 #pragma unroll
         for (int q = 0; q < 16; ++q) a[q] = Xs[row][4 * q + (lane >> 4)];
     } else {
+        const int rr = row < xrows ? row : xrows - 1;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) a[q] = row < xrows ? ld_coh(Xg + row + (int64_t)(4 * q + (lane >> 4)) * ldx) : 0.0;
+        for (int q = 0; q < 16; ++q) a[q] = ld_coh(Xg + rr + (int64_t)(4 * q + (lane >> 4)) * ldx);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) a[q] = row < xrows ? a[q] : 0.0;
     }
+}
+
+// acc[n][i] (+)= sum_m X(row, m) Y[col][m] over m < 64 with X from pf_xload,
+// wave w: row = 16 w + lane / 16 + 4 i, col = 16 n + lane % 16 (the D layout
+// of v_mfma_f64_16x16x4).  With accumulate, acc holds the addend on entry.
+GP_DEV void pf_mm(const double (&a)[16], const double (*Y)[DB + 1], gp_v4d (&acc)[4], int lane,
+                  bool accumulate = false) {
+    if (!accumulate) {
 #pragma unroll
-    for (int n = 0; n < 4; ++n) acc[n] = gp_v4d{0.0, 0.0, 0.0, 0.0};
+        for (int n = 0; n < 4; ++n) acc[n] = gp_v4d{0.0, 0.0, 0.0, 0.0};
+    }
 #pragma unroll
     for (int q = 0; q < 16; ++q)
 #pragma unroll
         for (int n = 0; n < 4; ++n)
             acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], Y[16 * n + (lane & 15)][4 * q + (lane >> 4)], acc[n], 0,
                                                           0, 0);
+}
+
+GP_DEV void pf_gemm(const double (*Xs)[DB + 1], const double *Xg, int64_t ldx, int xrows, const double (*Y)[DB + 1],
+                    gp_v4d (&acc)[4], int w, int lane) {
+    double a[16];
+    pf_xload(Xs, Xg, ldx, xrows, a, w, lane);
+    pf_mm(a, Y, acc, lane);
 }
 
 // M(row, col) += sgn acc for the wave's rows < rows and cols < cols (and col <= row
@@ -243,14 +261,39 @@ __global__ __launch_bounds__(256, 1) void k_panel_chol(double *A, int64_t lda, i
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int rb = K - DB * b < DB ? K - DB * b : DB;  // rows (and columns) of block b
     double *Ab = A + DB * b;                           // block row b: Ab[r + c lda]
+    double *Wc = W ? W + (int64_t)DB * b * ldw : nullptr;  // block column b of W: Wc[r + c ldw], r < K
     gp_v4d acc[4];
+    // the rest of W's block column b first: zeros above the diagonal block and
+    // T_sb = 0 below it (the stores drain while phase 1 waits)
+    if (W) {
+        for (int e = tid; e < DB * DB; e += 256) {
+            const int r = e & (DB - 1), c = e >> 6;
+            for (int s2 = 0; s2 < b; ++s2) Wc[DB * s2 + r + (int64_t)c * ldw] = 0.0;
+            for (int s2 = b + 1; s2 < nb; ++s2) st_coh(Wc + DB * s2 + r + (int64_t)c * ldw, 0.0);
+        }
+    }
 
     // ---- phase 1 ----
+    // S_bb stays in registers (the D layout of pf_mm) while the steps k < b
+    // subtract L_bk L_bk^T from it; the other blocks of block row b are
+    // updated in memory.
+    gp_v4d sbb[4];
+    if (factor) {
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * w + (lane >> 4) + 4 * i, c = 16 * n + (lane & 15);
+                sbb[n][i] = ld_coh(Ab + (r < rb ? r : rb - 1) + (int64_t)(DB * b + (c < rb ? c : rb - 1)) * lda);
+            }
+    }
     for (int k = 0; factor && k < b; ++k) {
+        double xa[16];  // S_bk: final once this workgroup's own updates of it are complete
+        pf_xload(nullptr, Ab + (int64_t)DB * k * lda, lda, rb, xa, w, lane);
         if (!pf_wait(flags, k * PF_MAXB + k, &s_ok, info)) return;
         pf_load<false>(sm.g.op, dinv + (int64_t)k * DB * DB, DB, DB, DB);  // W_k
         __syncthreads();
-        pf_gemm(nullptr, Ab + (int64_t)DB * k * lda, lda, rb, sm.g.op, acc, w, lane);  // L_bk = S_bk W_k^T
+        pf_mm(xa, sm.g.op, acc, lane);  // L_bk = S_bk W_k^T
 #pragma unroll
         for (int n = 0; n < 4; ++n)
 #pragma unroll
@@ -260,36 +303,47 @@ __global__ __launch_bounds__(256, 1) void k_panel_chol(double *A, int64_t lda, i
                 if (r < rb) st_coh(Ab + r + (int64_t)(DB * k + c) * lda, acc[n][i]);
             }
         pf_publish(flags, b * PF_MAXB + k);  // its barrier also orders the lb writes
-        for (int j = k + 1; j <= b; ++j) {
-            const double (*Y)[DB + 1] = sm.g.lb;
-            if (j < b) {
-                if (!pf_wait(flags, j * PF_MAXB + k, &s_ok, info)) return;
-                pf_load<false>(sm.g.op, A + DB * j + (int64_t)DB * k * lda, lda, DB, DB);  // L_jk
-                __syncthreads();
-                Y = sm.g.op;
-            }
-            pf_gemm(sm.g.lb, nullptr, 0, 0, Y, acc, w, lane);  // L_bk L_jk^T
-            // S_bj -= L_bk L_jk^T (the diagonal block's lower triangle only)
-            pf_accum(Ab + (int64_t)DB * j * lda, lda, acc, -1.0, rb, j < b ? DB : rb, j == b, w, lane);
+        {  // S_bb -= L_bk L_bk^T
+            double nl[16];
+            pf_xload(sm.g.lb, nullptr, 0, 0, nl, w, lane);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) nl[q] = -nl[q];
+            pf_mm(nl, sm.g.lb, sbb, lane, true);
+        }
+        for (int j = k + 1; j < b; ++j) {  // S_bj -= L_bk L_jk^T
+            if (!pf_wait(flags, j * PF_MAXB + k, &s_ok, info)) return;
+            pf_load<false>(sm.g.op, A + DB * j + (int64_t)DB * k * lda, lda, DB, DB);  // L_jk
+            __syncthreads();
+            pf_gemm(sm.g.lb, nullptr, 0, 0, sm.g.op, acc, w, lane);
+            pf_accum(Ab + (int64_t)DB * j * lda, lda, acc, -1.0, rb, DB, false, w, lane);
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
             __syncthreads();  // op is reloaded next; S_bj stores complete
         }
+        __syncthreads();  // lb and op are rewritten by the next step
     }
     // diagonal block: one wave factors and inverts it (or, when it is
-    // factored already, W_b is read back)
+    // factored already, W_b is read back).  The four waves stage the updated
+    // S_bb from their registers in LDS first (lower triangle; rows and
+    // columns past the block replaced by the identity).
+    double *D = Ab + (int64_t)DB * b * lda;
+    if (factor) {
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * w + (lane >> 4) + 4 * i, c = 16 * n + (lane & 15);
+                sm.d.ls[r][c] = (r < rb && c < rb) ? (c <= r ? sbb[n][i] : 0.0) : (r == c ? 1.0 : 0.0);
+            }
+        __syncthreads();
+    }
     if (!factor) {
         for (int e = tid; e < DB * DB; e += 256) sm.d.wl[e & (DB - 1)][e >> 6] = dinv[(int64_t)b * DB * DB + e];
         if (tid == 0) s_ok = 1;
     } else if (w == 0) {
         double a[DB];
-        double *D = Ab + (int64_t)DB * b * lda;
 #pragma unroll
-        for (int c = 0; c < DB; ++c) {
-            double v;
-            if (lane < rb && c < rb) v = (c <= lane) ? ld_coh(D + lane + (int64_t)c * lda) : 0.0;
-            else v = (lane == c) ? 1.0 : 0.0;
-            a[c] = v;
-        }
+        for (int c = 0; c < DB; ++c) a[c] = sm.d.ls[lane][c];
+        wave_lds_sync();
         const int fail = wave_chol64(a, lane, sm.d.ls, sm.d.u.pn);
         if (fail) {
             if (lane == 0) {
@@ -302,26 +356,26 @@ __global__ __launch_bounds__(256, 1) void k_panel_chol(double *A, int64_t lda, i
 #pragma unroll
             for (int c = 0; c < DB; ++c) sm.d.ls[lane][c] = a[c];
             wave_lds_sync();
-#pragma unroll
-            for (int c = 0; c < DB; ++c)
-                if (lane < rb && c < rb && c <= lane) st_coh(D + lane + (int64_t)c * lda, a[c]);
             wave_inv64_blocked(sm.d.ls, sm.d.wl, sm.d.u.t32, sm.d.rd, lane);
-            double *Wb = dinv + (int64_t)b * DB * DB;
-#pragma unroll 4
-            for (int c = 0; c < DB; ++c) st_coh(Wb + lane + c * DB, sm.d.wl[lane][c]);
         }
     }
     __syncthreads();
     if (!s_ok) return;
-    // phase 2 starts from W_b; its block column of W is written before the
-    // publication, while W_b is still in LDS
-    double *Wc = W ? W + (int64_t)DB * b * ldw : nullptr;  // block column b: Wc[r + c ldw], r < K
+    if (factor) {  // L_bb (lower triangle) and W_b out of LDS, 16 columns per wave
+        double *Wb = dinv + (int64_t)b * DB * DB;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int c = 16 * w + q;
+            if (lane < rb && c < rb && c <= lane) st_coh(D + lane + (int64_t)c * lda, sm.d.ls[lane][c]);
+            st_coh(Wb + lane + c * DB, sm.d.wl[lane][c]);
+        }
+    }
+    // phase 2 starts from W_b, written into its block column of W before the
+    // publication, while it is still in LDS
     if (W) {
         for (int e = tid; e < DB * DB; e += 256) {
             const int r = e & (DB - 1), c = e >> 6;
-            for (int s2 = 0; s2 < b; ++s2) Wc[DB * s2 + r + (int64_t)c * ldw] = 0.0;  // above the diagonal
-            st_coh(Wc + DB * b + r + (int64_t)c * ldw, sm.d.wl[r][c]);              // W_bb
-            for (int s2 = b + 1; s2 < nb; ++s2) st_coh(Wc + DB * s2 + r + (int64_t)c * ldw, 0.0);  // T_sb = 0
+            st_coh(Wc + DB * b + r + (int64_t)c * ldw, sm.d.wl[r][c]);  // W_bb
         }
     }
     pf_publish(flags, b * PF_MAXB + b);
