@@ -217,12 +217,12 @@ def main():
         if record:
             results["chol"].append(ev)
             torch.cuda.synchronize()
-            launches, ms, fl, by = h.profile_read()
+            launches, ms, fl, alg = h.profile_read()
             h.profile(False)
             syrk[0] += launches
             syrk[1] += ms
             syrk[2] += fl
-            syrk[3] += by
+            syrk[3] += alg
             assert int(info.item()) == 0
         # 2. FP64 log-likelihood evaluation (cov build + Cholesky + solves + logdet), alpha kept
         r, ev = timed(lambda: gp.loglik(X, y, th, S=S, ws=ws_l, want_alpha=True))
