@@ -42,12 +42,16 @@ def main(argv=None):
     if not a.batched_only:
         h.tune_clear()  # measure from scratch, not on top of a loaded table
     sizes = [] if a.batched_only else [int(v) for v in a.sizes.split(",") if v]
-    widths = {gp.GP_FP64: [512, 640, 768, 896, 1024], gp.GP_FP32_TRAIL: [384, 512, 640, 768],
+    widths = {gp.GP_FP64: [384, 512, 640, 768, 896, 1024], gp.GP_FP32_TRAIL: [384, 512, 640, 768],
               gp.GP_BF16_TRAIL: [384, 512, 640, 768]}
     if a.quick:
         widths = {p: w[1:3] for p, w in widths.items()}
+    tail = 512  # the automatic tail width (gp_options_t.tail_nb = 0)
     for n in sizes:
         for prec, cand in widths.items():
+            # a width above the tail width whose panels would all be the tail width
+            # (n <= 24 x tail) runs the same schedule as the tail width itself
+            cand = [w for w in cand if w <= tail or n > 24 * tail] or cand[:1]
             ms = h.tune_potrf(n, prec, nb=cand, panel_cus=(0,))
             o = h.options()
             print("n=%d prec=%d: %s -> nb %d slab %d" % (n, prec, {k[0]: round(v, 2) for k, v in ms.items()}, o.nb,
