@@ -131,3 +131,31 @@ def test_mixed_potrf_reconstruction(orc):
         rec = np.linalg.norm(L @ L.T - C) / np.linalg.norm(C)
         print("prec %d reconstruction %.2e" % (prec, rec))
         assert int(info.item()) == 0 and rec <= tol
+
+
+@pytest.mark.parametrize("prec", [gp.GP_FP32_TRAIL, gp.GP_BF16_TRAIL])
+def test_mixed_loglik_with_tail_panels(orc, prec):
+    # 512-wide panels while more than 24 x 128 columns remain, then 128-wide
+    # ones: packed panels of both widths, and a last panel of 4000 % 128 = 32
+    # columns, against the oracle at the mixed bar
+    n = 4000
+    X = synth.uniform_points(n, 61)
+    y = synth.smooth_field(X, 62, ell=0.1, t2=0.1)
+    t = logth(1.0, 0.1, 0.1)
+    ll, _, q = orc.loglik(0, t, X, y)
+    h = gp.handle()
+    saved = h.options()
+    try:
+        h.set_options(nb=512, tail_nb=128)
+        assert h.potrf_plan(n, prec)[0] == 512 and h.potrf_plan(n, prec)[3] == 128
+        r = gp.loglik(dev(X), dev(y), gp.theta(0, log=t), prec=prec)
+        out = r["out3"].cpu().numpy()
+        ir = r["ir"].cpu().numpy()
+    finally:
+        h.set_options(nb=saved.nb, tail_nb=saved.tail_nb)
+    err = abs(out[0] - ll) / abs(ll)
+    print("prec %d tail panels: rel loglik err %.2e ir=%s" % (prec, err, ir))
+    assert int(r["info"].item()) == 0
+    assert ir[2] == 1.0 and ir[1] <= 1e-10, ir
+    assert abs(out[2] - q) <= 1e-9 * abs(q)
+    assert err <= 1e-6
