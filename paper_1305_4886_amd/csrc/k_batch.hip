@@ -357,13 +357,19 @@ constexpr int BQ = 8;  // task queues
 // flag, then one flag per tile
 constexpr int BF_TICKET = 0, BF_ABORT = 32 * BQ, BF_TILES = 32 * BQ + 32;
 
+// Every buffer these touch is device memory: the global address space is
+// stated, so that code the compiler cannot trace back to a kernel argument
+// (the diagonal task's finish, a call of its own) still uses global rather
+// than flat accesses, which would also count in lgkmcnt and make each LDS
+// wait there wait for the stores in flight.
+typedef __attribute__((address_space(1))) uint64_t gu64;
+typedef __attribute__((address_space(1))) double gf64;
 GP_DEV double bld(const double *p) {
-    return __longlong_as_double((long long)__hip_atomic_load(
-        reinterpret_cast<uint64_t *>(const_cast<double *>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    return __longlong_as_double(
+        (long long)__hip_atomic_load((gu64 *)const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
 GP_DEV void bst(double *p, double v) {
-    __hip_atomic_store(reinterpret_cast<uint64_t *>(p), (uint64_t)__double_as_longlong(v), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store((gu64 *)p, (uint64_t)__double_as_longlong(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 GP_DEV int bflag(const int *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 GP_DEV int64_t tri64(int64_t r) { return r * (r + 1) / 2; }
@@ -973,11 +979,7 @@ __device__ __attribute__((noinline)) int diag128_finish(const BProb *__restrict_
                 }
             } else {
 #pragma unroll
-                for (int c = 0; c < DB; ++c) {
-                    Bd[lane][c] = a[c];
-                    if (o + lane < rk && o + c < rk && c <= lane)
-                        Lkk[(o + lane) + (int64_t)(o + c) * ld] = a[c];
-                }
+                for (int c = 0; c < DB; ++c) Bd[lane][c] = a[c];
                 wave_lds_sync();
                 sm.lg[o + lane] = o + lane < rk ? log(Bd[lane][lane]) : 0.0;
                 wave_inv64_blocked(Bd, Wo, sm.U.t32, sm.rd, lane);
@@ -985,6 +987,13 @@ __device__ __attribute__((noinline)) int diag128_finish(const BProb *__restrict_
         }
         __syncthreads();
         state = sm.state;
+        if (state == 1) {  // the factored block out of LDS by every wave (off the one-wave chain)
+            gf64 *Lg = (gf64 *)Lkk;
+            for (int e = tid; e < DB * DB; e += NT) {
+                const int r = e & (DB - 1), c = e >> 6;
+                if (c <= r && o + r < rk && o + c < rk) Lg[(o + r) + (int64_t)(o + c) * ld] = Bd[r][c];
+            }
+        }
         if (hb == 1 || state != 1) break;
         // L21 = A21 W11^T
 #pragma unroll
@@ -1004,7 +1013,7 @@ __device__ __attribute__((noinline)) int diag128_finish(const BProb *__restrict_
                     for (int r = 0; r < 4; ++r) {
                         const int rr = blk_row(wr, mi, lane, r), c = blk_col(wc, ni, lane);
                         D.B21[rr][c] = x[mi][ni][r];
-                        if (64 + rr < rk && c < rk) Lkk[(64 + rr) + (int64_t)c * ld] = x[mi][ni][r];
+                        if (64 + rr < rk && c < rk) ((gf64 *)Lkk)[(64 + rr) + (int64_t)c * ld] = x[mi][ni][r];
                     }
         }
         __syncthreads();

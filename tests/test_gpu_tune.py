@@ -138,3 +138,49 @@ def test_both_tile_shapes_factor_correctly(slab):
     err = np.linalg.norm(L - Lo) / np.linalg.norm(Lo)
     print("slab %d: factor rel err %.2e" % (slab, err))
     assert err <= 1e-12
+
+
+def trailing_launches(n, nb, tail):
+    """The trailing updates of a lookahead factorisation, as (M, N, K): the
+    panel [c0, c1) updates the next panel's columns, then the rest."""
+    def width(c):
+        w = tail if (0 < tail < nb and n - c <= 24 * tail) else nb
+        return min(w, n - c)
+    out, c0, c1 = [], 0, width(0)
+    while c1 < n:
+        c2 = c1 + width(c1)
+        out.append((n - c1, c2 - c1, c1 - c0))
+        if c2 < n:
+            out.append((n - c2, n - c2, c1 - c0))
+        c0, c1 = c1, c2
+    return out
+
+
+@pytest.mark.parametrize("n,nb,tail", [(4000, 512, 128), (4096, 768, -1), (2000, 384, 0), (3001, 512, 0)])
+def test_profile_counts_the_trailing_updates(n, nb, tail):
+    # the profile read that the benchmark's roofline is computed from: one
+    # launch per trailing update, 2 K E flops and 16 E bytes for E updated
+    # lower-trapezoid entries, E = N M - N (N - 1) / 2
+    X = synth.uniform_points(n, 9)
+    t = np.array([0.0, math.log(0.1), math.log(0.1)])
+    h = gp.handle()
+    saved = h.options()
+    S = gp.colmajor_storage(n)
+    try:
+        h.set_options(nb=nb, tail_nb=tail, lookahead=1)
+        gp.cov_build(torch.as_tensor(X, device="cuda"), gp.theta(0, log=t), S)
+        h.profile_read()  # drop anything counted before
+        h.profile(True)
+        info = gp.potrf(S, n)
+        torch.cuda.synchronize()
+        launches, ms, flops, nbytes = h.profile_read()
+    finally:
+        h.profile(False)
+        h.set_options(nb=saved.nb, tail_nb=saved.tail_nb, lookahead=saved.lookahead)
+    assert int(info.item()) == 0
+    sched = trailing_launches(n, nb, tail if tail != 0 else 512)
+    ent = [N * M - N * (N - 1) / 2 for M, N, K in sched]
+    assert launches == len(sched)
+    assert math.isclose(flops, sum(2 * K * e for (M, N, K), e in zip(sched, ent)), rel_tol=1e-12)
+    assert math.isclose(nbytes, sum(16 * e for e in ent), rel_tol=1e-12)
+    assert ms > 0.0
