@@ -981,7 +981,7 @@ __device__ __attribute__((noinline)) int diag128_finish(const BProb *__restrict_
 #pragma unroll
                 for (int c = 0; c < DB; ++c) Bd[lane][c] = a[c];
                 wave_lds_sync();
-                sm.lg[o + lane] = o + lane < rk ? log(Bd[lane][lane]) : 0.0;
+                sm.lg[o + lane] = Bd[lane][lane];  // its log is taken off the chain, below
                 wave_inv64_blocked(Bd, Wo, sm.U.t32, sm.rd, lane);
             }
         }
@@ -1096,6 +1096,7 @@ __device__ __attribute__((noinline)) int diag128_finish(const BProb *__restrict_
             }
             if (c < rk) bst(zbuf + P.z_off + k0 + c, zr);
             sm.zq[c] = c < rk ? zr * zr : 0.0;
+            sm.lg[c] = c < rk ? log(sm.lg[c]) : 0.0;
         }
         __syncthreads();
         if (tid == 0 || tid == 64) {  // the two partials, one wave each
