@@ -234,7 +234,10 @@ GP_DEV void pf_accum(double *M, int64_t ld, const gp_v4d (&acc)[4], double sgn, 
 __global__ __launch_bounds__(256, 1) void k_panel_chol(double *A, int64_t lda, int K, double *dinv, double *W,
                                                        int64_t ldw, int *flags, int32_t *info, int64_t col0,
                                                        int factor, int64_t sA, int64_t sD, int64_t sW, int64_t sF) {
-    // 74 KB, so that a workgroup fits beside one workgroup of the trailing update
+    // 74 KB, so that a workgroup fits beside one workgroup of the trailing
+    // update; for the same reason its registers (VGPRs rounded to 8, plus
+    // AGPRs) must stay within 288, the 512 of a SIMD less that workgroup's
+    // two waves of 112
     __shared__ union {
         struct {
             double op[DB][DB + 1];  // B operand of the current product
@@ -316,10 +319,12 @@ __global__ __launch_bounds__(256, 1) void k_panel_chol(double *A, int64_t lda, i
             __syncthreads();
             pf_gemm(sm.g.lb, nullptr, 0, 0, sm.g.op, acc, w, lane);
             pf_accum(Ab + (int64_t)DB * j * lda, lda, acc, -1.0, rb, DB, false, w, lane);
-            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-            __syncthreads();  // op is reloaded next; S_bj stores complete
+            __syncthreads();  // op is reloaded next
         }
-        __syncthreads();  // lb and op are rewritten by the next step
+        // the S_bj stores complete before any of them is read back (by other
+        // lanes of the same wave, at later steps); lb and op are rewritten next
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
     }
     // diagonal block: one wave factors and inverts it (or, when it is
     // factored already, W_b is read back).  The four waves stage the updated
