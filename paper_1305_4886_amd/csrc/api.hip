@@ -370,6 +370,34 @@ hipError_t trailing(gp_handle_t h, hipStream_t s, gp_prec_t prec, const double *
     return e;
 }
 
+// One part of a split FP64 trailing update (launch_syrk_split), bracketed
+// like trailing(); part 0 counts the work of the first ncols columns, part 1
+// that of the rest, so that the two sum to the unsplit pair.
+hipError_t trailing_part(gp_handle_t h, hipStream_t s, const double *P, int64_t ldp, double *C, int64_t ldc,
+                         int64_t M, int64_t ncols, int64_t K, const int32_t *info, int slab, int slots, int part) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (h->prof) {
+        while (h->prof_ev.size() < h->prof_used + 2) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return hipErrorOutOfMemory;
+            h->prof_ev.push_back(e);
+        }
+        e0 = h->prof_ev[h->prof_used];
+        e1 = h->prof_ev[h->prof_used + 1];
+        h->prof_used += 2;
+        hipEventRecord(e0, s);
+    }
+    hipError_t e = launch_syrk_split(s, P, ldp, C, ldc, M, ncols, K, info, part, slots, slab);
+    if (h->prof) {
+        hipEventRecord(e1, s);
+        const int64_t Mp = part == 0 ? M : M - ncols, Np = part == 0 ? ncols : M - ncols;
+        h->prof_flops += syrk_flops(Mp, Np, K);
+        h->prof_bytes += 16.0 * syrk_entries(Mp, Np);
+        h->prof_launches += 1;
+    }
+    return e;
+}
+
 // Low-precision trailing update from the packed panel, bracketed like trailing().
 hipError_t trailing_packed(gp_handle_t h, hipStream_t s, gp_prec_t prec, const double *P, int64_t ldp,
                            const void *Q, int64_t Mpack, int64_t qrow0, double *C, int64_t ldc, int64_t M,
@@ -555,6 +583,9 @@ int potrf_impl(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda,
 
     hipStream_t s = user, side = h->side;
     const bool la = h->opt.lookahead && n > width(0);
+    // workgroups of the trailing update that run at once: two per compute
+    // unit of the main stream
+    const int slots = 2 * (h->num_cu - (la ? ch.panel_cus : 0) > 0 ? h->num_cu - (la ? ch.panel_cus : 0) : 1);
     if (la && ch.panel_cus > 0) {
         int rc = make_masked_streams(h, ch.panel_cus);
         if (rc) return rc;
@@ -631,14 +662,24 @@ int potrf_impl(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda,
         if (la) {
             // columns of the next panel first; then, on the side stream, its
             // diagonal block and the rows below it (columns c1 .. c2, which
-            // the rest of this trailing update does not touch)
-            HIPCHK(update(c1, c2 - c1));
+            // the rest of this trailing update does not touch).  In FP64 the
+            // two updates are the parts of one split tile order, the first
+            // topped up with tiles of the rest to fill its last round.
+            const double *Pn = A + c1 + c0 * lda;
+            double *Ct = A + c1 + c1 * lda;
+            const bool split = !packed && prec == GP_FP64 && c2 < n &&
+                               launch_syrk_split(s, Pn, lda, Ct, lda, n - c1, c2 - c1, K, info, -1, slots,
+                                                 ch.slab) == hipSuccess;
+            HIPCHK(split ? trailing_part(h, s, Pn, lda, Ct, lda, n - c1, c2 - c1, K, info, ch.slab, slots, 0)
+                         : update(c1, c2 - c1));
             HIPCHK(hipEventRecord(h->ev_cols, s));
             HIPCHK(hipStreamWaitEvent(side, h->ev_cols, 0));
             if ((rc = diag_block(side, c1, c2))) return rc;
             if (c2 < n && (rc = below(side, c1, c2))) return rc;
             HIPCHK(hipEventRecord(h->ev_panel, side));
-            if (c2 < n) HIPCHK(update(c2, n - c2));
+            if (c2 < n)
+                HIPCHK(split ? trailing_part(h, s, Pn, lda, Ct, lda, n - c1, c2 - c1, K, info, ch.slab, slots, 1)
+                             : update(c2, n - c2));
             HIPCHK(hipStreamWaitEvent(s, h->ev_panel, 0));
         } else {
             HIPCHK(update(c1, n - c1));

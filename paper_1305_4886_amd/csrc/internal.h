@@ -420,6 +420,12 @@ hipError_t launch_gemm_f64(hipStream_t s, const GemmDesc &d);
 hipError_t launch_syrk_lower(hipStream_t s, gp_prec_t prec, int band, const double *P,
                              int64_t ldp, double *C, int64_t ldc, int64_t M, int64_t N, int64_t K,
                              const int32_t *info, int role, int slab = 0);
+// The FP64 trailing update of the lower triangle of order M in two launches
+// (part 0: the first ncols columns' tiles, topped up to a multiple of
+// `slots` with the first tiles of the rest; part 1: the rest).
+// hipErrorInvalidValue, with nothing launched, where the split does not apply.
+hipError_t launch_syrk_split(hipStream_t s, const double *P, int64_t ldp, double *C, int64_t ldc, int64_t M,
+                             int64_t ncols, int64_t K, const int32_t *info, int part, int slots, int slab);
 // Low-precision trailing updates from a packed copy of the panel: rows
 // 0 .. Mpack - 1 of P (FP64, ld ldp, K columns) rounded once into Q
 // (packed_panel_bytes(Mpack, K) bytes); a call then updates the M x N lower

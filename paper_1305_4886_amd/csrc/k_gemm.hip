@@ -30,9 +30,12 @@ struct TileMap {
     int64_t ntm, ntn, ntiles;
     int lower;
     int sgm, sgn;   // super-tile shape in tiles
-    int bandmode;   // 0 all tiles, 1 only 0 <= bi - bj < band (own enumeration), 2 only bi - bj >= band
+    int bandmode;   // 0 all tiles, 1 only 0 <= bi - bj < band (own enumeration), 2 only bi - bj >= band,
+                    // 3 the lower triangle with its first `band` tile columns first (split launches)
     int64_t band;
     int interleave; // 1: tile t = workgroup id (round-robin over the XCDs), 0: XCD-contiguous ranges
+    int64_t t0;     // first logical tile of this launch (tiles t0 .. ntiles - 1)
+    int64_t nfirst; // bandmode 3: tiles in the first `band` tile columns
 };
 
 GP_DEV void tri_decode(int64_t t, int64_t &bi, int64_t &bj) {
@@ -53,6 +56,26 @@ GP_DEV void tri_decode(int64_t t, int64_t &bi, int64_t &bj) {
 constexpr int SG = 8;
 
 GP_DEV bool decode_tile(const TileMap &tm, int64_t t, int64_t &bi, int64_t &bj) {
+    if (tm.bandmode == 3) {
+        // the first P = band tile columns (rows 0 .. P - 1 a triangle, then P
+        // tiles a row), then the triangle right of them, row by row
+        const int64_t P = tm.band;
+        if (t < tm.nfirst) {
+            const int64_t tri = P * (P + 1) / 2;
+            if (t < tri) {
+                tri_decode(t, bi, bj);
+            } else {
+                const int64_t u = t - tri;
+                bi = P + u / P;
+                bj = u - (bi - P) * P;
+            }
+        } else {
+            tri_decode(t - tm.nfirst, bi, bj);
+            bi += P;
+            bj += P;
+        }
+        return bi < tm.ntm;
+    }
     if (tm.bandmode == 1) {  // tiles on the first `band` tile diagonals: t = bj * band + offset
         bj = t / tm.band;
         bi = bj + (t - bj * tm.band);
@@ -87,9 +110,9 @@ GP_DEV bool decode_tile(const TileMap &tm, int64_t t, int64_t &bi, int64_t &bj) 
 // cluster in a few rows, which contiguous ranges would hand to one or two
 // XCDs.
 GP_DEV int64_t xcd_remap(const TileMap &tm) {
-    if (tm.interleave) return blockIdx.x;
+    if (tm.interleave) return tm.t0 + blockIdx.x;
     const int64_t g8 = gridDim.x >> 3;
-    return (int64_t)(blockIdx.x & 7) * g8 + (blockIdx.x >> 3);
+    return tm.t0 + (int64_t)(blockIdx.x & 7) * g8 + (blockIdx.x >> 3);
 }
 
 // ---------------------------------------------------------------------------
@@ -798,6 +821,8 @@ TileMap make_map(int64_t M, int64_t N, int BM, int BN, int lower) {
     tm.bandmode = 0;
     tm.band = 0;
     tm.interleave = 0;
+    tm.t0 = 0;
+    tm.nfirst = 0;
     tm.ntm = (M + BM - 1) / BM;
     tm.ntn = (N + BN - 1) / BN;
     if (lower && tm.ntn > tm.ntm) tm.ntn = tm.ntm;
@@ -1044,6 +1069,46 @@ hipError_t launch_syrk_lower(hipStream_t s, gp_prec_t prec, int band, const doub
         if (e != hipSuccess) return e;
     }
     return prec == GP_FP32_TRAIL ? run_lowp<1>(s, d, b) : run_lowp<2>(s, d, b);
+}
+
+// FP64 trailing update of the lower triangle of order M (C -= P P^T, P: M x K)
+// in two launches over one tile order in which the first ncols columns come
+// first: part 0 covers those tiles and, to fill the last round of its
+// `slots` concurrent workgroups when it has at least one full round, the
+// first tiles of the rest; part 1 the remaining tiles.  A caller that waits for the first ncols columns only
+// (the lookahead panel) waits for part 0, whose last round no longer runs
+// mostly empty.  Returns hipErrorInvalidValue (nothing launched) when the
+// split does not apply: FP64 only with 16-byte copies, ncols a positive
+// multiple of 128 below M, K a multiple of 8.  part = -1 only asks.
+hipError_t launch_syrk_split(hipStream_t s, const double *P, int64_t ldp, double *C, int64_t ldc, int64_t M,
+                             int64_t ncols, int64_t K, const int32_t *info, int part, int slots, int slab) {
+    GemmDesc d{};
+    d.A = P; d.lda = ldp; d.B = P; d.ldb = ldp; d.C = C; d.ldc = ldc;
+    d.M = M; d.N = M; d.K = K; d.alpha = -1.0; d.beta = 1.0;
+    d.ta = 0; d.tb = 1; d.lower = 1; d.batch = 1; d.info = info; d.slab = slab;
+    const bool x4 = M >= 2 && M % 2 == 0 && ldp % 2 == 0 && ((uintptr_t)P & 15) == 0;
+    if (!x4 || slab == 8 || K % 8 != 0 || ncols <= 0 || ncols % 128 != 0 || ncols >= M || slots <= 0)
+        return hipErrorInvalidValue;
+    if (part < 0) return hipSuccess;
+    TileMap tm = make_map(M, M, 128, 128, 1);
+    const int64_t T = tm.ntm, Pc = ncols / 128;
+    tm.sgm = tm.sgn = 1;
+    tm.bandmode = 3;
+    tm.band = Pc;
+    tm.nfirst = Pc * T - Pc * (Pc - 1) / 2;
+    const int64_t total = tm.nfirst + (T - Pc) * (T - Pc + 1) / 2;
+    // top up only a launch that has full rounds already: a last round of
+    // fewer tiles than compute units runs each tile alone on its unit, faster
+    // than a full round would
+    int64_t split = tm.nfirst;
+    if (tm.nfirst >= slots) split = (tm.nfirst + slots - 1) / slots * (int64_t)slots;
+    if (split > total) split = total;
+    tm.t0 = part == 0 ? 0 : split;
+    tm.ntiles = part == 0 ? split : total;
+    if (tm.ntiles <= tm.t0) return hipSuccess;
+    const int64_t g = ((tm.ntiles - tm.t0 + 7) / 8) * 8;
+    hipLaunchKernelGGL((k_syrk_dma<2, 16, 1, true, 8>), dim3((unsigned)g), dim3(512), 0, s, d, tm);
+    return hipGetLastError();
 }
 
 int64_t packed_rows(int64_t M) { return ((M + 127) / 128 + 1) * 128; }
