@@ -861,12 +861,16 @@ __global__ __launch_bounds__(256, 1) void k_bpersist(const BProb *__restrict__ p
 // W21 = -W22 (L21 W11) -- then forms z_k = W_k (y_k - sum_j L_kj z_j) and
 // the tile's log-determinant / quadratic-form partials.
 // ---------------------------------------------------------------------------
-constexpr int T2 = 128, BK2 = 16;
+// K-slabs of BK2 columns through an NST-stage ring (NST - 1 slabs in flight);
+// SPT slabs per 128-column step.  32-column slabs in two stages (half the
+// barriers, one slab in flight) measured 1 % slower.
+constexpr int T2 = 128, BK2 = 16, NST = 2048 / BK2 / 32, SPT = T2 / BK2;
+static_assert(NST >= 2 && NST * BK2 == 64, "the ring holds 64 columns of both operands (128 KB)");
 constexpr int BP_NW = 8;  // waves per workgroup of the 128-tile launch (two per SIMD)
 
 struct alignas(16) P128Smem {
     union {
-        double ring[4][2][BK2][T2];  // [stage][operand: 0 = L_kj, 1 = L_ij][column][row]
+        double ring[NST][2][BK2][T2];  // [stage][operand: 0 = L_kj, 1 = L_ij][column][row]
         double Wt[T2][T2 + 2];       // off-diagonal task: W_k as [c][m] (row c at 1040 bytes: no bank conflicts)
         struct {                     // diagonal task: 64 x 64 blocks
             double B11[DB][DB + 1], B21[DB][DB + 1], B22[DB][DB + 1], Wb[DB][DB + 1];
@@ -1160,16 +1164,16 @@ __global__ __launch_bounds__(64 * NW, 1) void k_bp128(const BProb *__restrict__ 
         if (tid == 0) sm.state = 1;
         __syncthreads();
         int ready = 0, state = 1;
-        const int nsl = 8 * k;  // K-slabs of the left-looking update (8 per tile column j < k)
+        const int nsl = SPT * k;  // K-slabs of the left-looking update (SPT per tile column j < k)
         const double *LK = uni_ptr(lt + (P.f_off + fk) * (T2 * T2));  // tile (k, 0); (k, j) at + j T2^2
         const double *LI = uni_ptr(lt + (P.f_off + fi) * (T2 * T2));
         // copy c of this wave for slab s into stage st: column w + NW q of the
         // slab, operand op (c = 2 q + op; a diagonal task copies L_kj only, c = q)
-        const int per = diag ? 16 / NW : 32 / NW;  // copies per wave and slab
+        const int per = diag ? BK2 / NW : 2 * BK2 / NW;  // copies per wave and slab
         auto copy_slot = [&](int s, int st, int c) {
             const int q = diag ? c : (c >> 1), op = diag ? 0 : (c & 1);
             const int tt = w + NW * q;
-            const int64_t col = (int64_t)(s >> 3) * T2 * T2 + (int64_t)(16 * (s & 7) + tt) * T2;
+            const int64_t col = (int64_t)(s / SPT) * T2 * T2 + (int64_t)(BK2 * (s % SPT) + tt) * T2;
             lds_dma_dwordx4(uni_ptr((op ? LI : LK) + col), 16u * lane,
                             __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)&sm.u.ring[st][op][tt][0]));
         };
@@ -1177,7 +1181,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_bp128(const BProb *__restrict__ 
             bensure(sm, flags, fl, fi, fk, 0, k, ready, state);
             if (state == 1) {
 #pragma nounroll
-                for (int s0 = 0; s0 < 3 && s0 < nsl; ++s0) {
+                for (int s0 = 0; s0 < NST - 1 && s0 < nsl; ++s0) {
 #pragma nounroll
                     for (int c = 0; c < per; ++c) copy_slot(s0, s0, c);
                 }
@@ -1189,27 +1193,28 @@ __global__ __launch_bounds__(64 * NW, 1) void k_bp128(const BProb *__restrict__ 
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) acc[mb][rb] = v4d{0.0, 0.0, 0.0, 0.0};
 
-        // 2. sum_j L_kj L_ij^T over the slabs through a four-stage ring: the
-        //    copies of slab s + 3 go out between the matrix instructions of
+        // 2. sum_j L_kj L_ij^T over the slabs through the NST-stage ring: the
+        //    copies of slab s + NST - 1 go out between the matrix instructions of
         //    slab s.  The ring's waits and barriers are explicit (vmcnt counts
         //    the copies; a __syncthreads would drain every copy in flight).
         for (int s = 0; s < nsl && state == 1; ++s) {
-            const int st = s & 3, sn = s + 3;
+            const int st = s % NST, sn = s + NST - 1;
             const bool more = sn < nsl;
-            if (more && (sn >> 3) >= ready) {
-                bensure(sm, flags, fl, fi, fk, sn >> 3, k, ready, state);
+            if (more && sn / SPT >= ready) {
+                bensure(sm, flags, fl, fi, fk, sn / SPT, k, ready, state);
                 if (state != 1) {
                     wait_vmcnt<0>();  // no copy may land in LDS after this task
                     continue;         // (the loop condition ends the loop)
                 }
             }
-            const int later = nsl - 1 - s < 2 ? nsl - 1 - s : 2;  // slabs after s already in flight
+            // slabs after s already in flight
+            const int later = nsl - 1 - s < NST - 2 ? nsl - 1 - s : NST - 2;
             if (diag)
-                wait_slabs<16 / NW, 2>(later);
+                wait_slabs<BK2 / NW, NST - 2>(later);
             else
-                wait_slabs<32 / NW, 2>(later);
+                wait_slabs<2 * BK2 / NW, NST - 2>(later);
             asm volatile("" ::: "memory");
-            __builtin_amdgcn_s_barrier();  // slab s is in stage st; stage (s + 3) & 3 was last read in slab s - 1
+            __builtin_amdgcn_s_barrier();  // slab s is in stage st; stage (s - 1) % NST was last read in slab s - 1
             asm volatile("" ::: "memory");
             const double(*Rk)[T2] = sm.u.ring[st][0];
             const double(*Ri)[T2] = sm.u.ring[st][diag ? 0 : 1];
@@ -1237,8 +1242,11 @@ __global__ __launch_bounds__(64 * NW, 1) void k_bp128(const BProb *__restrict__ 
                         for (int rb = 0; rb < RB; ++rb)
                             acc[mb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mb], bb[rb], acc[mb][rb], 0, 0, 0);
                     __builtin_amdgcn_sched_barrier(0);
-                    const int sl = 2 * kk + g;  // eight slots per slab, the copies spread over them
-                    if (more && (sl * per) / 8 != ((sl + 1) * per) / 8) copy_slot(sn, sn & 3, (sl * per) / 8);
+                    // BK2 / 2 slots per slab, the copies spread over them
+                    constexpr int NSLOT = BK2 / 2;
+                    const int sl = 2 * kk + g;
+                    if (more && (sl * per) / NSLOT != ((sl + 1) * per) / NSLOT)
+                        copy_slot(sn, sn % NST, (sl * per) / NSLOT);
                     __builtin_amdgcn_sched_barrier(0);
                 }
                 if (kk + 1 < BK2 / 4) {
