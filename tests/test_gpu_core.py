@@ -91,6 +91,9 @@ POTRF_CASES = [
     (4500, 512, 1, 0, 1, 0, 128), (4500, 512, 1, 8, 1, 3, 128), (4500, 512, 0, 0, 1, 0, 128),
     (8192, 768, 1, 0, 1, 0, 256), (3001, 384, 1, 0, 0, 3, 64), (700, 768, 1, 0, 1, 0, 0),
     (2500, 1024, 1, 0, 1, 0, 0),
+    # split lookahead updates (16-byte copies, ld = n) with compute units reserved
+    # for the panel chain, and with a panel width that is not a multiple of 128
+    (4096, 512, 1, 8, 1, 0, -1), (4098, 576, 1, 0, 1, 0, -1),
 ]
 
 
