@@ -585,7 +585,8 @@ int potrf_impl(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda,
     const bool la = h->opt.lookahead && n > width(0);
     // workgroups of the trailing update that run at once: two per compute
     // unit of the main stream
-    const int slots = 2 * (h->num_cu - (la ? ch.panel_cus : 0) > 0 ? h->num_cu - (la ? ch.panel_cus : 0) : 1);
+    const int main_cus = h->num_cu - (la ? ch.panel_cus : 0);
+    const int slots = 2 * (main_cus > 0 ? main_cus : 1);
     if (la && ch.panel_cus > 0) {
         int rc = make_masked_streams(h, ch.panel_cus);
         if (rc) return rc;
