@@ -102,14 +102,15 @@ void tune_store(gp_handle_t h, const TuneEntry &e) {
     h->tune.push_back(e);
 }
 
-// The factorisation's choices for (prec, n): explicit options (nb > 0) win;
-// with nb = 0 (automatic) a tuned entry for n's size bucket, else the
-// defaults.
 // The tail width: panels that start where at most TAIL_SPAN x tail columns
 // remain are that narrow (when it is below nb), because there a wide panel's
 // chain of diagonal-block steps on the side stream outlasts the trailing
 // update it overlaps.
 constexpr int64_t TAIL_SPAN = 24;
+
+// The factorisation's choices for (prec, n): explicit options (nb > 0) win;
+// with nb = 0 (automatic) a tuned entry for n's size bucket, else the
+// defaults; the tail width from the option (0: 512).
 struct PotrfChoice {
     int64_t nb;
     int panel_cus, slab;

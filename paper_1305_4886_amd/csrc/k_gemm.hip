@@ -1075,11 +1075,12 @@ hipError_t launch_syrk_lower(hipStream_t s, gp_prec_t prec, int band, const doub
 // in two launches over one tile order in which the first ncols columns come
 // first: part 0 covers those tiles and, to fill the last round of its
 // `slots` concurrent workgroups when it has at least one full round, the
-// first tiles of the rest; part 1 the remaining tiles.  A caller that waits for the first ncols columns only
-// (the lookahead panel) waits for part 0, whose last round no longer runs
-// mostly empty.  Returns hipErrorInvalidValue (nothing launched) when the
-// split does not apply: FP64 only with 16-byte copies, ncols a positive
-// multiple of 128 below M, K a multiple of 8.  part = -1 only asks.
+// first tiles of the rest; part 1 the remaining tiles.  A caller that waits
+// for the first ncols columns only (the lookahead panel) waits for part 0,
+// whose last round no longer runs mostly empty.  Returns
+// hipErrorInvalidValue (nothing launched) when the split does not apply:
+// FP64 only with 16-byte copies, ncols a positive multiple of 128 below M,
+// K a multiple of 8.  part = -1 only asks.
 hipError_t launch_syrk_split(hipStream_t s, const double *P, int64_t ldp, double *C, int64_t ldc, int64_t M,
                              int64_t ncols, int64_t K, const int32_t *info, int part, int slots, int slab) {
     GemmDesc d{};
