@@ -319,10 +319,12 @@ def handle():
 
 
 def colmajor_storage(n, ncols=None, ld=None, dtype=None):
-    """Device storage for an n x ncols column-major matrix with leading dim ld."""
+    """Device storage for an n x ncols column-major matrix with leading dim ld
+    (default: n rounded up to even, so that every column starts on a 16-byte
+    boundary and the factorisation's products take their 16-byte copies)."""
     torch = _torch()
     ncols = n if ncols is None else ncols
-    ld = max(n, 1) if ld is None else ld
+    ld = max(n + (n & 1), 1) if ld is None else ld
     return torch.zeros((max(ncols, 1), ld), dtype=dtype or torch.float64, device="cuda")
 
 

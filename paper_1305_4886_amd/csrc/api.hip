@@ -68,7 +68,7 @@ struct Layout {
 
 // Buffers of the panel steps of the factorisation (null when n <= NB).
 struct PanelBufs {
-    double *pbuf = nullptr;  // copy of the rows below a diagonal block, (n - NB) x NB
+    double *pbuf = nullptr;  // copy of the rows below a diagonal block, (n - NB + 1) x NB
     double *vinv = nullptr;  // inverse of a diagonal block, NB x NB
     double *vtmp = nullptr;  // products of the blocked inverse, trtri_tmp_elems(NB)
     void *qbuf = nullptr;    // low-precision packed panel (mixed modes)
@@ -224,7 +224,7 @@ Layout layout(gp_handle_t h, gp_op_t op, int64_t n, int64_t m, gp_prec_t prec) {
     const int64_t NB = panel_width(h, prec, n);
     auto take_panel = [&]() {
         if (n <= NB) return;
-        L.pbuf = take(sizeof(double) * (size_t)(n - NB) * (size_t)NB);
+        L.pbuf = take(sizeof(double) * (size_t)(n - NB + 1) * (size_t)NB);
         L.vinv = take(sizeof(double) * (size_t)NB * (size_t)NB);
         L.vtmp = take(sizeof(double) * trtri_tmp_elems(NB));
         if (prec != GP_FP64) L.qbuf = take(packed_panel_bytes(n - NB, NB));
@@ -298,7 +298,7 @@ Layout layout(gp_handle_t h, gp_op_t op, int64_t n, int64_t m, gp_prec_t prec) {
         L.pflags2 = take(panel_flags_bytes());
         const int64_t NB2 = panel_width(h, GP_FP64, m);
         if (m > NB2) {
-            L.pbuf2 = take(sizeof(double) * (size_t)(m - NB2) * (size_t)NB2);
+            L.pbuf2 = take(sizeof(double) * (size_t)(m - NB2 + 1) * (size_t)NB2);
             L.vinv2 = take(sizeof(double) * (size_t)NB2 * (size_t)NB2);
             L.vtmp2 = take(sizeof(double) * trtri_tmp_elems(NB2));
         }
@@ -627,10 +627,12 @@ int potrf_impl(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda,
     };
     // (2) for the panel [c0, c1), c1 < n
     auto below = [&](hipStream_t st, int64_t c0, int64_t c1) -> int {
-        const int64_t M = n - c1, K = c1 - c0;
-        HIPCHK(launch_copy2d(st, M, K, A + c1 + c0 * lda, lda, pb.pbuf, M));
+        // pbuf's leading dimension is even, with a spare row for an odd M, so
+        // that the product takes the 16-byte copies
+        const int64_t M = n - c1, K = c1 - c0, ldq = M + (M & 1);
+        HIPCHK(launch_copy2d(st, M, K, A + c1 + c0 * lda, lda, pb.pbuf, ldq));
         GemmDesc g{};
-        g.A = pb.pbuf; g.lda = M;
+        g.A = pb.pbuf; g.lda = ldq; g.odd_rows = 1;
         g.B = pb.vinv; g.ldb = K; g.tb = 1;  // op(B)[k, j] = V[j, k], zero for k > j
         g.khi_j = 1;
         g.C = A + c1 + c0 * lda; g.ldc = lda;

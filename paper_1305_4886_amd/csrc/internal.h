@@ -411,6 +411,10 @@ struct GemmDesc {
     int64_t sA, sB, sC; // element strides between batch members
     const int32_t *info; // skip everything if *info != 0 (may be null)
     int slab;            // FP64 direct-to-LDS kernel: K-slab of 16 columns in 2 stages (0, 16) or 8 in 4 (8)
+    int odd_rows;        // 1: one element past the last row of every column of A and of B lies in the
+                         // caller's storage (the factorisation's own panels), so that odd M and N can
+                         // take the 16-byte copies of the direct-to-LDS kernel, whose last row pair
+                         // then reads that element for the row past the matrix
 };
 hipError_t launch_gemm_f64(hipStream_t s, const GemmDesc &d);
 // Trailing updates C -= P P^T restricted to the lower triangle, compute type

@@ -395,9 +395,11 @@ __global__ __launch_bounds__(64 * NW, 2) void k_syrk_dma(GemmDesc d, TileMap tm)
     const int ktail = (int)(d.K - (int64_t)(kl - 1) * BKD);
 
     uint32_t offA[4], offB[4];
-    if (X4) {  // lane l: rows 2 l, 2 l + 1 (pairs past the matrix read its last two rows)
-        const int64_t ra = i0 + 2 * lane < d.M - 1 ? i0 + 2 * lane : d.M - 2;
-        const int64_t rb = j0 + 2 * lane < d.N - 1 ? j0 + 2 * lane : d.N - 2;
+    if (X4) {  // lane l: rows 2 l, 2 l + 1; pairs past the matrix read its last pair, which for an
+               // odd row count holds the element past the last row (odd_rows): it lands in the LDS
+               // row of the first row past the matrix, whose results are never stored
+        const int64_t ra = i0 + 2 * lane < d.M ? i0 + 2 * lane : ((d.M - 1) & ~(int64_t)1);
+        const int64_t rb = j0 + 2 * lane < d.N ? j0 + 2 * lane : ((d.N - 1) & ~(int64_t)1);
         offA[0] = (uint32_t)(8 * ra);
         offB[0] = (uint32_t)(8 * rb);
     } else {   // copy q: rows 32 q + lane / 2, dword lane % 2
@@ -1022,8 +1024,8 @@ hipError_t run_band_f64(hipStream_t s, const GemmDesc &d, int64_t band) {
 namespace {
 
 // Lower trapezoid of 128 x 128 tiles in row-major order (no super-tiles).
-// Operands whose columns start on 16-byte boundaries, with even row counts,
-// take 16-byte copies and two LDS stages of 16 panel columns; others four
+// Operands whose columns start on 16-byte boundaries, with even row counts
+// (or odd ones with GemmDesc::odd_rows), take 16-byte copies and two LDS stages of 16 panel columns; others four
 // stages of 8 columns with 4-byte copies.  Both rings are 64 KB (two
 // workgroups per CU; the 16-byte form runs eight waves per workgroup).  Measured at K = 512, M = 32256 / 16310 / 8210:
 // 65.0 / 60.7 / 53.0 TFLOP/s against 62.8 / 58.5 / 50.1.
@@ -1035,7 +1037,8 @@ hipError_t run_dma(hipStream_t s, const GemmDesc &d) {
     tm.ntiles = d.lower ? tm.ntn * (tm.ntn + 1) / 2 + (tm.ntm - tm.ntn) * tm.ntn : tm.ntm * tm.ntn;
     tm.interleave = (d.klo_i || d.klo_j || d.khi_i || d.khi_j) ? 1 : 0;
     const int64_t g = ((tm.ntiles + 7) / 8) * 8;
-    const bool x4 = d.M >= 2 && d.N >= 2 && d.M % 2 == 0 && d.N % 2 == 0 && d.lda % 2 == 0 && d.ldb % 2 == 0 &&
+    const bool x4 = d.M >= 2 && d.N >= 2 && (d.odd_rows || (d.M % 2 == 0 && d.N % 2 == 0)) && d.lda % 2 == 0 &&
+                    d.ldb % 2 == 0 &&
                     ((uintptr_t)d.A & 15) == 0 && ((uintptr_t)d.B & 15) == 0 &&
                     (d.batch == 1 || (d.sA % 2 == 0 && d.sB % 2 == 0));
     if (x4 && d.slab == 8)  // 8-column slabs in four stages
@@ -1058,6 +1061,7 @@ hipError_t launch_syrk_lower(hipStream_t s, gp_prec_t prec, int band, const doub
     d.A = P; d.lda = ldp; d.B = P; d.ldb = ldp; d.C = C; d.ldc = ldc;
     d.M = M; d.N = N; d.K = K; d.alpha = -1.0; d.beta = 1.0;
     d.ta = 0; d.tb = 1; d.lower = 1; d.batch = 1; d.info = info; d.slab = slab;
+    d.odd_rows = 1;  // P is a panel of the matrix being factored: row M of each of its columns exists
     if (prec == GP_FP64) {
         if (K % 8 == 0) return role == 1 ? run_dma<1>(s, d) : run_dma<2>(s, d);
         if (role == 1) return run_f64<128, 128, 2, 2, 0, 1, 1>(s, d);
@@ -1080,14 +1084,15 @@ hipError_t launch_syrk_lower(hipStream_t s, gp_prec_t prec, int band, const doub
 // whose last round no longer runs mostly empty.  Returns
 // hipErrorInvalidValue (nothing launched) when the split does not apply:
 // FP64 only with 16-byte copies, ncols a positive multiple of 128 below M,
-// K a multiple of 8.  part = -1 only asks.
+// K a multiple of 8.  part = -1 only asks.  P is a panel of the matrix being
+// factored (an odd M reads row M of its columns, see GemmDesc::odd_rows).
 hipError_t launch_syrk_split(hipStream_t s, const double *P, int64_t ldp, double *C, int64_t ldc, int64_t M,
                              int64_t ncols, int64_t K, const int32_t *info, int part, int slots, int slab) {
     GemmDesc d{};
     d.A = P; d.lda = ldp; d.B = P; d.ldb = ldp; d.C = C; d.ldc = ldc;
     d.M = M; d.N = M; d.K = K; d.alpha = -1.0; d.beta = 1.0;
-    d.ta = 0; d.tb = 1; d.lower = 1; d.batch = 1; d.info = info; d.slab = slab;
-    const bool x4 = M >= 2 && M % 2 == 0 && ldp % 2 == 0 && ((uintptr_t)P & 15) == 0;
+    d.ta = 0; d.tb = 1; d.lower = 1; d.batch = 1; d.info = info; d.slab = slab; d.odd_rows = 1;
+    const bool x4 = M >= 2 && ldp % 2 == 0 && ((uintptr_t)P & 15) == 0;
     if (!x4 || slab == 8 || K % 8 != 0 || ncols <= 0 || ncols % 128 != 0 || ncols >= M || slots <= 0)
         return hipErrorInvalidValue;
     if (part < 0) return hipSuccess;
@@ -1141,12 +1146,13 @@ hipError_t launch_band_f64(hipStream_t s, int band, const double *P, int64_t ldp
     d.A = P; d.lda = ldp; d.B = P; d.ldb = ldp; d.C = C; d.ldc = ldc;
     d.M = M; d.N = N; d.K = K; d.alpha = -1.0; d.beta = 1.0;
     d.ta = 0; d.tb = 1; d.lower = 1; d.batch = 1; d.info = info;
+    d.odd_rows = 1;  // P is a panel of the matrix being factored
     TileMap tb = make_map(M, N, 128, 128, 1);
     tb.bandmode = 1;
     tb.band = band;
     tb.ntiles = tb.ntn * band;
     const int64_t g = ((tb.ntiles + 7) / 8) * 8;
-    const bool x4 = M % 2 == 0 && N % 2 == 0 && M >= 2 && ldp % 2 == 0 && ((uintptr_t)P & 15) == 0;
+    const bool x4 = M >= 2 && N >= 2 && ldp % 2 == 0 && ((uintptr_t)P & 15) == 0;
     if (K % 8 != 0)
         hipLaunchKernelGGL((k_gemm_f64<128, 128, 2, 2, 0, 1, 4>), dim3((unsigned)g), dim3(256), 0, s, d, tb);
     else if (x4)

@@ -71,10 +71,11 @@ def test_cross_cov(orc, n, m):
 # (n, panel width (0: the default), lookahead, compute units reserved for the
 #  lookahead chain, fused panel kernel or the per-64-column launch chain,
 #  leading dimension - n, tail panel width (-1: none, 0: the default)).  An odd
-#  leading dimension keeps the trailing update on its 4-byte copies; ld = n
-#  with even n (the benchmark's layout) takes the 16-byte copies of the main
-#  trailing-update kernel.  A tail width w takes over once at most 24 w
-#  columns remain.
+#  leading dimension keeps the trailing update on its 4-byte copies; an even
+#  one (ld = n with even n, the benchmark's layout, or ld = n + 1 or n + 3
+#  with odd n, where the last row pair of a ragged tile reads the element past
+#  the matrix) takes the 16-byte copies of the main trailing-update kernel.
+#  A tail width w takes over once at most 24 w columns remain.
 POTRF_CASES = [
     (1, 256, 1, 8, 1, 3, -1), (2, 256, 1, 8, 1, 3, -1), (63, 256, 1, 8, 1, 3, -1), (64, 256, 1, 8, 1, 3, -1),
     (65, 256, 1, 8, 1, 3, -1), (127, 64, 0, 0, 1, 3, -1), (200, 128, 1, 8, 1, 3, -1), (257, 256, 1, 0, 1, 3, -1),
@@ -94,6 +95,11 @@ POTRF_CASES = [
     # split lookahead updates (16-byte copies, ld = n) with compute units reserved
     # for the panel chain, and with a panel width that is not a multiple of 128
     (4096, 512, 1, 8, 1, 0, -1), (4098, 576, 1, 0, 1, 0, -1),
+    # odd n with an even leading dimension (16-byte copies over an odd row count):
+    # default panel width with split updates, wide then narrow panels, no
+    # lookahead, the launch-chain panels with reserved compute units
+    (4097, 0, 1, 0, 1, 1, 0), (3001, 512, 1, 0, 1, 1, 128), (2049, 256, 0, 0, 1, 1, -1),
+    (1001, 256, 1, 8, 0, 1, -1), (8191, 768, 1, 0, 1, 1, 0),
 ]
 
 

@@ -55,7 +55,7 @@ def test_morton_order_is_sorted_permutation(n):
 
 
 @pytest.mark.parametrize("n,kernel,rho,t2,seed", [(2048, 0, 0.1, 0.1, 1), (3000, 1, 0.05, 0.01, 2),
-                                                  (4096, 1, 0.05, 0.01, 3)])
+                                                  (4096, 1, 0.05, 0.01, 3), (3001, 0, 0.1, 0.1, 4)])
 def test_mixed_fp32_loglik(orc, n, kernel, rho, t2, seed):
     X = synth.uniform_points(n, seed)
     y = synth.smooth_field(X, seed + 7, ell=rho, t2=t2)
@@ -76,7 +76,8 @@ def test_mixed_fp32_loglik(orc, n, kernel, rho, t2, seed):
 
 
 @pytest.mark.parametrize("split", [1, 0])
-@pytest.mark.parametrize("n,kernel,rho,t2,seed", [(2048, 0, 0.1, 0.1, 1), (4096, 1, 0.05, 0.01, 3)])
+@pytest.mark.parametrize("n,kernel,rho,t2,seed", [(2048, 0, 0.1, 0.1, 1), (4096, 1, 0.05, 0.01, 3),
+                                                  (3001, 0, 0.1, 0.1, 4)])
 def test_mixed_bf16_loglik(orc, n, kernel, rho, t2, seed, split):
     # split = 1 (default): hi/lo BF16 parts, about 16 significant bits per
     # operand: the spec bar, loglik within 1e-6 with the solve refined
