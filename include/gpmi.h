@@ -192,7 +192,10 @@ int gp_cross_cov_build(gp_handle_t h, gp_theta_t th, int64_t n, int64_t m, int32
  * panel's diagonal block is factored in 64-column steps and inverted, the rows
  * below it are multiplied by that inverse, then the trailing matrix is
  * updated; with opt.lookahead the next panel's diagonal block is factored on a
- * second stream during that update. */
+ * second stream during that update.  An even lda with A 16-byte aligned lets
+ * the FP64 trailing updates stream the panel with 16-byte copies (the faster
+ * form); with odd n those copies also read A's row n (inside the storage,
+ * since lda > n), whose contents never reach L. */
 int gp_potrf(gp_handle_t h, gp_prec_t prec, int64_t n, double *A, int64_t lda,
              int32_t *info_dev, void *ws, size_t ws_bytes);
 
