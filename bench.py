@@ -55,7 +55,8 @@ def parse():
     return ap.parse_args()
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_syrk_dma_trailing_n32768_hbm_traffic.md")
+TRAFFIC_N = 32768  # the workload size the committed counter summary was taken at
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_syrk_dma_trailing_n%d_hbm_traffic.md" % TRAFFIC_N)
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1305_4886_amd", "csrc", f) for f in ("k_gemm.hip", "internal.h")]
 
 
@@ -69,11 +70,15 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(n=TRAFFIC_N):
     """HBM bytes per trailing-SYRK launch from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by its reading for a plain copy of
-    known size), or None when the kernel sources changed since it was taken."""
+    known size), or None when the kernel sources changed since it was taken
+    or the workload size is not the one it was taken at."""
     import re
+
+    if n != TRAFFIC_N:
+        return None, "counters taken at n = %d only" % TRAFFIC_N
 
     try:
         with open(TRAFFIC_FILE) as fh:
@@ -352,7 +357,7 @@ def main():
                                    "all_finite": bool(torch.isfinite(last["batch"]["out3"]).all().item())}
     syrk_tflops = syrk[2] / (syrk[1] / 1e3) / 1e12 if syrk[1] > 0 else None
     syrk_per_launch_flops = syrk[2] / syrk[0] if syrk[0] else None
-    traffic, traffic_src = measured_traffic()
+    traffic, traffic_src = measured_traffic(n)
     # algorithmic HBM bytes of the same launches (from the library's count): the
     # lower-triangle C entries read and written once, 8 B each way
     alg_bytes = syrk[3] / syrk[0] if syrk[0] else None
